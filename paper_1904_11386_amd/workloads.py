@@ -1,0 +1,331 @@
+"""Seeded synthetic inputs for the two-component capsule lattice Boltzmann step.
+
+This module builds inputs only: initial density layers, triangulated capsule
+meshes and per-capsule parameters.  It holds none of the method's arithmetic
+(no populations, forces, deltas or collisions), so both the HIP path and the
+FP64 oracle may consume what it produces.
+
+Mesh: a geodesic icosphere of frequency n = 2^k (10 n^2 + 2 nodes, 20 n^2
+triangles), the same family of meshes the paper uses for its capsules
+(Sec. III, N_b = 1442 / N_f = 2880 is frequency 12).  It is built from the
+coordinate icosahedron (0, +-1, +-phi) and its cyclic permutations by
+midpoint subdivision with projection to the sphere.  That icosahedron is
+mirror-symmetric in x, y and z.
+
+Coordinates are snapped to multiples of 2^-20 lattice units.  With that
+grid every node position is exactly an integer anchor plus an FP32 offset
+(for offsets below 16 lu), so the FP32 device path and the FP64 oracle start
+from bit-identical positions.
+
+Workloads (sizes as stated, seeds numpy.random.default_rng(1904 + k)):
+  c1      32^3 periodic, A below z = 16, one R = 6 (642-node) capsule at z = 16
+  c2      128^3 periodic, interface z = 64, 8 capsules R = 8 (2562 nodes)
+  c2_64   64^3 periodic, interface z = 32, 2 capsules of the c2 kind
+  c3      256^3 periodic, B droplet R = 60 in A, 64 capsules R = 6 on a shell
+  c3_64   64^3 copy: droplet R = 15, shell 21, capsules R = 6 as many as fit
+  c4      192x96x96 channel, walls y = 0 / 95 at -+0.01, interface z = 48
+  c4_mini 48x24x24 channel, walls y = 0 / 23, one R = 4 (162-node) capsule
+  c5      512^3 periodic, 512 capsules of 162 / 642 / 2562 nodes (R 4 / 6 / 10)
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from typing import List, Optional
+
+import numpy as np
+
+SNAP = 2.0 ** -20
+
+# initial bulk densities of the layered configurations (majority, minority)
+RHO_MAJ = np.float32(0.7)
+RHO_MIN = np.float32(0.04)
+
+
+def _snap(a: np.ndarray) -> np.ndarray:
+    return np.round(np.asarray(a, dtype=np.float64) / SNAP) * SNAP
+
+
+def icosahedron():
+    """Vertices (0,+-1,+-phi) and cyclic permutations; faces found as vertex
+    triples with all three pairwise distances equal to the edge length 2,
+    oriented counter-clockwise seen from outside."""
+    p = (1.0 + math.sqrt(5.0)) / 2.0
+    v = []
+    for s1 in (-1.0, 1.0):
+        for s2 in (-1.0, 1.0):
+            v.append((0.0, s1, s2 * p))
+            v.append((s1, s2 * p, 0.0))
+            v.append((s2 * p, 0.0, s1))
+    v = np.array(v, dtype=np.float64)
+    faces = []
+    n = len(v)
+    for a in range(n):
+        for b in range(a + 1, n):
+            if abs(np.linalg.norm(v[a] - v[b]) - 2.0) > 1e-9:
+                continue
+            for c in range(b + 1, n):
+                if (abs(np.linalg.norm(v[a] - v[c]) - 2.0) < 1e-9
+                        and abs(np.linalg.norm(v[b] - v[c]) - 2.0) < 1e-9):
+                    nrm = np.cross(v[b] - v[a], v[c] - v[a])
+                    if np.dot(nrm, v[a] + v[b] + v[c]) > 0:
+                        faces.append((a, b, c))
+                    else:
+                        faces.append((a, c, b))
+    faces = np.array(faces, dtype=np.int64)
+    assert v.shape == (12, 3) and faces.shape == (20, 3)
+    return v, faces
+
+
+def icosphere(freq: int, radius: float):
+    """Geodesic icosphere of frequency freq (a power of two) and given
+    radius, centred at the origin.  Returns (xyz float64 [N,3] snapped to the
+    2^-20 grid, tri int32 [F,3] outward counter-clockwise)."""
+    if freq < 1 or (freq & (freq - 1)) != 0:
+        raise ValueError("frequency must be a power of two")
+    v, f = icosahedron()
+    v = v / np.linalg.norm(v, axis=1, keepdims=True)
+    verts = [tuple(x) for x in v]
+    faces = [tuple(x) for x in f]
+    level = 1
+    while level < freq:
+        cache = {}
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                m = (np.array(verts[a]) + np.array(verts[b])) * 0.5
+                m = m / np.linalg.norm(m)
+                verts.append(tuple(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for (a, b, c) in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+        level *= 2
+    xyz = np.array(verts, dtype=np.float64) * float(radius)
+    tri = np.array(faces, dtype=np.int32)
+    assert xyz.shape[0] == 10 * freq * freq + 2
+    assert tri.shape[0] == 20 * freq * freq
+    return _snap(xyz), tri
+
+
+@dataclass
+class Capsule:
+    centre: np.ndarray          # [3] float64 (snapped)
+    radius: float
+    freq: int
+    kS: float
+    C: float
+    kV: float
+    theta_deg: float
+
+    def mesh(self):
+        xyz, tri = icosphere(self.freq, self.radius)
+        return _snap(xyz + self.centre[None, :]), tri
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    rhoA: np.ndarray            # float32 [nz, ny, nx]
+    rhoB: np.ndarray            # float32 [nz, ny, nx]
+    capsules: List[Capsule] = field(default_factory=list)
+    tau: tuple = (1.0, 1.0)
+    G: float = 3.6
+    walls: int = 0
+    wall_u_lo: tuple = (0.0, 0.0, 0.0)
+    wall_u_hi: tuple = (0.0, 0.0, 0.0)
+    z_interface: float = 0.0
+    steps: int = 1
+    rho_maj: float = float(RHO_MAJ)
+    rho_min: float = float(RHO_MIN)
+    note: str = ""
+
+    @property
+    def n_lattice(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def meshes(self):
+        """Concatenated meshes: (nodes_per_cap, faces_per_cap, xyz [sum N,3]
+        float64, tri [sum F,3] int32 with capsule-local indices)."""
+        npc, fpc, xs, ts = [], [], [], []
+        for c in self.capsules:
+            xyz, tri = c.mesh()
+            npc.append(xyz.shape[0])
+            fpc.append(tri.shape[0])
+            xs.append(xyz)
+            ts.append(tri)
+        if not xs:
+            return (np.zeros(0, np.int32), np.zeros(0, np.int32),
+                    np.zeros((0, 3)), np.zeros((0, 3), np.int32))
+        return (np.array(npc, np.int32), np.array(fpc, np.int32),
+                np.concatenate(xs, 0), np.concatenate(ts, 0))
+
+    def cap_params(self):
+        a = lambda k: np.array([getattr(c, k) for c in self.capsules], np.float64)
+        return a("kS"), a("C"), a("kV"), a("theta_deg")
+
+
+# Volume-penalty modulus of the workloads.  The paper uses 20 with inertial
+# boundary nodes and bounce-back coupling (Sec. III.B); with massless
+# immersed-boundary nodes 20, 10 and 5 diverge within 100 steps of the 32^3
+# one-capsule case in FP64, and 2 is the largest of {20, 10, 5, 2, 1} that
+# stays stable for 1000 steps.
+KV_DEFAULT = 2.0
+
+
+def layered(nx, ny, nz, z_split):
+    """Component A at majority density for z < z_split, minority above; B the
+    opposite.  Returned float32 [nz, ny, nx]."""
+    z = np.arange(nz)[:, None, None]
+    lower = np.broadcast_to(z < z_split, (nz, ny, nx))
+    rhoA = np.where(lower, RHO_MAJ, RHO_MIN).astype(np.float32)
+    rhoB = np.where(lower, RHO_MIN, RHO_MAJ).astype(np.float32)
+    return np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB)
+
+
+def droplet(n, radius, centre):
+    """Component B droplet of the given radius in component A."""
+    g = np.arange(n, dtype=np.float64)
+    z, y, x = np.meshgrid(g, g, g, indexing="ij")
+    inside = ((x - centre[0]) ** 2 + (y - centre[1]) ** 2
+              + (z - centre[2]) ** 2) < radius * radius
+    rhoB = np.where(inside, RHO_MAJ, RHO_MIN).astype(np.float32)
+    rhoA = np.where(inside, RHO_MIN, RHO_MAJ).astype(np.float32)
+    return rhoA, rhoB
+
+
+def _periodic_dist(a, b, box):
+    d = np.abs(np.asarray(a) - np.asarray(b))
+    box = np.asarray(box, dtype=np.float64)
+    d = np.minimum(d, box - d)
+    return float(np.sqrt((d * d).sum()))
+
+
+def _seed_plane(rng, n_caps, radii, box, z_lo, z_hi, max_tries=200000):
+    centres = []
+    for k in range(n_caps):
+        for _ in range(max_tries):
+            c = np.array([rng.uniform(0, box[0]), rng.uniform(0, box[1]),
+                          rng.uniform(z_lo, z_hi)])
+            if all(_periodic_dist(c, o, box) >= radii[k] + radii[j] + 2.0
+                   for j, o in enumerate(centres)):
+                centres.append(c)
+                break
+        else:
+            raise RuntimeError("could not place capsule %d" % k)
+    return centres
+
+
+def _seed_shell(rng, n_caps, radius_cap, shell_r, centre, box, keep_fitting=False):
+    centres = []
+    tries = 0
+    while len(centres) < n_caps and tries < n_caps * 2000:
+        tries += 1
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        c = np.asarray(centre) + shell_r * d
+        if all(_periodic_dist(c, o, box) >= 2 * radius_cap + 2.0 for o in centres):
+            centres.append(c)
+        elif keep_fitting and tries > 50 * n_caps:
+            break
+    return centres
+
+
+def make(name: str, kV: Optional[float] = None) -> Workload:
+    """Build one named workload (see the module docstring)."""
+    kV = KV_DEFAULT if kV is None else kV
+    if name == "c1":
+        rhoA, rhoB = layered(32, 32, 32, 16)
+        cap = Capsule(_snap(np.array([16.0, 16.0, 16.0])), 6.0, 8, 0.01, 0.0, kV, 90.0)
+        return Workload("c1", 32, 32, 32, rhoA, rhoB, [cap], z_interface=15.5,
+                        steps=1000, note="32^3, one 642-node capsule, FP64 oracle case")
+    if name in ("c2", "c2_64"):
+        rng = np.random.default_rng(1904 + 1)
+        n = 128 if name == "c2" else 64
+        ncap = 8 if name == "c2" else 2
+        cs = _seed_plane(rng, ncap, [8.0] * ncap, (n, n, n), n / 2 - 4, n / 2 + 4)
+        caps = []
+        for c in cs:
+            kS = rng.uniform(0.002, 0.02)
+            th = rng.uniform(60.0, 120.0)
+            caps.append(Capsule(_snap(c), 8.0, 16, kS, 0.0, kV, th))
+        rhoA, rhoB = layered(n, n, n, n // 2)
+        return Workload(name, n, n, n, rhoA, rhoB, caps, z_interface=n / 2 - 0.5,
+                        steps=5000 if name == "c2" else 50)
+    if name in ("c3", "c3_64"):
+        rng = np.random.default_rng(1904 + 2)
+        if name == "c3":
+            n, rd, shell, ncap = 256, 60.0, 66.0, 64
+        else:
+            n, rd, shell, ncap = 64, 15.0, 21.0, 64
+        ctr = (n / 2, n / 2, n / 2)
+        cs = _seed_shell(rng, ncap, 6.0, shell, ctr, (n, n, n), keep_fitting=True)
+        caps = [Capsule(_snap(c), 6.0, 8, 0.01, 0.0, kV, rng.uniform(45.0, 135.0))
+                for c in cs]
+        rhoA, rhoB = droplet(n, rd, ctr)
+        return Workload(name, n, n, n, rhoA, rhoB, caps, z_interface=n / 2,
+                        steps=10000 if name == "c3" else 50)
+    if name in ("c4", "c4_mini"):
+        if name == "c4":
+            nx, ny, nz, R, f = 192, 96, 96, 10.0, 16
+        else:
+            nx, ny, nz, R, f = 48, 24, 24, 4.0, 4
+        rhoA, rhoB = layered(nx, ny, nz, nz // 2)
+        cap = Capsule(_snap(np.array([nx / 2, (ny - 1) / 2.0, nz / 2])), R, f,
+                      0.005, 0.0, kV, 75.0)
+        return Workload(name, nx, ny, nz, rhoA, rhoB, [cap], walls=1,
+                        wall_u_lo=(-0.01, 0.0, 0.0), wall_u_hi=(0.01, 0.0, 0.0),
+                        z_interface=nz / 2 - 0.5, steps=2000 if name == "c4" else 200)
+    if name == "c5":
+        rng = np.random.default_rng(1904 + 4)
+        n = 512
+        kinds = [(4.0, 4), (6.0, 8), (10.0, 16)]
+        radii = [kinds[k % 3][0] for k in range(512)]
+        cs = _seed_plane(rng, 512, radii, (n, n, n), n / 2 - 2, n / 2 + 2)
+        caps = []
+        for k, c in enumerate(cs):
+            R, f = kinds[k % 3]
+            kS = rng.uniform(0.002, 0.02)
+            th = rng.uniform(60.0, 120.0)
+            caps.append(Capsule(_snap(c), R, f, kS, 0.0, kV, th))
+        rhoA, rhoB = layered(n, n, n, n // 2)
+        return Workload("c5", n, n, n, rhoA, rhoB, caps, z_interface=n / 2 - 0.5,
+                        steps=300)
+    raise KeyError(name)
+
+
+def small(nx=40, ny=36, nz=44, ncap=2, freq=4, radius=4.0, theta=(70.0, 115.0),
+          kS=(0.01, 0.004), kV=None, seed=7, walls=0, wall_u=0.01, G=3.6,
+          tau=(1.0, 1.0), z_split=None) -> Workload:
+    """A small seeded workload for parity tests: a ragged box (sizes that are
+    not multiples of the kernel tile widths), a flat interface and a few
+    small capsules near it."""
+    kV = KV_DEFAULT if kV is None else kV
+    rng = np.random.default_rng(seed)
+    zs = nz // 2 if z_split is None else z_split
+    rhoA, rhoB = layered(nx, ny, nz, zs)
+    box = (nx, ny, nz)
+    centres = []
+    for k in range(ncap):
+        for _ in range(10000):
+            lo_y, hi_y = (radius + 4, ny - radius - 5) if walls else (0, ny)
+            c = np.array([rng.uniform(0, nx), rng.uniform(lo_y, hi_y),
+                          rng.uniform(zs - 2.5, zs + 1.5)])
+            if all(_periodic_dist(c, o, box) >= 2 * radius + 2 for o in centres):
+                centres.append(c)
+                break
+    caps = [Capsule(_snap(c), radius, freq, kS[k % len(kS)], 0.0, kV,
+                    theta[k % len(theta)]) for k, c in enumerate(centres)]
+    return Workload("small", nx, ny, nz, rhoA, rhoB, caps, tau=tau, G=G,
+                    walls=walls, wall_u_lo=(-wall_u, 0, 0) if walls else (0, 0, 0),
+                    wall_u_hi=(wall_u, 0, 0) if walls else (0, 0, 0),
+                    z_interface=zs - 0.5, steps=20)
