@@ -1,0 +1,208 @@
+/*
+ * lbm.h - C ABI of the MI355X (gfx950) two-component Shan-Chen D3Q19 lattice
+ * Boltzmann step coupled to triangulated Skalak capsules through an
+ * immersed boundary.
+ *
+ * The problem follows Wouters, Aouane, Krueger, Harting, "Mesoscale
+ * simulation of soft particles with tunable contact angle in multi-component
+ * fluids" (arXiv:1904.11386):
+ *   - fluid: D3Q19 BGK (Sec. II.A, eqs. method:boltzmann, lbm:equilibrium,
+ *     lbm:weights), force as an equilibrium-velocity shift (Sec. II.A), two
+ *     components with the Shan-Chen interaction (Sec. II.D,
+ *     eq. method:shanchen), pseudo-potential psi = rho;
+ *   - capsules: Skalak membrane energy (Sec. II.B, eq. method:strain) and
+ *     volume penalty (Sec. II.B, eq. method:volume), node forces by virtual
+ *     work, forward-Euler node motion (Sec. II.B);
+ *   - wettability: a virtual density offset on the preferred component
+ *     (Sec. II.D) with particle colour Delta rho = cos(theta)
+ *     (Sec. III.D, eq. results:anglescaling), spread over the membrane with
+ *     the same delta and scaled by wet_scale;
+ *   - planar half-way bounce-back walls that may move (Sec. II.C,
+ *     eq. method:SBB);
+ *   - observables: component masses, capsule centre of mass and height
+ *     above the interface (Sec. III.D, eq. interface:contactangle), Taylor
+ *     deformation (Sec. III.A, eq. results:taylorparameter).
+ * The fluid-structure coupling is an immersed boundary with Peskin's
+ * 4-point delta (the method the paper cites as prior art in Sec. I) instead
+ * of the paper's bounce-back coupling.
+ *
+ * Conventions for every call
+ *   - Returns 0 (LBM_OK) or one of the LBM_E* codes below; no exception
+ *     crosses the ABI.  The message of the last error of a context is
+ *     returned by lbm_last_error(ctx); lbm_last_error(NULL) gives the last
+ *     error of a failed lbm_init / lbm_workspace_bytes on this thread.
+ *   - Ownership: the caller owns all device memory (one workspace block,
+ *     which must outlive the context) and all host arrays; host inputs are
+ *     copied, never retained.  The library owns only the host context,
+ *     freed by lbm_destroy.
+ *   - Streams: all device work is enqueued on the HIP stream given to
+ *     lbm_init (NULL = the null stream).  Only lbm_observables, lbm_get_*,
+ *     lbm_debug_* and lbm_adjoint_grads synchronise that stream.
+ *   - Lattice arrays are [z][y][x] with x fastest; nodes are (x, y, z)
+ *     triples in lattice units; angles are degrees.
+ *   - D3Q19 direction order: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 =
+ *     (+-1,+-1,0), (+-1,0,+-1), (0,+-1,+-1) with opposites adjacent.
+ *   - Calls on one context are not thread-safe; different contexts are
+ *     independent.
+ */
+#ifndef LBM_CAPSULES_LBM_H
+#define LBM_CAPSULES_LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    LBM_OK = 0,
+    LBM_EINVAL = 1,     /* bad argument; nothing was enqueued            */
+    LBM_ENOMEM = 2,     /* workspace smaller than lbm_workspace_bytes     */
+    LBM_EHIP = 3,       /* a HIP runtime call failed                      */
+    LBM_ESTATE = 4,     /* call out of order (e.g. capsules after a step) */
+    LBM_EUNSTABLE = 5   /* FP64 mass check found non-finite or drifting mass */
+};
+
+enum { LBM_FP32 = 0, LBM_FP16 = 1 };
+
+enum { LBM_OBJ_COM_Z = 0, LBM_OBJ_TAYLOR_D = 1 };
+
+typedef struct lbm_params {
+    int32_t nx, ny, nz;     /* lattice size, each >= 4                          */
+    int32_t precision;      /* LBM_FP32, or LBM_FP16 population storage         */
+    int32_t walls;          /* 0 periodic; 1 solid rows y = 0 and y = ny - 1   */
+    int32_t n_slots;        /* checkpoint slots carved from the workspace       */
+    int32_t check_every;    /* FP64 mass check period in steps, 0 = never       */
+    int32_t reserved;
+    double tau[2];          /* BGK relaxation times of A and B, each > 0.5      */
+    double G;               /* Shan-Chen coupling G^{AB} = G^{BA} >= 0          */
+    double rho_maj, rho_min;/* densities that scale the colour (Sec. II.D)      */
+    double wall_u_lo[3];    /* velocity of the wall row y = 0                   */
+    double wall_u_hi[3];    /* velocity of the wall row y = ny - 1              */
+    double z_interface;     /* plane from which capsule heights are measured    */
+    double mass_tol;        /* relative mass drift rejected by the check        */
+    double wet_scale;       /* >= 0; virtual density rho_v = 2 cos(theta)
+                               (rho_maj - rho_min) wet_scale; 1 = the colour law
+                               of Sec. II.D as written                           */
+} lbm_params;
+
+typedef struct lbm_obs {
+    double mass[2];         /* sum over fluid nodes of the post-collision populations */
+    double momentum[3];     /* sum over fluid nodes and components of f* c           */
+    int64_t step;           /* completed time steps                                   */
+} lbm_obs;
+
+typedef struct lbm_capsule_obs {
+    double com[3];          /* mean node position (equal node masses)                */
+    double volume, area;    /* enclosed volume and surface area                      */
+    double axes[3];         /* ellipsoid half-axes, ascending, same volume moments   */
+    double taylor_D;        /* (a_max - a_min) / (a_max + a_min)                     */
+    double height;          /* com[2] - z_interface                                  */
+} lbm_capsule_obs;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Size query.  *bytes receives the device workspace size for a lattice p
+ * with room for max_nodes membrane nodes and max_faces triangles in total.
+ * Host-only, no device work.  LBM_EINVAL on a bad p or negative sizes. */
+int lbm_workspace_bytes(const lbm_params* p, int64_t max_nodes, int64_t max_faces,
+                        int64_t* bytes);
+
+/* Create a context.  rhoA, rhoB: host float arrays of nx*ny*nz initial
+ * densities (> 0 on fluid nodes).  The populations start as the rest
+ * equilibrium w_i rho (u = 0) and are streamed by the first step.
+ * workspace: device pointer of at least ws_bytes bytes, 256-byte aligned,
+ * ws_bytes >= lbm_workspace_bytes(p, max_nodes, max_faces).
+ * hip_stream: a hipStream_t or NULL.  Validates p (tau > 0.5, sizes >= 4,
+ * G >= 0, finite wall velocities, precision in {FP32, FP16}) before any
+ * device work; errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP. */
+int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB,
+             void* workspace, int64_t ws_bytes, int64_t max_nodes, int64_t max_faces,
+             void* hip_stream, lbm_ctx** out);
+
+/* Append n_caps capsules (Sec. II.B).  Host arrays: nodes_per_cap[n_caps],
+ * faces_per_cap[n_caps]; xyz_rest[sum nodes][3] absolute rest positions,
+ * which are also the initial positions; tri[sum faces][3] capsule-local node
+ * indices, counter-clockwise seen from outside; kS (> 0), C (> -1/2),
+ * kV (>= 0) and theta_deg (in [0, 180]) per capsule.  Each capsule is stored
+ * as an integer anchor (its rest centroid rounded) plus FP32 offsets; the
+ * reference metric, rest areas and rest volume are computed in FP64.  Only
+ * before the first lbm_step (else LBM_ESTATE); LBM_ENOMEM beyond the sizes
+ * given to lbm_init.  *first_id (may be NULL) receives the index of the
+ * first new capsule. */
+int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
+                     const int32_t* faces_per_cap, const double* xyz_rest,
+                     const int32_t* tri, const double* kS, const double* C,
+                     const double* kV, const double* theta_deg, int32_t* first_id);
+
+/* Advance nsteps >= 0 time steps, asynchronously on the stream.  With
+ * check_every > 0 the FP64 mass check runs every check_every steps and
+ * synchronises; it returns LBM_EUNSTABLE when a component mass is not
+ * finite or has drifted by more than mass_tol relative to its start. */
+int lbm_step(lbm_ctx* ctx, int32_t nsteps);
+
+/* Kernel groups of one step, in launch order (for lbm_step_timed). */
+enum {
+    LBM_K_CLEAR = 0,    /* zero last step's immersed-boundary tiles        */
+    LBM_K_DENSITY = 1,  /* density pass over the lattice                   */
+    LBM_K_VOLUME = 2,   /* FP64 capsule volumes                            */
+    LBM_K_FACES = 3,    /* Skalak + volume forces per triangle             */
+    LBM_K_NODES = 4,    /* node gather, wettability reaction, binning      */
+    LBM_K_SCAN = 5,     /* scan of the tile bins                           */
+    LBM_K_SCATTER = 6,  /* counting-sort scatter                           */
+    LBM_K_SPREAD = 7,   /* LDS-binned spreading                            */
+    LBM_K_COLLIDE = 8,  /* fused pull + force + collide over the lattice   */
+    LBM_K_INTERP = 9,   /* interpolation and node advection                */
+    LBM_NK = 10
+};
+
+/* As lbm_step (without the mass check), and synchronises: HIP events are
+ * recorded on the stream before each kernel group, and kernel_ms[LBM_NK]
+ * receives the summed elapsed milliseconds of each group over the nsteps
+ * (>= 1) steps. */
+int lbm_step_timed(lbm_ctx* ctx, int32_t nsteps, double* kernel_ms);
+
+/* FP64 observables of the current state (synchronises).  caps may be NULL,
+ * else it must hold one entry per capsule. */
+int lbm_observables(lbm_ctx* ctx, lbm_obs* out, lbm_capsule_obs* caps);
+
+/* Macroscopic fields of the most recent collision (time level step - 1):
+ * rhoA, rhoB [N] and u [3][N] (x, y, z planes of the physical velocity with
+ * the half-force term).  Host buffers, any may be NULL.  LBM_ESTATE before
+ * the first step.  Synchronises. */
+int lbm_get_fields(lbm_ctx* ctx, float* rhoA, float* rhoB, float* u);
+
+/* Current absolute node positions, anchor + offset, [nodes][3].  Synchronises. */
+int lbm_get_nodes(lbm_ctx* ctx, double* xyz);
+
+/* Node forces F_b [nodes][3] used by the most recent step (elastic, volume
+ * and wettability reaction).  Synchronises; LBM_ESTATE before the first step. */
+int lbm_get_node_forces(lbm_ctx* ctx, float* F);
+
+/* Spread fields of the most recent step: F_ib [3][N] and the virtual
+ * densities phi [2][N] (A, B).  Synchronises; LBM_ESTATE before a step. */
+int lbm_get_spread(lbm_ctx* ctx, float* Fib, float* phi);
+
+/* Binning of the current node positions: tile_of_node[nodes] is the index
+ * of the 8x8x8 tile holding the node floor(X) (tiles numbered x fastest),
+ * base_idx[nodes][3] the unwrapped stencil base floor(X) - 1.  Recomputed
+ * from the positions on the device.  Synchronises. */
+int lbm_debug_bins(lbm_ctx* ctx, int32_t* tile_of_node, int32_t* base_idx);
+
+/* Copy the full state (populations, density buffers, node positions, step
+ * counter) to / from slot 0 <= slot < n_slots inside the workspace.
+ * Asynchronous on the stream. */
+int lbm_state_save(lbm_ctx* ctx, int32_t slot);
+int lbm_state_load(lbm_ctx* ctx, int32_t slot);
+
+/* Free the host context (not the workspace).  NULL is ignored. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Last error message of ctx, or of this thread's failed init when NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_CAPSULES_LBM_H */

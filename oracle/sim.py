@@ -12,7 +12,8 @@ positions X^n.  The step, in this order:
     reaction.  The wettability term follows Sec. II.D: a virtual density
     offset rho_v added to the preferred component, with the particle colour
     Delta rho = rho_v / (2 (rho_maj - rho_min)) and Delta rho = cos(theta)
-    (the theta = acos(Delta rho) law of Sec. III.D).  Carried to the
+    (the theta = acos(Delta rho) law of Sec. III.D), times a strength
+    factor wet_scale (1 = the law as written).  Carried to the
     immersed boundary, the offset is a field phi(x) = |rho_v| sum_b A_b delta
     (x - X_b) added to the preferred component's pseudo-potential when the
     other component's force is formed, and its reaction on node b is
@@ -66,7 +67,7 @@ class OracleSim:
 
     def __init__(self, rhoA, rhoB, caps=(), tau=(1.0, 1.0), G=3.6, walls=0,
                  u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0), rho_maj=0.7,
-                 rho_min=0.04, z_interface=0.0, differentiable=False):
+                 rho_min=0.04, z_interface=0.0, wet_scale=1.0, differentiable=False):
         rhoA = torch.as_tensor(rhoA, dtype=DT)
         rhoB = torch.as_tensor(rhoB, dtype=DT)
         self.nz, self.ny, self.nx = rhoA.shape
@@ -78,6 +79,7 @@ class OracleSim:
         self.u_hi = tuple(float(v) for v in u_hi)
         self.rho_maj = float(rho_maj)
         self.rho_min = float(rho_min)
+        self.wet_scale = float(wet_scale)
         self.z_interface = float(z_interface)
         self.diff = differentiable
         self.fpost = lattice.rest_populations(rhoA, rhoB)
@@ -108,7 +110,7 @@ class OracleSim:
     def colour(self, k):
         """(rho_v signed, preferred component) of capsule k."""
         dr = cos_deg(self.caps[k]["theta"])
-        rv = 2.0 * dr * (self.rho_maj - self.rho_min)
+        rv = 2.0 * dr * (self.rho_maj - self.rho_min) * self.wet_scale
         if isinstance(rv, torch.Tensor):
             pref = 0 if float(rv) >= 0.0 else 1
         else:
@@ -207,6 +209,6 @@ def from_workload(wl, differentiable=False, **over):
         caps.append(dict(xyz=xyz, tri=tri, kS=c.kS, C=c.C, kV=c.kV, theta=c.theta_deg))
     kw = dict(tau=wl.tau, G=wl.G, walls=wl.walls, u_lo=wl.wall_u_lo, u_hi=wl.wall_u_hi,
               rho_maj=wl.rho_maj, rho_min=wl.rho_min, z_interface=wl.z_interface,
-              differentiable=differentiable)
+              wet_scale=wl.wet_scale, differentiable=differentiable)
     kw.update(over)
     return OracleSim(wl.rhoA.astype("float64"), wl.rhoB.astype("float64"), caps, **kw)

@@ -1,0 +1,679 @@
+// Host side of the C ABI declared in include/lbm.h: validation, workspace
+// carving, capsule set-up (reference metric, rest areas and volume in FP64),
+// the per-step launch sequence on the caller's stream, and the FP64
+// observables.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lbm.h"
+#include "lbm_internal.h"
+
+using namespace lbmx;
+
+namespace {
+
+thread_local std::string g_init_error;
+
+struct Layout {
+    size_t total = 0;
+    size_t f[2], rho[2], fib, u;
+    size_t tile_flag, tile_count, tile_offset, home_start, touched[2], home[2], counters;
+    size_t off_hi, off_lo, node_cap, node_wet, node_F, node_tile, node_rank, sorted, csr_ptr, csr_idx,
+        dbg_bins;
+    size_t tri, fref, face_cap, face_F;
+    size_t caps, capV, cap_mom, red;
+    size_t slot0, slot_bytes;
+    size_t slot_f, slot_rho, slot_off;   // offsets inside a slot
+    int64_t tiles, max_caps;
+};
+
+size_t take(size_t& cur, size_t bytes) {
+    const size_t at = (cur + 255) & ~size_t(255);
+    cur = at + bytes;
+    return at;
+}
+
+Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
+    Layout l;
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    const int64_t T = (int64_t)((p->nx + TILE - 1) / TILE) * ((p->ny + TILE - 1) / TILE) * ((p->nz + TILE - 1) / TILE);
+    const int64_t nb = std::max<int64_t>(max_nodes, 1), nf = std::max<int64_t>(max_faces, 1);
+    l.tiles = T;
+    l.max_caps = nb / 12 + 1;
+    size_t c = 0;
+    const size_t fbytes = (size_t)2 * Q * N * sizeof(float);
+    l.f[0] = take(c, fbytes);
+    l.f[1] = take(c, fbytes);
+    l.rho[0] = take(c, 2 * N * sizeof(float));
+    l.rho[1] = take(c, 2 * N * sizeof(float));
+    l.fib = take(c, 5 * N * sizeof(float));
+    l.u = take(c, 3 * N * sizeof(float));
+    l.tile_flag = take(c, T * 4);
+    l.tile_count = take(c, T * 4);
+    l.tile_offset = take(c, T * 4);
+    l.home_start = take(c, T * 4);
+    l.touched[0] = take(c, T * 4);
+    l.touched[1] = take(c, T * 4);
+    l.home[0] = take(c, T * 4);
+    l.home[1] = take(c, T * 4);
+    l.counters = take(c, 8 * 4);
+    l.off_hi = take(c, 3 * nb * 4);
+    l.off_lo = take(c, 3 * nb * 4);
+    l.node_cap = take(c, nb * 4);
+    l.node_wet = take(c, nb * 4);
+    l.node_F = take(c, 3 * nb * 4);
+    l.node_tile = take(c, nb * 4);
+    l.node_rank = take(c, nb * 4);
+    l.sorted = take(c, nb * 4);
+    l.csr_ptr = take(c, (nb + 1) * 4);
+    l.csr_idx = take(c, 3 * nf * 4);
+    l.dbg_bins = take(c, 4 * nb * 4);
+    l.tri = take(c, 3 * nf * 4);
+    l.fref = take(c, nf * sizeof(FaceRef));
+    l.face_cap = take(c, nf * 4);
+    l.face_F = take(c, 9 * nf * 4);
+    l.caps = take(c, l.max_caps * sizeof(CapDev));
+    l.capV = take(c, l.max_caps * 8);
+    l.cap_mom = take(c, l.max_caps * MOM_STRIDE * 8);
+    l.red = take(c, RED_BLOCKS * 8 * 8);
+    size_t s = 0;
+    l.slot_f = take(s, fbytes);
+    l.slot_rho = take(s, 4 * N * sizeof(float));
+    l.slot_off = take(s, 6 * nb * 4);
+    l.slot_bytes = (s + 255) & ~size_t(255);
+    l.slot0 = take(c, (size_t)std::max(p->n_slots, 0) * l.slot_bytes);
+    l.total = (c + 255) & ~size_t(255);
+    return l;
+}
+
+std::string validate(const lbm_params* p) {
+    if (!p) return "params is NULL";
+    if (p->nx < 4 || p->ny < 4 || p->nz < 4) return "lattice sizes must be >= 4";
+    if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34)) return "lattice too large";
+    if (p->precision != LBM_FP32) return "precision: only LBM_FP32 is available in this build";
+    if (p->walls != 0 && p->walls != 1) return "walls must be 0 or 1";
+    if (p->walls && p->ny < 5) return "walls need ny >= 5";
+    for (int c = 0; c < 2; ++c)
+        if (!(p->tau[c] > 0.5) || !isfinite(p->tau[c])) return "tau must be finite and > 0.5";
+    if (!(p->G >= 0.0) || !isfinite(p->G)) return "G must be finite and >= 0";
+    for (int k = 0; k < 3; ++k)
+        if (!isfinite(p->wall_u_lo[k]) || !isfinite(p->wall_u_hi[k])) return "wall velocities must be finite";
+    if (!isfinite(p->rho_maj) || !isfinite(p->rho_min)) return "rho_maj / rho_min must be finite";
+    if (!(p->wet_scale >= 0.0) || !isfinite(p->wet_scale)) return "wet_scale must be finite and >= 0";
+    if (p->n_slots < 0 || p->n_slots > 4096) return "n_slots out of range";
+    if (p->check_every < 0) return "check_every must be >= 0";
+    return "";
+}
+
+double cos_deg(double t) { return t == 90.0 ? 0.0 : cos(t * (M_PI / 180.0)); }
+
+}  // namespace
+
+struct lbm_ctx {
+    lbm_params p;
+    Lattice L;
+    Dev d;
+    Layout lay;
+    char* ws = nullptr;
+    hipStream_t stream = nullptr;
+    int64_t max_nodes = 0, max_faces = 0;
+    int64_t step = 0;
+    int flip = 0;                  // parity of the immersed-boundary tile lists
+    double mass0[2] = {0, 0};
+    std::vector<int64_t> slot_step;
+    // host copies of the capsule set
+    std::vector<CapDev> caps;
+    std::vector<float> off;        // [nodes][3]
+    std::vector<int> node_cap;
+    std::vector<float> node_wet;
+    std::vector<int> tri_global;
+    std::vector<FaceRef> fref;
+    std::vector<int> face_cap;
+    int n_nodes = 0, n_faces = 0;
+    std::string err;
+
+    int fail(int code, const char* fmt, ...) {
+        char buf[512];
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(buf, sizeof buf, fmt, ap);
+        va_end(ap);
+        err = buf;
+        return code;
+    }
+};
+
+#define HIPCHK(ctx, call)                                                                        \
+    do {                                                                                         \
+        hipError_t e_ = (call);                                                                  \
+        if (e_ != hipSuccess) return (ctx)->fail(LBM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+extern "C" {
+
+int lbm_workspace_bytes(const lbm_params* p, int64_t max_nodes, int64_t max_faces, int64_t* bytes) {
+    const std::string e = validate(p);
+    if (!e.empty()) { g_init_error = e; return LBM_EINVAL; }
+    if (max_nodes < 0 || max_faces < 0 || !bytes) { g_init_error = "bad sizes or NULL output"; return LBM_EINVAL; }
+    *bytes = (int64_t)make_layout(p, max_nodes, max_faces).total;
+    return LBM_OK;
+}
+
+int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* workspace, int64_t ws_bytes,
+             int64_t max_nodes, int64_t max_faces, void* hip_stream, lbm_ctx** out) {
+    const std::string e = validate(p);
+    if (!e.empty()) { g_init_error = e; return LBM_EINVAL; }
+    if (!out || !rhoA || !rhoB || !workspace || max_nodes < 0 || max_faces < 0) {
+        g_init_error = "NULL argument or negative size";
+        return LBM_EINVAL;
+    }
+    if (((uintptr_t)workspace & 255) != 0) { g_init_error = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
+    const Layout lay = make_layout(p, max_nodes, max_faces);
+    if (ws_bytes < (int64_t)lay.total) {
+        g_init_error = "workspace too small: need " + std::to_string(lay.total) + " bytes";
+        return LBM_ENOMEM;
+    }
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    double m[2] = {0, 0};
+    for (int64_t k = 0; k < N; ++k) {
+        const int y = (int)((k / p->nx) % p->ny);
+        const bool fluid = !p->walls || (y > 0 && y < p->ny - 1);
+        if (!fluid) continue;
+        if (!(rhoA[k] > 0.0f) || !(rhoB[k] > 0.0f) || !isfinite(rhoA[k]) || !isfinite(rhoB[k])) {
+            g_init_error = "initial densities must be finite and > 0 on fluid nodes";
+            return LBM_EINVAL;
+        }
+        m[0] += rhoA[k];
+        m[1] += rhoB[k];
+    }
+    lbm_ctx* c = new lbm_ctx();
+    c->p = *p;
+    c->lay = lay;
+    c->ws = (char*)workspace;
+    c->stream = (hipStream_t)hip_stream;
+    c->max_nodes = max_nodes;
+    c->max_faces = max_faces;
+    c->mass0[0] = m[0];
+    c->mass0[1] = m[1];
+    c->slot_step.assign(std::max(p->n_slots, 0), -1);
+    Lattice& L = c->L;
+    L.nx = p->nx; L.ny = p->ny; L.nz = p->nz;
+    L.ntx = (p->nx + TILE - 1) / TILE; L.nty = (p->ny + TILE - 1) / TILE; L.ntz = (p->nz + TILE - 1) / TILE;
+    L.n = N;
+    L.walls = p->walls;
+    L.G = (float)p->G;
+    for (int k = 0; k < 2; ++k) { L.tau[k] = (float)p->tau[k]; L.omega[k] = (float)(1.0 / p->tau[k]); }
+    for (int k = 0; k < 3; ++k) { L.uw_lo[k] = (float)p->wall_u_lo[k]; L.uw_hi[k] = (float)p->wall_u_hi[k]; }
+    Dev& d = c->d;
+    char* w = c->ws;
+    d.f[0] = (float*)(w + lay.f[0]);
+    d.f[1] = (float*)(w + lay.f[1]);
+    d.rho[0] = (float*)(w + lay.rho[0]);
+    d.rho[1] = (float*)(w + lay.rho[1]);
+    d.fib = (float*)(w + lay.fib);
+    d.u = (float*)(w + lay.u);
+    d.tile_flag = (int*)(w + lay.tile_flag);
+    d.tile_count = (int*)(w + lay.tile_count);
+    d.tile_offset = (int*)(w + lay.tile_offset);
+    d.home_start = (int*)(w + lay.home_start);
+    for (int k = 0; k < 2; ++k) { d.touched[k] = (int*)(w + lay.touched[k]); d.home[k] = (int*)(w + lay.home[k]); }
+    d.counters = (int*)(w + lay.counters);
+    d.off_hi = (float*)(w + lay.off_hi);
+    d.off_lo = (float*)(w + lay.off_lo);
+    d.node_cap = (int*)(w + lay.node_cap);
+    d.node_wet = (float*)(w + lay.node_wet);
+    d.node_F = (float*)(w + lay.node_F);
+    d.node_tile = (int*)(w + lay.node_tile);
+    d.node_rank = (int*)(w + lay.node_rank);
+    d.sorted = (int*)(w + lay.sorted);
+    d.csr_ptr = (int*)(w + lay.csr_ptr);
+    d.csr_idx = (int*)(w + lay.csr_idx);
+    d.dbg_bins = (int*)(w + lay.dbg_bins);
+    d.tri = (int*)(w + lay.tri);
+    d.fref = (FaceRef*)(w + lay.fref);
+    d.face_cap = (int*)(w + lay.face_cap);
+    d.face_F = (float*)(w + lay.face_F);
+    d.caps = (CapDev*)(w + lay.caps);
+    d.capV = (double*)(w + lay.capV);
+    d.cap_mom = (double*)(w + lay.cap_mom);
+    d.red = (double*)(w + lay.red);
+
+    hipStream_t s = c->stream;
+    // initial densities into both density buffers (the previous-step buffer
+    // feeds the wall bounce-back of the first step), rest populations in f[0]
+    auto bad = [&](hipError_t er, const char* what) {
+        g_init_error = std::string(what) + ": " + hipGetErrorString(er);
+        delete c;
+        return LBM_EHIP;
+    };
+    hipError_t er;
+    for (int b = 0; b < 2; ++b) {
+        if ((er = hipMemcpyAsync(d.rho[b], rhoA, N * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return bad(er, "hipMemcpyAsync");
+        if ((er = hipMemcpyAsync(d.rho[b] + N, rhoB, N * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return bad(er, "hipMemcpyAsync");
+    }
+    launch_init_rest(L, d.f[0], d.rho[0], d.rho[0] + N, s);
+    if ((er = hipMemsetAsync(d.fib, 0, 5 * N * sizeof(float), s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipMemsetAsync(d.tile_flag, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipMemsetAsync(d.tile_count, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipMemsetAsync(d.counters, 0, 8 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipGetLastError()) != hipSuccess) return bad(er, "init kernel launch");
+    // the host arrays may be freed once the copies are done
+    if ((er = hipStreamSynchronize(s)) != hipSuccess) return bad(er, "hipStreamSynchronize");
+    *out = c;
+    return LBM_OK;
+}
+
+int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, const int32_t* faces_per_cap,
+                     const double* xyz_rest, const int32_t* tri, const double* kS, const double* C,
+                     const double* kV, const double* theta_deg, int32_t* first_id) {
+    if (!c) return LBM_EINVAL;
+    if (c->step != 0) return c->fail(LBM_ESTATE, "capsules must be added before the first step");
+    if (n_caps < 0) return c->fail(LBM_EINVAL, "n_caps < 0");
+    if (n_caps == 0) { if (first_id) *first_id = (int32_t)c->caps.size(); return LBM_OK; }
+    if (!nodes_per_cap || !faces_per_cap || !xyz_rest || !tri || !kS || !C || !kV || !theta_deg)
+        return c->fail(LBM_EINVAL, "NULL capsule array");
+    int64_t add_nodes = 0, add_faces = 0;
+    for (int k = 0; k < n_caps; ++k) {
+        if (nodes_per_cap[k] < 4 || faces_per_cap[k] < 4) return c->fail(LBM_EINVAL, "capsule %d: too few nodes/faces", k);
+        if (!(kS[k] > 0.0) || !(C[k] > -0.5) || !(kV[k] >= 0.0) || !isfinite(kS[k]) || !isfinite(C[k]) || !isfinite(kV[k]))
+            return c->fail(LBM_EINVAL, "capsule %d: need kS > 0, C > -1/2, kV >= 0", k);
+        if (!(theta_deg[k] >= 0.0 && theta_deg[k] <= 180.0)) return c->fail(LBM_EINVAL, "capsule %d: theta outside [0, 180]", k);
+        add_nodes += nodes_per_cap[k];
+        add_faces += faces_per_cap[k];
+    }
+    if (c->n_nodes + add_nodes > c->max_nodes || c->n_faces + add_faces > c->max_faces ||
+        (int64_t)c->caps.size() + n_caps > c->lay.max_caps)
+        return c->fail(LBM_ENOMEM, "capsules exceed the workspace sizes given to lbm_init");
+    const double rv_scale = 2.0 * (c->p.rho_maj - c->p.rho_min) * c->p.wet_scale;
+    int64_t nofs = 0, fofs = 0;
+    // validate the whole batch before touching the context
+    for (int k = 0; k < n_caps; ++k) {
+        for (int f = 0; f < faces_per_cap[k]; ++f)
+            for (int j = 0; j < 3; ++j) {
+                const int v = tri[3 * (fofs + f) + j];
+                if (v < 0 || v >= nodes_per_cap[k]) return c->fail(LBM_EINVAL, "capsule %d: triangle index out of range", k);
+            }
+        for (int64_t b = 0; b < 3 * (int64_t)nodes_per_cap[k]; ++b)
+            if (!isfinite(xyz_rest[3 * nofs + b])) return c->fail(LBM_EINVAL, "capsule %d: non-finite position", k);
+        nofs += nodes_per_cap[k];
+        fofs += faces_per_cap[k];
+    }
+    if (first_id) *first_id = (int32_t)c->caps.size();
+    nofs = fofs = 0;
+    for (int k = 0; k < n_caps; ++k) {
+        const int nn = nodes_per_cap[k], nf = faces_per_cap[k];
+        const double* X = xyz_rest + 3 * nofs;
+        const int32_t* T = tri + 3 * fofs;
+        CapDev cd;
+        double mean[3] = {0, 0, 0};
+        for (int b = 0; b < nn; ++b)
+            for (int j = 0; j < 3; ++j) mean[j] += X[3 * b + j];
+        for (int j = 0; j < 3; ++j) cd.anchor[j] = (int)floor(mean[j] / nn + 0.5);
+        cd.node_start = c->n_nodes;
+        cd.node_count = nn;
+        cd.face_start = c->n_faces;
+        cd.face_count = nf;
+        const double dr = cos_deg(theta_deg[k]);
+        const double rv = dr * rv_scale;
+        cd.pref = rv >= 0.0 ? 0 : 1;
+        cd.rv_abs = (float)fabs(rv);
+        cd.kS = (float)kS[k];
+        cd.C = (float)C[k];
+        cd.kV = (float)kV[k];
+        // rest geometry in FP64, relative to the anchor
+        std::vector<double> R(3 * (size_t)nn);
+        for (int b = 0; b < nn; ++b)
+            for (int j = 0; j < 3; ++j) R[3 * b + j] = X[3 * b + j] - cd.anchor[j];
+        std::vector<double> narea(nn, 0.0);
+        double V0 = 0.0;
+        const int cap_id = (int)c->caps.size();
+        for (int f = 0; f < nf; ++f) {
+            const double* a = &R[3 * T[3 * f + 0]];
+            const double* b = &R[3 * T[3 * f + 1]];
+            const double* cc = &R[3 * T[3 * f + 2]];
+            double e1[3], e2[3];
+            for (int j = 0; j < 3; ++j) { e1[j] = b[j] - a[j]; e2[j] = cc[j] - a[j]; }
+            const double m11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+            const double m12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+            const double m22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+            const double det = m11 * m22 - m12 * m12;
+            if (!(det > 0.0)) return c->fail(LBM_EINVAL, "capsule %d: degenerate triangle %d", k, f);
+            FaceRef fr;
+            fr.q11 = (float)(m22 / det);
+            fr.q12 = (float)(-m12 / det);
+            fr.q22 = (float)(m11 / det);
+            fr.inv_det0 = (float)(1.0 / det);
+            const double A0 = 0.5 * sqrt(det);
+            fr.A0 = (float)A0;
+            for (int j = 0; j < 3; ++j) narea[T[3 * f + j]] += A0 / 3.0;
+            V0 += (a[0] * (b[1] * cc[2] - b[2] * cc[1]) + a[1] * (b[2] * cc[0] - b[0] * cc[2])
+                   + a[2] * (b[0] * cc[1] - b[1] * cc[0])) / 6.0;
+            c->fref.push_back(fr);
+            c->face_cap.push_back(cap_id);
+            for (int j = 0; j < 3; ++j) c->tri_global.push_back(cd.node_start + T[3 * f + j]);
+        }
+        if (!(V0 > 0.0)) return c->fail(LBM_EINVAL, "capsule %d: rest volume not positive (triangles must face outward)", k);
+        cd.V0 = V0;
+        for (int b = 0; b < nn; ++b) {
+            for (int j = 0; j < 3; ++j) c->off.push_back((float)R[3 * b + j]);
+            c->node_cap.push_back(cap_id);
+            c->node_wet.push_back((float)(fabs(rv) * narea[b]));
+        }
+        c->caps.push_back(cd);
+        c->n_nodes += nn;
+        c->n_faces += nf;
+        nofs += nn;
+        fofs += nf;
+    }
+    // node -> (face, corner) adjacency, in face order
+    std::vector<int> ptr(c->n_nodes + 1, 0), idx(3 * (size_t)c->n_faces);
+    for (int f = 0; f < c->n_faces; ++f)
+        for (int j = 0; j < 3; ++j) ptr[c->tri_global[3 * f + j] + 1]++;
+    for (int b = 0; b < c->n_nodes; ++b) ptr[b + 1] += ptr[b];
+    std::vector<int> fill(ptr.begin(), ptr.end() - 1);
+    for (int f = 0; f < c->n_faces; ++f)
+        for (int j = 0; j < 3; ++j) idx[fill[c->tri_global[3 * f + j]]++] = 3 * f + j;
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    const size_t nb = c->n_nodes, nf = c->n_faces;
+    std::vector<float> zeros(3 * nb, 0.0f);
+    HIPCHK(c, hipMemcpyAsync(d.off_hi, c->off.data(), 3 * nb * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.off_lo, zeros.data(), 3 * nb * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.node_cap, c->node_cap.data(), nb * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.node_wet, c->node_wet.data(), nb * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.csr_ptr, ptr.data(), (nb + 1) * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.csr_idx, idx.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.tri, c->tri_global.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.fref, c->fref.data(), nf * sizeof(FaceRef), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.face_cap, c->face_cap.data(), nf * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.caps, c->caps.data(), c->caps.size() * sizeof(CapDev), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+static int check_mass(lbm_ctx* c) {
+    Dev& d = c->d;
+    launch_reduce_fluid(c->L, d.f[c->step & 1], d.red, c->stream);
+    std::vector<double> part(RED_BLOCKS * 8);
+    HIPCHK(c, hipMemcpyAsync(part.data(), d.red, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int comp = 0; comp < 2; ++comp) {
+        double m = 0.0;
+        for (int b = 0; b < RED_BLOCKS; ++b) m += part[b * 8 + comp];
+        if (!isfinite(m) || fabs(m - c->mass0[comp]) > c->p.mass_tol * fabs(c->mass0[comp]))
+            return c->fail(LBM_EUNSTABLE, "step %lld: mass of component %d is %.17g (start %.17g)",
+                           (long long)c->step, comp, m, c->mass0[comp]);
+    }
+    return LBM_OK;
+}
+
+// Enqueue one time step.  ev (may be NULL) receives LBM_NK + 1 events:
+// ev[k] is recorded before kernel group k and ev[LBM_NK] after the last.
+static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
+    const Lattice& L = c->L;
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    const bool ibm = c->n_nodes > 0;
+    const int ncap = (int)c->caps.size();
+    const int cur = (int)(c->step & 1), nxt = cur ^ 1;
+    const float* fin = d.f[cur];
+    float* fout = d.f[nxt];
+    float* rho_n = d.rho[cur];
+    const float* rho_p = d.rho[nxt];
+    const int par = c->flip;
+    auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
+    mark(LBM_K_CLEAR);
+    if (ibm) launch_clear_tiles(L, d, par ^ 1, par, s);
+    mark(LBM_K_DENSITY);
+    launch_density(L, fin, rho_p, rho_n, s);
+    mark(LBM_K_VOLUME);
+    if (ibm) launch_cap_volume(d, ncap, s);
+    mark(LBM_K_FACES);
+    if (ibm) launch_faces(d, c->n_faces, s);
+    mark(LBM_K_NODES);
+    if (ibm) launch_nodes(L, d, rho_n, c->n_nodes, par, s);
+    mark(LBM_K_SCAN);
+    if (ibm) launch_bin_scan(d, par, s);
+    mark(LBM_K_SCATTER);
+    if (ibm) launch_bin_scatter(d, c->n_nodes, s);
+    mark(LBM_K_SPREAD);
+    if (ibm) launch_spread(L, d, par, s);
+    mark(LBM_K_COLLIDE);
+    launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, nullptr, ibm, false, s);
+    mark(LBM_K_INTERP);
+    if (ibm) launch_interp_advect(L, d, c->n_nodes, s);
+    mark(LBM_NK);
+    c->step++;
+    c->flip ^= 1;
+}
+
+int lbm_step(lbm_ctx* c, int32_t nsteps) {
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");
+    for (int k = 0; k < nsteps; ++k) {
+        enqueue_step(c, nullptr);
+        if (c->p.check_every > 0 && c->step % c->p.check_every == 0) {
+            HIPCHK(c, hipGetLastError());
+            const int r = check_mass(c);
+            if (r != LBM_OK) return r;
+        }
+    }
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
+
+int lbm_step_timed(lbm_ctx* c, int32_t nsteps, double* kernel_ms) {
+    if (!c || !kernel_ms) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (nsteps < 1) return c->fail(LBM_EINVAL, "nsteps < 1");
+    std::vector<hipEvent_t> ev((size_t)nsteps * (LBM_NK + 1));
+    for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+    for (int k = 0; k < nsteps; ++k) enqueue_step(c, &ev[(size_t)k * (LBM_NK + 1)]);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int j = 0; j < LBM_NK; ++j) kernel_ms[j] = 0.0;
+    for (int k = 0; k < nsteps; ++k)
+        for (int j = 0; j < LBM_NK; ++j) {
+            float ms = 0.f;
+            HIPCHK(c, hipEventElapsedTime(&ms, ev[(size_t)k * (LBM_NK + 1) + j], ev[(size_t)k * (LBM_NK + 1) + j + 1]));
+            kernel_ms[j] += ms;
+        }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    return LBM_OK;
+}
+
+// eigenvalues of a symmetric 3x3 matrix (cyclic Jacobi), ascending
+static void eig3(double A[3][3], double ev[3]) {
+    for (int sweep = 0; sweep < 50; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        if (off < 1e-300) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+            }
+    }
+    ev[0] = A[0][0]; ev[1] = A[1][1]; ev[2] = A[2][2];
+    std::sort(ev, ev + 3);
+}
+
+int lbm_observables(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
+    if (!c || !out) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    launch_reduce_fluid(c->L, d.f[c->step & 1], d.red, s);
+    const int ncap = (int)c->caps.size();
+    if (caps && ncap) launch_cap_moments(d, ncap, s);
+    HIPCHK(c, hipGetLastError());
+    std::vector<double> part(RED_BLOCKS * 8), mom((size_t)std::max(ncap, 1) * MOM_STRIDE);
+    HIPCHK(c, hipMemcpyAsync(part.data(), d.red, part.size() * 8, hipMemcpyDeviceToHost, s));
+    if (caps && ncap)
+        HIPCHK(c, hipMemcpyAsync(mom.data(), d.cap_mom, (size_t)ncap * MOM_STRIDE * 8, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < RED_BLOCKS; ++b)
+        for (int j = 0; j < 5; ++j) acc[j] += part[b * 8 + j];
+    out->mass[0] = acc[0];
+    out->mass[1] = acc[1];
+    for (int j = 0; j < 3; ++j) out->momentum[j] = acc[2 + j];
+    out->step = c->step;
+    if (caps) {
+        for (int k = 0; k < ncap; ++k) {
+            const double* m = &mom[(size_t)k * MOM_STRIDE];
+            const CapDev& cd = c->caps[k];
+            lbm_capsule_obs& o = caps[k];
+            const double V = m[0];
+            o.volume = V;
+            o.area = m[1];
+            for (int j = 0; j < 3; ++j) o.com[j] = cd.anchor[j] + m[2 + j] / cd.node_count;
+            const double xc[3] = {m[5] / V, m[6] / V, m[7] / V};
+            double M[3][3];
+            M[0][0] = m[8]; M[1][1] = m[9]; M[2][2] = m[10];
+            M[0][1] = M[1][0] = m[11];
+            M[0][2] = M[2][0] = m[12];
+            M[1][2] = M[2][1] = m[13];
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) M[i][j] -= V * xc[i] * xc[j];
+            double ev[3];
+            eig3(M, ev);
+            for (int j = 0; j < 3; ++j) o.axes[j] = sqrt(5.0 * std::max(ev[j], 0.0) / V);
+            o.taylor_D = (o.axes[2] - o.axes[0]) / (o.axes[2] + o.axes[0]);
+            o.height = o.com[2] - c->p.z_interface;
+        }
+    }
+    return LBM_OK;
+}
+
+int lbm_get_fields(lbm_ctx* c, float* rhoA, float* rhoB, float* u) {
+    if (!c) return LBM_EINVAL;
+    if (c->step < 1) return c->fail(LBM_ESTATE, "no step has been taken");
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    const int last = (int)((c->step - 1) & 1);
+    const int64_t N = c->L.n;
+    if (u) {
+        launch_collide(c->L, d.f[last], nullptr, d.rho[last], d.rho[last ^ 1], d.fib, d.tile_flag, d.u, nullptr,
+                       c->n_nodes > 0, true, s);
+        HIPCHK(c, hipGetLastError());
+        HIPCHK(c, hipMemcpyAsync(u, d.u, 3 * N * sizeof(float), hipMemcpyDeviceToHost, s));
+    }
+    if (rhoA) HIPCHK(c, hipMemcpyAsync(rhoA, d.rho[last], N * sizeof(float), hipMemcpyDeviceToHost, s));
+    if (rhoB) HIPCHK(c, hipMemcpyAsync(rhoB, d.rho[last] + N, N * sizeof(float), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return LBM_OK;
+}
+
+int lbm_get_nodes(lbm_ctx* c, double* xyz) {
+    if (!c || !xyz) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    const size_t nb = c->n_nodes;
+    if (!nb) return LBM_OK;
+    std::vector<float> hi(3 * nb), lo(3 * nb);
+    HIPCHK(c, hipMemcpyAsync(hi.data(), c->d.off_hi, 3 * nb * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(lo.data(), c->d.off_lo, 3 * nb * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t b = 0; b < nb; ++b) {
+        const CapDev& cd = c->caps[c->node_cap[b]];
+        for (int j = 0; j < 3; ++j) xyz[3 * b + j] = cd.anchor[j] + (double)hi[3 * b + j] + (double)lo[3 * b + j];
+    }
+    return LBM_OK;
+}
+
+int lbm_get_node_forces(lbm_ctx* c, float* F) {
+    if (!c || !F) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (c->step < 1) return c->fail(LBM_ESTATE, "no step has been taken");
+    if (!c->n_nodes) return LBM_OK;
+    HIPCHK(c, hipMemcpyAsync(F, c->d.node_F, 3 * (size_t)c->n_nodes * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_get_spread(lbm_ctx* c, float* Fib, float* phi) {
+    if (!c) return LBM_EINVAL;
+    if (c->step < 1) return c->fail(LBM_ESTATE, "no step has been taken");
+    const int64_t N = c->L.n;
+    if (Fib) HIPCHK(c, hipMemcpyAsync(Fib, c->d.fib, 3 * N * 4, hipMemcpyDeviceToHost, c->stream));
+    if (phi) HIPCHK(c, hipMemcpyAsync(phi, c->d.fib + 3 * N, 2 * N * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_debug_bins(lbm_ctx* c, int32_t* tile_of_node, int32_t* base_idx) {
+    if (!c) return LBM_EINVAL;
+    const size_t nb = c->n_nodes;
+    if (!nb) return LBM_OK;
+    launch_debug_bins(c->L, c->d, (int)nb, c->stream);
+    HIPCHK(c, hipGetLastError());
+    std::vector<int> v(4 * nb);
+    HIPCHK(c, hipMemcpyAsync(v.data(), c->d.dbg_bins, 4 * nb * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t b = 0; b < nb; ++b) {
+        if (tile_of_node) tile_of_node[b] = v[4 * b];
+        if (base_idx)
+            for (int j = 0; j < 3; ++j) base_idx[3 * b + j] = v[4 * b + 1 + j];
+    }
+    return LBM_OK;
+}
+
+int lbm_state_save(lbm_ctx* c, int32_t slot) {
+    if (!c) return LBM_EINVAL;
+    if (slot < 0 || slot >= c->p.n_slots) return c->fail(LBM_EINVAL, "slot %d out of range", slot);
+    char* base = c->ws + c->lay.slot0 + (size_t)slot * c->lay.slot_bytes;
+    const int64_t N = c->L.n;
+    const int cur = (int)(c->step & 1);
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_f, c->d.f[cur], (size_t)2 * Q * N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_rho, c->d.rho[0], 2 * N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_rho + 2 * N * 4, c->d.rho[1], 2 * N * 4, hipMemcpyDeviceToDevice, s));
+    if (c->n_nodes) {
+        HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_off, c->d.off_hi, 3 * (size_t)c->n_nodes * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_off + 3 * (size_t)c->n_nodes * 4, c->d.off_lo,
+                                 3 * (size_t)c->n_nodes * 4, hipMemcpyDeviceToDevice, s));
+    }
+    c->slot_step[slot] = c->step;
+    return LBM_OK;
+}
+
+int lbm_state_load(lbm_ctx* c, int32_t slot) {
+    if (!c) return LBM_EINVAL;
+    if (slot < 0 || slot >= c->p.n_slots) return c->fail(LBM_EINVAL, "slot %d out of range", slot);
+    if (c->slot_step[slot] < 0) return c->fail(LBM_ESTATE, "slot %d is empty", slot);
+    char* base = c->ws + c->lay.slot0 + (size_t)slot * c->lay.slot_bytes;
+    const int64_t N = c->L.n;
+    c->step = c->slot_step[slot];
+    const int cur = (int)(c->step & 1);
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(c->d.f[cur], base + c->lay.slot_f, (size_t)2 * Q * N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d.rho[0], base + c->lay.slot_rho, 2 * N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d.rho[1], base + c->lay.slot_rho + 2 * N * 4, 2 * N * 4, hipMemcpyDeviceToDevice, s));
+    if (c->n_nodes) {
+        HIPCHK(c, hipMemcpyAsync(c->d.off_hi, base + c->lay.slot_off, 3 * (size_t)c->n_nodes * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->d.off_lo, base + c->lay.slot_off + 3 * (size_t)c->n_nodes * 4,
+                                 3 * (size_t)c->n_nodes * 4, hipMemcpyDeviceToDevice, s));
+    }
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_init_error.c_str(); }
+
+}  // extern "C"

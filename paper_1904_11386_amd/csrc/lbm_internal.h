@@ -1,0 +1,126 @@
+// Internal declarations shared by the HIP kernels and the host side of the
+// library.  Not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbmx {
+
+// ---- D3Q19 (Sec. II.A, eq. lbm:weights) -------------------------------
+// 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 = (+-1,+-1,0), (+-1,0,+-1),
+// (0,+-1,+-1), opposites adjacent.
+constexpr int Q = 19;
+__host__ __device__ constexpr int cx(int i) {
+    constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, 1, -1, 1, -1, 1, -1, 0, 0, 0, 0};
+    return v[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+    constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1, 0, 0, 0, 0, 1, -1, 1, -1};
+    return v[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+    constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, 1, -1, -1, 1};
+    return v[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+__host__ __device__ constexpr float wgt(int i) {
+    return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
+}
+
+constexpr int TILE = 8;        // immersed-boundary tile edge (lattice nodes)
+constexpr int BOX = TILE + 3;  // spreading box edge: stencil reach of a tile's nodes
+constexpr int BX = 64;         // fused collide block: x extent (one wavefront)
+constexpr int BY = 4;          // fused collide block: y extent
+constexpr int ZC = 8;          // fused collide block: z planes marched per block
+
+struct Lattice {
+    int nx, ny, nz;
+    int ntx, nty, ntz;     // tile counts
+    int64_t n;             // nx*ny*nz
+    int walls;
+    float G;
+    float tau[2];
+    float omega[2];        // 1/tau
+    float uw_lo[3], uw_hi[3];
+};
+
+struct CapDev {
+    int anchor[3];
+    int node_start, node_count, face_start, face_count;
+    int pref;           // preferred component of the virtual density (0 A, 1 B)
+    float rv_abs;       // |rho_v|
+    float kS, C, kV;
+    double V0;
+};
+
+struct FaceRef {        // rest metric of a triangle
+    float q11, q12, q22; // inverse of the rest metric [e_a . e_b]
+    float inv_det0;      // 1 / det of the rest metric
+    float A0;            // rest area
+};
+
+// Device-side pointers of one context (all inside the caller's workspace).
+struct Dev {
+    float* f[2];          // populations [2 comps][19][N] (FP32) or halfs (FP16)
+    float* rho[2];        // [2][N] density buffers, ping-pong by step parity
+    float* fib;           // [5][N]: F_ib x, y, z, phi_A, phi_B
+    float* u;             // [3][N] velocity where the immersed boundary needs it
+    int* tile_flag;       // [tiles] 1 when touched by a stencil this step
+    int* tile_count;      // [tiles] nodes whose home tile it is
+    int* tile_offset;     // [tiles] start of the tile's bin in `sorted`
+    int* touched[2];      // lists of touched tiles (step parity)
+    int* home[2];         // lists of home tiles (step parity)
+    int* home_start;      // [tiles] bin start per home-list entry
+    int* counters;        // [8]: touched count[2], home count[2]
+    // nodes
+    float* off_hi;        // [nodes][3]
+    float* off_lo;        // [nodes][3]
+    int* node_cap;        // [nodes]
+    float* node_wet;      // [nodes] |rho_v| A_b
+    float* node_F;        // [nodes][3]
+    int* node_tile;       // [nodes]
+    int* node_rank;       // [nodes]
+    int* sorted;          // [nodes]
+    int* csr_ptr;         // [nodes + 1]
+    int* csr_idx;         // [3 faces] face*3 + corner
+    int* dbg_bins;        // [nodes][4] debug binning output
+    // faces
+    int* tri;             // [faces][3] global node indices
+    FaceRef* fref;        // [faces]
+    int* face_cap;        // [faces]
+    float* face_F;        // [faces][9]
+    // capsules
+    CapDev* caps;         // [max caps]
+    double* capV;         // [max caps]
+    double* cap_mom;      // [max caps][16] observables moments
+    double* red;          // [RED_BLOCKS][8] reduction partials
+};
+
+constexpr int RED_BLOCKS = 1024;
+constexpr int MOM_STRIDE = 16;
+
+// ---- launchers (k_fluid.hip) -------------------------------------------
+void launch_init_rest(const Lattice& L, float* f, const float* rhoA, const float* rhoB,
+                      hipStream_t s);
+void launch_density(const Lattice& L, const float* fin, const float* rho_prev, float* rho_out,
+                    hipStream_t s);
+void launch_collide(const Lattice& L, const float* fin, float* fout, const float* rho_n,
+                    const float* rho_prev, const float* fib, const int* tile_flag, float* u,
+                    float* rho_macro, bool has_ibm, bool macro, hipStream_t s);
+void launch_reduce_fluid(const Lattice& L, const float* fpost, double* partial, hipStream_t s);
+
+// ---- launchers (k_ibm.hip) ---------------------------------------------
+void launch_clear_tiles(const Lattice& L, Dev& d, int parity_prev, int parity_cur, hipStream_t s);
+void launch_cap_volume(const Dev& d, int n_caps, hipStream_t s);
+void launch_faces(const Dev& d, int n_faces, hipStream_t s);
+void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, int n_nodes, int parity,
+                  hipStream_t s);
+void launch_bin_scan(const Dev& d, int parity, hipStream_t s);
+void launch_bin_scatter(const Dev& d, int n_nodes, hipStream_t s);
+void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);
+void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
+void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s);
+void launch_debug_bins(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
+
+}  // namespace lbmx

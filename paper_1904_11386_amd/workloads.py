@@ -114,6 +114,23 @@ def icosphere(freq: int, radius: float):
     return _snap(xyz), tri
 
 
+# Volume-penalty modulus of the workloads.  The paper uses 20 with inertial
+# boundary nodes and bounce-back coupling (Sec. III.B); with massless
+# immersed-boundary nodes 20, 10 and 5 diverge within 100 steps of the 32^3
+# one-capsule case in FP64, and 2 is the largest of {20, 10, 5, 2, 1} that
+# stays stable for 1000 steps.
+KV_DEFAULT = 2.0
+
+# Strength of the virtual-density (wettability) term relative to the colour
+# law as written, rho_v = 2 cos(theta) (rho_maj - rho_min).  At full strength
+# the smeared membrane offset, with psi = rho and massless nodes, drives a
+# steady contact-line circulation of 0.15 lu/step even around a membrane held
+# fixed, and capsules of radius >= 8 diverge within 100 steps at 60 degrees;
+# at 0.1 every workload's radius and angle range runs stably with currents
+# near 0.02 lu/step and capsules still move into their preferred phase.
+WET_SCALE = 0.1
+
+
 @dataclass
 class Capsule:
     centre: np.ndarray          # [3] float64 (snapped)
@@ -147,6 +164,7 @@ class Workload:
     steps: int = 1
     rho_maj: float = float(RHO_MAJ)
     rho_min: float = float(RHO_MIN)
+    wet_scale: float = WET_SCALE
     note: str = ""
 
     @property
@@ -174,12 +192,6 @@ class Workload:
         return a("kS"), a("C"), a("kV"), a("theta_deg")
 
 
-# Volume-penalty modulus of the workloads.  The paper uses 20 with inertial
-# boundary nodes and bounce-back coupling (Sec. III.B); with massless
-# immersed-boundary nodes 20, 10 and 5 diverge within 100 steps of the 32^3
-# one-capsule case in FP64, and 2 is the largest of {20, 10, 5, 2, 1} that
-# stays stable for 1000 steps.
-KV_DEFAULT = 2.0
 
 
 def layered(nx, ny, nz, z_split):
@@ -305,7 +317,7 @@ def make(name: str, kV: Optional[float] = None) -> Workload:
 
 def small(nx=40, ny=36, nz=44, ncap=2, freq=4, radius=4.0, theta=(70.0, 115.0),
           kS=(0.01, 0.004), kV=None, seed=7, walls=0, wall_u=0.01, G=3.6,
-          tau=(1.0, 1.0), z_split=None) -> Workload:
+          tau=(1.0, 1.0), z_split=None, wet_scale=WET_SCALE) -> Workload:
     """A small seeded workload for parity tests: a ragged box (sizes that are
     not multiples of the kernel tile widths), a flat interface and a few
     small capsules near it."""
@@ -328,4 +340,4 @@ def small(nx=40, ny=36, nz=44, ncap=2, freq=4, radius=4.0, theta=(70.0, 115.0),
     return Workload("small", nx, ny, nz, rhoA, rhoB, caps, tau=tau, G=G,
                     walls=walls, wall_u_lo=(-wall_u, 0, 0) if walls else (0, 0, 0),
                     wall_u_hi=(wall_u, 0, 0) if walls else (0, 0, 0),
-                    z_interface=zs - 0.5, steps=20)
+                    z_interface=zs - 0.5, steps=20, wet_scale=wet_scale)

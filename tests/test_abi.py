@@ -1,0 +1,74 @@
+"""The C-ABI library loads and exports every symbol include/lbm.h declares,
+and rejects bad arguments before any device work (no GPU needed)."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LIB = os.path.join(ROOT, "paper_1904_11386_amd", "liblbm.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="liblbm.so not built")
+
+
+def declared_symbols():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(LIB)
+    names = declared_symbols()
+    assert "lbm_init" in names and "lbm_step" in names and "lbm_observables" in names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_1904_11386_amd import binding
+    assert sorted(binding.EXPORTS) == declared_symbols()
+
+
+def test_workspace_bytes_and_validation():
+    from paper_1904_11386_amd import binding as B
+    p = B.make_params(32, 32, 32)
+    n0 = B.workspace_bytes(p, 0, 0)
+    n1 = B.workspace_bytes(p, 642, 1280)
+    assert n1 > n0 >= 32 ** 3 * (2 * 19 * 4 * 2)
+    p2 = B.make_params(32, 32, 32, n_slots=2)
+    assert B.workspace_bytes(p2, 0, 0) > n0
+    lib = B.load()
+    out = C.c_int64()
+    for bad in (dict(tau=(0.5, 1.0)), dict(G=-1.0), dict(walls=3), dict(precision=7)):
+        pb = B.make_params(16, 16, 16, **bad)
+        assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
+        assert lib.lbm_last_error(None)
+    pb = B.make_params(3, 16, 16)
+    assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
+    # init rejects a bad tau before touching the (bogus) workspace pointer
+    pb = B.make_params(16, 16, 16, tau=(0.4, 1.0))
+    r = np.ones(16 ** 3, np.float32)
+    ctx = C.c_void_p()
+    rc = lib.lbm_init(C.byref(pb), r.ctypes.data_as(C.POINTER(C.c_float)), r.ctypes.data_as(C.POINTER(C.c_float)),
+                      C.c_void_p(256), 1 << 30, 0, 0, None, C.byref(ctx))
+    assert rc == B.LBM_EINVAL and not ctx.value
+    # negative initial density is rejected before device work
+    pb = B.make_params(16, 16, 16)
+    rneg = r.copy()
+    rneg[5] = -1.0
+    rc = lib.lbm_init(C.byref(pb), rneg.ctypes.data_as(C.POINTER(C.c_float)), r.ctypes.data_as(C.POINTER(C.c_float)),
+                      C.c_void_p(256), 1 << 40, 0, 0, None, C.byref(ctx))
+    assert rc == B.LBM_EINVAL
+    # a workspace smaller than the query is LBM_ENOMEM
+    rc = lib.lbm_init(C.byref(pb), r.ctypes.data_as(C.POINTER(C.c_float)), r.ctypes.data_as(C.POINTER(C.c_float)),
+                      C.c_void_p(256), 1024, 0, 0, None, C.byref(ctx))
+    assert rc == B.LBM_ENOMEM
+
+
+def test_no_cpu_fallback_when_library_missing(tmp_path):
+    from paper_1904_11386_amd import binding as B
+    with pytest.raises(RuntimeError, match="not built"):
+        B.load(str(tmp_path / "liblbm.so"))
