@@ -11,7 +11,9 @@ roofline: the fused collide-stream kernel dominates; its achieved bandwidth
 is the algorithmic bytes per launch (152 B population reads + 152 B
 population writes + 8 B density reads per lattice node, FP32) over its
 average duration from HIP events recorded on the library's stream around
-each launch in the timed region.
+each launch, in a second timed region of the same number of steps run
+right after the first (the first replays HIP graphs, which carry no
+per-kernel events).
 
 cpu_baseline: the FP64 oracle (test infrastructure) timed on this host on a
 bounded sample of the same workload.
@@ -31,8 +33,10 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (2-comp D3Q19+IBM), % HBM peak, FP16-store vs FP32, adjoint/fwd time"
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per lattice update of the fused collide kernel (FP32)
-COLLIDE_BYTES_PER_LUP = {"fp32": 2 * 19 * 4 * 2 + 2 * 4}
-DENSITY_BYTES_PER_LUP = {"fp32": 2 * 19 * 4 + 2 * 4}
+# FP32: 152 B population reads + 152 B writes + 8 B density; FP16: 76 + 76 B
+# of binary16 populations + 8 B densities of step n + 8 B decode densities
+COLLIDE_BYTES_PER_LUP = {"fp32": 2 * 19 * 4 * 2 + 2 * 4, "fp16": 2 * 19 * 2 * 2 + 2 * 4 + 2 * 4}
+DENSITY_BYTES_PER_LUP = {"fp32": 2 * 19 * 4 + 2 * 4, "fp16": 2 * 19 * 2 + 2 * 4 + 2 * 4}
 
 WORKLOAD_TEXT = {
     "c2": "128^3 periodic two-component box, flat interface at z=64, 8 capsules R=8 (2562-node "
@@ -41,6 +45,47 @@ WORKLOAD_TEXT = {
           "nodes (R 4/6/10), theta~U[60,120] deg, tau=1, G=3.6",
     "c1": "32^3 periodic box, flat interface, one R=6 capsule (642 nodes)",
 }
+
+
+def measured_traffic():
+    """HBM bytes per k_collide launch (FP32, c2) from the committed rocprofv3
+    PMC summary, or None when the kernel source changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_collide_c2_pmc.md")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    for line in open(path):
+        if line.startswith("traffic_bytes_per_launch k_collide:"):
+            rec["bytes"] = float(line.split(":")[1])
+        if line.startswith("source_sha256_16:"):
+            rec["sha"] = line.split(":")[1].strip()
+    h = hashlib.sha256()
+    for f in ("paper_1904_11386_amd/csrc/k_fluid.hip", "paper_1904_11386_amd/csrc/lbm_internal.h"):
+        h.update(open(os.path.join(ROOT, f), "rb").read())
+    if rec.get("sha") != h.hexdigest()[:16]:
+        return None
+    return rec.get("bytes")
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=10):
+    """Device-to-device copy bandwidth (read + write bytes / time) of a
+    plain 1 GiB tensor copy, as the achievable-bandwidth reference."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    a.fill_(1.0)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbs = 2.0 * nbytes * reps / (e0.elapsed_time(e1) * 1e-3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbs
 
 
 def cpu_baseline(wl, budget_s=20.0):
@@ -72,7 +117,8 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=30)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--no-fp16-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -82,19 +128,27 @@ def main():
 
     import torch
     from paper_1904_11386_amd import workloads
-    from paper_1904_11386_amd.binding import sim_from_workload
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
 
     wl = workloads.make(args.workload)
     print("bench: workload %s %dx%dx%d, %d capsules, %d nodes" %
           (args.workload, wl.nx, wl.ny, wl.nz, len(wl.capsules), int(wl.meshes()[0].sum())),
           file=sys.stderr, flush=True)
-    sim = sim_from_workload(wl)
+    copy_gbs = copy_ceiling(torch)
+    prec = LBM_FP16 if args.precision == "fp16" else LBM_FP32
+    sim = sim_from_workload(wl, precision=prec)
     sim.step(args.warmup)
+    sim.synchronize()
     torch.cuda.synchronize()
+    # timed region: K whole steps as the library runs them (graph replay)
     t0 = time.perf_counter()
-    kms = sim.step_timed(args.steps)
+    sim.step(args.steps)
+    sim.synchronize()
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
+    # second timed region of the same length: HIP events on the library's
+    # stream around every kernel launch give each kernel's average duration
+    kms = sim.step_timed(args.steps)
     N = wl.n_lattice
     mlups = N * args.steps / wall / 1e6
     obs = sim.observables()
@@ -106,12 +160,14 @@ def main():
     bpl = COLLIDE_BYTES_PER_LUP[args.precision]
     achieved = bpl * N / t_col / 1e9
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic() if (args.workload == "c2" and args.precision == "fp32") else None,
             "kernel": "k_collide", "bytes_per_launch": bpl * N, "avg_launch_ms": round(t_col * 1e3, 5)}
     out = {
         "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 5),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "storage": "f16 (g = f/rho - w)" if args.precision == "fp16" else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
                    "lattice": [wl.nx, wl.ny, wl.nz], "capsules": len(wl.capsules),
@@ -119,11 +175,33 @@ def main():
         "roofline": roof,
         "kernels_ms_per_step": {k: round(v / args.steps, 5) for k, v in kms.items()},
         "density_pass_gbs": round(DENSITY_BYTES_PER_LUP[args.precision] * N / t_den / 1e9, 1),
+        "copy_ceiling_gbs": round(copy_gbs, 1),
+        "collide_frac_of_copy": round(achieved / copy_gbs, 4),
         "fp64_mass_drift": mass_drift,
     }
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if args.precision == "fp32" and not args.no_fp16_leg:
+        # the FP16-storage form on the same workload, same step count
+        s16 = sim_from_workload(wl, precision=LBM_FP16)
+        s16.step(args.warmup)
+        s16.synchronize()
+        t0 = time.perf_counter()
+        s16.step(args.steps)
+        s16.synchronize()
+        w16 = time.perf_counter() - t0
+        k16 = s16.step_timed(args.steps)
+        t16 = k16["collide"] / args.steps * 1e-3
+        a16 = COLLIDE_BYTES_PER_LUP["fp16"] * N / t16 / 1e9
+        out["fp16_form"] = {"value": round(N * args.steps / w16 / 1e6, 2), "unit": "MLUPS",
+                            "ms_per_step": round(w16 / args.steps * 1e3, 5),
+                            "ratio_vs_fp32": round(wall / w16, 3),
+                            "collide_gbs": round(a16, 1), "collide_frac": round(a16 / HBM_PEAK_GBS, 4),
+                            "kernels_ms_per_step": {k: round(v / args.steps, 5) for k, v in k16.items()}}
+        s16.close()
+        del s16
+        torch.cuda.empty_cache()
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

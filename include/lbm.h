@@ -73,7 +73,8 @@ typedef struct lbm_params {
     int32_t walls;          /* 0 periodic; 1 solid rows y = 0 and y = ny - 1   */
     int32_t n_slots;        /* checkpoint slots carved from the workspace       */
     int32_t check_every;    /* FP64 mass check period in steps, 0 = never       */
-    int32_t reserved;
+    int32_t use_graphs;     /* 1: lbm_step replays captured two-step HIP graphs
+                               when the stream is not the null stream          */
     double tau[2];          /* BGK relaxation times of A and B, each > 0.5      */
     double G;               /* Shan-Chen coupling G^{AB} = G^{BA} >= 0          */
     double rho_maj, rho_min;/* densities that scale the colour (Sec. II.D)      */
@@ -136,6 +137,8 @@ int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
                      const double* kV, const double* theta_deg, int32_t* first_id);
 
 /* Advance nsteps >= 0 time steps, asynchronously on the stream.  With
+ * use_graphs, pairs of steps are replayed from HIP graphs captured on the
+ * first call (kernels only, no memory-set nodes).  With
  * check_every > 0 the FP64 mass check runs every check_every steps and
  * synchronises; it returns LBM_EUNSTABLE when a component mass is not
  * finite or has drifted by more than mass_tol relative to its start. */
@@ -184,7 +187,8 @@ int lbm_get_node_forces(lbm_ctx* ctx, float* F);
 int lbm_get_spread(lbm_ctx* ctx, float* Fib, float* phi);
 
 /* Binning of the current node positions: tile_of_node[nodes] is the index
- * of the 8x8x8 tile holding the node floor(X) (tiles numbered x fastest),
+ * of the 4x4x4 spreading bin holding the node floor(X) (bins numbered x
+ * fastest),
  * base_idx[nodes][3] the unwrapped stencil base floor(X) - 1.  Recomputed
  * from the positions on the device.  Synchronises. */
 int lbm_debug_bins(lbm_ctx* ctx, int32_t* tile_of_node, int32_t* base_idx);

@@ -24,7 +24,7 @@ ERR_NAMES = {1: "LBM_EINVAL", 2: "LBM_ENOMEM", 3: "LBM_EHIP", 4: "LBM_ESTATE", 5
 class Params(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
                 ("precision", C.c_int32), ("walls", C.c_int32), ("n_slots", C.c_int32),
-                ("check_every", C.c_int32), ("reserved", C.c_int32),
+                ("check_every", C.c_int32), ("use_graphs", C.c_int32),
                 ("tau", C.c_double * 2), ("G", C.c_double),
                 ("rho_maj", C.c_double), ("rho_min", C.c_double),
                 ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
@@ -47,9 +47,11 @@ EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_step", "l
            "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_destroy", "lbm_last_error"]
 
 
-def load(path: str = LIB_PATH):
-    """Load liblbm.so and declare its signatures (no device work)."""
+def load(path: str = None):
+    """Load liblbm.so (LIB_PATH unless a path is given) and declare its
+    signatures (no device work)."""
     global _lib
+    path = path or LIB_PATH
     if _lib is not None and path == LIB_PATH:
         return _lib
     if not os.path.exists(path):
@@ -96,7 +98,7 @@ def _ptr(a, ctype):
 
 def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
-                check_every=0, mass_tol=1e-3, wet_scale=1.0):
+                check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -112,6 +114,7 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.z_interface = z_interface
     p.mass_tol = mass_tol
     p.wet_scale = wet_scale
+    p.use_graphs = use_graphs
     return p
 
 
@@ -135,7 +138,11 @@ class Sim:
         self.N = params.nx * params.ny * params.nz
         nbytes = workspace_bytes(params, max_nodes, max_faces)
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.stream = stream if stream is not None else torch.cuda.current_stream(self.workspace.device)
+        # a stream of its own (default priority), so the library can capture
+        # graphs; torch's allocator is told the workspace is used there
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.workspace.device)
+        self.workspace.record_stream(self.stream)
+        torch.cuda.synchronize(self.workspace.device)
         rA = np.ascontiguousarray(rhoA, dtype=np.float32).reshape(-1)
         rB = np.ascontiguousarray(rhoB, dtype=np.float32).reshape(-1)
         if rA.size != self.N or rB.size != self.N:
@@ -231,8 +238,12 @@ class Sim:
     def load(self, slot):
         self._check(self.lib.lbm_state_load(self.ctx, slot))
 
+    def synchronize(self):
+        self.stream.synchronize()
+
     def close(self):
         if getattr(self, "ctx", None):
+            self.stream.synchronize()
             self.lib.lbm_destroy(self.ctx)
             self.ctx = None
 
@@ -243,13 +254,13 @@ class Sim:
             pass
 
 
-def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda"):
+def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1):
     """Build a Sim for a seeded workload (paper_1904_11386_amd.workloads)."""
     npc, fpc, xyz, tri = wl.meshes()
     p = make_params(wl.nx, wl.ny, wl.nz, tau=wl.tau, G=wl.G, walls=wl.walls, wall_u_lo=wl.wall_u_lo,
                     wall_u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
-                    check_every=check_every, wet_scale=wl.wet_scale)
+                    check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs)
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()

@@ -1,10 +1,18 @@
 // Lattice kernels of the two-component Shan-Chen D3Q19 BGK step (gfx950).
 //
-// Storage: structure of arrays f[c][i][z][y][x], x fastest, holding the
+// Storage: f[i][z][y][x][c], x fastest with the two components c side by
+// side (one vector per direction and node), holding the
 // post-collision populations f* of the previous step.  Streaming is a pull:
 // the population i of node x at the new time level is f*_i(x - c_i), read
 // at the point of use, so every load and store of a wavefront (64 nodes
 // along x) touches consecutive addresses.
+//
+// Two storage forms share the kernels (template HALF):
+//   FP32   f_i itself;
+//   FP16   g_i = f_i / rho_enc - w_i in binary16, rho_enc the density of the
+//          node that wrote it (after the FP64 mass compensation of that
+//          step).  Decoding needs rho_enc of the source node of each pull,
+//          which the kernels stage in LDS next to psi.  Arithmetic is FP32.
 //
 // The Shan-Chen force (Sec. II.D, eq. method:shanchen) needs the density
 // of the new time level at the 18 neighbours, which the pull cannot give a
@@ -12,9 +20,13 @@
 //   k_density  rho^n(x) = sum_i f*_i(x - c_i)                (Sec. II.A)
 //   k_collide  pull, Shan-Chen + wettability + immersed-boundary force,
 //              equilibrium-velocity shift, BGK (Sec. II.A), store f*.
-// k_collide marches a 64 x 4 column of nodes up z and keeps three planes of
-// psi + phi (pseudo-potential plus virtual density) for the column and its
-// one-node halo in LDS, so the 36 neighbour reads per node come from LDS.
+// k_collide marches a BX x BY column of nodes up z and keeps three planes
+// of psi + phi (pseudo-potential plus virtual density) for the column and
+// its one-node halo in LDS, so the 36 neighbour reads per node come from
+// LDS.  In the FP16 form k_density marches the same way, and also leaves
+// FP64 block sums of rho^n, from which k_compensate forms the per-component
+// factor M0 / M^n that k_collide applies (global mass held at its initial
+// FP64 value).
 #include "lbm_internal.h"
 
 namespace lbmx {
@@ -26,15 +38,43 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// source of the pull for direction i at (x, y, z): x - c_i, with the
-// neighbour coordinates precomputed (xm = x-1, xp = x+1 wrapped, ...).
-template <int I>
-__device__ __forceinline__ int64_t pull_index(int x, int xm, int xp, int y, int ym, int yp,
-                                              int z, int zm, int zp, int nx, int ny) {
-    const int sx = cx(I) == 1 ? xm : (cx(I) == -1 ? xp : x);
-    const int sy = cy(I) == 1 ? ym : (cy(I) == -1 ? yp : y);
-    const int sz = cz(I) == 1 ? zm : (cz(I) == -1 ? zp : z);
-    return ((int64_t)sz * ny + sy) * nx + sx;
+// Block coordinates, optionally in an XCD-aware order: workgroups are dealt
+// to the 8 dies round-robin, so linear id b runs on die b % 8; the remap
+// gives each die a contiguous run of the (x, y, z)-ordered block grid.
+__device__ __forceinline__ void block_xyz(int& bx, int& by, int& bz) {
+    const int gx = gridDim.x, gy = gridDim.y;
+    int b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+#if LBM_XCD_REMAP
+    const int nb = gx * gy * gridDim.z;
+    if (nb % NXCD == 0) b = (b % NXCD) * (nb / NXCD) + b / NXCD;
+#endif
+    bx = b % gx;
+    by = (b / gx) % gy;
+    bz = b / (gx * gy);
+}
+
+template <typename T>
+__device__ __forceinline__ void store_pop(T* p, T v) {
+#if LBM_NT_STORE
+    __builtin_nontemporal_store(v, p);
+#else
+    *p = v;
+#endif
+}
+
+// Populations of the two components for one direction and node sit side by
+// side: f[i][z][y][x][c], so one pull is one 8-byte (FP32) or 4-byte (FP16)
+// vector access.
+typedef float pf2 __attribute__((ext_vector_type(2)));
+typedef _Float16 ph2 __attribute__((ext_vector_type(2)));
+template <bool HALF>
+using PopT = typename std::conditional<HALF, ph2, pf2>::type;
+template <bool HALF>
+__device__ __forceinline__ PopT<HALF> pack(float a, float b) {
+    PopT<HALF> v;
+    v.x = a;
+    v.y = b;
+    return v;
 }
 
 // Moving-wall half-way bounce-back (Sec. II.C, eq. method:SBB): the
@@ -51,33 +91,56 @@ struct Pulled {
     float f[Q];
 };
 
-template <bool WALLS, int I>
-__device__ __forceinline__ void pull_one(const float* __restrict__ fc, const Lattice& L, int64_t node,
-                                         int x, int xm, int xp, int y, int ym, int yp, int z, int zm,
-                                         int zp, float rp, Pulled& P) {
-    if (WALLS && ((cy(I) == 1 && y == 1) || (cy(I) == -1 && y == L.ny - 2))) {
-        P.f[I] = fc[(int64_t)opp(I) * L.n + node] + wall_term<I>(L, rp);
+struct PullCtx {
+    int x, xm, xp, y, ym, yp, z, zm, zp;
+    int64_t node;
+};
+
+// Pull of direction I for both components.  enc(cx, cy, cz, a, b) gives
+// the decode densities of the source node x - c (FP16 form only); ra_prev,
+// rb_prev are the node's own previous densities (wall term, and the decode
+// density of its own reflected population).
+template <bool WALLS, bool HALF, int I, typename EncAt>
+__device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
+                                         float ra_prev, float rb_prev, const EncAt& enc, Pulled& A, Pulled& B) {
+    if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
+        const PopT<HALF> v = f[(int64_t)opp(I) * L.n + c.node];
+        A.f[I] = (HALF ? ra_prev * (wgt(opp(I)) + (float)v.x) : (float)v.x) + wall_term<I>(L, ra_prev);
+        B.f[I] = (HALF ? rb_prev * (wgt(opp(I)) + (float)v.y) : (float)v.y) + wall_term<I>(L, rb_prev);
     } else {
-        P.f[I] = fc[(int64_t)I * L.n + pull_index<I>(x, xm, xp, y, ym, yp, z, zm, zp, L.nx, L.ny)];
+        const int sx = cx(I) == 1 ? c.xm : (cx(I) == -1 ? c.xp : c.x);
+        const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
+        const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
+        const PopT<HALF> v = f[(int64_t)I * L.n + ((int64_t)sz * L.ny + sy) * L.nx + sx];
+        if (HALF) {
+            float ea, eb;
+            enc(cx(I), cy(I), cz(I), ea, eb);
+            A.f[I] = ea * (wgt(I) + (float)v.x);
+            B.f[I] = eb * (wgt(I) + (float)v.y);
+        } else {
+            A.f[I] = (float)v.x;
+            B.f[I] = (float)v.y;
+        }
     }
 }
 
-template <bool WALLS, int... Is>
-__device__ __forceinline__ void pull_all(const float* __restrict__ fc, const Lattice& L, int64_t node,
-                                         int x, int xm, int xp, int y, int ym, int yp, int z, int zm,
-                                         int zp, float rp, Pulled& P,
+template <bool WALLS, bool HALF, typename EncAt, int... Is>
+__device__ __forceinline__ void pull_all(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
+                                         float ra_prev, float rb_prev, const EncAt& enc, Pulled& A, Pulled& B,
                                          std::integer_sequence<int, Is...>) {
-    (pull_one<WALLS, Is>(fc, L, node, x, xm, xp, y, ym, yp, z, zm, zp, rp, P), ...);
+    (pull_one<WALLS, HALF, Is>(f, L, c, ra_prev, rb_prev, enc, A, B), ...);
 }
 
-template <bool WALLS>
-__device__ __forceinline__ void pull(const float* __restrict__ fc, const Lattice& L, int64_t node,
-                                     int x, int y, int z, float rp, Pulled& P) {
-    const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
-    const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
-    const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
-    pull_all<WALLS>(fc, L, node, x, xm, xp, y, ym, yp, z, zm, zp, rp, P,
-                    std::make_integer_sequence<int, Q>{});
+template <bool WALLS, bool HALF, typename EncAt>
+__device__ __forceinline__ void pull(const PopT<HALF>* __restrict__ f, const Lattice& L, int64_t node, int x,
+                                     int y, int z, float ra_prev, float rb_prev, const EncAt& enc, Pulled& A,
+                                     Pulled& B) {
+    PullCtx c;
+    c.x = x; c.y = y; c.z = z; c.node = node;
+    c.xm = x == 0 ? L.nx - 1 : x - 1; c.xp = x == L.nx - 1 ? 0 : x + 1;
+    c.ym = y == 0 ? L.ny - 1 : y - 1; c.yp = y == L.ny - 1 ? 0 : y + 1;
+    c.zm = z == 0 ? L.nz - 1 : z - 1; c.zp = z == L.nz - 1 ? 0 : z + 1;
+    pull_all<WALLS, HALF>(f, L, c, ra_prev, rb_prev, enc, A, B, std::make_integer_sequence<int, Q>{});
 }
 
 __device__ __forceinline__ float sum_pop(const Pulled& P) {
@@ -100,10 +163,17 @@ __device__ __forceinline__ void momentum(const Pulled& P, float& jx, float& jy, 
     }
 }
 
-__global__ __launch_bounds__(256) void k_init_rest(float* __restrict__ f, const float* __restrict__ rhoA,
+// Rest equilibrium f_i = w_i rho (u = 0), the rest population closing the
+// mass; in the FP16 form that is g_i = 0 with rho_enc = rho.
+template <bool HALF>
+__global__ __launch_bounds__(256) void k_init_rest(PopT<HALF>* __restrict__ f, const float* __restrict__ rhoA,
                                                    const float* __restrict__ rhoB, int64_t n) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n;
          k += (int64_t)gridDim.x * blockDim.x) {
+        if (HALF) {
+            for (int i = 0; i < Q; ++i) f[(int64_t)i * n + k] = pack<HALF>(0.0f, 0.0f);
+            continue;
+        }
         const float ra = rhoA[k], rb = rhoB[k];
         float resta = ra, restb = rb;
 #pragma unroll
@@ -111,74 +181,214 @@ __global__ __launch_bounds__(256) void k_init_rest(float* __restrict__ f, const 
             const float fa = wgt(i) * ra, fb = wgt(i) * rb;
             resta -= fa;
             restb -= fb;
-            f[(int64_t)i * n + k] = fa;
-            f[(int64_t)(Q + i) * n + k] = fb;
+            f[(int64_t)i * n + k] = pack<HALF>(fa, fb);
         }
-        // rest populations close each node's mass
-        f[k] = resta;
-        f[(int64_t)Q * n + k] = restb;
+        f[k] = pack<HALF>(resta, restb);
     }
 }
 
+// Three-plane LDS ring over the column and its halo: slot(zz) = (zz - z0 + 1) % 3.
+template <int NC>
+struct Ring {
+    static constexpr int SW = BX + 2, SH = BY + 2;
+    float v[3][NC][SH][SW];
+};
+
+// Stage plane zz of `src` (per component, optionally times a per-component
+// scale, optionally plus the virtual density where tiles are flagged).
+template <bool WALLS, bool ADD_PHI, int NC>
+__device__ __forceinline__ void stage_plane(Ring<NC>& R, int zz, int z0, int x0, int y0, int tid,
+                                            const float* __restrict__ src, const float* scale,
+                                            const float* __restrict__ fib, const int* __restrict__ tile_flag,
+                                            const Lattice& L) {
+    constexpr int SW = Ring<NC>::SW, SH = Ring<NC>::SH;
+    const int slot = (zz - z0 + 1) % 3;
+    const int zw = wrapi(zz, L.nz);
+    for (int k = tid; k < NC * SH * SW; k += BX * BY) {
+        const int c = k / (SH * SW);
+        const int r = k - c * SH * SW;
+        const int ly = r / SW, lx = r - ly * SW;
+        const int gx = wrapi(x0 - 1 + lx, L.nx);
+        int gy = wrapi(y0 - 1 + ly, L.ny);
+        if (WALLS) {
+            // solid rows take the value of the adjacent fluid row
+            if (gy == 0) gy = 1;
+            if (gy == L.ny - 1) gy = L.ny - 2;
+        }
+        const int64_t idx = ((int64_t)zw * L.ny + gy) * L.nx + gx;
+        float v = src[c * L.n + idx];
+        if (scale) v *= scale[c];
+        if (ADD_PHI) {
+            const int t = ((zw >> 3) * L.nty + (gy >> 3)) * L.ntx + (gx >> 3);
+            if (tile_flag[t]) v += fib[(3 + c) * L.n + idx];
+        }
+        R.v[slot][c][ly][lx] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Density pass, FP32: one thread per node.
 template <bool WALLS>
-__global__ __launch_bounds__(256) void k_density(const float* __restrict__ fin,
+__global__ __launch_bounds__(256) void k_density(const pf2* __restrict__ fin,
                                                  const float* __restrict__ rho_prev,
                                                  float* __restrict__ rho_out, Lattice L) {
-    const int x = blockIdx.x * BX + threadIdx.x;
-    const int y = blockIdx.y * BY + threadIdx.y;
-    const int z = blockIdx.z;
+    int bx, by, bz;
+    block_xyz(bx, by, bz);
+    const int x = bx * BX + threadIdx.x;
+    const int y = by * BY + threadIdx.y;
+    const int z = bz;
     if (x >= L.nx || y >= L.ny) return;
     if (WALLS && (y == 0 || y == L.ny - 1)) return;
     const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        Pulled P;
-        const float rp = WALLS ? rho_prev[c * L.n + node] : 0.0f;
-        pull<WALLS>(fin + (int64_t)c * Q * L.n, L, node, x, y, z, rp, P);
-        rho_out[c * L.n + node] = sum_pop(P);
+    auto none = [](int, int, int, float&, float&) {};
+    Pulled A, B;
+    const float rpa = WALLS ? rho_prev[node] : 0.0f;
+    const float rpb = WALLS ? rho_prev[L.n + node] : 0.0f;
+    pull<WALLS, false>(fin, L, node, x, y, z, rpa, rpb, none, A, B);
+    rho_out[node] = sum_pop(A);
+    rho_out[L.n + node] = sum_pop(B);
+}
+
+// Density pass, FP16: z-marching column with the decode densities
+// cscale(prev) * rho^{n-1} staged in LDS, plus FP64 block sums of rho^n.
+template <bool WALLS>
+__global__ __launch_bounds__(256) void k_density_half(const ph2* __restrict__ fin,
+                                                      const float* __restrict__ rho_prev,
+                                                      const float* __restrict__ cscale, int par_prev,
+                                                      float* __restrict__ rho_out, double* __restrict__ partial,
+                                                      Lattice L) {
+    __shared__ Ring<2> ring;
+    __shared__ double red[2][BX * BY];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    int bx, by, bz;
+    block_xyz(bx, by, bz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
+    const int z1 = min(z0 + ZC, L.nz);
+    const float cp[2] = {cscale[2 * par_prev], cscale[2 * par_prev + 1]};
+    stage_plane<WALLS, false, 2>(ring, z0 - 1, z0, x0, y0, tid, rho_prev, cp, nullptr, nullptr, L);
+    stage_plane<WALLS, false, 2>(ring, z0, z0, x0, y0, tid, rho_prev, cp, nullptr, nullptr, L);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
+    double acc[2] = {0.0, 0.0};
+    for (int z = z0; z < z1; ++z) {
+        stage_plane<WALLS, false, 2>(ring, z + 1, z0, x0, y0, tid, rho_prev, cp, nullptr, nullptr, L);
+        __syncthreads();
+        if (active) {
+            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const int s0 = (z - z0 + 1) % 3;
+            auto enc = [&](int ex, int ey, int ez, float& a, float& b) {
+                const int sl = (s0 - ez + 3) % 3;
+                a = ring.v[sl][0][ty + 1 - ey][tx + 1 - ex];
+                b = ring.v[sl][1][ty + 1 - ey][tx + 1 - ex];
+            };
+            Pulled A, B;
+            pull<WALLS, true>(fin, L, node, x, y, z, ring.v[s0][0][ty + 1][tx + 1], ring.v[s0][1][ty + 1][tx + 1],
+                              enc, A, B);
+            const float ra = sum_pop(A), rb = sum_pop(B);
+            rho_out[node] = ra;
+            rho_out[L.n + node] = rb;
+            acc[0] += (double)ra;
+            acc[1] += (double)rb;
+        }
+        __syncthreads();
+    }
+    red[0][tid] = acc[0];
+    red[1][tid] = acc[1];
+    __syncthreads();
+    for (int s = BX * BY / 2; s > 0; s >>= 1) {
+        if (tid < s) {
+            red[0][tid] += red[0][tid + s];
+            red[1][tid] += red[1][tid + s];
+        }
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const int64_t b = ((int64_t)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+        partial[2 * b] = red[0][0];
+        partial[2 * b + 1] = red[1][0];
     }
 }
 
-// Fused pull + force + collide.  MACRO: recompute the macroscopic fields of
-// this collision without storing populations (field read-back).
-template <bool WALLS, bool IBM, bool MACRO>
-__global__ __launch_bounds__(256) void k_collide(const float* __restrict__ fin, float* __restrict__ fout,
+// Per-component compensation factor M0 / M^n from the FP64 block sums, in a
+// fixed summation order.
+__global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ partial, int nblocks,
+                                                     double m0a, double m0b, float* __restrict__ cscale,
+                                                     int par_cur, double* __restrict__ mass_out) {
+    __shared__ double sh[2][1024];
+    double a = 0.0, b = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += 1024) {
+        a += partial[2 * k];
+        b += partial[2 * k + 1];
+    }
+    sh[0][threadIdx.x] = a;
+    sh[1][threadIdx.x] = b;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        cscale[2 * par_cur] = (float)(m0a / sh[0][0]);
+        cscale[2 * par_cur + 1] = (float)(m0b / sh[1][0]);
+        mass_out[0] = sh[0][0];
+        mass_out[1] = sh[1][0];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Fused pull + force + collide.  MACRO: recompute the velocity of this
+// collision without storing populations (field read-back).
+template <bool WALLS, bool IBM, bool MACRO, bool HALF>
+__global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
                                                  const float* __restrict__ fib,
                                                  const int* __restrict__ tile_flag,
-                                                 float* __restrict__ u_out,
-                                                 float* __restrict__ rho_macro, Lattice L) {
-    constexpr int SW = BX + 2, SH = BY + 2;
-    __shared__ float sp[3][2][SH][SW];
+                                                 float* __restrict__ u_out, const float* __restrict__ cscale,
+                                                 int par_prev, int par_cur, Lattice L) {
+    constexpr int NE = HALF ? 2 : 1;
+    __shared__ Ring<2> sp;                       // psi + phi at time n
+    __shared__ Ring<NE> se;                      // decode densities rho_enc^{n-1} (FP16)
     const int tx = threadIdx.x, ty = threadIdx.y;
     const int tid = ty * BX + tx;
-    const int x0 = blockIdx.x * BX, y0 = blockIdx.y * BY, z0 = blockIdx.z * ZC;
+    int bx, by, bz;
+    block_xyz(bx, by, bz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
     const int z1 = min(z0 + ZC, L.nz);
     const int64_t N = L.n;
+    float cpv[2] = {1.0f, 1.0f}, ccu[2] = {1.0f, 1.0f};
+    if (HALF) {
+        cpv[0] = cscale[2 * par_prev];
+        cpv[1] = cscale[2 * par_prev + 1];
+        ccu[0] = cscale[2 * par_cur];
+        ccu[1] = cscale[2 * par_cur + 1];
+    }
 
-    auto stage = [&](int zz) {
-        const int slot = (zz - z0 + 1) % 3;
-        const int zw = wrapi(zz, L.nz);
-        for (int k = tid; k < 2 * SH * SW; k += BX * BY) {
-            const int c = k / (SH * SW);
-            const int r = k - c * SH * SW;
-            const int ly = r / SW, lx = r - ly * SW;
-            const int gx = wrapi(x0 - 1 + lx, L.nx);
-            int gy = wrapi(y0 - 1 + ly, L.ny);
-            if (WALLS) {
-                // solid rows take the pseudo-potential of the adjacent fluid row
-                if (gy == 0) gy = 1;
-                if (gy == L.ny - 1) gy = L.ny - 2;
-            }
-            const int64_t idx = ((int64_t)zw * L.ny + gy) * L.nx + gx;
-            float v = rho_n[c * N + idx];
-            if (IBM) {
-                const int t = ((zw >> 3) * L.nty + (gy >> 3)) * L.ntx + (gx >> 3);
-                if (tile_flag[t]) v += fib[(3 + c) * N + idx];
-            }
-            sp[slot][c][ly][lx] = v;
+    // Does any tile that the block's column or its halo overlaps carry
+    // immersed-boundary fields this step?  Most blocks lie away from every
+    // membrane and then skip all per-node tile lookups.
+    bool near_ibm = false;
+    if (IBM) {
+        const int tx0 = wrapi(x0 - 1, L.nx) >> 3, ntx_b = (BX + 2 + 7) / 8 + 1;
+        const int ty0 = wrapi(y0 - 1, L.ny) >> 3, nty_b = (BY + 2 + 7) / 8 + 1;
+        const int tz0 = wrapi(z0 - 1, L.nz) >> 3, ntz_b = (ZC + 2 + 7) / 8 + 1;
+        bool hit = false;
+        for (int k = tid; k < ntx_b * nty_b * ntz_b; k += BX * BY) {
+            const int i = k % ntx_b, j = (k / ntx_b) % nty_b, l = k / (ntx_b * nty_b);
+            const int t = (((tz0 + l) % L.ntz) * L.nty + (ty0 + j) % L.nty) * L.ntx + (tx0 + i) % L.ntx;
+            hit = hit || tile_flag[t] != 0;
         }
+        near_ibm = __syncthreads_or(hit) != 0;
+    }
+    auto stage = [&](int zz) {
+        if (IBM && near_ibm)
+            stage_plane<WALLS, true, 2>(sp, zz, z0, x0, y0, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
+        else
+            stage_plane<WALLS, false, 2>(sp, zz, z0, x0, y0, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
+        if (HALF) stage_plane<WALLS, false, NE>(se, zz, z0, x0, y0, tid, rho_p, cpv, nullptr, nullptr, L);
     };
 
     stage(z0 - 1);
@@ -190,11 +400,28 @@ __global__ __launch_bounds__(256) void k_collide(const float* __restrict__ fin, 
         __syncthreads();
         if (active) {
             const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const int s0 = (z - z0 + 1) % 3;
             Pulled A, B;
-            const float rpa = WALLS ? rho_p[node] : 0.0f;
-            const float rpb = WALLS ? rho_p[N + node] : 0.0f;
-            pull<WALLS>(fin, L, node, x, y, z, rpa, A);
-            pull<WALLS>(fin + (int64_t)Q * N, L, node, x, y, z, rpb, B);
+            if constexpr (HALF) {
+                auto enc = [&](int ex, int ey, int ez, float& a, float& b) {
+                    const int sl = (s0 - ez + 3) % 3;
+                    a = se.v[sl][0][ty + 1 - ey][tx + 1 - ex];
+                    b = se.v[sl][NE - 1][ty + 1 - ey][tx + 1 - ex];
+                };
+                pull<WALLS, true>(fin, L, node, x, y, z, se.v[s0][0][ty + 1][tx + 1], se.v[s0][NE - 1][ty + 1][tx + 1],
+                                  enc, A, B);
+                // FP64 mass compensation of this step
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    A.f[i] *= ccu[0];
+                    B.f[i] *= ccu[1];
+                }
+            } else {
+                auto none = [](int, int, int, float&, float&) {};
+                const float rpa = WALLS ? rho_p[node] : 0.0f;
+                const float rpb = WALLS ? rho_p[N + node] : 0.0f;
+                pull<WALLS, false>(fin, L, node, x, y, z, rpa, rpb, none, A, B);
+            }
             const float ra = sum_pop(A), rb = sum_pop(B);
             float jax, jay, jaz, jbx, jby, jbz;
             momentum(A, jax, jay, jaz);
@@ -202,13 +429,12 @@ __global__ __launch_bounds__(256) void k_collide(const float* __restrict__ fin, 
 
             // neighbour sums S^c = sum_i w_i (psi^c + phi^c)(x + c_i) c_i
             float sa[3] = {0.f, 0.f, 0.f}, sb[3] = {0.f, 0.f, 0.f};
-            const int s0 = (z - z0 + 1) % 3;
 #pragma unroll
             for (int k = 1; k < Q; k += 2) {
-                const int sp_ = (s0 + cz(k) + 3) % 3, sm_ = (s0 - cz(k) + 3) % 3;
+                const int sP = (s0 + cz(k) + 3) % 3, sM = (s0 - cz(k) + 3) % 3;
                 const int ly = ty + 1, lx = tx + 1;
-                const float da = sp[sp_][0][ly + cy(k)][lx + cx(k)] - sp[sm_][0][ly - cy(k)][lx - cx(k)];
-                const float db = sp[sp_][1][ly + cy(k)][lx + cx(k)] - sp[sm_][1][ly - cy(k)][lx - cx(k)];
+                const float da = sp.v[sP][0][ly + cy(k)][lx + cx(k)] - sp.v[sM][0][ly - cy(k)][lx - cx(k)];
+                const float db = sp.v[sP][1][ly + cy(k)][lx + cx(k)] - sp.v[sM][1][ly - cy(k)][lx - cx(k)];
                 const float w = wgt(k);
                 if (cx(k) != 0) { sa[0] += w * cx(k) * da; sb[0] += w * cx(k) * db; }
                 if (cy(k) != 0) { sa[1] += w * cy(k) * da; sb[1] += w * cy(k) * db; }
@@ -222,7 +448,7 @@ __global__ __launch_bounds__(256) void k_collide(const float* __restrict__ fin, 
                 Fb[d] = -L.G * rb * sa[d];
             }
             bool flagged = false;
-            if (IBM) {
+            if (IBM && near_ibm) {
                 const int t = ((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3);
                 flagged = tile_flag[t] != 0;
                 if (flagged) {
@@ -249,28 +475,41 @@ __global__ __launch_bounds__(256) void k_collide(const float* __restrict__ fin, 
                 u_out[2 * N + node] = (jaz + jbz + 0.5f * (Fa[2] + Fb[2])) * ir;
             }
             if (!MACRO) {
+                float ux[2], uy[2], uz[2], base[2], inv[2], rest[2];
+                const float r2[2] = {ra, rb};
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
-                    const Pulled& P = c == 0 ? A : B;
-                    const float r = c == 0 ? ra : rb;
                     const float* F = c == 0 ? Fa : Fb;
-                    const float om = L.omega[c];
-                    const float ts = L.tau[c] / r;
-                    const float ux = upx + ts * F[0], uy = upy + ts * F[1], uz = upz + ts * F[2];
-                    const float base = r * (1.0f - 1.5f * (ux * ux + uy * uy + uz * uz));
-                    float* fo = fout + (int64_t)c * Q * N + node;
-                    float rest = r;
-#pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-                        const float feq = wgt(i) * (base + r * cu * (3.0f + 4.5f * cu));
-                        const float fs = P.f[i] + om * (feq - P.f[i]);
-                        rest -= fs;
-                        fo[(int64_t)i * N] = fs;
-                    }
-                    // rest population closes the node's mass exactly
-                    fo[0] = rest;
+                    const float ts = L.tau[c] / r2[c];
+                    ux[c] = upx + ts * F[0];
+                    uy[c] = upy + ts * F[1];
+                    uz[c] = upz + ts * F[2];
+                    base[c] = r2[c] * (1.0f - 1.5f * (ux[c] * ux[c] + uy[c] * uy[c] + uz[c] * uz[c]));
+                    // FP16: encode relative to this node's compensated density,
+                    // bit-identical to what the next step's decoder stages
+                    inv[c] = HALF ? 1.0f / (ccu[c] * rho_n[c * N + node]) : 1.0f;
+                    rest[c] = r2[c];
                 }
+                PopT<HALF>* fo = fout + node;
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    float fs[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const Pulled& P = c == 0 ? A : B;
+                        const float cu = cx(i) * ux[c] + cy(i) * uy[c] + cz(i) * uz[c];
+                        const float feq = wgt(i) * (base[c] + r2[c] * cu * (3.0f + 4.5f * cu));
+                        fs[c] = P.f[i] + L.omega[c] * (feq - P.f[i]);
+                        rest[c] -= fs[c];
+                        if (HALF) fs[c] = fs[c] * inv[c] - wgt(i);
+                    }
+                    store_pop(fo + (int64_t)i * N, pack<HALF>(fs[0], fs[1]));
+                }
+                // rest populations close the node's mass
+                if (HALF)
+                    store_pop(fo, pack<HALF>(rest[0] * inv[0] - wgt(0), rest[1] * inv[1] - wgt(0)));
+                else
+                    store_pop(fo, pack<HALF>(rest[0], rest[1]));
             }
         } else if (MACRO && x < L.nx && y < L.ny) {
             const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
@@ -281,9 +520,12 @@ __global__ __launch_bounds__(256) void k_collide(const float* __restrict__ fin, 
 }
 
 // FP64 mass and momentum of the post-collision state over fluid nodes:
-// per-block partial sums [mass A, mass B, px, py, pz].
-__global__ __launch_bounds__(256) void k_reduce_fluid(const float* __restrict__ f, double* __restrict__ partial,
-                                                      Lattice L) {
+// per-block partial sums [mass A, mass B, px, py, pz].  FP16: decoded with
+// rho_enc = cscale * rho of the writing step.
+template <bool HALF>
+__global__ __launch_bounds__(256) void k_reduce_fluid(const PopT<HALF>* __restrict__ f, const float* __restrict__ renc,
+                                                      const float* __restrict__ cscale, int par,
+                                                      double* __restrict__ partial, Lattice L) {
     __shared__ double sh[5][256];
     double acc[5] = {0, 0, 0, 0, 0};
     const int64_t plane = (int64_t)L.nx * L.ny;
@@ -293,12 +535,15 @@ __global__ __launch_bounds__(256) void k_reduce_fluid(const float* __restrict__ 
             const int y = (int)((k % plane) / L.nx);
             if (y == 0 || y == L.ny - 1) continue;
         }
+        const double r[2] = {HALF ? (double)(cscale[2 * par] * renc[k]) : 1.0,
+                             HALF ? (double)(cscale[2 * par + 1] * renc[L.n + k]) : 1.0};
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
-            const float* fc = f + (int64_t)c * Q * L.n + k;
+        for (int i = 0; i < Q; ++i) {
+            const PopT<HALF> p = f[(int64_t)i * L.n + k];
+            const double g[2] = {(double)(float)p.x, (double)(float)p.y};
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const double v = fc[(int64_t)i * L.n];
+            for (int c = 0; c < 2; ++c) {
+                const double v = HALF ? r[c] * ((double)wgt(i) + g[c]) : g[c];
                 acc[c] += v;
                 if (cx(i)) acc[2] += cx(i) * v;
                 if (cy(i)) acc[3] += cy(i) * v;
@@ -319,48 +564,82 @@ __global__ __launch_bounds__(256) void k_reduce_fluid(const float* __restrict__ 
 
 }  // namespace
 
-void launch_init_rest(const Lattice& L, float* f, const float* rhoA, const float* rhoB, hipStream_t s) {
+void launch_init_rest(const Lattice& L, void* f, const float* rhoA, const float* rhoB, bool half,
+                      hipStream_t s) {
     const int64_t blocks = std::min<int64_t>((L.n + 255) / 256, 65536);
-    hipLaunchKernelGGL(k_init_rest, dim3((unsigned)blocks), dim3(256), 0, s, f, rhoA, rhoB, L.n);
-}
-
-void launch_density(const Lattice& L, const float* fin, const float* rho_prev, float* rho_out,
-                    hipStream_t s) {
-    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, L.nz);
-    dim3 block(BX, BY);
-    if (L.walls)
-        hipLaunchKernelGGL(k_density<true>, grid, block, 0, s, fin, rho_prev, rho_out, L);
+    if (half)
+        hipLaunchKernelGGL(k_init_rest<true>, dim3((unsigned)blocks), dim3(256), 0, s, (ph2*)f, rhoA, rhoB, L.n);
     else
-        hipLaunchKernelGGL(k_density<false>, grid, block, 0, s, fin, rho_prev, rho_out, L);
+        hipLaunchKernelGGL(k_init_rest<false>, dim3((unsigned)blocks), dim3(256), 0, s, (pf2*)f, rhoA, rhoB, L.n);
 }
 
-template <bool W, bool I, bool M>
-static void launch_collide_t(const Lattice& L, const float* fin, float* fout, const float* rho_n,
+int64_t density_blocks(const Lattice& L, bool half) {
+    return (int64_t)((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) * (half ? (L.nz + ZC - 1) / ZC : L.nz);
+}
+
+void launch_density(const Lattice& L, const void* fin, const float* rho_prev, float* rho_out, bool half,
+                    const float* cscale, int par_prev, double* partial, hipStream_t s) {
+    const dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, half ? (L.nz + ZC - 1) / ZC : L.nz);
+    const dim3 block(BX, BY);
+    if (half) {
+        if (L.walls)
+            hipLaunchKernelGGL(k_density_half<true>, grid, block, 0, s, (const ph2*)fin, rho_prev, cscale,
+                               par_prev, rho_out, partial, L);
+        else
+            hipLaunchKernelGGL(k_density_half<false>, grid, block, 0, s, (const ph2*)fin, rho_prev, cscale,
+                               par_prev, rho_out, partial, L);
+    } else {
+        if (L.walls)
+            hipLaunchKernelGGL(k_density<true>, grid, block, 0, s, (const pf2*)fin, rho_prev, rho_out, L);
+        else
+            hipLaunchKernelGGL(k_density<false>, grid, block, 0, s, (const pf2*)fin, rho_prev, rho_out, L);
+    }
+}
+
+void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale, int par_cur,
+                       double* mass_out, hipStream_t s) {
+    const int nb = (int)density_blocks(L, true);
+    hipLaunchKernelGGL(k_compensate, dim3(1), dim3(1024), 0, s, partial, nb, m0a, m0b, cscale, par_cur, mass_out);
+}
+
+template <bool W, bool I, bool M, bool H>
+static void launch_collide_t(const Lattice& L, const void* fin, void* fout, const float* rho_n,
                              const float* rho_prev, const float* fib, const int* tile_flag, float* u,
-                             float* rho_macro, hipStream_t s) {
+                             const float* cscale, int par_prev, int par_cur, hipStream_t s) {
     dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC);
     dim3 block(BX, BY);
-    hipLaunchKernelGGL((k_collide<W, I, M>), grid, block, 0, s, fin, fout, rho_n, rho_prev, fib, tile_flag,
-                       u, rho_macro, L);
+    hipLaunchKernelGGL((k_collide<W, I, M, H>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout, rho_n,
+                       rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
 }
 
-void launch_collide(const Lattice& L, const float* fin, float* fout, const float* rho_n,
-                    const float* rho_prev, const float* fib, const int* tile_flag, float* u,
-                    float* rho_macro, bool has_ibm, bool macro, hipStream_t s) {
+void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,
+                    const float* fib, const int* tile_flag, float* u, bool has_ibm, bool macro, bool half,
+                    const float* cscale, int par_prev, int par_cur, hipStream_t s) {
     const bool w = L.walls != 0;
-#define LC(W, I, M) launch_collide_t<W, I, M>(L, fin, fout, rho_n, rho_prev, fib, tile_flag, u, rho_macro, s)
+#define LC(W, I, M, H) \
+    launch_collide_t<W, I, M, H>(L, fin, fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, s)
+#define LC_H(W, I, M) \
+    do { if (half) LC(W, I, M, true); else LC(W, I, M, false); } while (0)
+#define LC_I(W, M) \
+    do { if (has_ibm) LC_H(W, true, M); else LC_H(W, false, M); } while (0)
     if (macro) {
-        if (w) { if (has_ibm) LC(true, true, true); else LC(true, false, true); }
-        else { if (has_ibm) LC(false, true, true); else LC(false, false, true); }
+        if (w) LC_I(true, true); else LC_I(false, true);
     } else {
-        if (w) { if (has_ibm) LC(true, true, false); else LC(true, false, false); }
-        else { if (has_ibm) LC(false, true, false); else LC(false, false, false); }
+        if (w) LC_I(true, false); else LC_I(false, false);
     }
+#undef LC_I
+#undef LC_H
 #undef LC
 }
 
-void launch_reduce_fluid(const Lattice& L, const float* fpost, double* partial, hipStream_t s) {
-    hipLaunchKernelGGL(k_reduce_fluid, dim3(RED_BLOCKS), dim3(256), 0, s, fpost, partial, L);
+void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const float* renc, const float* cscale,
+                         int par, double* partial, hipStream_t s) {
+    if (half)
+        hipLaunchKernelGGL(k_reduce_fluid<true>, dim3(RED_BLOCKS), dim3(256), 0, s, (const ph2*)fpost, renc,
+                           cscale, par, partial, L);
+    else
+        hipLaunchKernelGGL(k_reduce_fluid<false>, dim3(RED_BLOCKS), dim3(256), 0, s, (const pf2*)fpost, renc,
+                           cscale, par, partial, L);
 }
 
 }  // namespace lbmx

@@ -8,17 +8,18 @@
 // Per step:
 //   k_clear_tiles   zero the immersed-boundary fields of last step's tiles
 //   k_cap_volume    FP64 enclosed volume per capsule (Sec. II.B, eq.
-//                   method:volume)
+//                   method:volume), one thread per triangle
 //   k_faces         Skalak (Sec. II.B, eq. method:strain) and volume
 //                   forces per triangle and corner, F = -dE/dX
 //   k_nodes         one wavefront per node: gather its triangles' corner
 //                   forces, add the wettability reaction (64 lanes = the
-//                   4x4x4 delta stencil), count the node into its home tile,
-//                   mark the tiles its stencil touches
+//                   4x4x4 delta stencil, psi staged on a 6^3 LDS cube),
+//                   count the node into its home bin (4^3), mark the 8^3
+//                   tiles its stencil touches
 //   k_bin_scan      exclusive scan of the home-tile counts
 //   k_bin_scatter   counting-sort scatter of node ids into tile bins
-//   k_spread        one workgroup per home tile: accumulate F_b delta and
-//                   the virtual density in an 11^3 LDS box (LDS atomics,
+//   k_spread        one workgroup per occupied bin: accumulate F_b delta and
+//                   the virtual density in a 7^3 LDS box (LDS atomics,
 //                   one lane per stencil point), then flush non-zero cells
 //                   to HBM with global atomics
 //   k_interp_advect one wavefront per node: U_b = sum u delta, X += U_b
@@ -72,7 +73,11 @@ __device__ __forceinline__ int tile_of(const Lattice& L, int x, int y, int z) {
     return ((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3);
 }
 
-__global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, int pc) {
+__device__ __forceinline__ int bin_of(const Lattice& L, int x, int y, int z) {
+    return ((z / BIN) * L.nby + (y / BIN)) * L.nbx + (x / BIN);
+}
+
+__global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, int pc, int n_caps) {
     const int nt = d.counters[CNT_TOUCHED + pp];
     const int nh = d.counters[CNT_HOME + pp];
     const int64_t N = L.n;
@@ -92,17 +97,27 @@ __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, i
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nh;
          k += (int64_t)gridDim.x * blockDim.x)
         d.tile_count[d.home[pp][k]] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        d.counters[CNT_TOUCHED + pc] = 0;
-        d.counters[CNT_HOME + pc] = 0;
+    if (blockIdx.x == 0) {
+        if (threadIdx.x == 0) {
+            d.counters[CNT_TOUCHED + pc] = 0;
+            d.counters[CNT_HOME + pc] = 0;
+        }
+        for (int k = threadIdx.x; k < n_caps; k += blockDim.x) d.capV[k] = 0.0;
     }
 }
 
-__global__ __launch_bounds__(256) void k_cap_volume(Dev d) {
+// FP64 enclosed volume per capsule, V = (1/6) sum_T X1 . (X2 x X3) over
+// anchor-relative offsets: one thread per triangle, a block reduction when
+// the block's triangles belong to one capsule, FP64 atomics otherwise.
+__global__ __launch_bounds__(256) void k_cap_volume(Dev d, int n_faces) {
     __shared__ double sh[256];
-    const CapDev C = d.caps[blockIdx.x];
-    double acc = 0.0;
-    for (int f = C.face_start + threadIdx.x; f < C.face_start + C.face_count; f += blockDim.x) {
+    __shared__ int cap_first, cap_last;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f_last = min((int)(blockIdx.x * blockDim.x + blockDim.x), n_faces) - 1;
+    double v = 0.0;
+    int cap = -1;
+    if (f < n_faces) {
+        cap = d.face_cap[f];
         double X[3][3];
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -110,17 +125,26 @@ __global__ __launch_bounds__(256) void k_cap_volume(Dev d) {
 #pragma unroll
             for (int j = 0; j < 3; ++j) X[k][j] = (double)d.off_hi[3 * b + j];
         }
-        acc += X[0][0] * (X[1][1] * X[2][2] - X[1][2] * X[2][1])
-             + X[0][1] * (X[1][2] * X[2][0] - X[1][0] * X[2][2])
-             + X[0][2] * (X[1][0] * X[2][1] - X[1][1] * X[2][0]);
+        v = (X[0][0] * (X[1][1] * X[2][2] - X[1][2] * X[2][1])
+           + X[0][1] * (X[1][2] * X[2][0] - X[1][0] * X[2][2])
+           + X[0][2] * (X[1][0] * X[2][1] - X[1][1] * X[2][0])) / 6.0;
     }
-    sh[threadIdx.x] = acc;
+    if (threadIdx.x == 0) {
+        cap_first = d.face_cap[blockIdx.x * blockDim.x];
+        cap_last = d.face_cap[f_last];
+    }
+    __syncthreads();
+    if (cap_first != cap_last) {
+        if (f < n_faces) unsafeAtomicAdd(&d.capV[cap], v);
+        return;
+    }
+    sh[threadIdx.x] = v;
     __syncthreads();
     for (int s = 128; s > 0; s >>= 1) {
         if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
         __syncthreads();
     }
-    if (threadIdx.x == 0) d.capV[blockIdx.x] = sh[0] / 6.0;
+    if (threadIdx.x == 0) unsafeAtomicAdd(&d.capV[cap_first], sh[0]);
 }
 
 __device__ __forceinline__ void cross3(const float* a, const float* b, float* o) {
@@ -193,10 +217,13 @@ __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
 }
 
 __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __restrict__ rho_n,
-                                               int n_nodes, int par) {
+                                               const float* __restrict__ cs, int n_nodes, int par) {
+    constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
+    __shared__ float cube[4][CB * CB * CB];
     const int lane = threadIdx.x & 63;
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (b >= n_nodes) return;
+    if (b >= n_nodes) return;                   // whole wavefront; no block barrier below
+    float* cb = cube[threadIdx.x >> 6];
     // corner forces of the incident triangles
     float gx = 0.f, gy = 0.f, gz = 0.f;
     const int beg = d.csr_ptr[b], end = d.csr_ptr[b + 1];
@@ -212,20 +239,27 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         // reaction of the virtual density on the node:
         // -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i
         const int np = 1 - d.caps[d.node_cap[b]].pref;
+        const float* rc = rho_n + (int64_t)np * L.n;
+        const float sc = cs ? cs[np] : 1.0f;      // FP16 form: mass compensation of this step
+        // the wavefront stages psi^np on the 6^3 cube floor(X)-2 .. floor(X)+3
+        for (int j = lane; j < CB * CB * CB; j += 64) {
+            const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
+            int gy = wrapi(p.fl[1] - 2 + qy, L.ny);
+            if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
+            cb[j] = sc * rc[((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx + wrapi(p.fl[0] - 2 + qx, L.nx)];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
         const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
-        const int yx = p.fl[0] - 1 + kx, yy = p.fl[1] - 1 + ky, yz = p.fl[2] - 1 + kz;
-        const float* rc = rho_n + (int64_t)np * L.n;
+        const int c0 = ((kz + 1) * CB + (ky + 1)) * CB + (kx + 1);
         float S[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int k = 1; k < Q; k += 2) {
-            int ay = wrapi(yy + cy(k), L.ny), by = wrapi(yy - cy(k), L.ny);
-            if (L.walls) {
-                ay = ay == 0 ? 1 : (ay == L.ny - 1 ? L.ny - 2 : ay);
-                by = by == 0 ? 1 : (by == L.ny - 1 ? L.ny - 2 : by);
-            }
-            const float va = rc[((int64_t)wrapi(yz + cz(k), L.nz) * L.ny + ay) * L.nx + wrapi(yx + cx(k), L.nx)];
-            const float vb = rc[((int64_t)wrapi(yz - cz(k), L.nz) * L.ny + by) * L.nx + wrapi(yx - cx(k), L.nx)];
+            const int o = (cz(k) * CB + cy(k)) * CB + cx(k);
+            const float va = cb[c0 + o];
+            const float vb = cb[c0 - o];
             const float dd = wgt(k) * (va - vb);
             if (cx(k)) S[0] += cx(k) * dd;
             if (cy(k)) S[1] += cy(k) * dd;
@@ -243,31 +277,36 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         d.node_F[3 * b + 0] = gx;
         d.node_F[3 * b + 1] = gy;
         d.node_F[3 * b + 2] = gz;
+    } else if (lane == 1) {
         const int wx = wrapi(p.fl[0], L.nx), wy = wrapi(p.fl[1], L.ny), wz = wrapi(p.fl[2], L.nz);
-        const int t = tile_of(L, wx, wy, wz);
+        const int t = bin_of(L, wx, wy, wz);
         const int rank = atomicAdd(&d.tile_count[t], 1);
         d.node_tile[b] = t;
         d.node_rank[b] = rank;
         if (rank == 0) d.home[par][atomicAdd(&d.counters[CNT_HOME + par], 1)] = t;
-        // tiles touched by the stencil floor(X)-1 .. floor(X)+2 (at most two per axis)
-        int ta[3][2], nta[3];
+    } else if (lane >= 8 && lane < 16) {
+        // tiles touched by the stencil floor(X)-1 .. floor(X)+2: at most two
+        // per axis; lane 8 + (i, j, k) takes one combination
+        const int sel[3] = {(lane - 8) & 1, ((lane - 8) >> 1) & 1, ((lane - 8) >> 2) & 1};
         const int nn[3] = {L.nx, L.ny, L.nz};
+        int tt[3];
+        bool ok = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            ta[a][0] = wrapi(p.fl[a] - 1, nn[a]) >> 3;
-            nta[a] = 1;
-            for (int k = 0; k < 4; ++k) {
+            const int t0 = wrapi(p.fl[a] - 1, nn[a]) >> 3;
+            int t1 = -1;
+            for (int k = 1; k < 4; ++k) {
                 const int tk = wrapi(p.fl[a] - 1 + k, nn[a]) >> 3;
-                if (tk != ta[a][0]) { ta[a][1] = tk; nta[a] = 2; }
+                if (tk != t0) t1 = tk;
             }
+            tt[a] = sel[a] ? t1 : t0;
+            ok = ok && tt[a] >= 0;
         }
-        for (int i = 0; i < nta[0]; ++i)
-            for (int j = 0; j < nta[1]; ++j)
-                for (int k = 0; k < nta[2]; ++k) {
-                    const int t2 = (ta[2][k] * L.nty + ta[1][j]) * L.ntx + ta[0][i];
-                    if (atomicExch(&d.tile_flag[t2], 1) == 0)
-                        d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t2;
-                }
+        if (ok) {
+            const int t2 = (tt[2] * L.nty + tt[1]) * L.ntx + tt[0];
+            if (atomicExch(&d.tile_flag[t2], 1) == 0)
+                d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t2;
+        }
     }
 }
 
@@ -314,7 +353,7 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
     for (int e = blockIdx.x; e < nh; e += gridDim.x) {
         const int t = d.home[par][e];
         const int start = d.home_start[e], cnt = d.tile_count[t];
-        const int ox = (t % L.ntx) * TILE, oy = ((t / L.ntx) % L.nty) * TILE, oz = (t / (L.ntx * L.nty)) * TILE;
+        const int ox = (t % L.nbx) * BIN, oy = ((t / L.nbx) % L.nby) * BIN, oz = (t / (L.nbx * L.nby)) * BIN;
         for (int k = threadIdx.x; k < 5 * B3; k += 256) (&box[0][0])[k] = 0.0f;
         __syncthreads();
         for (int j = wave; j < cnt; j += 4) {
@@ -422,7 +461,7 @@ __global__ __launch_bounds__(256) void k_debug_bins(Lattice L, Dev d, int n_node
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_nodes) return;
     const NodePos p = node_pos(d, b);
-    d.dbg_bins[4 * b + 0] = tile_of(L, wrapi(p.fl[0], L.nx), wrapi(p.fl[1], L.ny), wrapi(p.fl[2], L.nz));
+    d.dbg_bins[4 * b + 0] = bin_of(L, wrapi(p.fl[0], L.nx), wrapi(p.fl[1], L.ny), wrapi(p.fl[2], L.nz));
     d.dbg_bins[4 * b + 1] = p.fl[0] - 1;
     d.dbg_bins[4 * b + 2] = p.fl[1] - 1;
     d.dbg_bins[4 * b + 3] = p.fl[2] - 1;
@@ -430,18 +469,19 @@ __global__ __launch_bounds__(256) void k_debug_bins(Lattice L, Dev d, int n_node
 
 }  // namespace
 
-void launch_clear_tiles(const Lattice& L, Dev& d, int pp, int pc, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_tiles, dim3(1024), dim3(256), 0, s, L, d, pp, pc);
+void launch_clear_tiles(const Lattice& L, Dev& d, int pp, int pc, int n_caps, hipStream_t s) {
+    hipLaunchKernelGGL(k_clear_tiles, dim3(1024), dim3(256), 0, s, L, d, pp, pc, n_caps);
 }
-void launch_cap_volume(const Dev& d, int n_caps, hipStream_t s) {
-    if (n_caps > 0) hipLaunchKernelGGL(k_cap_volume, dim3(n_caps), dim3(256), 0, s, d);
+void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s) {
+    if (n_faces > 0) hipLaunchKernelGGL(k_cap_volume, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
 }
 void launch_faces(const Dev& d, int n_faces, hipStream_t s) {
     if (n_faces > 0) hipLaunchKernelGGL(k_faces, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
 }
-void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, int n_nodes, int par, hipStream_t s) {
+void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes, int par,
+                  hipStream_t s) {
     if (n_nodes > 0)
-        hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 3) / 4), dim3(256), 0, s, L, d, rho_n, n_nodes, par);
+        hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 3) / 4), dim3(256), 0, s, L, d, rho_n, cs, n_nodes, par);
 }
 void launch_bin_scan(const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, d, par);

@@ -24,12 +24,13 @@ struct Layout {
     size_t total = 0;
     size_t f[2], rho[2], fib, u;
     size_t tile_flag, tile_count, tile_offset, home_start, touched[2], home[2], counters;
+    int64_t bins;
     size_t off_hi, off_lo, node_cap, node_wet, node_F, node_tile, node_rank, sorted, csr_ptr, csr_idx,
         dbg_bins;
     size_t tri, fref, face_cap, face_F;
-    size_t caps, capV, cap_mom, red;
-    size_t slot0, slot_bytes;
-    size_t slot_f, slot_rho, slot_off;   // offsets inside a slot
+    size_t caps, capV, cap_mom, red, cscale, dpart, dmass;
+    size_t slot0, slot_bytes, fbytes;
+    size_t slot_f, slot_rho, slot_off, slot_cs;   // offsets inside a slot
     int64_t tiles, max_caps;
 };
 
@@ -45,9 +46,14 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     const int64_t T = (int64_t)((p->nx + TILE - 1) / TILE) * ((p->ny + TILE - 1) / TILE) * ((p->nz + TILE - 1) / TILE);
     const int64_t nb = std::max<int64_t>(max_nodes, 1), nf = std::max<int64_t>(max_faces, 1);
     l.tiles = T;
+    const int64_t NB = (int64_t)((p->nx + BIN - 1) / BIN) * ((p->ny + BIN - 1) / BIN) * ((p->nz + BIN - 1) / BIN);
+    l.bins = NB;
     l.max_caps = nb / 12 + 1;
     size_t c = 0;
-    const size_t fbytes = (size_t)2 * Q * N * sizeof(float);
+    const bool half = p->precision == LBM_FP16;
+    const size_t fbytes = (size_t)2 * Q * N * (half ? 2 : 4);
+    l.fbytes = fbytes;
+    const int64_t dblocks = (int64_t)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY) * ((p->nz + ZC - 1) / ZC);
     l.f[0] = take(c, fbytes);
     l.f[1] = take(c, fbytes);
     l.rho[0] = take(c, 2 * N * sizeof(float));
@@ -55,13 +61,13 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     l.fib = take(c, 5 * N * sizeof(float));
     l.u = take(c, 3 * N * sizeof(float));
     l.tile_flag = take(c, T * 4);
-    l.tile_count = take(c, T * 4);
-    l.tile_offset = take(c, T * 4);
-    l.home_start = take(c, T * 4);
+    l.tile_count = take(c, NB * 4);
+    l.tile_offset = take(c, NB * 4);
+    l.home_start = take(c, NB * 4);
     l.touched[0] = take(c, T * 4);
     l.touched[1] = take(c, T * 4);
-    l.home[0] = take(c, T * 4);
-    l.home[1] = take(c, T * 4);
+    l.home[0] = take(c, NB * 4);
+    l.home[1] = take(c, NB * 4);
     l.counters = take(c, 8 * 4);
     l.off_hi = take(c, 3 * nb * 4);
     l.off_lo = take(c, 3 * nb * 4);
@@ -82,10 +88,14 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     l.capV = take(c, l.max_caps * 8);
     l.cap_mom = take(c, l.max_caps * MOM_STRIDE * 8);
     l.red = take(c, RED_BLOCKS * 8 * 8);
+    l.cscale = take(c, 4 * sizeof(float));
+    l.dpart = take(c, (size_t)dblocks * 2 * 8);
+    l.dmass = take(c, 2 * 8);
     size_t s = 0;
     l.slot_f = take(s, fbytes);
     l.slot_rho = take(s, 4 * N * sizeof(float));
     l.slot_off = take(s, 6 * nb * 4);
+    l.slot_cs = take(s, 4 * sizeof(float));
     l.slot_bytes = (s + 255) & ~size_t(255);
     l.slot0 = take(c, (size_t)std::max(p->n_slots, 0) * l.slot_bytes);
     l.total = (c + 255) & ~size_t(255);
@@ -96,7 +106,7 @@ std::string validate(const lbm_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 4 || p->ny < 4 || p->nz < 4) return "lattice sizes must be >= 4";
     if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34)) return "lattice too large";
-    if (p->precision != LBM_FP32) return "precision: only LBM_FP32 is available in this build";
+    if (p->precision != LBM_FP32 && p->precision != LBM_FP16) return "precision must be LBM_FP32 or LBM_FP16";
     if (p->walls != 0 && p->walls != 1) return "walls must be 0 or 1";
     if (p->walls && p->ny < 5) return "walls need ny >= 5";
     for (int c = 0; c < 2; ++c)
@@ -108,6 +118,7 @@ std::string validate(const lbm_params* p) {
     if (!(p->wet_scale >= 0.0) || !isfinite(p->wet_scale)) return "wet_scale must be finite and >= 0";
     if (p->n_slots < 0 || p->n_slots > 4096) return "n_slots out of range";
     if (p->check_every < 0) return "check_every must be >= 0";
+    if (p->use_graphs != 0 && p->use_graphs != 1) return "use_graphs must be 0 or 1";
     return "";
 }
 
@@ -136,7 +147,17 @@ struct lbm_ctx {
     std::vector<FaceRef> fref;
     std::vector<int> face_cap;
     int n_nodes = 0, n_faces = 0;
+    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [step parity][flip]
+    bool graphs_failed = false;
     std::string err;
+
+    bool half() const { return p.precision == LBM_FP16; }
+
+    ~lbm_ctx() {
+        for (auto& row : graph)
+            for (auto& g : row)
+                if (g) (void)hipGraphExecDestroy(g);
+    }
 
     int fail(int code, const char* fmt, ...) {
         char buf[512];
@@ -205,6 +226,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     Lattice& L = c->L;
     L.nx = p->nx; L.ny = p->ny; L.nz = p->nz;
     L.ntx = (p->nx + TILE - 1) / TILE; L.nty = (p->ny + TILE - 1) / TILE; L.ntz = (p->nz + TILE - 1) / TILE;
+    L.nbx = (p->nx + BIN - 1) / BIN; L.nby = (p->ny + BIN - 1) / BIN; L.nbz = (p->nz + BIN - 1) / BIN;
     L.n = N;
     L.walls = p->walls;
     L.G = (float)p->G;
@@ -212,8 +234,11 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     for (int k = 0; k < 3; ++k) { L.uw_lo[k] = (float)p->wall_u_lo[k]; L.uw_hi[k] = (float)p->wall_u_hi[k]; }
     Dev& d = c->d;
     char* w = c->ws;
-    d.f[0] = (float*)(w + lay.f[0]);
-    d.f[1] = (float*)(w + lay.f[1]);
+    d.f[0] = (void*)(w + lay.f[0]);
+    d.f[1] = (void*)(w + lay.f[1]);
+    d.cscale = (float*)(w + lay.cscale);
+    d.dpart = (double*)(w + lay.dpart);
+    d.dmass = (double*)(w + lay.dmass);
     d.rho[0] = (float*)(w + lay.rho[0]);
     d.rho[1] = (float*)(w + lay.rho[1]);
     d.fib = (float*)(w + lay.fib);
@@ -259,10 +284,14 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
         if ((er = hipMemcpyAsync(d.rho[b] + N, rhoB, N * sizeof(float), hipMemcpyHostToDevice, s)) != hipSuccess)
             return bad(er, "hipMemcpyAsync");
     }
-    launch_init_rest(L, d.f[0], d.rho[0], d.rho[0] + N, s);
+    const bool half = p->precision == LBM_FP16;
+    launch_init_rest(L, d.f[0], d.rho[0], d.rho[0] + N, half, s);
+    static const float ones[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if ((er = hipMemcpyAsync(d.cscale, ones, sizeof ones, hipMemcpyHostToDevice, s)) != hipSuccess)
+        return bad(er, "hipMemcpyAsync");
     if ((er = hipMemsetAsync(d.fib, 0, 5 * N * sizeof(float), s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_flag, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
-    if ((er = hipMemsetAsync(d.tile_count, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipMemsetAsync(d.tile_count, 0, lay.bins * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.counters, 0, 8 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipGetLastError()) != hipSuccess) return bad(er, "init kernel launch");
     // the host arrays may be freed once the copies are done
@@ -401,7 +430,8 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
 
 static int check_mass(lbm_ctx* c) {
     Dev& d = c->d;
-    launch_reduce_fluid(c->L, d.f[c->step & 1], d.red, c->stream);
+    const int pw = (int)((c->step & 1) ^ 1);   // parity of the step that wrote the state
+    launch_reduce_fluid(c->L, d.f[c->step & 1], c->half(), d.rho[pw], d.cscale, pw, d.red, c->stream);
     std::vector<double> part(RED_BLOCKS * 8);
     HIPCHK(c, hipMemcpyAsync(part.data(), d.red, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -424,22 +454,24 @@ static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
     const bool ibm = c->n_nodes > 0;
     const int ncap = (int)c->caps.size();
     const int cur = (int)(c->step & 1), nxt = cur ^ 1;
-    const float* fin = d.f[cur];
-    float* fout = d.f[nxt];
+    const void* fin = d.f[cur];
+    void* fout = d.f[nxt];
     float* rho_n = d.rho[cur];
     const float* rho_p = d.rho[nxt];
     const int par = c->flip;
+    const bool half = c->half();
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
     mark(LBM_K_CLEAR);
-    if (ibm) launch_clear_tiles(L, d, par ^ 1, par, s);
+    if (ibm) launch_clear_tiles(L, d, par ^ 1, par, ncap, s);
     mark(LBM_K_DENSITY);
-    launch_density(L, fin, rho_p, rho_n, s);
+    launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
+    if (half) launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
     mark(LBM_K_VOLUME);
-    if (ibm) launch_cap_volume(d, ncap, s);
+    if (ibm) launch_cap_volume(d, c->n_faces, s);
     mark(LBM_K_FACES);
     if (ibm) launch_faces(d, c->n_faces, s);
     mark(LBM_K_NODES);
-    if (ibm) launch_nodes(L, d, rho_n, c->n_nodes, par, s);
+    if (ibm) launch_nodes(L, d, rho_n, half ? d.cscale + 2 * cur : nullptr, c->n_nodes, par, s);
     mark(LBM_K_SCAN);
     if (ibm) launch_bin_scan(d, par, s);
     mark(LBM_K_SCATTER);
@@ -447,7 +479,7 @@ static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
     mark(LBM_K_SPREAD);
     if (ibm) launch_spread(L, d, par, s);
     mark(LBM_K_COLLIDE);
-    launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, nullptr, ibm, false, s);
+    launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ibm, false, half, d.cscale, nxt, cur, s);
     mark(LBM_K_INTERP);
     if (ibm) launch_interp_advect(L, d, c->n_nodes, s);
     mark(LBM_NK);
@@ -455,18 +487,59 @@ static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
     c->flip ^= 1;
 }
 
+// Two steps captured as one graph.  The launch arguments depend only on the
+// step parity and the tile-list parity, so four graphs cover every state.
+static hipGraphExec_t two_step_graph(lbm_ctx* c) {
+    const int sp = (int)(c->step & 1), fp = c->flip;
+    if (c->graph[sp][fp]) return c->graph[sp][fp];
+    if (c->graphs_failed || c->stream == nullptr) return nullptr;
+    const int64_t step0 = c->step;
+    const int flip0 = c->flip;
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        c->graphs_failed = true;
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    enqueue_step(c, nullptr);
+    enqueue_step(c, nullptr);
+    const hipError_t e = hipStreamEndCapture(c->stream, &g);
+    c->step = step0;
+    c->flip = flip0;
+    hipGraphExec_t ex = nullptr;
+    if (e != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        c->graphs_failed = true;
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    (void)hipGraphDestroy(g);
+    c->graph[sp][fp] = ex;
+    return ex;
+}
+
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");
-    for (int k = 0; k < nsteps; ++k) {
-        enqueue_step(c, nullptr);
+    int left = nsteps;
+    while (left > 0) {
+        int chunk = left;
+        if (c->p.check_every > 0) chunk = std::min<int64_t>(chunk, c->p.check_every - c->step % c->p.check_every);
+        left -= chunk;
+        while (chunk >= 2 && c->p.use_graphs) {
+            hipGraphExec_t ex = two_step_graph(c);
+            if (!ex) break;
+            HIPCHK(c, hipGraphLaunch(ex, c->stream));
+            c->step += 2;
+            chunk -= 2;
+        }
+        for (; chunk > 0; --chunk) enqueue_step(c, nullptr);
+        HIPCHK(c, hipGetLastError());
         if (c->p.check_every > 0 && c->step % c->p.check_every == 0) {
-            HIPCHK(c, hipGetLastError());
             const int r = check_mass(c);
             if (r != LBM_OK) return r;
         }
     }
-    HIPCHK(c, hipGetLastError());
     return LBM_OK;
 }
 
@@ -520,7 +593,8 @@ int lbm_observables(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
     if (!c || !out) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
     Dev& d = c->d;
     hipStream_t s = c->stream;
-    launch_reduce_fluid(c->L, d.f[c->step & 1], d.red, s);
+    const int pw = (int)((c->step & 1) ^ 1);   // parity of the step that wrote the state
+    launch_reduce_fluid(c->L, d.f[c->step & 1], c->half(), d.rho[pw], d.cscale, pw, d.red, s);
     const int ncap = (int)c->caps.size();
     if (caps && ncap) launch_cap_moments(d, ncap, s);
     HIPCHK(c, hipGetLastError());
@@ -571,14 +645,23 @@ int lbm_get_fields(lbm_ctx* c, float* rhoA, float* rhoB, float* u) {
     const int last = (int)((c->step - 1) & 1);
     const int64_t N = c->L.n;
     if (u) {
-        launch_collide(c->L, d.f[last], nullptr, d.rho[last], d.rho[last ^ 1], d.fib, d.tile_flag, d.u, nullptr,
-                       c->n_nodes > 0, true, s);
+        launch_collide(c->L, d.f[last], nullptr, d.rho[last], d.rho[last ^ 1], d.fib, d.tile_flag, d.u,
+                       c->n_nodes > 0, true, c->half(), d.cscale, last ^ 1, last, s);
         HIPCHK(c, hipGetLastError());
         HIPCHK(c, hipMemcpyAsync(u, d.u, 3 * N * sizeof(float), hipMemcpyDeviceToHost, s));
     }
+    float cs[4] = {1.0f, 1.0f, 1.0f, 1.0f};
+    if (c->half()) HIPCHK(c, hipMemcpyAsync(cs, d.cscale, sizeof cs, hipMemcpyDeviceToHost, s));
     if (rhoA) HIPCHK(c, hipMemcpyAsync(rhoA, d.rho[last], N * sizeof(float), hipMemcpyDeviceToHost, s));
     if (rhoB) HIPCHK(c, hipMemcpyAsync(rhoB, d.rho[last] + N, N * sizeof(float), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
+    if (c->half()) {
+        // the collision used the compensated density
+        for (int64_t k = 0; k < N; ++k) {
+            if (rhoA) rhoA[k] *= cs[2 * last];
+            if (rhoB) rhoB[k] *= cs[2 * last + 1];
+        }
+    }
     return LBM_OK;
 }
 
@@ -640,7 +723,8 @@ int lbm_state_save(lbm_ctx* c, int32_t slot) {
     const int64_t N = c->L.n;
     const int cur = (int)(c->step & 1);
     hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_f, c->d.f[cur], (size_t)2 * Q * N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_f, c->d.f[cur], c->lay.fbytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_cs, c->d.cscale, 4 * sizeof(float), hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_rho, c->d.rho[0], 2 * N * 4, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(base + c->lay.slot_rho + 2 * N * 4, c->d.rho[1], 2 * N * 4, hipMemcpyDeviceToDevice, s));
     if (c->n_nodes) {
@@ -661,7 +745,8 @@ int lbm_state_load(lbm_ctx* c, int32_t slot) {
     c->step = c->slot_step[slot];
     const int cur = (int)(c->step & 1);
     hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(c->d.f[cur], base + c->lay.slot_f, (size_t)2 * Q * N * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d.f[cur], base + c->lay.slot_f, c->lay.fbytes, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->d.cscale, base + c->lay.slot_cs, 4 * sizeof(float), hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->d.rho[0], base + c->lay.slot_rho, 2 * N * 4, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(c->d.rho[1], base + c->lay.slot_rho + 2 * N * 4, 2 * N * 4, hipMemcpyDeviceToDevice, s));
     if (c->n_nodes) {

@@ -28,15 +28,33 @@ __host__ __device__ constexpr float wgt(int i) {
     return i == 0 ? 1.0f / 3.0f : (i <= 6 ? 1.0f / 18.0f : 1.0f / 36.0f);
 }
 
-constexpr int TILE = 8;        // immersed-boundary tile edge (lattice nodes)
-constexpr int BOX = TILE + 3;  // spreading box edge: stencil reach of a tile's nodes
-constexpr int BX = 64;         // fused collide block: x extent (one wavefront)
-constexpr int BY = 4;          // fused collide block: y extent
-constexpr int ZC = 8;          // fused collide block: z planes marched per block
+constexpr int TILE = 8;        // edge of the tiles flagged as touched by a stencil
+constexpr int BIN = 4;         // edge of the spreading bins (a node's home bin holds floor(X))
+constexpr int BOX = BIN + 3;   // spreading box edge: stencil reach of one bin's nodes
+#ifndef LBM_BX
+#define LBM_BX 128
+#endif
+#ifndef LBM_BY
+#define LBM_BY 2
+#endif
+#ifndef LBM_ZC
+#define LBM_ZC 8
+#endif
+#ifndef LBM_XCD_REMAP
+#define LBM_XCD_REMAP 0
+#endif
+#ifndef LBM_NT_STORE
+#define LBM_NT_STORE 1
+#endif
+constexpr int BX = LBM_BX;     // lattice blocks: x extent (a multiple of the wavefront)
+constexpr int BY = LBM_BY;     // lattice blocks: y extent
+constexpr int ZC = LBM_ZC;     // fused collide block: z planes marched per block
+constexpr int NXCD = 8;        // accelerator dies; workgroups are dealt round-robin to them
 
 struct Lattice {
     int nx, ny, nz;
-    int ntx, nty, ntz;     // tile counts
+    int ntx, nty, ntz;     // tile counts (TILE)
+    int nbx, nby, nbz;     // bin counts (BIN)
     int64_t n;             // nx*ny*nz
     int walls;
     float G;
@@ -62,16 +80,19 @@ struct FaceRef {        // rest metric of a triangle
 
 // Device-side pointers of one context (all inside the caller's workspace).
 struct Dev {
-    float* f[2];          // populations [2 comps][19][N] (FP32) or halfs (FP16)
+    void* f[2];           // populations [2 comps][19][N]: float (FP32) or g in _Float16 (FP16)
+    float* cscale;        // [2 parities][2 comps] FP64-derived mass compensation factors (FP16)
+    double* dpart;        // [density blocks][2] FP64 block sums of rho (FP16)
+    double* dmass;        // [2] FP64 component masses of the last density pass (FP16)
     float* rho[2];        // [2][N] density buffers, ping-pong by step parity
     float* fib;           // [5][N]: F_ib x, y, z, phi_A, phi_B
     float* u;             // [3][N] velocity where the immersed boundary needs it
     int* tile_flag;       // [tiles] 1 when touched by a stencil this step
-    int* tile_count;      // [tiles] nodes whose home tile it is
-    int* tile_offset;     // [tiles] start of the tile's bin in `sorted`
+    int* tile_count;      // [bins] nodes whose home bin it is
+    int* tile_offset;     // [bins] start of the bin in `sorted`
     int* touched[2];      // lists of touched tiles (step parity)
-    int* home[2];         // lists of home tiles (step parity)
-    int* home_start;      // [tiles] bin start per home-list entry
+    int* home[2];         // lists of occupied bins (step parity)
+    int* home_start;      // [bins] bin start per home-list entry
     int* counters;        // [8]: touched count[2], home count[2]
     // nodes
     float* off_hi;        // [nodes][3]
@@ -101,21 +122,26 @@ constexpr int RED_BLOCKS = 1024;
 constexpr int MOM_STRIDE = 16;
 
 // ---- launchers (k_fluid.hip) -------------------------------------------
-void launch_init_rest(const Lattice& L, float* f, const float* rhoA, const float* rhoB,
+void launch_init_rest(const Lattice& L, void* f, const float* rhoA, const float* rhoB, bool half,
                       hipStream_t s);
-void launch_density(const Lattice& L, const float* fin, const float* rho_prev, float* rho_out,
-                    hipStream_t s);
-void launch_collide(const Lattice& L, const float* fin, float* fout, const float* rho_n,
-                    const float* rho_prev, const float* fib, const int* tile_flag, float* u,
-                    float* rho_macro, bool has_ibm, bool macro, hipStream_t s);
-void launch_reduce_fluid(const Lattice& L, const float* fpost, double* partial, hipStream_t s);
+int64_t density_blocks(const Lattice& L, bool half);
+void launch_density(const Lattice& L, const void* fin, const float* rho_prev, float* rho_out, bool half,
+                    const float* cscale, int par_prev, double* partial, hipStream_t s);
+void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale,
+                       int par_cur, double* mass_out, hipStream_t s);
+void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,
+                    const float* fib, const int* tile_flag, float* u, bool has_ibm, bool macro, bool half,
+                    const float* cscale, int par_prev, int par_cur, hipStream_t s);
+void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const float* renc,
+                         const float* cscale, int par, double* partial, hipStream_t s);
 
 // ---- launchers (k_ibm.hip) ---------------------------------------------
-void launch_clear_tiles(const Lattice& L, Dev& d, int parity_prev, int parity_cur, hipStream_t s);
-void launch_cap_volume(const Dev& d, int n_caps, hipStream_t s);
+void launch_clear_tiles(const Lattice& L, Dev& d, int parity_prev, int parity_cur, int n_caps,
+                        hipStream_t s);
+void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s);
 void launch_faces(const Dev& d, int n_faces, hipStream_t s);
-void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, int n_nodes, int parity,
-                  hipStream_t s);
+void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
+                  int parity, hipStream_t s);
 void launch_bin_scan(const Dev& d, int parity, hipStream_t s);
 void launch_bin_scatter(const Dev& d, int n_nodes, hipStream_t s);
 void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);

@@ -132,7 +132,7 @@ def test_bins_and_stencil_base_bit_exact():
     npc, fpc, xyz, tri = wl.meshes()
     assert np.array_equal(X.numpy(), xyz)          # positions handed over exactly
     _, _, ob = oibm.stencil(torch.tensor(xyz), (wl.nx, wl.ny, wl.nz))
-    ot = oibm.tile_of(torch.tensor(xyz), (wl.nx, wl.ny, wl.nz))
+    ot = oibm.tile_of(torch.tensor(xyz), (wl.nx, wl.ny, wl.nz), tile=4)
     assert np.array_equal(base, ob.numpy())
     assert np.array_equal(t, ot.numpy())
 
@@ -143,13 +143,14 @@ def test_mass_momentum_fp64_observables_and_checkpoint():
     g = sim_from_workload(wl, n_slots=1)
     o0 = g.observables()
     m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
-    # FP32 rest populations w_i rho with the rest population closing the mass
-    assert np.allclose(o0["mass"], m0, rtol=1e-7)
+    # the FP32 rest populations w_i rho represent the FP64 initial mass to
+    # FP32 resolution; conservation is then measured from the stored state
+    assert np.allclose(o0["mass"], m0, rtol=1e-6)
     g.step(50)
     g.save(0)
     g.step(50)
     ob = g.observables()
-    assert np.allclose(ob["mass"], m0, rtol=2e-6), ob["mass"] - m0
+    assert np.allclose(ob["mass"], o0["mass"], rtol=1e-6), ob["mass"] - o0["mass"]
     assert np.abs(ob["momentum"]).max() < 1e-6 * m0.sum()
     X1 = g.nodes()
     ra1, rb1, u1 = g.fields()
@@ -178,6 +179,26 @@ def test_mass_momentum_fp64_observables_and_checkpoint():
         assert np.allclose(oc_k["com"], com.numpy(), atol=1e-9)
         assert np.allclose(oc_k["axes"], ax.numpy(), rtol=1e-7)
         ofs += n
+
+
+def test_graph_replay_matches_eager():
+    """Steps replayed from captured HIP graphs against eager launches, with
+    eager work and synchronisation between the replays; every replay is
+    compared (spreading uses float atomics, so agreement is to rounding)."""
+    wl = W.small(nx=40, ny=36, nz=44, ncap=2, theta=(65.0, 110.0))
+    ge = _sim(wl, use_graphs=0)
+    gg = _sim(wl, use_graphs=1)
+    for chunk in (2, 4, 3, 6, 2):
+        ge.step(chunk)
+        gg.step(chunk)
+        oe, og = ge.observables(), gg.observables()
+        assert oe["step"] == og["step"]
+        ra_e, rb_e, u_e = ge.fields()
+        ra_g, rb_g, u_g = gg.fields()
+        assert np.abs(ra_e - ra_g).max() < 1e-6 and np.abs(rb_e - rb_g).max() < 1e-6
+        assert np.abs(u_e - u_g).max() < 1e-7
+        assert np.abs(ge.nodes() - gg.nodes()).max() < 1e-6
+        assert np.allclose(oe["mass"], og["mass"], rtol=1e-7)
 
 
 def test_neutral_capsule_height_gpu():
@@ -213,3 +234,61 @@ def test_full_size_c2_first_steps_parity():
     assert np.allclose(ob["mass"], m0, rtol=1e-6)
     assert np.abs(ob["momentum"]).max() < 1e-6 * m0.sum()
     assert all(np.isfinite(c["height"]) for c in ob["caps"])
+
+
+# ---- FP16 population storage ------------------------------------------------
+
+def _droplet_workload(n=48, R=12.0, ncap=6, seed=5):
+    rng = np.random.default_rng(seed)
+    ctr = (n / 2, n / 2, n / 2)
+    rhoA, rhoB = W.droplet(n, R, ctr)
+    cs = W._seed_shell(rng, ncap, 4.0, R + 4.0, ctr, (n, n, n))
+    caps = [W.Capsule(W._snap(c), 4.0, 4, 0.01, 0.0, 2.0, float(rng.uniform(45.0, 135.0))) for c in cs]
+    return W.Workload("droplet%d" % n, n, n, n, rhoA, rhoB, caps, z_interface=n / 2)
+
+
+def test_fp16_storage_parity_droplet():
+    """FP16 g-storage with FP32 arithmetic against the FP64 oracle: relative
+    density error <= 1e-3 per component and capsule heights within 0.05 lu."""
+    from paper_1904_11386_amd.binding import LBM_FP16
+    wl = _droplet_workload()
+    steps = 300
+    _say("case", wl.name, "caps", len(wl.capsules), "steps", steps, "fp16")
+    g = _sim(wl, precision=LBM_FP16)
+    g.step(steps)
+    o = from_workload(wl).run(steps)
+    ra, rb, u = g.fields()
+    ea = _rel(ra, o.rho_last[0].numpy())
+    eb = _rel(rb, o.rho_last[1].numpy())
+    ob = g.observables()
+    dh = max(abs(c["height"] - float(o.capsule_obs(k)["height"])) for k, c in enumerate(ob["caps"]))
+    _say("  fp16 rho rel err %.3e %.3e  max height err %.3e lu" % (ea, eb, dh))
+    assert ea <= 1e-3 and eb <= 1e-3
+    assert dh <= 0.05
+    m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
+    # FP64 compensation holds each component's mass at its initial value
+    assert np.allclose(ob["mass"], m0, rtol=1e-6), ob["mass"] / m0 - 1
+
+
+def test_fp16_walls_and_checkpoint():
+    from paper_1904_11386_amd.binding import LBM_FP16, sim_from_workload
+    wl = W.make("c4_mini")
+    g = sim_from_workload(wl, precision=LBM_FP16, n_slots=1)
+    g.step(60)
+    g.save(0)
+    g.step(40)
+    ra1, rb1, u1 = g.fields()
+    X1 = g.nodes()
+    g.load(0)
+    g.step(40)
+    ra2, rb2, u2 = g.fields()
+    # spreading sums in float atomics: the replay differs by rounding, which
+    # FP16 storage rounds again
+    assert np.abs(ra1 - ra2).max() < 1e-4 and np.abs(g.nodes() - X1).max() < 1e-4
+    o = from_workload(wl).run(100)
+    fm = _fluid(wl)
+    ea = _rel(ra2[:, fm], o.rho_last[0].numpy()[:, fm])
+    du = float(np.abs(u2[:, :, fm] - o.u_last.numpy()[:, :, fm]).max())
+    _say("  fp16 channel rho rel err %.3e  |du| %.3e (wall speed 0.01)" % (ea, du))
+    assert ea <= 1e-3
+    assert du <= 1e-3 * 0.01 * 10
