@@ -112,7 +112,7 @@ class OracleSim:
         dr = cos_deg(self.caps[k]["theta"])
         rv = 2.0 * dr * (self.rho_maj - self.rho_min) * self.wet_scale
         if isinstance(rv, torch.Tensor):
-            pref = 0 if float(rv) >= 0.0 else 1
+            pref = 0 if float(rv.detach()) >= 0.0 else 1
         else:
             pref = 0 if rv >= 0.0 else 1
         return rv, pref
@@ -212,3 +212,70 @@ def from_workload(wl, differentiable=False, **over):
               wet_scale=wl.wet_scale, differentiable=differentiable)
     kw.update(over)
     return OracleSim(wl.rhoA.astype("float64"), wl.rhoB.astype("float64"), caps, **kw)
+
+
+# ---- gradients of capsule objectives (reference for the adjoint) ----------
+
+def objective(sim, kind, cap=0):
+    """J at the current state: 'com_z' = node-mean z of capsule `cap` minus
+    the interface plane (Sec. III.D, eq. interface:contactangle), or
+    'taylor_D' (Sec. III.A, eq. results:taylorparameter)."""
+    X = sim.X[cap]
+    if kind == "com_z":
+        return X[:, 2].mean() - sim.z_interface
+    if kind == "taylor_D":
+        return membrane.taylor_D(X, sim.caps[cap]["mesh"].tri)
+    raise KeyError(kind)
+
+
+def gradient(make_sim, steps, every, kind, cap=0):
+    """J and dJ/d(theta [rad], kS, G) by reverse-mode autograd with
+    checkpoint and recompute: the forward keeps the state every `every`
+    steps; the backward replays each segment from its checkpoint with the
+    graph recorded and pulls the adjoint through it.  theta, kS act on every
+    capsule (the derivative is the sum over capsules).
+
+    make_sim(theta_deg, kS, G) must return a fresh OracleSim with
+    differentiable=True whose capsules use those (possibly tensor) values."""
+    th0, ks0, g0 = make_sim.params
+    sim = make_sim(th0, ks0, g0)
+    ckpts = []
+    with torch.no_grad():
+        for k in range(steps):
+            if k % every == 0:
+                ckpts.append((k, sim.fpost.clone(), [x.clone() for x in sim.X]))
+            sim.step()
+        J = float(objective(sim, kind, cap))
+    # seed at the final state
+    Xf = [x.detach().clone().requires_grad_(True) for x in sim.X]
+    with torch.enable_grad():
+        sim.X = Xf
+        Jt = objective(sim, kind, cap)
+        lam_X = list(torch.autograd.grad(Jt, Xf, allow_unused=True))
+    lam_X = [torch.zeros_like(x) if l is None else l for l, x in zip(lam_X, Xf)]
+    lam_f = torch.zeros_like(sim.fpost)
+    g = torch.zeros(3, dtype=DT)
+    for (k0, f0, X0) in reversed(ckpts):
+        n = min(every, steps - k0)
+        th = torch.tensor(float(th0), dtype=DT, requires_grad=True)
+        ks = torch.tensor(float(ks0), dtype=DT, requires_grad=True)
+        G = torch.tensor(float(g0), dtype=DT, requires_grad=True)
+        with torch.enable_grad():
+            seg = make_sim(th, ks, G)
+            fs = f0.clone().requires_grad_(True)
+            Xs = [x.clone().requires_grad_(True) for x in X0]
+            seg.fpost = fs
+            seg.X = list(Xs)
+            for _ in range(n):
+                seg.step()
+            outs = [seg.fpost] + list(seg.X)
+            grads = torch.autograd.grad(outs, [fs] + Xs + [th, ks, G], grad_outputs=[lam_f] + lam_X,
+                                        allow_unused=True)
+        lam_f = grads[0]
+        lam_X = [gx if gx is not None else torch.zeros_like(x) for gx, x in zip(grads[1:1 + len(Xs)], Xs)]
+        for i, gp in enumerate(grads[1 + len(Xs):]):
+            if gp is not None:
+                g[i] += gp.detach()
+    # theta was in degrees inside the simulation: report d/d(radian)
+    g[0] = g[0] * (180.0 / math.pi)
+    return J, g
