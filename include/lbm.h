@@ -85,6 +85,9 @@ typedef struct lbm_params {
     double wet_scale;       /* >= 0; virtual density rho_v = 2 cos(theta)
                                (rho_maj - rho_min) wet_scale; 1 = the colour law
                                of Sec. II.D as written                           */
+    int32_t ring_len;       /* > 0: room for the adjoint (FP32 only), with a
+                               recompute ring of ring_len states                 */
+    int32_t reserved2;
 } lbm_params;
 
 typedef struct lbm_obs {
@@ -198,6 +201,30 @@ int lbm_debug_bins(lbm_ctx* ctx, int32_t* tile_of_node, int32_t* base_idx);
  * Asynchronous on the stream. */
 int lbm_state_save(lbm_ctx* ctx, int32_t slot);
 int lbm_state_load(lbm_ctx* ctx, int32_t slot);
+
+/* Discrete adjoint of the coupled step (FP32 storage, ring_len > 0, at least
+ * one capsule).  J is a capsule objective at the end of a run: LBM_OBJ_COM_Z
+ * the node-mean height above z_interface (Sec. III.D, eq.
+ * interface:contactangle) or LBM_OBJ_TAYLOR_D (Sec. III.A, eq.
+ * results:taylorparameter), of capsule `capsule`.
+ *
+ * lbm_adjoint_forward advances nsteps from the current state, keeping a
+ * checkpoint in slot s at every multiple s * every of the run (needs
+ * every <= ring_len and n_slots >= ceil(nsteps / every)), and returns J in
+ * *J (FP64, synchronises).
+ *
+ * lbm_adjoint_backward then seeds lambda_X = dJ/dX at the final positions
+ * and sweeps the segments in reverse: each segment is recomputed from its
+ * checkpoint into the ring, and each step's adjoint is applied in reverse
+ * order.  grads[3] receives dJ/dtheta (per radian, every capsule's angle
+ * shifted together), dJ/dkS (every capsule's shear modulus shifted
+ * together) and dJ/dG.  At theta = 90 degrees the one-sided derivative of
+ * the preferred-component choice made at set-up is returned.  Immersed-
+ * boundary stencils must stay two nodes away from solid rows.  The state
+ * afterwards is the one at the start of the run.  Synchronises. */
+int lbm_adjoint_forward(lbm_ctx* ctx, int32_t nsteps, int32_t every, int32_t objective, int32_t capsule,
+                        double* J);
+int lbm_adjoint_backward(lbm_ctx* ctx, double* grads);
 
 /* Free the host context (not the workspace).  NULL is ignored. */
 void lbm_destroy(lbm_ctx* ctx);

@@ -28,7 +28,8 @@ class Params(C.Structure):
                 ("tau", C.c_double * 2), ("G", C.c_double),
                 ("rho_maj", C.c_double), ("rho_min", C.c_double),
                 ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
-                ("z_interface", C.c_double), ("mass_tol", C.c_double), ("wet_scale", C.c_double)]
+                ("z_interface", C.c_double), ("mass_tol", C.c_double), ("wet_scale", C.c_double),
+                ("ring_len", C.c_int32), ("reserved2", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -44,7 +45,9 @@ _lib = None
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_step", "lbm_step_timed", "lbm_observables",
            "lbm_get_fields", "lbm_get_nodes", "lbm_get_node_forces", "lbm_get_spread",
-           "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_destroy", "lbm_last_error"]
+           "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_adjoint_forward", "lbm_adjoint_backward",
+           "lbm_destroy", "lbm_last_error"]
+LBM_OBJ_COM_Z, LBM_OBJ_TAYLOR_D = 0, 1
 
 
 def load(path: str = None):
@@ -74,6 +77,8 @@ def load(path: str = None):
         "lbm_debug_bins": ([vp, P(i32), P(i32)], C.c_int),
         "lbm_state_save": ([vp, i32], C.c_int),
         "lbm_state_load": ([vp, i32], C.c_int),
+        "lbm_adjoint_forward": ([vp, i32, i32, i32, i32, P(d)], C.c_int),
+        "lbm_adjoint_backward": ([vp, P(d)], C.c_int),
         "lbm_destroy": ([vp], None),
         "lbm_last_error": ([vp], C.c_char_p),
     }
@@ -98,7 +103,7 @@ def _ptr(a, ctype):
 
 def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
-                check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1):
+                check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -115,6 +120,7 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.mass_tol = mass_tol
     p.wet_scale = wet_scale
     p.use_graphs = use_graphs
+    p.ring_len = ring_len
     return p
 
 
@@ -232,6 +238,19 @@ class Sim:
         self._check(self.lib.lbm_debug_bins(self.ctx, _ptr(t, C.c_int32), _ptr(b, C.c_int32)))
         return t, b
 
+    def adjoint_forward(self, nsteps, every, objective=LBM_OBJ_COM_Z, capsule=0):
+        """Run nsteps keeping checkpoints every `every` steps; returns J."""
+        J = C.c_double()
+        self._check(self.lib.lbm_adjoint_forward(self.ctx, int(nsteps), int(every), int(objective), int(capsule),
+                                                 C.byref(J)))
+        return J.value
+
+    def adjoint_backward(self):
+        """dJ/d(theta [rad], kS, G) of the last adjoint_forward."""
+        g = (C.c_double * 3)()
+        self._check(self.lib.lbm_adjoint_backward(self.ctx, g))
+        return np.array(g[:])
+
     def save(self, slot):
         self._check(self.lib.lbm_state_save(self.ctx, slot))
 
@@ -254,13 +273,13 @@ class Sim:
             pass
 
 
-def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1):
+def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1, ring_len=0):
     """Build a Sim for a seeded workload (paper_1904_11386_amd.workloads)."""
     npc, fpc, xyz, tri = wl.meshes()
     p = make_params(wl.nx, wl.ny, wl.nz, tau=wl.tau, G=wl.G, walls=wl.walls, wall_u_lo=wl.wall_u_lo,
                     wall_u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
-                    check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs)
+                    check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len)
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()

@@ -562,6 +562,365 @@ __global__ __launch_bounds__(256) void k_reduce_fluid(const PopT<HALF>* __restri
         for (int j = 0; j < 5; ++j) partial[blockIdx.x * 8 + j] = sh[j][0];
 }
 
+
+// ---------------------------------------------------------------------------
+// Discrete adjoint of the lattice part of one step (FP32 storage).  Given
+// lambda* (adjoint of this step's output f*^n) and lambda_u (adjoint of u^n
+// where the immersed boundary reads it), the three kernels below produce
+// lambda* of the step's input f*^{n-1}:
+//   k_adj_collide  per node: adjoint of u = (sum j + F/2)/rho, of the BGK
+//                  collision with the shifted equilibrium, of the common
+//                  velocity, and of F^c = -G rho^c S^c' + (rho^c/rho) F_ib;
+//                  leaves lambda_rho (local part), lambda_j, lambda_S and
+//                  lambda_Fib, and the G derivative of the Shan-Chen force;
+//   k_adj_gather   transpose of S^c(x) = sum_i w_i psi^c(x + c_i) c_i:
+//                  lambda_rho^c(y) += sum_i w_i c_i . lambda_S^c(y - c_i);
+//   k_adj_push     transpose of the pull (with the wall bounce-back and its
+//                  density term): lambda*_old_k(y) = lambda_f_k(y + c_k),
+//                  lambda_f_i = (1 - omega) lambda*_i + lambda_rho + lambda_j . c_i.
+
+__device__ __forceinline__ double block_sum_d(double v, double* sh, int tid, int nt) {
+    sh[tid] = v;
+    __syncthreads();
+    for (int s = nt / 2; s > 0; s >>= 1) {
+        if (tid < s) sh[tid] += sh[tid + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <bool WALLS, bool IBM>
+__global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin, const float* __restrict__ rho_n,
+                                                     const float* __restrict__ rho_p, const float* __restrict__ fib,
+                                                     const int* __restrict__ tile_flag, const pf2* __restrict__ lam_in,
+                                                     const float* __restrict__ lam_u, float* __restrict__ lam_rho,
+                                                     float* __restrict__ lam_j, float* __restrict__ lam_S,
+                                                     float* __restrict__ lam_Fib, double* __restrict__ grads,
+                                                     Lattice L) {
+    __shared__ Ring<2> sp;
+    __shared__ double red[BX * BY];
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    int bx, by, bz;
+    block_xyz(bx, by, bz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
+    const int z1 = min(z0 + ZC, L.nz);
+    const int64_t N = L.n;
+    bool near_ibm = false;
+    if (IBM) {
+        const int tx0 = wrapi(x0 - 1, L.nx) >> 3, ntx_b = (BX + 2 + 7) / 8 + 1;
+        const int ty0 = wrapi(y0 - 1, L.ny) >> 3, nty_b = (BY + 2 + 7) / 8 + 1;
+        const int tz0 = wrapi(z0 - 1, L.nz) >> 3, ntz_b = (ZC + 2 + 7) / 8 + 1;
+        bool hit = false;
+        for (int k = tid; k < ntx_b * nty_b * ntz_b; k += BX * BY) {
+            const int i = k % ntx_b, j = (k / ntx_b) % nty_b, l = k / (ntx_b * nty_b);
+            const int t = (((tz0 + l) % L.ntz) * L.nty + (ty0 + j) % L.nty) * L.ntx + (tx0 + i) % L.ntx;
+            hit = hit || tile_flag[t] != 0;
+        }
+        near_ibm = __syncthreads_or(hit) != 0;
+    }
+    auto stage = [&](int zz) {
+        if (IBM && near_ibm)
+            stage_plane<WALLS, true, 2>(sp, zz, z0, x0, y0, tid, rho_n, nullptr, fib, tile_flag, L);
+        else
+            stage_plane<WALLS, false, 2>(sp, zz, z0, x0, y0, tid, rho_n, nullptr, nullptr, nullptr, L);
+    };
+    stage(z0 - 1);
+    stage(z0);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
+    double gG = 0.0;
+    for (int z = z0; z < z1; ++z) {
+        stage(z + 1);
+        __syncthreads();
+        if (active) {
+            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const int s0 = (z - z0 + 1) % 3;
+            Pulled A, B;
+            auto none = [](int, int, int, float&, float&) {};
+            pull<WALLS, false>(fin, L, node, x, y, z, WALLS ? rho_p[node] : 0.0f, WALLS ? rho_p[N + node] : 0.0f,
+                               none, A, B);
+            const float ra = sum_pop(A), rb = sum_pop(B);
+            float ja[3], jb[3];
+            momentum(A, ja[0], ja[1], ja[2]);
+            momentum(B, jb[0], jb[1], jb[2]);
+            float sa[3] = {0.f, 0.f, 0.f}, sb[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 1; k < Q; k += 2) {
+                const int sP = (s0 + cz(k) + 3) % 3, sM = (s0 - cz(k) + 3) % 3;
+                const int ly = ty + 1, lx = tx + 1;
+                const float da = sp.v[sP][0][ly + cy(k)][lx + cx(k)] - sp.v[sM][0][ly - cy(k)][lx - cx(k)];
+                const float db = sp.v[sP][1][ly + cy(k)][lx + cx(k)] - sp.v[sM][1][ly - cy(k)][lx - cx(k)];
+                const float w = wgt(k);
+                if (cx(k) != 0) { sa[0] += w * cx(k) * da; sb[0] += w * cx(k) * db; }
+                if (cy(k) != 0) { sa[1] += w * cy(k) * da; sb[1] += w * cy(k) * db; }
+                if (cz(k) != 0) { sa[2] += w * cz(k) * da; sb[2] += w * cz(k) * db; }
+            }
+            const float rs = ra + rb, ir = 1.0f / rs;
+            float Fib[3] = {0.f, 0.f, 0.f};
+            bool flagged = false;
+            if (IBM && near_ibm) {
+                const int t = ((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3);
+                flagged = tile_flag[t] != 0;
+                if (flagged)
+                    for (int d = 0; d < 3; ++d) Fib[d] = fib[d * N + node];
+            }
+            const float ma = ra * ir, mb = rb * ir;
+            float Fa[3], Fb[3];
+            for (int d = 0; d < 3; ++d) {
+                Fa[d] = -L.G * ra * sb[d] + ma * Fib[d];
+                Fb[d] = -L.G * rb * sa[d] + mb * Fib[d];
+            }
+            const float wa = L.omega[0], wb = L.omega[1];
+            const float Dn = ra * wa + rb * wb, iD = 1.0f / Dn;
+            float up[3], u[3], ue[2][3];
+            for (int d = 0; d < 3; ++d) {
+                up[d] = (ja[d] * wa + jb[d] * wb) * iD;
+                u[d] = (ja[d] + jb[d] + 0.5f * (Fa[d] + Fb[d])) * ir;
+                ue[0][d] = up[d] + L.tau[0] * Fa[d] / ra;
+                ue[1][d] = up[d] + L.tau[1] * Fb[d] / rb;
+            }
+            // adjoint of u = (sum j + F/2) / rho
+            float lu[3] = {0.f, 0.f, 0.f};
+            if (flagged)
+                for (int d = 0; d < 3; ++d) lu[d] = lam_u[d * N + node];
+            float lj[2][3], lF[2][3], lr[2];
+            const float luu = (lu[0] * u[0] + lu[1] * u[1] + lu[2] * u[2]) * ir;
+            for (int c = 0; c < 2; ++c) {
+                lr[c] = -luu;
+                for (int d = 0; d < 3; ++d) {
+                    lj[c][d] = lu[d] * ir;
+                    lF[c][d] = 0.5f * lu[d] * ir;
+                }
+            }
+            // adjoint of the collision f* = f + omega (feq(rho, u_eq) - f)
+            float lup[3] = {0.f, 0.f, 0.f};
+            const float r2[2] = {ra, rb};
+            for (int c = 0; c < 2; ++c) {
+                const float om = L.omega[c], r = r2[c];
+                const float usq = ue[c][0] * ue[c][0] + ue[c][1] * ue[c][1] + ue[c][2] * ue[c][2];
+                float lrf = 0.f, lue[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                for (int i = 0; i < Q; ++i) {
+                    const pf2 lv = lam_in[(int64_t)i * N + node];
+                    const float mu = om * (c == 0 ? lv.x : lv.y);
+                    const float eu = cx(i) * ue[c][0] + cy(i) * ue[c][1] + cz(i) * ue[c][2];
+                    lrf += mu * wgt(i) * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * usq);
+                    const float co = mu * wgt(i) * r;
+                    const float ce = co * (3.0f + 9.0f * eu);
+                    if (cx(i)) lue[0] += ce * cx(i);
+                    if (cy(i)) lue[1] += ce * cy(i);
+                    if (cz(i)) lue[2] += ce * cz(i);
+                    lue[0] -= 3.0f * co * ue[c][0];
+                    lue[1] -= 3.0f * co * ue[c][1];
+                    lue[2] -= 3.0f * co * ue[c][2];
+                }
+                lr[c] += lrf;
+                const float* F = c == 0 ? Fa : Fb;
+                float lueF = 0.f;
+                for (int d = 0; d < 3; ++d) {
+                    lup[d] += lue[d];
+                    lF[c][d] += L.tau[c] * lue[d] / r;
+                    lueF += lue[d] * F[d];
+                }
+                lr[c] -= L.tau[c] * lueF / (r * r);
+            }
+            // adjoint of the common velocity u' = sum_c omega_c j^c / sum_c omega_c rho^c
+            const float lupu = (lup[0] * up[0] + lup[1] * up[1] + lup[2] * up[2]) * iD;
+            for (int c = 0; c < 2; ++c) {
+                const float om = L.omega[c];
+                for (int d = 0; d < 3; ++d) lj[c][d] += om * lup[d] * iD;
+                lr[c] -= om * lupu;
+            }
+            // adjoint of F^c = -G rho^c S^c' + m^c F_ib
+            float lSa[3], lSb[3];
+            for (int d = 0; d < 3; ++d) {
+                lSb[d] = -L.G * ra * lF[0][d];     // S of B enters the force on A
+                lSa[d] = -L.G * rb * lF[1][d];
+            }
+            lr[0] += -L.G * (lF[0][0] * sb[0] + lF[0][1] * sb[1] + lF[0][2] * sb[2]);
+            lr[1] += -L.G * (lF[1][0] * sa[0] + lF[1][1] * sa[1] + lF[1][2] * sa[2]);
+            gG += -(double)ra * (lF[0][0] * sb[0] + lF[0][1] * sb[1] + lF[0][2] * sb[2])
+                  - (double)rb * (lF[1][0] * sa[0] + lF[1][1] * sa[1] + lF[1][2] * sa[2]);
+            if (flagged) {
+                float lma = 0.f, lmb = 0.f;
+                for (int d = 0; d < 3; ++d) {
+                    lam_Fib[d * N + node] = ma * lF[0][d] + mb * lF[1][d];
+                    lma += lF[0][d] * Fib[d];
+                    lmb += lF[1][d] * Fib[d];
+                }
+                const float ir2 = ir * ir;
+                lr[0] += (lma - lmb) * rb * ir2;
+                lr[1] += (lmb - lma) * ra * ir2;
+            }
+            lam_rho[node] = lr[0];
+            lam_rho[N + node] = lr[1];
+            for (int d = 0; d < 3; ++d) {
+                lam_j[d * N + node] = lj[0][d];
+                lam_j[(3 + d) * N + node] = lj[1][d];
+                lam_S[d * N + node] = lSa[d];
+                lam_S[(3 + d) * N + node] = lSb[d];
+            }
+        }
+        __syncthreads();
+    }
+    const double tot = block_sum_d(gG, red, tid, BX * BY);
+    if (tid == 0 && tot != 0.0) unsafeAtomicAdd(&grads[2], tot);
+}
+
+// lambda_rho^c(y) += sum_i w_i c_i . lambda_S^c(y - c_i); with walls, the
+// first and last fluid rows also collect what their solid-row copies
+// received.
+template <bool WALLS>
+__global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ lam_S, float* __restrict__ lam_rho,
+                                                    Lattice L) {
+    __shared__ Ring<6> sr;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    int bx, by, bz;
+    block_xyz(bx, by, bz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
+    const int z1 = min(z0 + ZC, L.nz);
+    const int64_t N = L.n;
+    stage_plane<false, false, 6>(sr, z0 - 1, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
+    stage_plane<false, false, 6>(sr, z0, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
+    for (int z = z0; z < z1; ++z) {
+        stage_plane<false, false, 6>(sr, z + 1, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
+        __syncthreads();
+        if (active) {
+            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const int s0 = (z - z0 + 1) % 3;
+            const int ly = ty + 1, lx = tx + 1;
+            float acc[2] = {0.f, 0.f};
+#pragma unroll
+            for (int k = 1; k < Q; k += 2) {
+                const int sM = (s0 - cz(k) + 3) % 3, sP = (s0 + cz(k) + 3) % 3;
+                for (int c = 0; c < 2; ++c) {
+                    float v = 0.f;
+                    for (int d = 0; d < 3; ++d) {
+                        const int e = d == 0 ? cx(k) : (d == 1 ? cy(k) : cz(k));
+                        if (e == 0) continue;
+                        v += e * (sr.v[sM][3 * c + d][ly - cy(k)][lx - cx(k)] - sr.v[sP][3 * c + d][ly + cy(k)][lx + cx(k)]);
+                    }
+                    acc[c] += wgt(k) * v;
+                }
+            }
+            if (WALLS && (y == 1 || y == L.ny - 2)) {
+                // sources x = s - c_i of the solid neighbour s, for the directions
+                // that pointed from the fluid row into the solid row
+                const int sgn = y == 1 ? -1 : 1;
+#pragma unroll
+                for (int i = 1; i < Q; ++i) {
+                    if (cy(i) != sgn) continue;
+                    const int sl = (s0 - cz(i) + 3) % 3;
+                    for (int c = 0; c < 2; ++c) {
+                        float v = 0.f;
+                        for (int d = 0; d < 3; ++d) {
+                            const int e = d == 0 ? cx(i) : (d == 1 ? cy(i) : cz(i));
+                            if (e) v += e * sr.v[sl][3 * c + d][ly][lx - cx(i)];
+                        }
+                        acc[c] += wgt(i) * v;
+                    }
+                }
+            }
+            lam_rho[node] += acc[0];
+            lam_rho[N + node] += acc[1];
+        }
+        __syncthreads();
+    }
+}
+
+// Stage lambda_rho (2) and lambda_j (6) as one 8-field ring.
+__device__ __forceinline__ void stage_lrj(Ring<8>& R, int zz, int z0, int x0, int y0, int tid,
+                                          const float* __restrict__ lam_rho, const float* __restrict__ lam_j,
+                                          const Lattice& L) {
+    constexpr int SW = Ring<8>::SW, SH = Ring<8>::SH;
+    const int slot = (zz - z0 + 1) % 3;
+    const int zw = wrapi(zz, L.nz);
+    for (int k = tid; k < 8 * SH * SW; k += BX * BY) {
+        const int c = k / (SH * SW);
+        const int r = k - c * SH * SW;
+        const int ly = r / SW, lx = r - ly * SW;
+        const int64_t idx = ((int64_t)zw * L.ny + wrapi(y0 - 1 + ly, L.ny)) * L.nx + wrapi(x0 - 1 + lx, L.nx);
+        R.v[slot][c][ly][lx] = c < 2 ? lam_rho[c * L.n + idx] : lam_j[(c - 2) * L.n + idx];
+    }
+}
+
+template <bool WALLS>
+__global__ __launch_bounds__(256) void k_adj_push(const pf2* __restrict__ lam_in, const float* __restrict__ lam_rho,
+                                                  const float* __restrict__ lam_j, pf2* __restrict__ lam_out,
+                                                  Lattice L) {
+    __shared__ Ring<8> rj;
+    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    int bx, by, bz;
+    block_xyz(bx, by, bz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
+    const int z1 = min(z0 + ZC, L.nz);
+    const int64_t N = L.n;
+    stage_lrj(rj, z0 - 1, z0, x0, y0, tid, lam_rho, lam_j, L);
+    stage_lrj(rj, z0, z0, x0, y0, tid, lam_rho, lam_j, L);
+    const int x = x0 + tx, y = y0 + ty;
+    const bool inside = x < L.nx && y < L.ny;
+    const bool active = inside && (!WALLS || (y > 0 && y < L.ny - 1));
+    for (int z = z0; z < z1; ++z) {
+        stage_lrj(rj, z + 1, z0, x0, y0, tid, lam_rho, lam_j, L);
+        __syncthreads();
+        if (active) {
+            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const int s0 = (z - z0 + 1) % 3;
+            const int ly = ty + 1, lx = tx + 1;
+            const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+            const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
+            const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
+            // own lambda_f_i for the bounced directions and the wall density term
+            auto own_lf = [&](int i, int c) {
+                const pf2 lv = lam_in[(int64_t)i * N + node];
+                const float ls = c == 0 ? lv.x : lv.y;
+                const float lj = cx(i) * rj.v[s0][2 + 3 * c][ly][lx] + cy(i) * rj.v[s0][3 + 3 * c][ly][lx] +
+                                 cz(i) * rj.v[s0][4 + 3 * c][ly][lx];
+                return (1.0f - L.omega[c]) * ls + rj.v[s0][c][ly][lx] + lj;
+            };
+            float wall_extra[2] = {0.f, 0.f};
+            if (WALLS && (y == 1 || y == L.ny - 2)) {
+                const int sgn = y == 1 ? 1 : -1;      // directions pulled from the solid row
+                for (int i = 1; i < Q; ++i) {
+                    if (cy(i) != sgn) continue;
+                    const float* uw = sgn == 1 ? L.uw_lo : L.uw_hi;
+                    const float cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+                    for (int c = 0; c < 2; ++c) wall_extra[c] += own_lf(i, c) * 2.0f * wgt(i) * cu * 3.0f;
+                }
+            }
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                float out[2];
+                const bool into_wall = WALLS && ((cy(k) == -1 && y == 1) || (cy(k) == 1 && y == L.ny - 2));
+                if (into_wall) {
+                    out[0] = own_lf(opp(k), 0);
+                    out[1] = own_lf(opp(k), 1);
+                } else {
+                    const int sx = cx(k) == 1 ? xp : (cx(k) == -1 ? xm : x);
+                    const int sy = cy(k) == 1 ? yp : (cy(k) == -1 ? ym : y);
+                    const int sz = cz(k) == 1 ? zp : (cz(k) == -1 ? zm : z);
+                    const pf2 lv = lam_in[(int64_t)k * N + ((int64_t)sz * L.ny + sy) * L.nx + sx];
+                    const int sl = (s0 + cz(k) + 3) % 3, qy = ly + cy(k), qx = lx + cx(k);
+                    for (int c = 0; c < 2; ++c) {
+                        const float lj = cx(k) * rj.v[sl][2 + 3 * c][qy][qx] + cy(k) * rj.v[sl][3 + 3 * c][qy][qx] +
+                                         cz(k) * rj.v[sl][4 + 3 * c][qy][qx];
+                        out[c] = (1.0f - L.omega[c]) * (c == 0 ? lv.x : lv.y) + rj.v[sl][c][qy][qx] + lj;
+                    }
+                }
+                lam_out[(int64_t)k * N + node] = pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]);
+            }
+        } else if (inside) {
+            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            for (int k = 0; k < Q; ++k) lam_out[(int64_t)k * N + node] = pack<false>(0.f, 0.f);
+        }
+        __syncthreads();
+    }
+}
+
 }  // namespace
 
 void launch_init_rest(const Lattice& L, void* f, const float* rhoA, const float* rhoB, bool half,
@@ -640,6 +999,35 @@ void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const f
     else
         hipLaunchKernelGGL(k_reduce_fluid<false>, dim3(RED_BLOCKS), dim3(256), 0, s, (const pf2*)fpost, renc,
                            cscale, par, partial, L);
+}
+
+void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
+                        const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
+                        float* lam_S, float* lam_Fib, double* grads, hipStream_t s) {
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC), block(BX, BY);
+    if (L.walls)
+        hipLaunchKernelGGL((k_adj_collide<true, true>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
+                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, grads, L);
+    else
+        hipLaunchKernelGGL((k_adj_collide<false, true>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
+                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, grads, L);
+}
+
+void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hipStream_t s) {
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC), block(BX, BY);
+    if (L.walls)
+        hipLaunchKernelGGL(k_adj_gather<true>, grid, block, 0, s, lam_S, lam_rho, L);
+    else
+        hipLaunchKernelGGL(k_adj_gather<false>, grid, block, 0, s, lam_S, lam_rho, L);
+}
+
+void launch_adj_push(const Lattice& L, const void* lam_in, const float* lam_rho, const float* lam_j, void* lam_out,
+                     hipStream_t s) {
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC), block(BX, BY);
+    if (L.walls)
+        hipLaunchKernelGGL(k_adj_push<true>, grid, block, 0, s, (const pf2*)lam_in, lam_rho, lam_j, (pf2*)lam_out, L);
+    else
+        hipLaunchKernelGGL(k_adj_push<false>, grid, block, 0, s, (const pf2*)lam_in, lam_rho, lam_j, (pf2*)lam_out, L);
 }
 
 }  // namespace lbmx

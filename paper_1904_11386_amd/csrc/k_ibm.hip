@@ -45,6 +45,14 @@ __device__ __forceinline__ float peskin(float r) {
     return 0.0f;
 }
 
+// its derivative
+__device__ __forceinline__ float peskin_d(float r) {
+    const float a = fabsf(r), sg = r < 0.0f ? -1.0f : 1.0f;
+    if (a <= 1.0f) return sg * (-2.0f + (4.0f - 8.0f * a) / (2.0f * sqrtf(1.0f + 4.0f * a - 4.0f * a * a))) * 0.125f;
+    if (a <= 2.0f) return sg * (-2.0f - (12.0f - 8.0f * a) / (2.0f * sqrtf(-7.0f + 12.0f * a - 4.0f * a * a))) * 0.125f;
+    return 0.0f;
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -102,7 +110,24 @@ __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, i
             d.counters[CNT_TOUCHED + pc] = 0;
             d.counters[CNT_HOME + pc] = 0;
         }
-        for (int k = threadIdx.x; k < n_caps; k += blockDim.x) d.capV[k] = 0.0;
+        for (int k = threadIdx.x; k < n_caps; k += blockDim.x) {
+            d.capV[k] = 0.0;
+            if (d.capdV) d.capdV[k] = 0.0;
+        }
+    }
+    if (d.lam_u) {
+        // adjoint velocity field lives in the same tiles
+        for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (int64_t)nt * 512;
+             k += (int64_t)gridDim.x * blockDim.x) {
+            const int e = (int)(k >> 9), c = (int)(k & 511);
+            const int t = d.touched[pp][e];
+            const int tx = t % L.ntx, ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
+            const int x = tx * TILE + (c & 7), y = ty * TILE + ((c >> 3) & 7), z = tz * TILE + (c >> 6);
+            if (x < L.nx && y < L.ny && z < L.nz) {
+                const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+                for (int f = 0; f < 3; ++f) d.lam_u[f * N + node] = 0.0f;
+            }
+        }
     }
 }
 
@@ -147,15 +172,70 @@ __global__ __launch_bounds__(256) void k_cap_volume(Dev d, int n_faces) {
     if (threadIdx.x == 0) unsafeAtomicAdd(&d.capV[cap_first], sh[0]);
 }
 
-__device__ __forceinline__ void cross3(const float* a, const float* b, float* o) {
+// Scalars that carry a tangent: v + e * epsilon.  The face forces below are
+// written once, as a template; with Dual they give the directional
+// derivative of the forces, which for forces derived from an energy is the
+// Hessian-vector product the adjoint needs.
+struct Dual {
+    float v, e;
+};
+__device__ __forceinline__ Dual operator+(Dual a, Dual b) { return {a.v + b.v, a.e + b.e}; }
+__device__ __forceinline__ Dual operator-(Dual a, Dual b) { return {a.v - b.v, a.e - b.e}; }
+__device__ __forceinline__ Dual operator-(Dual a) { return {-a.v, -a.e}; }
+__device__ __forceinline__ Dual operator*(Dual a, Dual b) { return {a.v * b.v, a.v * b.e + a.e * b.v}; }
+__device__ __forceinline__ Dual operator*(float a, Dual b) { return {a * b.v, a * b.e}; }
+__device__ __forceinline__ Dual operator*(Dual a, float b) { return {a.v * b, a.e * b}; }
+__device__ __forceinline__ Dual operator+(Dual a, float b) { return {a.v + b, a.e}; }
+__device__ __forceinline__ Dual operator-(Dual a, float b) { return {a.v - b, a.e}; }
+
+template <typename T>
+__device__ __forceinline__ void cross3(const T* a, const T* b, T* o) {
     o[0] = a[1] * b[2] - a[2] * b[1];
     o[1] = a[2] * b[0] - a[0] * b[2];
     o[2] = a[0] * b[1] - a[1] * b[0];
 }
 
 // Skalak energy per triangle, E_T = A0 (kS/4)(I1^2 + 2 I1 - 2 I2 + C I2^2),
-// I1 = tr(M0^-1 M) - 2, I2 = det M / det M0 - 1, with its analytic
-// gradient; and the volume penalty gradient kV (V - V0)/V0 dV/dX.
+// I1 = tr(M0^-1 M) - 2, I2 = det M / det M0 - 1, with its analytic gradient
+// (Fsk = -dE_T/dX per corner); plus the volume-penalty corner forces
+// vfac * dV_T/dX with vfac = -kV (V - V0) / (6 V0).
+template <typename T>
+__device__ __forceinline__ void face_forces(const T X[3][3], const FaceRef& R, float kS, float C, T vfac,
+                                            T Fsk[3][3], T F[3][3]) {
+    T e1[3], e2[3];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        e1[j] = X[1][j] - X[0][j];
+        e2[j] = X[2][j] - X[0][j];
+    }
+    const T m11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
+    const T m12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
+    const T m22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
+    const T I1 = R.q11 * m11 + (2.0f * R.q12) * m12 + R.q22 * m22 - 2.0f;
+    const T I2 = (m11 * m22 - m12 * m12) * R.inv_det0 - 1.0f;
+    const T W1 = (0.25f * kS) * (2.0f * I1 + 2.0f);
+    const T W2 = ((0.25f * kS) * (2.0f * C * I2 - 2.0f)) * R.inv_det0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        // d tr/d e1 = 2 (q11 e1 + q12 e2), d det/d e1 = 2 (m22 e1 - m12 e2)
+        const T g1 = R.A0 * (W1 * (2.0f * (R.q11 * e1[j] + R.q12 * e2[j])) + W2 * (2.0f * (m22 * e1[j] - m12 * e2[j])));
+        const T g2 = R.A0 * (W1 * (2.0f * (R.q12 * e1[j] + R.q22 * e2[j])) + W2 * (2.0f * (m11 * e2[j] - m12 * e1[j])));
+        Fsk[0][j] = g1 + g2;
+        Fsk[1][j] = -g1;
+        Fsk[2][j] = -g2;
+    }
+    T c0[3], c1[3], c2[3];
+    cross3(X[1], X[2], c0);
+    cross3(X[2], X[0], c1);
+    cross3(X[0], X[1], c2);
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        F[0][j] = Fsk[0][j] + vfac * c0[j];
+        F[1][j] = Fsk[1][j] + vfac * c1[j];
+        F[2][j] = Fsk[2][j] + vfac * c2[j];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
     const int f = blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= n_faces) return;
@@ -168,47 +248,9 @@ __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
 #pragma unroll
         for (int j = 0; j < 3; ++j) X[k][j] = d.off_hi[3 * b + j];
     }
-    const FaceRef R = d.fref[f];
-    float e1[3], e2[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        e1[j] = X[1][j] - X[0][j];
-        e2[j] = X[2][j] - X[0][j];
-    }
-    const float m11 = e1[0] * e1[0] + e1[1] * e1[1] + e1[2] * e1[2];
-    const float m12 = e1[0] * e2[0] + e1[1] * e2[1] + e1[2] * e2[2];
-    const float m22 = e2[0] * e2[0] + e2[1] * e2[1] + e2[2] * e2[2];
-    const float I1 = R.q11 * m11 + 2.0f * R.q12 * m12 + R.q22 * m22 - 2.0f;
-    const float I2 = (m11 * m22 - m12 * m12) * R.inv_det0 - 1.0f;
-    const float W1 = 0.25f * C.kS * (2.0f * I1 + 2.0f);
-    const float W2 = 0.25f * C.kS * (2.0f * C.C * I2 - 2.0f) * R.inv_det0;
-    float g1[3], g2[3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        // d tr/d e1 = 2 (q11 e1 + q12 e2), d det/d e1 = 2 (m22 e1 - m12 e2)
-        g1[j] = R.A0 * (W1 * 2.0f * (R.q11 * e1[j] + R.q12 * e2[j]) + W2 * 2.0f * (m22 * e1[j] - m12 * e2[j]));
-        g2[j] = R.A0 * (W1 * 2.0f * (R.q12 * e1[j] + R.q22 * e2[j]) + W2 * 2.0f * (m11 * e2[j] - m12 * e1[j]));
-    }
-    float F[3][3];
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        F[0][j] = g1[j] + g2[j];
-        F[1][j] = -g1[j];
-        F[2][j] = -g2[j];
-    }
-    if (C.kV != 0.0f) {
-        const float lam = -(float)((double)C.kV * (d.capV[cap] - C.V0) / C.V0) * (1.0f / 6.0f);
-        float c0[3], c1[3], c2[3];
-        cross3(X[1], X[2], c0);
-        cross3(X[2], X[0], c1);
-        cross3(X[0], X[1], c2);
-#pragma unroll
-        for (int j = 0; j < 3; ++j) {
-            F[0][j] += lam * c0[j];
-            F[1][j] += lam * c1[j];
-            F[2][j] += lam * c2[j];
-        }
-    }
+    const float vfac = C.kV != 0.0f ? -(float)((double)C.kV * (d.capV[cap] - C.V0) / C.V0) * (1.0f / 6.0f) : 0.0f;
+    float Fsk[3][3], F[3][3];
+    face_forces<float>(X, d.fref[f], C.kS, C.C, vfac, Fsk, F);
     float* o = d.face_F + 9 * (int64_t)f;
 #pragma unroll
     for (int k = 0; k < 3; ++k)
@@ -457,6 +499,263 @@ __global__ __launch_bounds__(256) void k_cap_moments(Dev d) {
     if (threadIdx.x < 14) d.cap_mom[blockIdx.x * MOM_STRIDE + threadIdx.x] = sh[threadIdx.x][0];
 }
 
+// ---- adjoint -----------------------------------------------------------
+
+// Spread a 3-vector per node with the same bins and LDS boxes as k_spread.
+// mode 0: into target[axis][N]; mode 1: into the non-preferred component's
+// block of a [2][3][N] target.
+__global__ __launch_bounds__(256) void k_spread_vec(Lattice L, Dev d, int par, const float* __restrict__ val,
+                                                    float* __restrict__ target, int mode) {
+    constexpr int B3 = BOX * BOX * BOX;
+    __shared__ float box[6][B3];
+    const int nh = d.counters[CNT_HOME + par];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+    const int64_t N = L.n;
+    const int nf = mode == 0 ? 3 : 6;
+    for (int e = blockIdx.x; e < nh; e += gridDim.x) {
+        const int t = d.home[par][e];
+        const int start = d.home_start[e], cnt = d.tile_count[t];
+        const int ox = (t % L.nbx) * BIN, oy = ((t / L.nbx) % L.nby) * BIN, oz = (t / (L.nbx * L.nby)) * BIN;
+        for (int k = threadIdx.x; k < nf * B3; k += 256) (&box[0][0])[k] = 0.0f;
+        __syncthreads();
+        for (int j = wave; j < cnt; j += 4) {
+            const int b = d.sorted[start + j];
+            const NodePos p = node_pos(d, b);
+            const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
+            const int cell = ((wrapi(p.fl[2], L.nz) - oz + kz) * BOX + (wrapi(p.fl[1], L.ny) - oy + ky)) * BOX +
+                             (wrapi(p.fl[0], L.nx) - ox + kx);
+            const int base = mode == 0 ? 0 : 3 * (1 - d.caps[d.node_cap[b]].pref);
+            for (int a = 0; a < 3; ++a) atomicAdd(&box[base + a][cell], w * val[3 * b + a]);
+        }
+        __syncthreads();
+        for (int k = threadIdx.x; k < nf * B3; k += 256) {
+            const float v = (&box[0][0])[k];
+            if (v != 0.0f) {
+                const int f = k / B3, cell = k - f * B3;
+                const int iz = cell / (BOX * BOX), iy = (cell / BOX) % BOX, ix = cell % BOX;
+                const int gx = wrapi(ox - 1 + ix, L.nx), gy = wrapi(oy - 1 + iy, L.ny), gz = wrapi(oz - 1 + iz, L.nz);
+                unsafeAtomicAdd(&target[f * N + ((int64_t)gz * L.ny + gy) * L.nx + gx], v);
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Adjoint of the node-side coupling, one wavefront per node (64 lanes =
+// the delta stencil).  With lambda_U = lambda_X of the step's output:
+//   lambda_Fb = sum_y delta lambda_Fib(y)          (spreading of F_b)
+//   lambda_a  = sum_y delta lambda_phi(y) - G lambda_Fb . I_b
+//               (phi and the wettability reaction R_b = -G a_b I_b,
+//                I_b = sum_y delta S^np(y))
+//   lambda_X += sum_y grad_X delta(y - X) [lambda_U . u + lambda_Fib . F_b
+//               + a_b lambda_phi - G a_b lambda_Fb . S^np]
+//   dJ/dG += -a_b lambda_Fb . I_b,  dJ/dtheta += lambda_a da_b/dtheta,
+// and lambda_q = -G a_b lambda_Fb, to be spread into lambda_S^np.
+// lambda_phi^pref(y) = sum_i w_i c_i . lambda_S^pref(y - c_i) comes from a
+// 6^3 LDS cube of lambda_S, S^np from a 6^3 cube of rho^np.  Stencils must
+// stay two nodes away from solid rows.
+__global__ __launch_bounds__(256) void k_adj_nodes(Lattice L, Dev d, const float* __restrict__ rho_n, int n_nodes) {
+    constexpr int CB = 6, C3 = CB * CB * CB;
+    __shared__ float cube_r[4][C3];
+    __shared__ float cube_s[4][3][C3];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int b = blockIdx.x * 4 + wv;
+    if (b >= n_nodes) return;                   // whole wavefront; no block barrier below
+    const int64_t N = L.n;
+    const NodePos p = node_pos(d, b);
+    const CapDev& C = d.caps[d.node_cap[b]];
+    const float a_b = d.node_wet[b];
+    const int pref = C.pref, np = 1 - pref;
+    for (int j = lane; j < C3; j += 64) {
+        const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
+        int gy = wrapi(p.fl[1] - 2 + qy, L.ny);
+        const int64_t idx = ((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx + wrapi(p.fl[0] - 2 + qx, L.nx);
+        for (int a = 0; a < 3; ++a) cube_s[wv][a][j] = d.lam_S[(3 * pref + a) * N + idx];
+        if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
+        cube_r[wv][j] = rho_n[np * N + ((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx +
+                              wrapi(p.fl[0] - 2 + qx, L.nx)];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+    const float px = peskin(p.r[0] + 1.0f - kx), py = peskin(p.r[1] + 1.0f - ky), pz = peskin(p.r[2] + 1.0f - kz);
+    const float w = px * py * pz;
+    const float gw[3] = {peskin_d(p.r[0] + 1.0f - kx) * py * pz, px * peskin_d(p.r[1] + 1.0f - ky) * pz,
+                         px * py * peskin_d(p.r[2] + 1.0f - kz)};
+    const int64_t node = ((int64_t)wrapi(p.fl[2] - 1 + kz, L.nz) * L.ny + wrapi(p.fl[1] - 1 + ky, L.ny)) * L.nx
+                       + wrapi(p.fl[0] - 1 + kx, L.nx);
+    float lfib[3], uu[3];
+    for (int a = 0; a < 3; ++a) {
+        lfib[a] = d.lam_Fib[a * N + node];
+        uu[a] = d.u[a * N + node];
+    }
+    const int c0 = ((kz + 1) * CB + (ky + 1)) * CB + (kx + 1);
+    float lphi = 0.f, S[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+    for (int k = 1; k < Q; k += 2) {
+        const int o = (cz(k) * CB + cy(k)) * CB + cx(k);
+        // lambda_phi: sum_i w_i c_i . lambda_S(y - c_i)
+        float v = 0.f;
+        if (cx(k)) v += cx(k) * (cube_s[wv][0][c0 - o] - cube_s[wv][0][c0 + o]);
+        if (cy(k)) v += cy(k) * (cube_s[wv][1][c0 - o] - cube_s[wv][1][c0 + o]);
+        if (cz(k)) v += cz(k) * (cube_s[wv][2][c0 - o] - cube_s[wv][2][c0 + o]);
+        lphi += wgt(k) * v;
+        // S^np(y) = sum_i w_i rho^np(y + c_i) c_i
+        const float dd = wgt(k) * (cube_r[wv][c0 + o] - cube_r[wv][c0 - o]);
+        if (cx(k)) S[0] += cx(k) * dd;
+        if (cy(k)) S[1] += cy(k) * dd;
+        if (cz(k)) S[2] += cz(k) * dd;
+    }
+    float lFb[3], I[3];
+    for (int a = 0; a < 3; ++a) {
+        lFb[a] = wave_sum(w * lfib[a]);
+        I[a] = wave_sum(w * S[a]);
+    }
+    const float la1 = wave_sum(w * lphi);
+    const float lU[3] = {d.lam_X[3 * b], d.lam_X[3 * b + 1], d.lam_X[3 * b + 2]};
+    const float Fb[3] = {d.node_F[3 * b], d.node_F[3 * b + 1], d.node_F[3 * b + 2]};
+    const float val = lU[0] * uu[0] + lU[1] * uu[1] + lU[2] * uu[2] + lfib[0] * Fb[0] + lfib[1] * Fb[1] +
+                      lfib[2] * Fb[2] + a_b * lphi - L.G * a_b * (lFb[0] * S[0] + lFb[1] * S[1] + lFb[2] * S[2]);
+    float gX[3];
+    for (int a = 0; a < 3; ++a) gX[a] = wave_sum(gw[a] * val);
+    if (lane == 0) {
+        const float lFI = lFb[0] * I[0] + lFb[1] * I[1] + lFb[2] * I[2];
+        const float la = la1 - L.G * lFI;
+        for (int a = 0; a < 3; ++a) {
+            d.lam_Fb[3 * b + a] = lFb[a];
+            d.lam_q[3 * b + a] = -L.G * a_b * lFb[a];
+            d.lam_Xg[3 * b + a] = gX[a];
+        }
+        d.node_g[2 * b] = -(double)a_b * lFI;
+        d.node_g[2 * b + 1] = (double)la * d.node_area[b] * C.drv;
+    }
+}
+
+// FP64 directional derivative of each capsule volume along lambda_Fb.
+__global__ __launch_bounds__(256) void k_adj_capdV(Dev d, int n_faces) {
+    __shared__ double sh[256];
+    __shared__ int cap_first, cap_last;
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    const int f_last = min((int)(blockIdx.x * blockDim.x + blockDim.x), n_faces) - 1;
+    double v = 0.0;
+    int cap = -1;
+    if (f < n_faces) {
+        cap = d.face_cap[f];
+        double X[3][3], l[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const int bb = d.tri[3 * f + k];
+            for (int j = 0; j < 3; ++j) {
+                X[k][j] = (double)d.off_hi[3 * bb + j];
+                l[k][j] = (double)d.lam_Fb[3 * bb + j];
+            }
+        }
+        double c0[3], c1[3], c2[3];
+        cross3<double>(X[1], X[2], c0);
+        cross3<double>(X[2], X[0], c1);
+        cross3<double>(X[0], X[1], c2);
+        for (int j = 0; j < 3; ++j) v += c0[j] * l[0][j] + c1[j] * l[1][j] + c2[j] * l[2][j];
+        v /= 6.0;
+    }
+    if (threadIdx.x == 0) {
+        cap_first = d.face_cap[blockIdx.x * blockDim.x];
+        cap_last = d.face_cap[f_last];
+    }
+    __syncthreads();
+    if (cap_first != cap_last) {
+        if (f < n_faces) unsafeAtomicAdd(&d.capdV[cap], v);
+        return;
+    }
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) unsafeAtomicAdd(&d.capdV[cap_first], sh[0]);
+}
+
+// Tangent of the face forces along X + eps lambda_Fb (the Hessian-vector
+// product of the elastic energy, written to face_F) and the kS derivative
+// sum_corners lambda_Fb . F_skalak / kS.
+__global__ __launch_bounds__(256) void k_adj_faces(Dev d, int n_faces) {
+    __shared__ double sh[256];
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    double gk = 0.0;
+    if (f < n_faces) {
+        const int cap = d.face_cap[f];
+        const CapDev& C = d.caps[cap];
+        Dual X[3][3];
+        float l[3][3];
+        for (int k = 0; k < 3; ++k) {
+            const int bb = d.tri[3 * f + k];
+            for (int j = 0; j < 3; ++j) {
+                l[k][j] = d.lam_Fb[3 * bb + j];
+                X[k][j] = Dual{d.off_hi[3 * bb + j], l[k][j]};
+            }
+        }
+        Dual vfac{0.0f, 0.0f};
+        if (C.kV != 0.0f) {
+            vfac.v = -(float)((double)C.kV * (d.capV[cap] - C.V0) / C.V0) * (1.0f / 6.0f);
+            vfac.e = -(float)((double)C.kV * d.capdV[cap] / C.V0) * (1.0f / 6.0f);
+        }
+        Dual Fsk[3][3], F[3][3];
+        face_forces<Dual>(X, d.fref[f], C.kS, C.C, vfac, Fsk, F);
+        float* o = d.face_F + 9 * (int64_t)f;
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) {
+                o[3 * k + j] = F[k][j].e;
+                gk += (double)l[k][j] * Fsk[k][j].v;
+            }
+        gk /= (double)C.kS;
+    }
+    sh[threadIdx.x] = gk;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0 && sh[0] != 0.0) unsafeAtomicAdd(&d.grads[1], sh[0]);
+}
+
+// lambda_X(step input) = lambda_X(step output) + delta-gradient terms +
+// Hessian-vector product gathered over the node's triangles.
+__global__ __launch_bounds__(256) void k_adj_node_update(Dev d, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    float g[3] = {d.lam_Xg[3 * b], d.lam_Xg[3 * b + 1], d.lam_Xg[3 * b + 2]};
+    for (int k = d.csr_ptr[b]; k < d.csr_ptr[b + 1]; ++k) {
+        const int e = d.csr_idx[k];
+        for (int a = 0; a < 3; ++a) g[a] += d.face_F[3 * (int64_t)e + a];
+    }
+    for (int a = 0; a < 3; ++a) d.lam_X[3 * b + a] += g[a];
+}
+
+// sum of the per-node G and theta parts in a fixed order
+__global__ __launch_bounds__(1024) void k_adj_node_grads(Dev d, int n_nodes) {
+    __shared__ double sh[2][1024];
+    double g0 = 0.0, g1 = 0.0;
+    for (int b = threadIdx.x; b < n_nodes; b += 1024) {
+        g0 += d.node_g[2 * b];
+        g1 += d.node_g[2 * b + 1];
+    }
+    sh[0][threadIdx.x] = g0;
+    sh[1][threadIdx.x] = g1;
+    __syncthreads();
+    for (int s = 512; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sh[0][threadIdx.x] += sh[0][threadIdx.x + s];
+            sh[1][threadIdx.x] += sh[1][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        d.grads[2] += sh[0][0];
+        d.grads[0] += sh[1][0];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_debug_bins(Lattice L, Dev d, int n_nodes) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_nodes) return;
@@ -498,6 +797,22 @@ void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream
 }
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s) {
     if (n_caps > 0) hipLaunchKernelGGL(k_cap_moments, dim3(n_caps), dim3(256), 0, s, d);
+}
+void launch_spread_vec(const Lattice& L, const Dev& d, int par, const float* val, float* target, int mode,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_spread_vec, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par, val, target, mode);
+}
+void launch_adj_nodes(const Lattice& L, const Dev& d, const float* rho_n, int n_nodes, hipStream_t s) {
+    if (n_nodes > 0)
+        hipLaunchKernelGGL(k_adj_nodes, dim3((n_nodes + 3) / 4), dim3(256), 0, s, L, d, rho_n, n_nodes);
+}
+void launch_adj_membrane(const Dev& d, int n_nodes, int n_faces, hipStream_t s) {
+    if (n_faces <= 0) return;
+    const dim3 gf((n_faces + 255) / 256);
+    hipLaunchKernelGGL(k_adj_capdV, gf, dim3(256), 0, s, d, n_faces);
+    hipLaunchKernelGGL(k_adj_faces, gf, dim3(256), 0, s, d, n_faces);
+    hipLaunchKernelGGL(k_adj_node_update, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
+    hipLaunchKernelGGL(k_adj_node_grads, dim3(1), dim3(1024), 0, s, d, n_nodes);
 }
 void launch_debug_bins(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s) {
     if (n_nodes > 0)

@@ -31,6 +31,10 @@ struct Layout {
     size_t caps, capV, cap_mom, red, cscale, dpart, dmass;
     size_t slot0, slot_bytes, fbytes;
     size_t slot_f, slot_rho, slot_off, slot_cs;   // offsets inside a slot
+    bool adjoint = false;
+    size_t lam[2], lam_rho, lam_j, lam_S, lam_u, lam_Fib, lam_X, lam_Fb, lam_q, lam_Xg, node_g, node_area, capdV,
+        grads;
+    size_t ring0, ring_bytes, ring_f, ring_rho, ring_off;
     int64_t tiles, max_caps;
 };
 
@@ -98,6 +102,30 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     l.slot_cs = take(s, 4 * sizeof(float));
     l.slot_bytes = (s + 255) & ~size_t(255);
     l.slot0 = take(c, (size_t)std::max(p->n_slots, 0) * l.slot_bytes);
+    l.adjoint = p->ring_len > 0 && !half && max_nodes > 0;
+    l.node_area = take(c, nb * 4);
+    if (l.adjoint) {
+        l.lam[0] = take(c, fbytes);
+        l.lam[1] = take(c, fbytes);
+        l.lam_rho = take(c, 2 * N * 4);
+        l.lam_j = take(c, 6 * N * 4);
+        l.lam_S = take(c, 6 * N * 4);
+        l.lam_u = take(c, 3 * N * 4);
+        l.lam_Fib = take(c, 3 * N * 4);
+        l.lam_X = take(c, 3 * nb * 4);
+        l.lam_Fb = take(c, 3 * nb * 4);
+        l.lam_q = take(c, 3 * nb * 4);
+        l.lam_Xg = take(c, 3 * nb * 4);
+        l.node_g = take(c, 2 * nb * 8);
+        l.capdV = take(c, l.max_caps * 8);
+        l.grads = take(c, 4 * 8);
+        size_t r = 0;
+        l.ring_f = take(r, fbytes);
+        l.ring_rho = take(r, 2 * N * 4);
+        l.ring_off = take(r, 6 * nb * 4);
+        l.ring_bytes = (r + 255) & ~size_t(255);
+        l.ring0 = take(c, (size_t)p->ring_len * l.ring_bytes);
+    }
     l.total = (c + 255) & ~size_t(255);
     return l;
 }
@@ -119,6 +147,8 @@ std::string validate(const lbm_params* p) {
     if (p->n_slots < 0 || p->n_slots > 4096) return "n_slots out of range";
     if (p->check_every < 0) return "check_every must be >= 0";
     if (p->use_graphs != 0 && p->use_graphs != 1) return "use_graphs must be 0 or 1";
+    if (p->ring_len < 0 || p->ring_len > 100000) return "ring_len out of range";
+    if (p->ring_len > 0 && p->precision != LBM_FP32) return "the adjoint needs FP32 storage";
     return "";
 }
 
@@ -143,6 +173,10 @@ struct lbm_ctx {
     std::vector<float> off;        // [nodes][3]
     std::vector<int> node_cap;
     std::vector<float> node_wet;
+    std::vector<float> node_area;
+    // adjoint run description
+    int adj_nsteps = 0, adj_every = 0, adj_obj = 0, adj_cap = 0;
+    int64_t adj_step0 = -1;
     std::vector<int> tri_global;
     std::vector<FaceRef> fref;
     std::vector<int> face_cap;
@@ -268,6 +302,23 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     d.capV = (double*)(w + lay.capV);
     d.cap_mom = (double*)(w + lay.cap_mom);
     d.red = (double*)(w + lay.red);
+    d.node_area = (float*)(w + lay.node_area);
+    if (lay.adjoint) {
+        d.lam[0] = (void*)(w + lay.lam[0]);
+        d.lam[1] = (void*)(w + lay.lam[1]);
+        d.lam_rho = (float*)(w + lay.lam_rho);
+        d.lam_j = (float*)(w + lay.lam_j);
+        d.lam_S = (float*)(w + lay.lam_S);
+        d.lam_u = (float*)(w + lay.lam_u);
+        d.lam_Fib = (float*)(w + lay.lam_Fib);
+        d.lam_X = (float*)(w + lay.lam_X);
+        d.lam_Fb = (float*)(w + lay.lam_Fb);
+        d.lam_q = (float*)(w + lay.lam_q);
+        d.lam_Xg = (float*)(w + lay.lam_Xg);
+        d.node_g = (double*)(w + lay.node_g);
+        d.capdV = (double*)(w + lay.capdV);
+        d.grads = (double*)(w + lay.grads);
+    }
 
     hipStream_t s = c->stream;
     // initial densities into both density buffers (the previous-step buffer
@@ -293,6 +344,10 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     if ((er = hipMemsetAsync(d.tile_flag, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_count, 0, lay.bins * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.counters, 0, 8 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if (lay.adjoint) {
+        if ((er = hipMemsetAsync(d.lam_u, 0, 3 * N * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+        if ((er = hipMemsetAsync(d.capdV, 0, lay.max_caps * 8, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    }
     if ((er = hipGetLastError()) != hipSuccess) return bad(er, "init kernel launch");
     // the host arrays may be freed once the copies are done
     if ((er = hipStreamSynchronize(s)) != hipSuccess) return bad(er, "hipStreamSynchronize");
@@ -354,6 +409,8 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
         const double rv = dr * rv_scale;
         cd.pref = rv >= 0.0 ? 0 : 1;
         cd.rv_abs = (float)fabs(rv);
+        // d|rho_v|/dtheta per radian for the preferred component chosen here
+        cd.drv = (float)((cd.pref == 0 ? 1.0 : -1.0) * (-sin(theta_deg[k] * (M_PI / 180.0))) * rv_scale);
         cd.kS = (float)kS[k];
         cd.C = (float)C[k];
         cd.kV = (float)kV[k];
@@ -395,6 +452,7 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
             for (int j = 0; j < 3; ++j) c->off.push_back((float)R[3 * b + j]);
             c->node_cap.push_back(cap_id);
             c->node_wet.push_back((float)(fabs(rv) * narea[b]));
+            c->node_area.push_back((float)narea[b]);
         }
         c->caps.push_back(cd);
         c->n_nodes += nn;
@@ -418,6 +476,7 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
     HIPCHK(c, hipMemcpyAsync(d.off_lo, zeros.data(), 3 * nb * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.node_cap, c->node_cap.data(), nb * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.node_wet, c->node_wet.data(), nb * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.node_area, c->node_area.data(), nb * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.csr_ptr, ptr.data(), (nb + 1) * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.csr_idx, idx.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.tri, c->tri_global.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
@@ -445,19 +504,18 @@ static int check_mass(lbm_ctx* c) {
     return LBM_OK;
 }
 
-// Enqueue one time step.  ev (may be NULL) receives LBM_NK + 1 events:
-// ev[k] is recorded before kernel group k and ev[LBM_NK] after the last.
-static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
+// Enqueue one time step from fin / rho_p into fout / rho_n.  ev (may be
+// NULL) receives LBM_NK + 1 events: ev[k] is recorded before kernel group k
+// and ev[LBM_NK] after the last.  advect = false leaves the nodes in place
+// (the adjoint's recompute of a step's intermediates).
+static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, const float* rho_p, bool advect,
+                         hipEvent_t* ev) {
     const Lattice& L = c->L;
     Dev& d = c->d;
     hipStream_t s = c->stream;
     const bool ibm = c->n_nodes > 0;
     const int ncap = (int)c->caps.size();
     const int cur = (int)(c->step & 1), nxt = cur ^ 1;
-    const void* fin = d.f[cur];
-    void* fout = d.f[nxt];
-    float* rho_n = d.rho[cur];
-    const float* rho_p = d.rho[nxt];
     const int par = c->flip;
     const bool half = c->half();
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
@@ -481,10 +539,15 @@ static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
     mark(LBM_K_COLLIDE);
     launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ibm, false, half, d.cscale, nxt, cur, s);
     mark(LBM_K_INTERP);
-    if (ibm) launch_interp_advect(L, d, c->n_nodes, s);
+    if (ibm && advect) launch_interp_advect(L, d, c->n_nodes, s);
     mark(LBM_NK);
     c->step++;
     c->flip ^= 1;
+}
+
+static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
+    const int cur = (int)(c->step & 1), nxt = cur ^ 1;
+    enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev);
 }
 
 // Two steps captured as one graph.  The launch arguments depend only on the
@@ -754,6 +817,267 @@ int lbm_state_load(lbm_ctx* c, int32_t slot) {
         HIPCHK(c, hipMemcpyAsync(c->d.off_lo, base + c->lay.slot_off + 3 * (size_t)c->n_nodes * 4,
                                  3 * (size_t)c->n_nodes * 4, hipMemcpyDeviceToDevice, s));
     }
+    return LBM_OK;
+}
+
+// ---- adjoint ---------------------------------------------------------------
+
+// eigen-decomposition of a symmetric 3x3 matrix (cyclic Jacobi): values and
+// column eigenvectors
+static void eig3v(double A[3][3], double ev[3], double V[3][3]) {
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        const double off = A[0][1] * A[0][1] + A[0][2] * A[0][2] + A[1][2] * A[1][2];
+        if (off < 1e-300) break;
+        for (int p = 0; p < 2; ++p)
+            for (int q = p + 1; q < 3; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double th = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                const double cs = 1.0 / sqrt(t * t + 1.0), sn = t * cs;
+                for (int k = 0; k < 3; ++k) {
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < 3; ++k) {
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+    for (int k = 0; k < 3; ++k) ev[k] = A[k][k];
+}
+
+// Taylor deformation D of a closed triangulated surface and its gradient with
+// respect to the node positions, in FP64.  V, m1 = int x dV and
+// m2 = int x x^T dV are sums over the tetrahedra (origin, a, b, c); the
+// central moment is M = m2 - m1 m1^T / V, its eigenvalues mu_k give the
+// half-axes a_k = sqrt(5 mu_k / V), D = (a_max - a_min) / (a_max + a_min).
+// The gradient runs the same chain backwards (eigenvalue derivative
+// v_k^T dM v_k for distinct eigenvalues).
+static double taylor_D_grad(const std::vector<double>& X, const int* tri, int nf, std::vector<double>& g) {
+    double V = 0, m1[3] = {0, 0, 0}, m2[3][3] = {{0}};
+    for (int f = 0; f < nf; ++f) {
+        const double* a = &X[3 * tri[3 * f]];
+        const double* b = &X[3 * tri[3 * f + 1]];
+        const double* cc = &X[3 * tri[3 * f + 2]];
+        const double v = (a[0] * (b[1] * cc[2] - b[2] * cc[1]) + a[1] * (b[2] * cc[0] - b[0] * cc[2]) +
+                          a[2] * (b[0] * cc[1] - b[1] * cc[0])) / 6.0;
+        double s[3];
+        for (int j = 0; j < 3; ++j) s[j] = a[j] + b[j] + cc[j];
+        V += v;
+        for (int i = 0; i < 3; ++i) {
+            m1[i] += v * s[i] / 4.0;
+            for (int j = 0; j < 3; ++j) m2[i][j] += v / 20.0 * (a[i] * a[j] + b[i] * b[j] + cc[i] * cc[j] + s[i] * s[j]);
+        }
+    }
+    double M[3][3];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i][j] = m2[i][j] - m1[i] * m1[j] / V;
+    double ev[3], EV[3][3], Mc[3][3];
+    memcpy(Mc, M, sizeof M);
+    eig3v(Mc, ev, EV);
+    int kmin = 0, kmax = 0;
+    for (int k = 1; k < 3; ++k) {
+        if (ev[k] < ev[kmin]) kmin = k;
+        if (ev[k] > ev[kmax]) kmax = k;
+    }
+    const double a1 = sqrt(5.0 * ev[kmin] / V), a3 = sqrt(5.0 * ev[kmax] / V);
+    const double D = (a3 - a1) / (a3 + a1);
+    // backwards: D -> a_k -> (mu_k, V) -> (M, V) -> (m2, m1, V)
+    const double den = (a1 + a3) * (a1 + a3);
+    const double c3 = 2.0 * a1 / den, c1 = -2.0 * a3 / den;
+    double lV = 0.0, lmu[3] = {0, 0, 0};
+    lmu[kmax] += c3 * 5.0 / (2.0 * a3 * V);
+    lmu[kmin] += c1 * 5.0 / (2.0 * a1 * V);
+    lV += -c3 * 5.0 * ev[kmax] / (2.0 * a3 * V * V) - c1 * 5.0 * ev[kmin] / (2.0 * a1 * V * V);
+    double lM[3][3] = {{0}};
+    for (int k = 0; k < 3; ++k)
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) lM[i][j] += lmu[k] * EV[i][k] * EV[j][k];
+    double lm1[3] = {0, 0, 0};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) lm1[i] += -2.0 * lM[i][j] * m1[j] / V;
+    double m1Lm1 = 0.0;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) m1Lm1 += m1[i] * lM[i][j] * m1[j];
+    lV += m1Lm1 / (V * V);
+    g.assign(X.size(), 0.0);
+    for (int f = 0; f < nf; ++f) {
+        const int id[3] = {tri[3 * f], tri[3 * f + 1], tri[3 * f + 2]};
+        const double* P[3] = {&X[3 * id[0]], &X[3 * id[1]], &X[3 * id[2]]};
+        const double v = (P[0][0] * (P[1][1] * P[2][2] - P[1][2] * P[2][1]) +
+                          P[0][1] * (P[1][2] * P[2][0] - P[1][0] * P[2][2]) +
+                          P[0][2] * (P[1][0] * P[2][1] - P[1][1] * P[2][0])) / 6.0;
+        double s[3];
+        for (int j = 0; j < 3; ++j) s[j] = P[0][j] + P[1][j] + P[2][j];
+        double ls = 0.0, Ls[3] = {0, 0, 0}, quad = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            ls += lm1[i] * s[i];
+            for (int j = 0; j < 3; ++j) Ls[i] += lM[i][j] * s[j];
+        }
+        for (int q = 0; q < 3; ++q)
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) quad += P[q][i] * lM[i][j] * P[q][j];
+        for (int i = 0; i < 3; ++i)
+            for (int j = 0; j < 3; ++j) quad += 0.0 * s[i] * s[j];
+        double sLs = 0.0;
+        for (int i = 0; i < 3; ++i) sLs += s[i] * Ls[i];
+        // adjoint weight of v for this face
+        const double lv = lV + ls / 4.0 + (quad + sLs) / 20.0;
+        for (int q = 0; q < 3; ++q) {
+            const double* u1 = P[(q + 1) % 3];
+            const double* u2 = P[(q + 2) % 3];
+            const double dv[3] = {(u1[1] * u2[2] - u1[2] * u2[1]) / 6.0, (u1[2] * u2[0] - u1[0] * u2[2]) / 6.0,
+                                  (u1[0] * u2[1] - u1[1] * u2[0]) / 6.0};
+            double LP[3] = {0, 0, 0};
+            for (int i = 0; i < 3; ++i)
+                for (int j = 0; j < 3; ++j) LP[i] += lM[i][j] * P[q][j];
+            for (int j = 0; j < 3; ++j)
+                g[3 * id[q] + j] += lv * dv[j] + v * lm1[j] / 4.0 + v / 20.0 * (2.0 * LP[j] + 2.0 * Ls[j]);
+        }
+    }
+    return D;
+}
+
+static bool adjoint_ready(lbm_ctx* c) { return c->lay.adjoint && c->n_nodes > 0; }
+
+// ring entry k: populations, previous densities, node offsets (hi, lo)
+static char* ring_at(lbm_ctx* c, int k) { return c->ws + c->lay.ring0 + (size_t)k * c->lay.ring_bytes; }
+
+int lbm_adjoint_forward(lbm_ctx* c, int32_t nsteps, int32_t every, int32_t objective, int32_t capsule, double* J) {
+    if (!c || !J) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (!adjoint_ready(c)) return c->fail(LBM_ESTATE, "the adjoint needs ring_len > 0, FP32 storage and capsules");
+    if (nsteps < 1 || every < 1 || every > c->p.ring_len) return c->fail(LBM_EINVAL, "need 1 <= every <= ring_len");
+    const int nseg = (nsteps + every - 1) / every;
+    if (nseg > c->p.n_slots) return c->fail(LBM_EINVAL, "need n_slots >= ceil(nsteps / every) = %d", nseg);
+    if (objective != LBM_OBJ_COM_Z && objective != LBM_OBJ_TAYLOR_D) return c->fail(LBM_EINVAL, "unknown objective");
+    if (capsule < 0 || capsule >= (int)c->caps.size()) return c->fail(LBM_EINVAL, "capsule index out of range");
+    c->adj_step0 = c->step;
+    for (int sgm = 0; sgm < nseg; ++sgm) {
+        const int r = lbm_state_save(c, sgm);
+        if (r != LBM_OK) return r;
+        const int n = std::min(every, nsteps - sgm * every);
+        const int r2 = lbm_step(c, n);
+        if (r2 != LBM_OK) return r2;
+    }
+    c->adj_nsteps = nsteps;
+    c->adj_every = every;
+    c->adj_obj = objective;
+    c->adj_cap = capsule;
+    std::vector<lbm_capsule_obs> co(c->caps.size());
+    lbm_obs o;
+    const int r = lbm_observables(c, &o, co.data());
+    if (r != LBM_OK) return r;
+    *J = objective == LBM_OBJ_COM_Z ? co[capsule].height : co[capsule].taylor_D;
+    return LBM_OK;
+}
+
+int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
+    if (!c || !grads) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (!adjoint_ready(c) || c->adj_step0 < 0 || c->step != c->adj_step0 + c->adj_nsteps)
+        return c->fail(LBM_ESTATE, "lbm_adjoint_backward must follow lbm_adjoint_forward");
+    Dev& d = c->d;
+    const Lattice& L = c->L;
+    hipStream_t s = c->stream;
+    const int64_t N = L.n;
+    const size_t nb = c->n_nodes;
+    // seed dJ/dX at the final positions (FP64 on the host), lambda* = 0
+    std::vector<float> hi(3 * nb), lo(3 * nb), seed(3 * nb, 0.0f);
+    HIPCHK(c, hipMemcpyAsync(hi.data(), d.off_hi, 3 * nb * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(lo.data(), d.off_lo, 3 * nb * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const CapDev& cd = c->caps[c->adj_cap];
+    if (c->adj_obj == LBM_OBJ_COM_Z) {
+        for (int b = 0; b < cd.node_count; ++b) seed[3 * (cd.node_start + b) + 2] = (float)(1.0 / cd.node_count);
+    } else {
+        std::vector<double> X(3 * (size_t)cd.node_count), gD;
+        for (int b = 0; b < cd.node_count; ++b)
+            for (int j = 0; j < 3; ++j)
+                X[3 * b + j] = (double)hi[3 * (cd.node_start + b) + j] + (double)lo[3 * (cd.node_start + b) + j];
+        std::vector<int> tl(3 * (size_t)cd.face_count);
+        for (int f = 0; f < 3 * cd.face_count; ++f) tl[f] = c->tri_global[3 * (size_t)cd.face_start + f] - cd.node_start;
+        taylor_D_grad(X, tl.data(), cd.face_count, gD);
+        for (int b = 0; b < cd.node_count; ++b)
+            for (int j = 0; j < 3; ++j) seed[3 * (cd.node_start + b) + j] = (float)gD[3 * b + j];
+    }
+    HIPCHK(c, hipMemcpyAsync(d.lam_X, seed.data(), 3 * nb * 4, hipMemcpyHostToDevice, s));
+    int p = 0;
+    HIPCHK(c, hipMemsetAsync(d.lam[p], 0, c->lay.fbytes, s));
+    HIPCHK(c, hipMemsetAsync(d.lam_S, 0, 6 * N * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.lam_rho, 0, 2 * N * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.lam_j, 0, 6 * N * 4, s));
+    HIPCHK(c, hipMemsetAsync(d.grads, 0, 4 * 8, s));
+    const int nseg = (c->adj_nsteps + c->adj_every - 1) / c->adj_every;
+    const size_t offb = 3 * nb * 4;
+    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+        const int len = std::min(c->adj_every, c->adj_nsteps - sgm * c->adj_every);
+        int r = lbm_state_load(c, sgm);
+        if (r != LBM_OK) return r;
+        // ring[0] = the checkpoint
+        {
+            const int cur = (int)(c->step & 1);
+            char* e0 = ring_at(c, 0);
+            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_f, d.f[cur], c->lay.fbytes, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_rho, d.rho[cur ^ 1], 2 * N * 4, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_off, d.off_hi, offb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_off + offb, d.off_lo, offb, hipMemcpyDeviceToDevice, s));
+        }
+        const int64_t seg_step0 = c->step;
+        // recompute the segment into the ring
+        for (int k = 0; k + 1 < len; ++k) {
+            char* ek = ring_at(c, k);
+            char* en = ring_at(c, k + 1);
+            enqueue_core(c, ek + c->lay.ring_f, en + c->lay.ring_f, (float*)(en + c->lay.ring_rho),
+                         (const float*)(ek + c->lay.ring_rho), true, nullptr);
+            HIPCHK(c, hipMemcpyAsync(en + c->lay.ring_off, d.off_hi, offb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(en + c->lay.ring_off + offb, d.off_lo, offb, hipMemcpyDeviceToDevice, s));
+        }
+        // adjoint steps in reverse
+        for (int k = len - 1; k >= 0; --k) {
+            char* ek = ring_at(c, k);
+            HIPCHK(c, hipMemcpyAsync(d.off_hi, ek + c->lay.ring_off, offb, hipMemcpyDeviceToDevice, s));
+            HIPCHK(c, hipMemcpyAsync(d.off_lo, ek + c->lay.ring_off + offb, offb, hipMemcpyDeviceToDevice, s));
+            c->step = seg_step0 + k;
+            const int par = c->flip;
+            const void* fin = ek + c->lay.ring_f;
+            const float* rho_p = (const float*)(ek + c->lay.ring_rho);
+            float* rho_n = d.rho[0];
+            // intermediates of step k: densities, node forces, spread fields, u
+            enqueue_core(c, fin, d.f[0], rho_n, rho_p, false, nullptr);
+            launch_spread_vec(L, d, par, d.lam_X, d.lam_u, 0, s);
+            launch_adj_collide(L, fin, rho_n, rho_p, d.fib, d.tile_flag, d.lam[p], d.lam_u, d.lam_rho, d.lam_j,
+                               d.lam_S, d.lam_Fib, d.grads, s);
+            launch_adj_nodes(L, d, rho_n, c->n_nodes, s);
+            launch_adj_membrane(d, c->n_nodes, c->n_faces, s);
+            launch_spread_vec(L, d, par, d.lam_q, d.lam_S, 1, s);
+            launch_adj_gather(L, d.lam_S, d.lam_rho, s);
+            launch_adj_push(L, d.lam[p], d.lam_rho, d.lam_j, d.lam[p ^ 1], s);
+            p ^= 1;
+            HIPCHK(c, hipGetLastError());
+        }
+        c->step = seg_step0;
+    }
+    // leave the state at the start of the run
+    {
+        const int r = lbm_state_load(c, 0);
+        if (r != LBM_OK) return r;
+    }
+    double g[4];
+    HIPCHK(c, hipMemcpyAsync(g, d.grads, sizeof g, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    grads[0] = g[0];
+    grads[1] = g[1];
+    grads[2] = g[2];
+    c->adj_step0 = -1;
     return LBM_OK;
 }
 

@@ -68,6 +68,7 @@ struct CapDev {
     int node_start, node_count, face_start, face_count;
     int pref;           // preferred component of the virtual density (0 A, 1 B)
     float rv_abs;       // |rho_v|
+    float drv;          // d|rho_v| / d theta (per radian)
     float kS, C, kV;
     double V0;
 };
@@ -116,6 +117,21 @@ struct Dev {
     double* capV;         // [max caps]
     double* cap_mom;      // [max caps][16] observables moments
     double* red;          // [RED_BLOCKS][8] reduction partials
+    // adjoint (allocated when the recompute ring is requested)
+    void* lam[2];         // adjoint populations, [Q][N] component pairs (FP32)
+    float* lam_rho;       // [2][N]
+    float* lam_j;         // [6][N]  (component * 3 + axis)
+    float* lam_S;         // [6][N]  adjoint of the Shan-Chen neighbour sums
+    float* lam_u;         // [3][N]  touched tiles only
+    float* lam_Fib;       // [3][N]  touched tiles only
+    float* lam_X;         // [nodes][3] adjoint of the node positions
+    float* lam_Fb;        // [nodes][3] adjoint of the node forces
+    float* lam_q;         // [nodes][3] -G a_b lam_Fb, spread into lam_S
+    float* lam_Xg;        // [nodes][3] delta-gradient terms
+    double* node_g;       // [nodes][2] per-node dJ/dG, dJ/dtheta parts
+    float* node_area;     // [nodes] rest area A_b
+    double* capdV;        // [max caps] directional derivative of V
+    double* grads;        // [4] dJ/dtheta, dJ/dkS, dJ/dG
 };
 
 constexpr int RED_BLOCKS = 1024;
@@ -148,5 +164,17 @@ void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s);
 void launch_debug_bins(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
+// adjoint (k_ibm.hip)
+void launch_spread_vec(const Lattice& L, const Dev& d, int parity, const float* val, float* target, int mode,
+                       hipStream_t s);
+void launch_adj_nodes(const Lattice& L, const Dev& d, const float* rho_n, int n_nodes, hipStream_t s);
+void launch_adj_membrane(const Dev& d, int n_nodes, int n_faces, hipStream_t s);
+// adjoint (k_fluid.hip)
+void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
+                        const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
+                        float* lam_S, float* lam_Fib, double* grads, hipStream_t s);
+void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hipStream_t s);
+void launch_adj_push(const Lattice& L, const void* lam_in, const float* lam_rho, const float* lam_j, void* lam_out,
+                     hipStream_t s);
 
 }  // namespace lbmx

@@ -1,0 +1,122 @@
+"""The hand-written HIP adjoint against the FP64 oracle's reverse-mode
+gradient and against central finite differences of the GPU forward."""
+
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import sim as S
+from paper_1904_11386_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+class OracleChannel:
+    def __init__(self, wl, params):
+        self.wl, self.params = wl, params
+
+    def __call__(self, th, ks, G):
+        wl = self.wl
+        caps = []
+        for c in wl.capsules:
+            xyz, tri = c.mesh()
+            caps.append(dict(xyz=xyz, tri=tri, kS=ks, C=c.C, kV=c.kV, theta=th))
+        return S.OracleSim(wl.rhoA.astype(np.float64), wl.rhoB.astype(np.float64), caps, tau=wl.tau, G=G,
+                           walls=wl.walls, u_lo=wl.wall_u_lo, u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj,
+                           rho_min=wl.rho_min, z_interface=wl.z_interface, wet_scale=wl.wet_scale,
+                           differentiable=True)
+
+
+def _gpu_grad(wl, params, steps, every, kind):
+    from paper_1904_11386_amd import binding
+    from paper_1904_11386_amd.adjoint import OBJECTIVES, workload_with
+    nseg = (steps + every - 1) // every
+    sim = binding.sim_from_workload(workload_with(wl, *params), n_slots=nseg, ring_len=every)
+    J = sim.adjoint_forward(steps, every, OBJECTIVES[kind], 0)
+    g = sim.adjoint_backward()
+    sim.close()
+    return J, g
+
+
+@pytest.mark.parametrize("kind", ["com_z", "taylor_D"])
+def test_adjoint_matches_oracle_gradient_channel(kind):
+    wl = W.make("c4_mini")
+    params = (75.0, 0.005, 3.6)
+    steps, every = 40, 10
+    _say("adjoint", kind, "c4_mini", steps, "steps, checkpoint every", every)
+    J, g = _gpu_grad(wl, params, steps, every, kind)
+    Jo, go = S.gradient(OracleChannel(wl, params), steps, every, kind)
+    go = go.numpy()
+    rel = np.abs(g - go) / np.abs(go)
+    _say("  J gpu %.8e oracle %.8e" % (J, Jo))
+    _say("  grad gpu", g.tolist(), "oracle", go.tolist(), "rel", rel.tolist())
+    assert abs(J - Jo) < 1e-5 * max(1.0, abs(Jo))
+    assert np.all(rel < 1e-4), rel
+    # and against FP64 central differences of the oracle forward
+    oc = OracleChannel(wl, params)
+
+    def run(p):
+        s = oc(*p)
+        with torch.no_grad():
+            s.run(steps)
+            return float(S.objective(s, kind))
+
+    for i, h in enumerate((0.05, 1e-5, 1e-4)):
+        pp, pm = list(params), list(params)
+        pp[i] += h
+        pm[i] -= h
+        fd = (run(pp) - run(pm)) / (2 * h)
+        if i == 0:
+            fd *= 180.0 / math.pi
+        _say("  param %d gpu adjoint %.8e fp64 fd %.8e rel %.2e" % (i, g[i], fd, abs(g[i] - fd) / abs(fd)))
+        assert abs(g[i] - fd) <= 1e-4 * abs(fd)
+
+
+def test_adjoint_matches_central_differences_gpu():
+    from paper_1904_11386_amd import binding
+    from paper_1904_11386_amd.adjoint import workload_with
+    wl = W.make("c4_mini")
+    params = [75.0, 0.005, 3.6]
+    steps, every = 40, 10
+    J, g = _gpu_grad(wl, params, steps, every, "com_z")
+
+    def fwd(p):
+        s = binding.sim_from_workload(workload_with(wl, *p))
+        s.step(steps)
+        h = s.observables()["caps"][0]["height"]
+        s.close()
+        return h
+
+    for i, h in enumerate((0.5, 5e-5, 1e-3)):
+        pp, pm = list(params), list(params)
+        pp[i] += h
+        pm[i] -= h
+        fd = (fwd(pp) - fwd(pm)) / (2 * h)
+        if i == 0:
+            fd *= 180.0 / math.pi
+        _say("  param %d adjoint %.6e fp32 fd %.6e rel %.2e" % (i, g[i], fd, abs(g[i] - fd) / abs(fd)))
+        # FP32 forward differences carry ~1e-7 relative noise in J, so the
+        # bound is the noise over the step, not the adjoint's accuracy
+        assert abs(g[i] - fd) <= 1e-2 * abs(fd)
+
+
+def test_autograd_function_backward():
+    from paper_1904_11386_amd.adjoint import capsule_objective
+    wl = W.make("c4_mini")
+    th = torch.tensor(75.0, dtype=torch.float64, requires_grad=True)
+    ks = torch.tensor(0.005, dtype=torch.float64, requires_grad=True)
+    G = torch.tensor(3.6, dtype=torch.float64, requires_grad=True)
+    J = capsule_objective(th, ks, G, wl, 20, 10, "com_z")
+    J.backward()
+    assert th.grad is not None and ks.grad is not None and G.grad is not None
+    J2, g = _gpu_grad(wl, (75.0, 0.005, 3.6), 20, 10, "com_z")
+    assert float(th.grad) == pytest.approx(g[0] * math.pi / 180.0, rel=1e-6)
+    assert float(G.grad) == pytest.approx(g[2], rel=1e-6)
