@@ -111,6 +111,43 @@ def cpu_baseline(wl, budget_s=20.0):
                       "untimed step, %.1f s" % (n, wl.nx, wl.ny, wl.nz, len(wl.capsules), el)}
 
 
+def adjoint_leg(torch, steps=2000, every=100):
+    """Forward and backward wall time of the hand-written adjoint on the
+    192x96x96 sheared channel (one 2562-node capsule, theta 75 deg,
+    kS 0.005, G 3.6): J = capsule height after 2000 steps, checkpoint every
+    100 steps."""
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import LBM_OBJ_COM_Z, sim_from_workload
+    wl = workloads.make("c4")
+    print("bench: adjoint leg on c4 (%d steps, checkpoint every %d)" % (steps, every), file=sys.stderr, flush=True)
+    plain = sim_from_workload(wl)
+    plain.step(20)
+    plain.synchronize()
+    t0 = time.perf_counter()
+    plain.step(steps)
+    plain.synchronize()
+    t_plain = time.perf_counter() - t0
+    plain.close()
+    del plain
+    torch.cuda.empty_cache()
+    sim = sim_from_workload(wl, n_slots=(steps + every - 1) // every, ring_len=every)
+    t0 = time.perf_counter()
+    J = sim.adjoint_forward(steps, every, LBM_OBJ_COM_Z, 0)
+    t_fwd = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    g = sim.adjoint_backward()
+    t_bwd = time.perf_counter() - t0
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": "192x96x96 channel, walls at y=0/95 moving -+0.01, interface z=48, one 2562-node R=10 "
+                        "capsule, theta 75 deg, kS 0.005, G 3.6",
+            "steps": steps, "checkpoint_every": every, "J_com_height": J,
+            "grad_theta_per_rad": g[0], "grad_kS": g[1], "grad_G": g[2],
+            "forward_s": round(t_plain, 4), "forward_with_checkpoints_s": round(t_fwd, 4),
+            "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -119,6 +156,7 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-fp16-leg", action="store_true")
+    ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -202,6 +240,8 @@ def main():
         s16.close()
         del s16
         torch.cuda.empty_cache()
+    if args.precision == "fp32" and not args.no_adjoint_leg:
+        out["adjoint"] = adjoint_leg(torch)
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)

@@ -68,7 +68,7 @@ enum { LBM_FP32 = 0, LBM_FP16 = 1 };
 enum { LBM_OBJ_COM_Z = 0, LBM_OBJ_TAYLOR_D = 1 };
 
 typedef struct lbm_params {
-    int32_t nx, ny, nz;     /* lattice size, each >= 4                          */
+    int32_t nx, ny, nz;     /* lattice size, each >= 4, nx*ny*nz <= 2^30        */
     int32_t precision;      /* LBM_FP32, or LBM_FP16 population storage         */
     int32_t walls;          /* 0 periodic; 1 solid rows y = 0 and y = ny - 1   */
     int32_t n_slots;        /* checkpoint slots carved from the workspace       */

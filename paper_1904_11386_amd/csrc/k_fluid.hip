@@ -53,6 +53,24 @@ __device__ __forceinline__ void block_xyz(int& bx, int& by, int& bz) {
     bz = b / (gx * gy);
 }
 
+// Lattice addressing.  Blocks are BX x BY threads with BX a multiple of the
+// wavefront, so all lanes of a wavefront share y (and z): the row offset
+// (z * ny + y) * nx is wave-uniform and goes to scalar registers, and each
+// lane adds only its x as a 32-bit byte offset (global accesses with a
+// scalar base).  The host keeps every array below 2^32 bytes per component
+// and direction.
+static_assert(BX % 64 == 0, "a wavefront must lie within one row of the block");
+__device__ __forceinline__ int uniform_ty() { return __builtin_amdgcn_readfirstlane((int)threadIdx.y); }
+
+template <typename T>
+__device__ __forceinline__ T ldx(const T* __restrict__ row, uint32_t x) {
+    return *(const T*)((const char*)row + x * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ T* ptrx(T* row, uint32_t x) {
+    return (T*)((char*)row + x * (uint32_t)sizeof(T));
+}
+
 template <typename T>
 __device__ __forceinline__ void store_pop(T* p, T v) {
 #if LBM_NT_STORE
@@ -94,6 +112,7 @@ struct Pulled {
 struct PullCtx {
     int x, xm, xp, y, ym, yp, z, zm, zp;
     int64_t node;
+    uint32_t row;
 };
 
 // Pull of direction I for both components.  enc(cx, cy, cz, a, b) gives
@@ -104,14 +123,15 @@ template <bool WALLS, bool HALF, int I, typename EncAt>
 __device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                          float ra_prev, float rb_prev, const EncAt& enc, Pulled& A, Pulled& B) {
     if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
-        const PopT<HALF> v = f[(int64_t)opp(I) * L.n + c.node];
+        const PopT<HALF> v = ldx(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
         A.f[I] = (HALF ? ra_prev * (wgt(opp(I)) + (float)v.x) : (float)v.x) + wall_term<I>(L, ra_prev);
         B.f[I] = (HALF ? rb_prev * (wgt(opp(I)) + (float)v.y) : (float)v.y) + wall_term<I>(L, rb_prev);
     } else {
         const int sx = cx(I) == 1 ? c.xm : (cx(I) == -1 ? c.xp : c.x);
         const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
         const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
-        const PopT<HALF> v = f[(int64_t)I * L.n + ((int64_t)sz * L.ny + sy) * L.nx + sx];
+        const uint32_t srow = (uint32_t)((sz * L.ny + sy) * L.nx);
+        const PopT<HALF> v = ldx(f + (int64_t)I * L.n + srow, (uint32_t)sx);
         if (HALF) {
             float ea, eb;
             enc(cx(I), cy(I), cz(I), ea, eb);
@@ -137,10 +157,90 @@ __device__ __forceinline__ void pull(const PopT<HALF>* __restrict__ f, const Lat
                                      Pulled& B) {
     PullCtx c;
     c.x = x; c.y = y; c.z = z; c.node = node;
+    c.row = (uint32_t)((z * L.ny + y) * L.nx);
     c.xm = x == 0 ? L.nx - 1 : x - 1; c.xp = x == L.nx - 1 ? 0 : x + 1;
     c.ym = y == 0 ? L.ny - 1 : y - 1; c.yp = y == L.ny - 1 ? 0 : y + 1;
     c.zm = z == 0 ? L.nz - 1 : z - 1; c.zp = z == L.nz - 1 ? 0 : z + 1;
     pull_all<WALLS, HALF>(f, L, c, ra_prev, rb_prev, enc, A, B, std::make_integer_sequence<int, Q>{});
+}
+
+// The same pull in two phases, so that a z-marching kernel can issue the
+// loads of the next plane before it computes the current one: load_raw
+// only reads the 19 vectors (addresses depend on x, y, z and, at walls, on
+// the row), decode turns them into populations.
+template <bool HALF>
+struct Raw {
+    PopT<HALF> v[Q];
+};
+
+template <bool WALLS, bool HALF, int I>
+__device__ __forceinline__ void load_raw_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
+                                             Raw<HALF>& R) {
+    if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
+        R.v[I] = ldx(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
+    } else {
+        const int sx = cx(I) == 1 ? c.xm : (cx(I) == -1 ? c.xp : c.x);
+        const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
+        const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
+        const uint32_t srow = (uint32_t)((sz * L.ny + sy) * L.nx);
+        R.v[I] = ldx(f + (int64_t)I * L.n + srow, (uint32_t)sx);
+    }
+}
+
+template <bool WALLS, bool HALF, int... Is>
+__device__ __forceinline__ void load_raw_all(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
+                                             Raw<HALF>& R, std::integer_sequence<int, Is...>) {
+    (load_raw_one<WALLS, HALF, Is>(f, L, c, R), ...);
+}
+
+__device__ __forceinline__ PullCtx pull_ctx(const Lattice& L, int64_t node, int x, int y, int z) {
+    PullCtx c;
+    c.x = x; c.y = y; c.z = z; c.node = node;
+    c.row = (uint32_t)((z * L.ny + y) * L.nx);
+    c.xm = x == 0 ? L.nx - 1 : x - 1; c.xp = x == L.nx - 1 ? 0 : x + 1;
+    c.ym = y == 0 ? L.ny - 1 : y - 1; c.yp = y == L.ny - 1 ? 0 : y + 1;
+    c.zm = z == 0 ? L.nz - 1 : z - 1; c.zp = z == L.nz - 1 ? 0 : z + 1;
+    // Fresh lane offsets for every plane: each load is then a scalar row
+    // base plus one of three 32-bit x offsets, instead of one 64-bit
+    // pointer per direction held in registers across the march.
+    asm volatile("" : "+v"(c.xm), "+v"(c.x), "+v"(c.xp));
+    return c;
+}
+
+template <bool WALLS, bool HALF>
+__device__ __forceinline__ void load_raw(const PopT<HALF>* __restrict__ f, const Lattice& L, int64_t node, int x,
+                                         int y, int z, Raw<HALF>& R) {
+    load_raw_all<WALLS, HALF>(f, L, pull_ctx(L, node, x, y, z), R, std::make_integer_sequence<int, Q>{});
+}
+
+template <bool WALLS, bool HALF, int I, typename EncAt>
+__device__ __forceinline__ void decode_one(const Lattice& L, int y, const Raw<HALF>& R, float ra_prev, float rb_prev,
+                                           const EncAt& enc, Pulled& A, Pulled& B) {
+    const PopT<HALF> v = R.v[I];
+    if (WALLS && ((cy(I) == 1 && y == 1) || (cy(I) == -1 && y == L.ny - 2))) {
+        A.f[I] = (HALF ? ra_prev * (wgt(opp(I)) + (float)v.x) : (float)v.x) + wall_term<I>(L, ra_prev);
+        B.f[I] = (HALF ? rb_prev * (wgt(opp(I)) + (float)v.y) : (float)v.y) + wall_term<I>(L, rb_prev);
+    } else if (HALF) {
+        float ea, eb;
+        enc(cx(I), cy(I), cz(I), ea, eb);
+        A.f[I] = ea * (wgt(I) + (float)v.x);
+        B.f[I] = eb * (wgt(I) + (float)v.y);
+    } else {
+        A.f[I] = (float)v.x;
+        B.f[I] = (float)v.y;
+    }
+}
+
+template <bool WALLS, bool HALF, typename EncAt, int... Is>
+__device__ __forceinline__ void decode_all(const Lattice& L, int y, const Raw<HALF>& R, float ra_prev, float rb_prev,
+                                           const EncAt& enc, Pulled& A, Pulled& B, std::integer_sequence<int, Is...>) {
+    (decode_one<WALLS, HALF, Is>(L, y, R, ra_prev, rb_prev, enc, A, B), ...);
+}
+
+template <bool WALLS, bool HALF, typename EncAt>
+__device__ __forceinline__ void decode(const Lattice& L, int y, const Raw<HALF>& R, float ra_prev, float rb_prev,
+                                       const EncAt& enc, Pulled& A, Pulled& B) {
+    decode_all<WALLS, HALF>(L, y, R, ra_prev, rb_prev, enc, A, B, std::make_integer_sequence<int, Q>{});
 }
 
 __device__ __forceinline__ float sum_pop(const Pulled& P) {
@@ -226,6 +326,88 @@ __device__ __forceinline__ void stage_plane(Ring<NC>& R, int zz, int z0, int x0,
     }
 }
 
+// The same staging without per-plane index arithmetic: stage_positions
+// fixes, once per block, the plane positions a thread stages (they do not
+// depend on z); stage_load reads one plane at those positions into
+// registers and stage_store writes them into the ring.
+struct StagePos {
+    static constexpr int SW = BX + 2, SH = BY + 2;
+    static constexpr int POS = SH * SW;
+    static constexpr int NIT = (POS + BX * BY - 1) / (BX * BY);
+    uint32_t xy[NIT];    // gy * nx + gx of the position
+    uint32_t txy[NIT];   // its tile within a plane of tiles
+};
+
+template <int NC>
+struct StageRegs {
+    float v[StagePos::NIT][NC];
+};
+
+// Position k = ly * SW + lx of the plane is also its offset within one
+// component plane of the ring.
+__device__ __forceinline__ bool stage_has(int tid, int it) { return tid + it * BX * BY < StagePos::POS; }
+
+template <bool WALLS>
+__device__ __forceinline__ StagePos stage_positions(int x0, int y0, int tid, const Lattice& L) {
+    StagePos P;
+#pragma unroll
+    for (int it = 0; it < StagePos::NIT; ++it) {
+        const int k = min(tid + it * BX * BY, StagePos::POS - 1);
+        const int ly = k / StagePos::SW, lx = k - ly * StagePos::SW;
+        const int gx = wrapi(x0 - 1 + lx, L.nx);
+        int gy = wrapi(y0 - 1 + ly, L.ny);
+        if (WALLS) {
+            // solid rows take the value of the adjacent fluid row
+            if (gy == 0) gy = 1;
+            if (gy == L.ny - 1) gy = L.ny - 2;
+        }
+        P.xy[it] = (uint32_t)(gy * L.nx + gx);
+        P.txy[it] = (uint32_t)((gy >> 3) * L.ntx + (gx >> 3));
+    }
+    return P;
+}
+
+template <bool ADD_PHI, int NC>
+__device__ __forceinline__ void stage_load(StageRegs<NC>& S, const StagePos& P, int zz, int tid,
+                                           const float* __restrict__ src, const float* scale,
+                                           const float* __restrict__ fib, const int* __restrict__ tile_flag,
+                                           const Lattice& L) {
+    const int zw = wrapi(zz, L.nz);
+    const int64_t zoff = (int64_t)zw * L.ny * L.nx;
+    const int tz = (zw >> 3) * L.nty * L.ntx;
+#pragma unroll
+    for (int it = 0; it < StagePos::NIT; ++it) {
+        if (stage_has(tid, it)) {
+            bool flag = false;
+            if (ADD_PHI) flag = tile_flag[tz + P.txy[it]] != 0;
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                float v = ldx(src + c * L.n + zoff, P.xy[it]);
+                if (scale) v *= scale[c];
+                if (ADD_PHI) {
+                    // the load goes out unconditionally so that no wait on
+                    // the flag sits between the loads in flight
+                    const float phi = ldx(fib + (3 + c) * L.n + zoff, P.xy[it]);
+                    v += flag ? phi : 0.0f;
+                }
+                S.v[it][c] = v;
+            }
+        }
+    }
+}
+
+template <int NC>
+__device__ __forceinline__ void stage_store(Ring<NC>& R, const StageRegs<NC>& S, int zz, int z0, int tid) {
+    const int slot = (zz - z0 + 1) % 3;
+#pragma unroll
+    for (int it = 0; it < StagePos::NIT; ++it) {
+        if (stage_has(tid, it)) {
+#pragma unroll
+            for (int c = 0; c < NC; ++c) (&R.v[slot][c][0][0])[tid + it * BX * BY] = S.v[it][c];
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Density pass, FP32: one thread per node.
 template <bool WALLS>
@@ -235,18 +417,19 @@ __global__ __launch_bounds__(256) void k_density(const pf2* __restrict__ fin,
     int bx, by, bz;
     block_xyz(bx, by, bz);
     const int x = bx * BX + threadIdx.x;
-    const int y = by * BY + threadIdx.y;
+    const int y = by * BY + uniform_ty();
     const int z = bz;
     if (x >= L.nx || y >= L.ny) return;
     if (WALLS && (y == 0 || y == L.ny - 1)) return;
     const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+    const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx);
     auto none = [](int, int, int, float&, float&) {};
     Pulled A, B;
-    const float rpa = WALLS ? rho_prev[node] : 0.0f;
-    const float rpb = WALLS ? rho_prev[L.n + node] : 0.0f;
+    const float rpa = WALLS ? ldx(rho_prev + row, (uint32_t)x) : 0.0f;
+    const float rpb = WALLS ? ldx(rho_prev + L.n + row, (uint32_t)x) : 0.0f;
     pull<WALLS, false>(fin, L, node, x, y, z, rpa, rpb, none, A, B);
-    rho_out[node] = sum_pop(A);
-    rho_out[L.n + node] = sum_pop(B);
+    *ptrx(rho_out + row, (uint32_t)x) = sum_pop(A);
+    *ptrx(rho_out + L.n + row, (uint32_t)x) = sum_pop(B);
 }
 
 // Density pass, FP16: z-marching column with the decode densities
@@ -259,22 +442,30 @@ __global__ __launch_bounds__(256) void k_density_half(const ph2* __restrict__ fi
                                                       Lattice L) {
     __shared__ Ring<2> ring;
     __shared__ double red[2][BX * BY];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
     block_xyz(bx, by, bz);
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
-    const int z1 = min(z0 + ZC, L.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
+    const int z1 = min(z0 + L.zc, L.nz);
     const float cp[2] = {cscale[2 * par_prev], cscale[2 * par_prev + 1]};
-    stage_plane<WALLS, false, 2>(ring, z0 - 1, z0, x0, y0, tid, rho_prev, cp, nullptr, nullptr, L);
-    stage_plane<WALLS, false, 2>(ring, z0, z0, x0, y0, tid, rho_prev, cp, nullptr, nullptr, L);
+    const StagePos P = stage_positions<WALLS>(x0, y0, tid, L);
+    StageRegs<2> st;
+    stage_load<false, 2>(st, P, z0 - 1, tid, rho_prev, cp, nullptr, nullptr, L);
+    stage_store<2>(ring, st, z0 - 1, z0, tid);
+    stage_load<false, 2>(st, P, z0, tid, rho_prev, cp, nullptr, nullptr, L);
+    stage_store<2>(ring, st, z0, z0, tid);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
     double acc[2] = {0.0, 0.0};
+    Raw<true> rcur;
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        stage_plane<WALLS, false, 2>(ring, z + 1, z0, x0, y0, tid, rho_prev, cp, nullptr, nullptr, L);
+        stage_load<false, 2>(st, P, z + 1, tid, rho_prev, cp, nullptr, nullptr, L);
+        stage_store<2>(ring, st, z + 1, z0, tid);
         __syncthreads();
+        if (active) load_raw<WALLS, true>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
         if (active) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx);
             const int s0 = (z - z0 + 1) % 3;
             auto enc = [&](int ex, int ey, int ez, float& a, float& b) {
                 const int sl = (s0 - ez + 3) % 3;
@@ -282,11 +473,10 @@ __global__ __launch_bounds__(256) void k_density_half(const ph2* __restrict__ fi
                 b = ring.v[sl][1][ty + 1 - ey][tx + 1 - ex];
             };
             Pulled A, B;
-            pull<WALLS, true>(fin, L, node, x, y, z, ring.v[s0][0][ty + 1][tx + 1], ring.v[s0][1][ty + 1][tx + 1],
-                              enc, A, B);
+            decode<WALLS, true>(L, y, rcur, ring.v[s0][0][ty + 1][tx + 1], ring.v[s0][1][ty + 1][tx + 1], enc, A, B);
             const float ra = sum_pop(A), rb = sum_pop(B);
-            rho_out[node] = ra;
-            rho_out[L.n + node] = rb;
+            *ptrx(rho_out + row, (uint32_t)x) = ra;
+            *ptrx(rho_out + L.n + row, (uint32_t)x) = rb;
             acc[0] += (double)ra;
             acc[1] += (double)rb;
         }
@@ -352,12 +542,12 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
     constexpr int NE = HALF ? 2 : 1;
     __shared__ Ring<2> sp;                       // psi + phi at time n
     __shared__ Ring<NE> se;                      // decode densities rho_enc^{n-1} (FP16)
-    const int tx = threadIdx.x, ty = threadIdx.y;
+    const int tx = threadIdx.x, ty = uniform_ty();
     const int tid = ty * BX + tx;
     int bx, by, bz;
     block_xyz(bx, by, bz);
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
-    const int z1 = min(z0 + ZC, L.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
+    const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
     float cpv[2] = {1.0f, 1.0f}, ccu[2] = {1.0f, 1.0f};
     if (HALF) {
@@ -374,7 +564,7 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
     if (IBM) {
         const int tx0 = wrapi(x0 - 1, L.nx) >> 3, ntx_b = (BX + 2 + 7) / 8 + 1;
         const int ty0 = wrapi(y0 - 1, L.ny) >> 3, nty_b = (BY + 2 + 7) / 8 + 1;
-        const int tz0 = wrapi(z0 - 1, L.nz) >> 3, ntz_b = (ZC + 2 + 7) / 8 + 1;
+        const int tz0 = wrapi(z0 - 1, L.nz) >> 3, ntz_b = (L.zc + 2 + 7) / 8 + 1;
         bool hit = false;
         for (int k = tid; k < ntx_b * nty_b * ntz_b; k += BX * BY) {
             const int i = k % ntx_b, j = (k / ntx_b) % nty_b, l = k / (ntx_b * nty_b);
@@ -383,23 +573,36 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
         }
         near_ibm = __syncthreads_or(hit) != 0;
     }
-    auto stage = [&](int zz) {
+    const StagePos P = stage_positions<WALLS>(x0, y0, tid, L);
+    StageRegs<2> np;
+    StageRegs<NE> ne;
+    auto load_plane = [&](int zz) {
         if (IBM && near_ibm)
-            stage_plane<WALLS, true, 2>(sp, zz, z0, x0, y0, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
+            stage_load<true, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
         else
-            stage_plane<WALLS, false, 2>(sp, zz, z0, x0, y0, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
-        if (HALF) stage_plane<WALLS, false, NE>(se, zz, z0, x0, y0, tid, rho_p, cpv, nullptr, nullptr, L);
+            stage_load<false, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
+        if (HALF) stage_load<false, NE>(ne, P, zz, tid, rho_p, cpv, nullptr, nullptr, L);
+    };
+    auto store_plane = [&](int zz) {
+        stage_store<2>(sp, np, zz, z0, tid);
+        if (HALF) stage_store<NE>(se, ne, zz, z0, tid);
     };
 
-    stage(z0 - 1);
-    stage(z0);
+    load_plane(z0 - 1);
+    store_plane(z0 - 1);
+    load_plane(z0);
+    store_plane(z0);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
+    Raw<HALF> rcur;
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        stage(z + 1);
+        load_plane(z + 1);
+        store_plane(z + 1);
         __syncthreads();
+        if (active) load_raw<WALLS, HALF>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
         if (active) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx), xo = (uint32_t)x;
             const int s0 = (z - z0 + 1) % 3;
             Pulled A, B;
             if constexpr (HALF) {
@@ -408,8 +611,7 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                     a = se.v[sl][0][ty + 1 - ey][tx + 1 - ex];
                     b = se.v[sl][NE - 1][ty + 1 - ey][tx + 1 - ex];
                 };
-                pull<WALLS, true>(fin, L, node, x, y, z, se.v[s0][0][ty + 1][tx + 1], se.v[s0][NE - 1][ty + 1][tx + 1],
-                                  enc, A, B);
+                decode<WALLS, true>(L, y, rcur, se.v[s0][0][ty + 1][tx + 1], se.v[s0][NE - 1][ty + 1][tx + 1], enc, A, B);
                 // FP64 mass compensation of this step
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
@@ -418,9 +620,9 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                 }
             } else {
                 auto none = [](int, int, int, float&, float&) {};
-                const float rpa = WALLS ? rho_p[node] : 0.0f;
-                const float rpb = WALLS ? rho_p[N + node] : 0.0f;
-                pull<WALLS, false>(fin, L, node, x, y, z, rpa, rpb, none, A, B);
+                const float rpa = WALLS ? ldx(rho_p + row, xo) : 0.0f;
+                const float rpb = WALLS ? ldx(rho_p + N + row, xo) : 0.0f;
+                decode<WALLS, false>(L, y, rcur, rpa, rpb, none, A, B);
             }
             const float ra = sum_pop(A), rb = sum_pop(B);
             float jax, jay, jaz, jbx, jby, jbz;
@@ -456,7 +658,7 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                     const float fa = ra / rsum, fb = rb / rsum;
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
-                        const float Fi = fib[d * N + node];
+                        const float Fi = ldx(fib + d * N + row, xo);
                         Fa[d] += fa * Fi;
                         Fb[d] += fb * Fi;
                     }
@@ -470,9 +672,9 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
             const float upz = (jaz * wa + jbz * wb) * den;
             if (MACRO || (IBM && flagged)) {
                 const float ir = 1.0f / rsum;
-                u_out[node] = (jax + jbx + 0.5f * (Fa[0] + Fb[0])) * ir;
-                u_out[N + node] = (jay + jby + 0.5f * (Fa[1] + Fb[1])) * ir;
-                u_out[2 * N + node] = (jaz + jbz + 0.5f * (Fa[2] + Fb[2])) * ir;
+                *ptrx(u_out + row, xo) = (jax + jbx + 0.5f * (Fa[0] + Fb[0])) * ir;
+                *ptrx(u_out + N + row, xo) = (jay + jby + 0.5f * (Fa[1] + Fb[1])) * ir;
+                *ptrx(u_out + 2 * N + row, xo) = (jaz + jbz + 0.5f * (Fa[2] + Fb[2])) * ir;
             }
             if (!MACRO) {
                 float ux[2], uy[2], uz[2], base[2], inv[2], rest[2];
@@ -487,10 +689,10 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                     base[c] = r2[c] * (1.0f - 1.5f * (ux[c] * ux[c] + uy[c] * uy[c] + uz[c] * uz[c]));
                     // FP16: encode relative to this node's compensated density,
                     // bit-identical to what the next step's decoder stages
-                    inv[c] = HALF ? 1.0f / (ccu[c] * rho_n[c * N + node]) : 1.0f;
+                    inv[c] = HALF ? 1.0f / (ccu[c] * ldx(rho_n + c * N + row, xo)) : 1.0f;
                     rest[c] = r2[c];
                 }
-                PopT<HALF>* fo = fout + node;
+                PopT<HALF>* fo = fout + row;
 #pragma unroll
                 for (int i = 1; i < Q; ++i) {
                     float fs[2];
@@ -503,13 +705,13 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                         rest[c] -= fs[c];
                         if (HALF) fs[c] = fs[c] * inv[c] - wgt(i);
                     }
-                    store_pop(fo + (int64_t)i * N, pack<HALF>(fs[0], fs[1]));
+                    store_pop(ptrx(fo + (int64_t)i * N, xo), pack<HALF>(fs[0], fs[1]));
                 }
                 // rest populations close the node's mass
                 if (HALF)
-                    store_pop(fo, pack<HALF>(rest[0] * inv[0] - wgt(0), rest[1] * inv[1] - wgt(0)));
+                    store_pop(ptrx(fo, xo), pack<HALF>(rest[0] * inv[0] - wgt(0), rest[1] * inv[1] - wgt(0)));
                 else
-                    store_pop(fo, pack<HALF>(rest[0], rest[1]));
+                    store_pop(ptrx(fo, xo), pack<HALF>(rest[0], rest[1]));
             }
         } else if (MACRO && x < L.nx && y < L.ny) {
             const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
@@ -597,21 +799,21 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
                                                      const int* __restrict__ tile_flag, const pf2* __restrict__ lam_in,
                                                      const float* __restrict__ lam_u, float* __restrict__ lam_rho,
                                                      float* __restrict__ lam_j, float* __restrict__ lam_S,
-                                                     float* __restrict__ lam_Fib, double* __restrict__ grads,
-                                                     Lattice L) {
+                                                     float* __restrict__ lam_Fib, float* __restrict__ u_out,
+                                                     double* __restrict__ grads, Lattice L) {
     __shared__ Ring<2> sp;
     __shared__ double red[BX * BY];
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
     block_xyz(bx, by, bz);
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
-    const int z1 = min(z0 + ZC, L.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
+    const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
     bool near_ibm = false;
     if (IBM) {
         const int tx0 = wrapi(x0 - 1, L.nx) >> 3, ntx_b = (BX + 2 + 7) / 8 + 1;
         const int ty0 = wrapi(y0 - 1, L.ny) >> 3, nty_b = (BY + 2 + 7) / 8 + 1;
-        const int tz0 = wrapi(z0 - 1, L.nz) >> 3, ntz_b = (ZC + 2 + 7) / 8 + 1;
+        const int tz0 = wrapi(z0 - 1, L.nz) >> 3, ntz_b = (L.zc + 2 + 7) / 8 + 1;
         bool hit = false;
         for (int k = tid; k < ntx_b * nty_b * ntz_b; k += BX * BY) {
             const int i = k % ntx_b, j = (k / ntx_b) % nty_b, l = k / (ntx_b * nty_b);
@@ -681,10 +883,14 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
                 ue[0][d] = up[d] + L.tau[0] * Fa[d] / ra;
                 ue[1][d] = up[d] + L.tau[1] * Fb[d] / rb;
             }
-            // adjoint of u = (sum j + F/2) / rho
+            // adjoint of u = (sum j + F/2) / rho; u itself is left where the
+            // membrane adjoint reads it
             float lu[3] = {0.f, 0.f, 0.f};
             if (flagged)
-                for (int d = 0; d < 3; ++d) lu[d] = lam_u[d * N + node];
+                for (int d = 0; d < 3; ++d) {
+                    lu[d] = lam_u[d * N + node];
+                    u_out[d * N + node] = u[d];
+                }
             float lj[2][3], lF[2][3], lr[2];
             const float luu = (lu[0] * u[0] + lu[1] * u[1] + lu[2] * u[2]) * ir;
             for (int c = 0; c < 2; ++c) {
@@ -776,11 +982,11 @@ template <bool WALLS>
 __global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ lam_S, float* __restrict__ lam_rho,
                                                     Lattice L) {
     __shared__ Ring<6> sr;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
     block_xyz(bx, by, bz);
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
-    const int z1 = min(z0 + ZC, L.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
+    const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
     stage_plane<false, false, 6>(sr, z0 - 1, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
     stage_plane<false, false, 6>(sr, z0, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
@@ -853,11 +1059,11 @@ __global__ __launch_bounds__(256) void k_adj_push(const pf2* __restrict__ lam_in
                                                   const float* __restrict__ lam_j, pf2* __restrict__ lam_out,
                                                   Lattice L) {
     __shared__ Ring<8> rj;
-    const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * BX + tx;
+    const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
     block_xyz(bx, by, bz);
-    const int x0 = bx * BX, y0 = by * BY, z0 = bz * ZC;
-    const int z1 = min(z0 + ZC, L.nz);
+    const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
+    const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
     stage_lrj(rj, z0 - 1, z0, x0, y0, tid, lam_rho, lam_j, L);
     stage_lrj(rj, z0, z0, x0, y0, tid, lam_rho, lam_j, L);
@@ -933,12 +1139,12 @@ void launch_init_rest(const Lattice& L, void* f, const float* rhoA, const float*
 }
 
 int64_t density_blocks(const Lattice& L, bool half) {
-    return (int64_t)((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) * (half ? (L.nz + ZC - 1) / ZC : L.nz);
+    return (int64_t)((L.nx + BX - 1) / BX) * ((L.ny + BY - 1) / BY) * (half ? (L.nz + L.zc - 1) / L.zc : L.nz);
 }
 
 void launch_density(const Lattice& L, const void* fin, const float* rho_prev, float* rho_out, bool half,
                     const float* cscale, int par_prev, double* partial, hipStream_t s) {
-    const dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, half ? (L.nz + ZC - 1) / ZC : L.nz);
+    const dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, half ? (L.nz + L.zc - 1) / L.zc : L.nz);
     const dim3 block(BX, BY);
     if (half) {
         if (L.walls)
@@ -965,7 +1171,7 @@ template <bool W, bool I, bool M, bool H>
 static void launch_collide_t(const Lattice& L, const void* fin, void* fout, const float* rho_n,
                              const float* rho_prev, const float* fib, const int* tile_flag, float* u,
                              const float* cscale, int par_prev, int par_cur, hipStream_t s) {
-    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC);
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc);
     dim3 block(BX, BY);
     hipLaunchKernelGGL((k_collide<W, I, M, H>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout, rho_n,
                        rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
@@ -1003,18 +1209,18 @@ void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const f
 
 void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
                         const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
-                        float* lam_S, float* lam_Fib, double* grads, hipStream_t s) {
-    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC), block(BX, BY);
+                        float* lam_S, float* lam_Fib, float* u_out, double* grads, hipStream_t s) {
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc), block(BX, BY);
     if (L.walls)
         hipLaunchKernelGGL((k_adj_collide<true, true>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
-                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, grads, L);
+                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, u_out, grads, L);
     else
         hipLaunchKernelGGL((k_adj_collide<false, true>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
-                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, grads, L);
+                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, u_out, grads, L);
 }
 
 void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hipStream_t s) {
-    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC), block(BX, BY);
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc), block(BX, BY);
     if (L.walls)
         hipLaunchKernelGGL(k_adj_gather<true>, grid, block, 0, s, lam_S, lam_rho, L);
     else
@@ -1023,7 +1229,7 @@ void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hip
 
 void launch_adj_push(const Lattice& L, const void* lam_in, const float* lam_rho, const float* lam_j, void* lam_out,
                      hipStream_t s) {
-    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + ZC - 1) / ZC), block(BX, BY);
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc), block(BX, BY);
     if (L.walls)
         hipLaunchKernelGGL(k_adj_push<true>, grid, block, 0, s, (const pf2*)lam_in, lam_rho, lam_j, (pf2*)lam_out, L);
     else

@@ -130,10 +130,20 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     return l;
 }
 
+// z planes per lattice block.  A longer march amortises the two halo planes
+// of the ring; the FP16 form gains from it when the grid still holds at
+// least 8192 blocks (32 per compute unit), the FP32 form does not.
+int zc_for(const lbm_params* p) {
+    const int64_t cols = (int64_t)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY);
+    if (p->precision == LBM_FP16 && cols * ((p->nz + 2 * ZC - 1) / (2 * ZC)) >= 8192) return 2 * ZC;
+    return ZC;
+}
+
 std::string validate(const lbm_params* p) {
     if (!p) return "params is NULL";
     if (p->nx < 4 || p->ny < 4 || p->nz < 4) return "lattice sizes must be >= 4";
-    if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 34)) return "lattice too large";
+    // kernels address one component of one direction with 32-bit offsets
+    if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 30)) return "lattice too large (more than 2^30 nodes)";
     if (p->precision != LBM_FP32 && p->precision != LBM_FP16) return "precision must be LBM_FP32 or LBM_FP16";
     if (p->walls != 0 && p->walls != 1) return "walls must be 0 or 1";
     if (p->walls && p->ny < 5) return "walls need ny >= 5";
@@ -262,6 +272,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     L.ntx = (p->nx + TILE - 1) / TILE; L.nty = (p->ny + TILE - 1) / TILE; L.ntz = (p->nz + TILE - 1) / TILE;
     L.nbx = (p->nx + BIN - 1) / BIN; L.nby = (p->ny + BIN - 1) / BIN; L.nbz = (p->nz + BIN - 1) / BIN;
     L.n = N;
+    L.zc = zc_for(p);
     L.walls = p->walls;
     L.G = (float)p->G;
     for (int k = 0; k < 2; ++k) { L.tau[k] = (float)p->tau[k]; L.omega[k] = (float)(1.0 / p->tau[k]); }
@@ -522,8 +533,8 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_CLEAR);
     if (ibm) launch_clear_tiles(L, d, par ^ 1, par, ncap, s);
     mark(LBM_K_DENSITY);
-    launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
-    if (half) launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
+    if (fout) launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
+    if (half && fout) launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
     mark(LBM_K_VOLUME);
     if (ibm) launch_cap_volume(d, c->n_faces, s);
     mark(LBM_K_FACES);
@@ -537,6 +548,11 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_SPREAD);
     if (ibm) launch_spread(L, d, par, s);
     mark(LBM_K_COLLIDE);
+    if (!fout) {
+        // the adjoint's recompute stops here: intermediates of the step only
+        c->flip ^= 1;
+        return;
+    }
     launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ibm, false, half, d.cscale, nxt, cur, s);
     mark(LBM_K_INTERP);
     if (ibm && advect) launch_interp_advect(L, d, c->n_nodes, s);
@@ -1050,12 +1066,15 @@ int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
             const int par = c->flip;
             const void* fin = ek + c->lay.ring_f;
             const float* rho_p = (const float*)(ek + c->lay.ring_rho);
-            float* rho_n = d.rho[0];
-            // intermediates of step k: densities, node forces, spread fields, u
-            enqueue_core(c, fin, d.f[0], rho_n, rho_p, false, nullptr);
+            // the densities of step k are the next ring entry's previous
+            // densities; only the segment's last step computes them again
+            float* rho_n = k + 1 < len ? (float*)(ring_at(c, k + 1) + c->lay.ring_rho) : d.rho[0];
+            if (k + 1 >= len) launch_density(L, fin, rho_p, rho_n, false, d.cscale, 0, d.dpart, s);
+            // membrane intermediates of step k: node forces, bins, spread fields
+            enqueue_core(c, fin, nullptr, rho_n, rho_p, false, nullptr);
             launch_spread_vec(L, d, par, d.lam_X, d.lam_u, 0, s);
             launch_adj_collide(L, fin, rho_n, rho_p, d.fib, d.tile_flag, d.lam[p], d.lam_u, d.lam_rho, d.lam_j,
-                               d.lam_S, d.lam_Fib, d.grads, s);
+                               d.lam_S, d.lam_Fib, d.u, d.grads, s);
             launch_adj_nodes(L, d, rho_n, c->n_nodes, s);
             launch_adj_membrane(d, c->n_nodes, c->n_faces, s);
             launch_spread_vec(L, d, par, d.lam_q, d.lam_S, 1, s);

@@ -48,13 +48,14 @@ constexpr int BOX = BIN + 3;   // spreading box edge: stencil reach of one bin's
 #endif
 constexpr int BX = LBM_BX;     // lattice blocks: x extent (a multiple of the wavefront)
 constexpr int BY = LBM_BY;     // lattice blocks: y extent
-constexpr int ZC = LBM_ZC;     // fused collide block: z planes marched per block
+constexpr int ZC = LBM_ZC;     // lattice blocks: fewest z planes marched per block
 constexpr int NXCD = 8;        // accelerator dies; workgroups are dealt round-robin to them
 
 struct Lattice {
     int nx, ny, nz;
     int ntx, nty, ntz;     // tile counts (TILE)
     int nbx, nby, nbz;     // bin counts (BIN)
+    int zc;                // z planes marched per lattice block (a multiple of ZC)
     int64_t n;             // nx*ny*nz
     int walls;
     float G;
@@ -172,7 +173,7 @@ void launch_adj_membrane(const Dev& d, int n_nodes, int n_faces, hipStream_t s);
 // adjoint (k_fluid.hip)
 void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
                         const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
-                        float* lam_S, float* lam_Fib, double* grads, hipStream_t s);
+                        float* lam_S, float* lam_Fib, float* u_out, double* grads, hipStream_t s);
 void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hipStream_t s);
 void launch_adj_push(const Lattice& L, const void* lam_in, const float* lam_rho, const float* lam_j, void* lam_out,
                      hipStream_t s);

@@ -30,6 +30,7 @@ Workloads (sizes as stated, seeds numpy.random.default_rng(1904 + k)):
 
 from __future__ import annotations
 
+import functools
 import math
 from dataclasses import dataclass, field
 from typing import List, Optional
@@ -78,12 +79,22 @@ def icosahedron():
     return v, faces
 
 
+@functools.lru_cache(maxsize=None)
+def _unit_icosphere(freq: int):
+    return _icosphere_build(freq)
+
+
 def icosphere(freq: int, radius: float):
     """Geodesic icosphere of frequency freq (a power of two) and given
     radius, centred at the origin.  Returns (xyz float64 [N,3] snapped to the
     2^-20 grid, tri int32 [F,3] outward counter-clockwise)."""
     if freq < 1 or (freq & (freq - 1)) != 0:
         raise ValueError("frequency must be a power of two")
+    unit, tri = _unit_icosphere(freq)
+    return _snap(unit * float(radius)), tri.copy()
+
+
+def _icosphere_build(freq: int):
     v, f = icosahedron()
     v = v / np.linalg.norm(v, axis=1, keepdims=True)
     verts = [tuple(x) for x in v]
@@ -107,11 +118,11 @@ def icosphere(freq: int, radius: float):
             nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
         faces = nf
         level *= 2
-    xyz = np.array(verts, dtype=np.float64) * float(radius)
+    xyz = np.array(verts, dtype=np.float64)
     tri = np.array(faces, dtype=np.int32)
     assert xyz.shape[0] == 10 * freq * freq + 2
     assert tri.shape[0] == 20 * freq * freq
-    return _snap(xyz), tri
+    return xyz, tri
 
 
 # Volume-penalty modulus of the workloads.  The paper uses 20 with inertial
