@@ -19,9 +19,9 @@
 //   k_bin_scan      exclusive scan of the home-tile counts
 //   k_bin_scatter   counting-sort scatter of node ids into tile bins
 //   k_spread        one workgroup per occupied bin: accumulate F_b delta and
-//                   the virtual density in a 7^3 LDS box (LDS atomics,
-//                   one lane per stencil point), then flush non-zero cells
-//                   to HBM with global atomics
+//                   the virtual density in 7^3 LDS boxes (one per wavefront,
+//                   one lane per stencil point, no LDS atomics), then flush
+//                   the non-zero cells to HBM with global atomics
 //   k_interp_advect one wavefront per node: U_b = sum u delta, X += U_b
 #include "lbm_internal.h"
 
@@ -36,6 +36,20 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
     return v < 0 ? v + n : v;
 }
+
+// Periodic wrap without a division, for v in [-n, 3n) (stencil and box
+// offsets from an already wrapped base; every lattice edge is >= 4).
+__device__ __forceinline__ int wrap3(int v, int n) {
+    v += v < 0 ? n : 0;
+    v -= v >= n ? n : 0;
+    v -= v >= n ? n : 0;
+    return v;
+}
+
+// The index of this lane's wavefront within the block, as a wave-uniform
+// (scalar) value: everything derived from it (node ids, positions) then
+// lives in scalar registers and is read with scalar loads.
+__device__ __forceinline__ int wave_id() { return __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)); }
 
 // Peskin 4-point kernel
 __device__ __forceinline__ float peskin(float r) {
@@ -75,6 +89,13 @@ __device__ __forceinline__ NodePos node_pos(const Dev& d, int b) {
         p.r[k] = o - fo;
     }
     return p;
+}
+
+// floor(X) wrapped into the lattice
+__device__ __forceinline__ void wrapped_floor(const Lattice& L, const NodePos& p, int w[3]) {
+    w[0] = wrapi(p.fl[0], L.nx);
+    w[1] = wrapi(p.fl[1], L.ny);
+    w[2] = wrapi(p.fl[2], L.nz);
 }
 
 __device__ __forceinline__ int tile_of(const Lattice& L, int x, int y, int z) {
@@ -263,9 +284,10 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
     constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
     __shared__ float cube[4][CB * CB * CB];
     const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int wv = wave_id();
+    const int b = blockIdx.x * 4 + wv;
     if (b >= n_nodes) return;                   // whole wavefront; no block barrier below
-    float* cb = cube[threadIdx.x >> 6];
+    float* cb = cube[wv];
     // corner forces of the incident triangles
     float gx = 0.f, gy = 0.f, gz = 0.f;
     const int beg = d.csr_ptr[b], end = d.csr_ptr[b + 1];
@@ -276,6 +298,8 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         gz += d.face_F[3 * (int64_t)e + 2];
     }
     const NodePos p = node_pos(d, b);
+    int pw[3];
+    wrapped_floor(L, p, pw);
     const float wet = d.node_wet[b];
     if (wet != 0.0f) {
         // reaction of the virtual density on the node:
@@ -284,11 +308,16 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         const float* rc = rho_n + (int64_t)np * L.n;
         const float sc = cs ? cs[np] : 1.0f;      // FP16 form: mass compensation of this step
         // the wavefront stages psi^np on the 6^3 cube floor(X)-2 .. floor(X)+3
-        for (int j = lane; j < CB * CB * CB; j += 64) {
-            const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
-            int gy = wrapi(p.fl[1] - 2 + qy, L.ny);
-            if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
-            cb[j] = sc * rc[((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx + wrapi(p.fl[0] - 2 + qx, L.nx)];
+#pragma unroll
+        for (int it = 0; it < (CB * CB * CB + 63) / 64; ++it) {
+            const int j = lane + 64 * it;
+            if (j < CB * CB * CB) {
+                const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
+                int gy = wrap3(pw[1] - 2 + qy, L.ny);
+                if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
+                const int gz = wrap3(pw[2] - 2 + qz, L.nz), gx = wrap3(pw[0] - 2 + qx, L.nx);
+                cb[j] = sc * rc[(uint32_t)((gz * L.ny + gy) * L.nx + gx)];
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -320,8 +349,7 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         d.node_F[3 * b + 1] = gy;
         d.node_F[3 * b + 2] = gz;
     } else if (lane == 1) {
-        const int wx = wrapi(p.fl[0], L.nx), wy = wrapi(p.fl[1], L.ny), wz = wrapi(p.fl[2], L.nz);
-        const int t = bin_of(L, wx, wy, wz);
+        const int t = bin_of(L, pw[0], pw[1], pw[2]);
         const int rank = atomicAdd(&d.tile_count[t], 1);
         d.node_tile[b] = t;
         d.node_rank[b] = rank;
@@ -335,10 +363,11 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         bool ok = true;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
-            const int t0 = wrapi(p.fl[a] - 1, nn[a]) >> 3;
+            const int t0 = wrap3(pw[a] - 1, nn[a]) >> 3;
             int t1 = -1;
+#pragma unroll
             for (int k = 1; k < 4; ++k) {
-                const int tk = wrapi(p.fl[a] - 1 + k, nn[a]) >> 3;
+                const int tk = wrap3(pw[a] - 1 + k, nn[a]) >> 3;
                 if (tk != t0) t1 = tk;
             }
             tt[a] = sel[a] ? t1 : t0;
@@ -346,7 +375,10 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         }
         if (ok) {
             const int t2 = (tt[2] * L.nty + tt[1]) * L.ntx + tt[0];
-            if (atomicExch(&d.tile_flag[t2], 1) == 0)
+            // most tiles are already marked by another node: a plain read
+            // first keeps the atomics to the few first visits (flags are all
+            // clear when the kernel starts, so a set flag is never stale)
+            if (d.tile_flag[t2] == 0 && atomicExch(&d.tile_flag[t2], 1) == 0)
                 d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t2;
         }
     }
@@ -387,39 +419,69 @@ constexpr int SPREAD_GRID = 2048;
 
 __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
     constexpr int B3 = BOX * BOX * BOX;
-    __shared__ float box[5][B3];
+    constexpr int CH = 128;                     // nodes staged per round
+    // one box per wavefront: a wavefront adds its nodes one after another
+    // with plain LDS read-modify-writes (the 64 lanes of one node hit
+    // distinct cells), which is far cheaper than LDS float atomics; the
+    // flush sums the four boxes
+    __shared__ float box[4][5][B3];
+    // the bin's nodes, staged by one thread each: per-axis delta weights,
+    // force, virtual-density weight, the box cell of the stencil origin and
+    // the field the virtual density goes to
+    __shared__ float sw[12][CH];
+    __shared__ float sf[4][CH];
+    __shared__ int scell[CH], sfield[CH];
     const int nh = d.counters[CNT_HOME + par];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
     const int64_t N = L.n;
+    float* mybox = &box[wave][0][0];
     for (int e = blockIdx.x; e < nh; e += gridDim.x) {
         const int t = d.home[par][e];
         const int start = d.home_start[e], cnt = d.tile_count[t];
+        if (cnt == 0) continue;                 // (a home bin holds a node; block-uniform)
         const int ox = (t % L.nbx) * BIN, oy = ((t / L.nbx) % L.nby) * BIN, oz = (t / (L.nbx * L.nby)) * BIN;
-        for (int k = threadIdx.x; k < 5 * B3; k += 256) (&box[0][0])[k] = 0.0f;
-        __syncthreads();
-        for (int j = wave; j < cnt; j += 4) {
-            const int b = d.sorted[start + j];
-            const NodePos p = node_pos(d, b);
-            const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
-            const int ix = wrapi(p.fl[0], L.nx) - ox + kx;
-            const int iy = wrapi(p.fl[1], L.ny) - oy + ky;
-            const int iz = wrapi(p.fl[2], L.nz) - oz + kz;
-            const int cell = (iz * BOX + iy) * BOX + ix;
-            atomicAdd(&box[0][cell], w * d.node_F[3 * b + 0]);
-            atomicAdd(&box[1][cell], w * d.node_F[3 * b + 1]);
-            atomicAdd(&box[2][cell], w * d.node_F[3 * b + 2]);
-            const float wet = d.node_wet[b];
-            if (wet != 0.0f) atomicAdd(&box[3 + d.caps[d.node_cap[b]].pref][cell], w * wet);
+        for (int k = threadIdx.x; k < 4 * 5 * B3; k += 256) (&box[0][0][0])[k] = 0.0f;
+        // (the barrier after staging also orders the zeroing above)
+        for (int c0 = 0; c0 < cnt; c0 += CH) {
+            const int m = min(cnt - c0, CH);
+            if ((int)threadIdx.x < m) {
+                const int b = d.sorted[start + c0 + threadIdx.x];
+                const NodePos p = node_pos(d, b);
+                int pw[3];
+                wrapped_floor(L, p, pw);
+#pragma unroll
+                for (int a = 0; a < 3; ++a)
+#pragma unroll
+                    for (int k = 0; k < 4; ++k) sw[4 * a + k][threadIdx.x] = peskin(p.r[a] + 1.0f - k);
+                sf[0][threadIdx.x] = d.node_F[3 * b + 0];
+                sf[1][threadIdx.x] = d.node_F[3 * b + 1];
+                sf[2][threadIdx.x] = d.node_F[3 * b + 2];
+                const float wet = d.node_wet[b];
+                sf[3][threadIdx.x] = wet;
+                sfield[threadIdx.x] = wet != 0.0f ? 3 + d.caps[d.node_cap[b]].pref : -1;
+                scell[threadIdx.x] = ((pw[2] - oz) * BOX + (pw[1] - oy)) * BOX + (pw[0] - ox);
+            }
+            __syncthreads();
+            for (int j = wave; j < m; j += 4) {
+                const float w = sw[kx][j] * sw[4 + ky][j] * sw[8 + kz][j];
+                const int cell = scell[j] + (kz * BOX + ky) * BOX + kx;
+                mybox[0 * B3 + cell] += w * sf[0][j];
+                mybox[1 * B3 + cell] += w * sf[1][j];
+                mybox[2 * B3 + cell] += w * sf[2][j];
+                const int fld = sfield[j];
+                if (fld >= 0) mybox[fld * B3 + cell] += w * sf[3][j];
+            }
+            __syncthreads();
         }
-        __syncthreads();
         for (int k = threadIdx.x; k < 5 * B3; k += 256) {
-            const float v = (&box[0][0])[k];
+            const float* bx = &box[0][0][0];
+            const float v = (bx[k] + bx[5 * B3 + k]) + (bx[10 * B3 + k] + bx[15 * B3 + k]);
             if (v != 0.0f) {
                 const int f = k / B3, cell = k - f * B3;
                 const int iz = cell / (BOX * BOX), iy = (cell / BOX) % BOX, ix = cell % BOX;
-                const int gx = wrapi(ox - 1 + ix, L.nx), gy = wrapi(oy - 1 + iy, L.ny), gz = wrapi(oz - 1 + iz, L.nz);
-                unsafeAtomicAdd(&d.fib[f * N + ((int64_t)gz * L.ny + gy) * L.nx + gx], v);
+                const int gx = wrap3(ox - 1 + ix, L.nx), gy = wrap3(oy - 1 + iy, L.ny), gz = wrap3(oz - 1 + iz, L.nz);
+                unsafeAtomicAdd(&d.fib[f * N + (uint32_t)((gz * L.ny + gy) * L.nx + gx)], v);
             }
         }
         __syncthreads();
@@ -428,13 +490,15 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
 
 __global__ __launch_bounds__(256) void k_interp_advect(Lattice L, Dev d, int n_nodes) {
     const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int b = blockIdx.x * 4 + wave_id();
     if (b >= n_nodes) return;
     const NodePos p = node_pos(d, b);
+    int pw[3];
+    wrapped_floor(L, p, pw);
     const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
     const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
-    const int64_t node = ((int64_t)wrapi(p.fl[2] - 1 + kz, L.nz) * L.ny + wrapi(p.fl[1] - 1 + ky, L.ny)) * L.nx
-                       + wrapi(p.fl[0] - 1 + kx, L.nx);
+    const uint32_t node = (uint32_t)((wrap3(pw[2] - 1 + kz, L.nz) * L.ny + wrap3(pw[1] - 1 + ky, L.ny)) * L.nx
+                                     + wrap3(pw[0] - 1 + kx, L.nx));
     const float ux = wave_sum(w * d.u[node]);
     const float uy = wave_sum(w * d.u[L.n + node]);
     const float uz = wave_sum(w * d.u[2 * L.n + node]);
@@ -507,35 +571,39 @@ __global__ __launch_bounds__(256) void k_cap_moments(Dev d) {
 __global__ __launch_bounds__(256) void k_spread_vec(Lattice L, Dev d, int par, const float* __restrict__ val,
                                                     float* __restrict__ target, int mode) {
     constexpr int B3 = BOX * BOX * BOX;
-    __shared__ float box[6][B3];
+    // one box per wavefront, plain LDS adds (as in k_spread)
+    __shared__ float box[4][6][B3];
     const int nh = d.counters[CNT_HOME + par];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wave = wave_id();
     const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
     const int64_t N = L.n;
     const int nf = mode == 0 ? 3 : 6;
+    float* mybox = &box[wave][0][0];
     for (int e = blockIdx.x; e < nh; e += gridDim.x) {
         const int t = d.home[par][e];
         const int start = d.home_start[e], cnt = d.tile_count[t];
         const int ox = (t % L.nbx) * BIN, oy = ((t / L.nbx) % L.nby) * BIN, oz = (t / (L.nbx * L.nby)) * BIN;
-        for (int k = threadIdx.x; k < nf * B3; k += 256) (&box[0][0])[k] = 0.0f;
+        for (int k = threadIdx.x; k < 4 * 6 * B3; k += 256) (&box[0][0][0])[k] = 0.0f;
         __syncthreads();
         for (int j = wave; j < cnt; j += 4) {
             const int b = d.sorted[start + j];
             const NodePos p = node_pos(d, b);
+            int pw[3];
+            wrapped_floor(L, p, pw);
             const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
-            const int cell = ((wrapi(p.fl[2], L.nz) - oz + kz) * BOX + (wrapi(p.fl[1], L.ny) - oy + ky)) * BOX +
-                             (wrapi(p.fl[0], L.nx) - ox + kx);
+            const int cell = ((pw[2] - oz + kz) * BOX + (pw[1] - oy + ky)) * BOX + (pw[0] - ox + kx);
             const int base = mode == 0 ? 0 : 3 * (1 - d.caps[d.node_cap[b]].pref);
-            for (int a = 0; a < 3; ++a) atomicAdd(&box[base + a][cell], w * val[3 * b + a]);
+            for (int a = 0; a < 3; ++a) mybox[(base + a) * B3 + cell] += w * val[3 * b + a];
         }
         __syncthreads();
         for (int k = threadIdx.x; k < nf * B3; k += 256) {
-            const float v = (&box[0][0])[k];
+            const float* bx = &box[0][0][0];
+            const float v = (bx[k] + bx[6 * B3 + k]) + (bx[12 * B3 + k] + bx[18 * B3 + k]);
             if (v != 0.0f) {
                 const int f = k / B3, cell = k - f * B3;
                 const int iz = cell / (BOX * BOX), iy = (cell / BOX) % BOX, ix = cell % BOX;
-                const int gx = wrapi(ox - 1 + ix, L.nx), gy = wrapi(oy - 1 + iy, L.ny), gz = wrapi(oz - 1 + iz, L.nz);
-                unsafeAtomicAdd(&target[f * N + ((int64_t)gz * L.ny + gy) * L.nx + gx], v);
+                const int gx = wrap3(ox - 1 + ix, L.nx), gy = wrap3(oy - 1 + iy, L.ny), gz = wrap3(oz - 1 + iz, L.nz);
+                unsafeAtomicAdd(&target[f * N + (uint32_t)((gz * L.ny + gy) * L.nx + gx)], v);
             }
         }
         __syncthreads();
