@@ -294,42 +294,12 @@ struct Ring {
     float v[3][NC][SH][SW];
 };
 
-// Stage plane zz of `src` (per component, optionally times a per-component
-// scale, optionally plus the virtual density where tiles are flagged).
-template <bool WALLS, bool ADD_PHI, int NC>
-__device__ __forceinline__ void stage_plane(Ring<NC>& R, int zz, int z0, int x0, int y0, int tid,
-                                            const float* __restrict__ src, const float* scale,
-                                            const float* __restrict__ fib, const int* __restrict__ tile_flag,
-                                            const Lattice& L) {
-    constexpr int SW = Ring<NC>::SW, SH = Ring<NC>::SH;
-    const int slot = (zz - z0 + 1) % 3;
-    const int zw = wrapi(zz, L.nz);
-    for (int k = tid; k < NC * SH * SW; k += BX * BY) {
-        const int c = k / (SH * SW);
-        const int r = k - c * SH * SW;
-        const int ly = r / SW, lx = r - ly * SW;
-        const int gx = wrapi(x0 - 1 + lx, L.nx);
-        int gy = wrapi(y0 - 1 + ly, L.ny);
-        if (WALLS) {
-            // solid rows take the value of the adjacent fluid row
-            if (gy == 0) gy = 1;
-            if (gy == L.ny - 1) gy = L.ny - 2;
-        }
-        const int64_t idx = ((int64_t)zw * L.ny + gy) * L.nx + gx;
-        float v = src[c * L.n + idx];
-        if (scale) v *= scale[c];
-        if (ADD_PHI) {
-            const int t = ((zw >> 3) * L.nty + (gy >> 3)) * L.ntx + (gx >> 3);
-            if (tile_flag[t]) v += fib[(3 + c) * L.n + idx];
-        }
-        R.v[slot][c][ly][lx] = v;
-    }
-}
-
-// The same staging without per-plane index arithmetic: stage_positions
-// fixes, once per block, the plane positions a thread stages (they do not
-// depend on z); stage_load reads one plane at those positions into
-// registers and stage_store writes them into the ring.
+// Staging a plane of the ring.  stage_positions fixes, once per block, the
+// plane positions a thread stages (they do not depend on z; with WALLS the
+// solid rows take the value of the adjacent fluid row); stage_load reads
+// one plane zz at those positions into registers (per component, optionally
+// times a per-component scale, optionally plus the virtual density where
+// tiles are flagged) and stage_store writes them into the ring.
 struct StagePos {
     static constexpr int SW = BX + 2, SH = BY + 2;
     static constexpr int POS = SH * SW;
@@ -396,14 +366,16 @@ __device__ __forceinline__ void stage_load(StageRegs<NC>& S, const StagePos& P, 
     }
 }
 
-template <int NC>
-__device__ __forceinline__ void stage_store(Ring<NC>& R, const StageRegs<NC>& S, int zz, int z0, int tid) {
+// (components c of the registers go to ring fields C0 + c)
+template <int NC, int NR, int C0 = 0>
+__device__ __forceinline__ void stage_store(Ring<NR>& R, const StageRegs<NC>& S, int zz, int z0, int tid) {
+    static_assert(C0 + NC <= NR, "ring too small");
     const int slot = (zz - z0 + 1) % 3;
 #pragma unroll
     for (int it = 0; it < StagePos::NIT; ++it) {
         if (stage_has(tid, it)) {
 #pragma unroll
-            for (int c = 0; c < NC; ++c) (&R.v[slot][c][0][0])[tid + it * BX * BY] = S.v[it][c];
+            for (int c = 0; c < NC; ++c) (&R.v[slot][C0 + c][0][0])[tid + it * BX * BY] = S.v[it][c];
         }
     }
 }
@@ -822,27 +794,33 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
         }
         near_ibm = __syncthreads_or(hit) != 0;
     }
+    const StagePos P = stage_positions<WALLS>(x0, y0, tid, L);
+    StageRegs<2> np;
     auto stage = [&](int zz) {
         if (IBM && near_ibm)
-            stage_plane<WALLS, true, 2>(sp, zz, z0, x0, y0, tid, rho_n, nullptr, fib, tile_flag, L);
+            stage_load<true, 2>(np, P, zz, tid, rho_n, nullptr, fib, tile_flag, L);
         else
-            stage_plane<WALLS, false, 2>(sp, zz, z0, x0, y0, tid, rho_n, nullptr, nullptr, nullptr, L);
+            stage_load<false, 2>(np, P, zz, tid, rho_n, nullptr, nullptr, nullptr, L);
+        stage_store<2>(sp, np, zz, z0, tid);
     };
     stage(z0 - 1);
     stage(z0);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
     double gG = 0.0;
+    Raw<false> rcur;
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
         stage(z + 1);
         __syncthreads();
+        if (active) load_raw<WALLS, false>(fin, L, 0, x, y, z, rcur);
         if (active) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx), xo = (uint32_t)x;
             const int s0 = (z - z0 + 1) % 3;
             Pulled A, B;
             auto none = [](int, int, int, float&, float&) {};
-            pull<WALLS, false>(fin, L, node, x, y, z, WALLS ? rho_p[node] : 0.0f, WALLS ? rho_p[N + node] : 0.0f,
-                               none, A, B);
+            decode<WALLS, false>(L, y, rcur, WALLS ? ldx(rho_p + row, xo) : 0.0f,
+                                 WALLS ? ldx(rho_p + N + row, xo) : 0.0f, none, A, B);
             const float ra = sum_pop(A), rb = sum_pop(B);
             float ja[3], jb[3];
             momentum(A, ja[0], ja[1], ja[2]);
@@ -866,7 +844,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
                 const int t = ((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3);
                 flagged = tile_flag[t] != 0;
                 if (flagged)
-                    for (int d = 0; d < 3; ++d) Fib[d] = fib[d * N + node];
+                    for (int d = 0; d < 3; ++d) Fib[d] = ldx(fib + d * N + row, xo);
             }
             const float ma = ra * ir, mb = rb * ir;
             float Fa[3], Fb[3];
@@ -888,8 +866,8 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
             float lu[3] = {0.f, 0.f, 0.f};
             if (flagged)
                 for (int d = 0; d < 3; ++d) {
-                    lu[d] = lam_u[d * N + node];
-                    u_out[d * N + node] = u[d];
+                    lu[d] = ldx(lam_u + d * N + row, xo);
+                    *ptrx(u_out + d * N + row, xo) = u[d];
                 }
             float lj[2][3], lF[2][3], lr[2];
             const float luu = (lu[0] * u[0] + lu[1] * u[1] + lu[2] * u[2]) * ir;
@@ -909,7 +887,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
                 float lrf = 0.f, lue[3] = {0.f, 0.f, 0.f};
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const pf2 lv = lam_in[(int64_t)i * N + node];
+                    const pf2 lv = ldx(lam_in + (int64_t)i * N + row, xo);
                     const float mu = om * (c == 0 ? lv.x : lv.y);
                     const float eu = cx(i) * ue[c][0] + cy(i) * ue[c][1] + cz(i) * ue[c][2];
                     lrf += mu * wgt(i) * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * usq);
@@ -952,7 +930,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
             if (flagged) {
                 float lma = 0.f, lmb = 0.f;
                 for (int d = 0; d < 3; ++d) {
-                    lam_Fib[d * N + node] = ma * lF[0][d] + mb * lF[1][d];
+                    *ptrx(lam_Fib + d * N + row, xo) = ma * lF[0][d] + mb * lF[1][d];
                     lma += lF[0][d] * Fib[d];
                     lmb += lF[1][d] * Fib[d];
                 }
@@ -960,13 +938,13 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
                 lr[0] += (lma - lmb) * rb * ir2;
                 lr[1] += (lmb - lma) * ra * ir2;
             }
-            lam_rho[node] = lr[0];
-            lam_rho[N + node] = lr[1];
+            *ptrx(lam_rho + row, xo) = lr[0];
+            *ptrx(lam_rho + N + row, xo) = lr[1];
             for (int d = 0; d < 3; ++d) {
-                lam_j[d * N + node] = lj[0][d];
-                lam_j[(3 + d) * N + node] = lj[1][d];
-                lam_S[d * N + node] = lSa[d];
-                lam_S[(3 + d) * N + node] = lSb[d];
+                *ptrx(lam_j + d * N + row, xo) = lj[0][d];
+                *ptrx(lam_j + (3 + d) * N + row, xo) = lj[1][d];
+                *ptrx(lam_S + d * N + row, xo) = lSa[d];
+                *ptrx(lam_S + (3 + d) * N + row, xo) = lSb[d];
             }
         }
         __syncthreads();
@@ -988,15 +966,22 @@ __global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ la
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
     const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
-    stage_plane<false, false, 6>(sr, z0 - 1, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
-    stage_plane<false, false, 6>(sr, z0, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
+    const StagePos P = stage_positions<false>(x0, y0, tid, L);
+    StageRegs<6> st;
+    auto stage = [&](int zz) {
+        stage_load<false, 6>(st, P, zz, tid, lam_S, nullptr, nullptr, nullptr, L);
+        stage_store<6>(sr, st, zz, z0, tid);
+    };
+    stage(z0 - 1);
+    stage(z0);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        stage_plane<false, false, 6>(sr, z + 1, z0, x0, y0, tid, lam_S, nullptr, nullptr, nullptr, L);
+        stage(z + 1);
         __syncthreads();
         if (active) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx), xo = (uint32_t)x;
             const int s0 = (z - z0 + 1) % 3;
             const int ly = ty + 1, lx = tx + 1;
             float acc[2] = {0.f, 0.f};
@@ -1031,26 +1016,10 @@ __global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ la
                     }
                 }
             }
-            lam_rho[node] += acc[0];
-            lam_rho[N + node] += acc[1];
+            *ptrx(lam_rho + row, xo) += acc[0];
+            *ptrx(lam_rho + N + row, xo) += acc[1];
         }
         __syncthreads();
-    }
-}
-
-// Stage lambda_rho (2) and lambda_j (6) as one 8-field ring.
-__device__ __forceinline__ void stage_lrj(Ring<8>& R, int zz, int z0, int x0, int y0, int tid,
-                                          const float* __restrict__ lam_rho, const float* __restrict__ lam_j,
-                                          const Lattice& L) {
-    constexpr int SW = Ring<8>::SW, SH = Ring<8>::SH;
-    const int slot = (zz - z0 + 1) % 3;
-    const int zw = wrapi(zz, L.nz);
-    for (int k = tid; k < 8 * SH * SW; k += BX * BY) {
-        const int c = k / (SH * SW);
-        const int r = k - c * SH * SW;
-        const int ly = r / SW, lx = r - ly * SW;
-        const int64_t idx = ((int64_t)zw * L.ny + wrapi(y0 - 1 + ly, L.ny)) * L.nx + wrapi(x0 - 1 + lx, L.nx);
-        R.v[slot][c][ly][lx] = c < 2 ? lam_rho[c * L.n + idx] : lam_j[(c - 2) * L.n + idx];
     }
 }
 
@@ -1065,24 +1034,38 @@ __global__ __launch_bounds__(256) void k_adj_push(const pf2* __restrict__ lam_in
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
     const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
-    stage_lrj(rj, z0 - 1, z0, x0, y0, tid, lam_rho, lam_j, L);
-    stage_lrj(rj, z0, z0, x0, y0, tid, lam_rho, lam_j, L);
+    // lambda_rho and lambda_j share one 8-field ring (fields 0-1 and 2-7);
+    // the positions wrap periodically in y as the push reads them
+    const StagePos P = stage_positions<false>(x0, y0, tid, L);
+    StageRegs<2> sr2;
+    StageRegs<6> sr6;
+    auto stage = [&](int zz) {
+        stage_load<false, 2>(sr2, P, zz, tid, lam_rho, nullptr, nullptr, nullptr, L);
+        stage_load<false, 6>(sr6, P, zz, tid, lam_j, nullptr, nullptr, nullptr, L);
+        stage_store<2, 8, 0>(rj, sr2, zz, z0, tid);
+        stage_store<6, 8, 2>(rj, sr6, zz, z0, tid);
+    };
+    stage(z0 - 1);
+    stage(z0);
     const int x = x0 + tx, y = y0 + ty;
     const bool inside = x < L.nx && y < L.ny;
     const bool active = inside && (!WALLS || (y > 0 && y < L.ny - 1));
+#pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        stage_lrj(rj, z + 1, z0, x0, y0, tid, lam_rho, lam_j, L);
+        stage(z + 1);
         __syncthreads();
         if (active) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx), xo = (uint32_t)x;
             const int s0 = (z - z0 + 1) % 3;
             const int ly = ty + 1, lx = tx + 1;
-            const int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1;
+            int xm = x == 0 ? L.nx - 1 : x - 1, xp = x == L.nx - 1 ? 0 : x + 1, xc = x;
+            // fresh lane offsets per plane (scalar row base plus 32-bit x)
+            asm volatile("" : "+v"(xm), "+v"(xc), "+v"(xp));
             const int ym = y == 0 ? L.ny - 1 : y - 1, yp = y == L.ny - 1 ? 0 : y + 1;
             const int zm = z == 0 ? L.nz - 1 : z - 1, zp = z == L.nz - 1 ? 0 : z + 1;
             // own lambda_f_i for the bounced directions and the wall density term
             auto own_lf = [&](int i, int c) {
-                const pf2 lv = lam_in[(int64_t)i * N + node];
+                const pf2 lv = ldx(lam_in + (int64_t)i * N + row, xo);
                 const float ls = c == 0 ? lv.x : lv.y;
                 const float lj = cx(i) * rj.v[s0][2 + 3 * c][ly][lx] + cy(i) * rj.v[s0][3 + 3 * c][ly][lx] +
                                  cz(i) * rj.v[s0][4 + 3 * c][ly][lx];
@@ -1106,10 +1089,10 @@ __global__ __launch_bounds__(256) void k_adj_push(const pf2* __restrict__ lam_in
                     out[0] = own_lf(opp(k), 0);
                     out[1] = own_lf(opp(k), 1);
                 } else {
-                    const int sx = cx(k) == 1 ? xp : (cx(k) == -1 ? xm : x);
+                    const int sx = cx(k) == 1 ? xp : (cx(k) == -1 ? xm : xc);
                     const int sy = cy(k) == 1 ? yp : (cy(k) == -1 ? ym : y);
                     const int sz = cz(k) == 1 ? zp : (cz(k) == -1 ? zm : z);
-                    const pf2 lv = lam_in[(int64_t)k * N + ((int64_t)sz * L.ny + sy) * L.nx + sx];
+                    const pf2 lv = ldx(lam_in + (int64_t)k * N + (uint32_t)((sz * L.ny + sy) * L.nx), (uint32_t)sx);
                     const int sl = (s0 + cz(k) + 3) % 3, qy = ly + cy(k), qx = lx + cx(k);
                     for (int c = 0; c < 2; ++c) {
                         const float lj = cx(k) * rj.v[sl][2 + 3 * c][qy][qx] + cy(k) * rj.v[sl][3 + 3 * c][qy][qx] +
@@ -1117,11 +1100,11 @@ __global__ __launch_bounds__(256) void k_adj_push(const pf2* __restrict__ lam_in
                         out[c] = (1.0f - L.omega[c]) * (c == 0 ? lv.x : lv.y) + rj.v[sl][c][qy][qx] + lj;
                     }
                 }
-                lam_out[(int64_t)k * N + node] = pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]);
+                *ptrx(lam_out + (int64_t)k * N + row, xo) = pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]);
             }
         } else if (inside) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
-            for (int k = 0; k < Q; ++k) lam_out[(int64_t)k * N + node] = pack<false>(0.f, 0.f);
+            const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx);
+            for (int k = 0; k < Q; ++k) *ptrx(lam_out + (int64_t)k * N + row, (uint32_t)x) = pack<false>(0.f, 0.f);
         }
         __syncthreads();
     }
