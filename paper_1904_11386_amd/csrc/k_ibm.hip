@@ -14,10 +14,10 @@
 //   k_nodes         one wavefront per node: gather its triangles' corner
 //                   forces, add the wettability reaction (64 lanes = the
 //                   4x4x4 delta stencil, psi staged on a 6^3 LDS cube),
-//                   count the node into its home bin (4^3), mark the 8^3
-//                   tiles its stencil touches
-//   k_bin_scan      exclusive scan of the home-tile counts
-//   k_bin_scatter   counting-sort scatter of node ids into tile bins
+//                   count the node into its home bin (4^3)
+//   k_bin_scan      exclusive scan of the home-bin counts
+//   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
+//                   the 8^3 tiles the bins' stencils can reach
 //   k_spread        one workgroup per occupied bin: accumulate F_b delta and
 //                   the virtual density in 7^3 LDS boxes (one per wavefront,
 //                   one lane per stencil point, no LDS atomics), then flush
@@ -354,33 +354,6 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         d.node_tile[b] = t;
         d.node_rank[b] = rank;
         if (rank == 0) d.home[par][atomicAdd(&d.counters[CNT_HOME + par], 1)] = t;
-    } else if (lane >= 8 && lane < 16) {
-        // tiles touched by the stencil floor(X)-1 .. floor(X)+2: at most two
-        // per axis; lane 8 + (i, j, k) takes one combination
-        const int sel[3] = {(lane - 8) & 1, ((lane - 8) >> 1) & 1, ((lane - 8) >> 2) & 1};
-        const int nn[3] = {L.nx, L.ny, L.nz};
-        int tt[3];
-        bool ok = true;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const int t0 = wrap3(pw[a] - 1, nn[a]) >> 3;
-            int t1 = -1;
-#pragma unroll
-            for (int k = 1; k < 4; ++k) {
-                const int tk = wrap3(pw[a] - 1 + k, nn[a]) >> 3;
-                if (tk != t0) t1 = tk;
-            }
-            tt[a] = sel[a] ? t1 : t0;
-            ok = ok && tt[a] >= 0;
-        }
-        if (ok) {
-            const int t2 = (tt[2] * L.nty + tt[1]) * L.ntx + tt[0];
-            // most tiles are already marked by another node: a plain read
-            // first keeps the atomics to the few first visits (flags are all
-            // clear when the kernel starts, so a set flag is never stale)
-            if (d.tile_flag[t2] == 0 && atomicExch(&d.tile_flag[t2], 1) == 0)
-                d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t2;
-        }
     }
 }
 
@@ -409,10 +382,39 @@ __global__ __launch_bounds__(1024) void k_bin_scan(Dev d, int par) {
     }
 }
 
-__global__ __launch_bounds__(256) void k_bin_scatter(Dev d, int n_nodes) {
+// Counting-sort scatter of the node ids, and the lattice tiles that the
+// delta stencils can reach: a node of home bin c (floor(X) in [4c, 4c+3] per
+// axis) has its stencil in [4c-1, 4c+5], so each occupied bin flags every
+// tile that range meets on each axis (at most three when an edge is not a
+// multiple of the tile).  A small superset of the exact set, from one
+// thread per bin instead of per node.
+__global__ __launch_bounds__(256) void k_bin_scatter(Lattice L, Dev d, int n_nodes, int par) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_nodes) return;
-    d.sorted[d.tile_offset[d.node_tile[b]] + d.node_rank[b]] = b;
+    if (b < n_nodes) d.sorted[d.tile_offset[d.node_tile[b]] + d.node_rank[b]] = b;
+    const int nh = d.counters[CNT_HOME + par];
+    if (b >= nh) return;
+    const int h = d.home[par][b];
+    const int bc[3] = {h % L.nbx, (h / L.nbx) % L.nby, h / (L.nbx * L.nby)};
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    int tt[3][3], nt[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nt[a] = 0;
+#pragma unroll
+        for (int k = 0; k < BIN + 3; ++k) {
+            const int tk = wrap3(BIN * bc[a] - 1 + k, nn[a]) >> 3;
+            bool seen = false;
+            for (int q = 0; q < nt[a]; ++q) seen = seen || tt[a][q] == tk;
+            if (!seen && nt[a] < 3) tt[a][nt[a]++] = tk;
+        }
+    }
+    for (int k = 0; k < nt[2]; ++k)
+        for (int j = 0; j < nt[1]; ++j)
+            for (int i = 0; i < nt[0]; ++i) {
+                const int t = (tt[2][k] * L.nty + tt[1][j]) * L.ntx + tt[0][i];
+                if (atomicExch(&d.tile_flag[t], 1) == 0)
+                    d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t;
+            }
 }
 
 constexpr int SPREAD_GRID = 2048;
@@ -853,8 +855,9 @@ void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const floa
 void launch_bin_scan(const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, d, par);
 }
-void launch_bin_scatter(const Dev& d, int n_nodes, hipStream_t s) {
-    if (n_nodes > 0) hipLaunchKernelGGL(k_bin_scatter, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
+void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s) {
+    if (n_nodes > 0)
+        hipLaunchKernelGGL(k_bin_scatter, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, par);
 }
 void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_spread, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);

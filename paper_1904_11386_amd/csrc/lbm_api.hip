@@ -544,7 +544,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_SCAN);
     if (ibm) launch_bin_scan(d, par, s);
     mark(LBM_K_SCATTER);
-    if (ibm) launch_bin_scatter(d, c->n_nodes, s);
+    if (ibm) launch_bin_scatter(L, d, c->n_nodes, par, s);
     mark(LBM_K_SPREAD);
     if (ibm) launch_spread(L, d, par, s);
     mark(LBM_K_COLLIDE);

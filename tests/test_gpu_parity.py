@@ -97,6 +97,17 @@ def test_capsules_ragged_box_60_steps():
     _compare_run(wl, 60, 5e-6, 1e-5, tol_x=2e-5)
 
 
+def test_capsule_across_one_cell_partial_tiles():
+    # lattice edges of 8k+1 cells: the last 8^3 tile along x and y is one
+    # cell thick, and a capsule straddling the periodic wrap has stencils
+    # that reach three tiles per axis (the tiles flagged for the forcing
+    # must include the one-cell tile)
+    wl = W.small(nx=33, ny=33, nz=38, ncap=2, theta=(60.0, 110.0), wet_scale=0.5)
+    wl.capsules[0].centre = W._snap(np.array([32.3, 32.4, wl.z_interface + 0.7]))
+    wl.capsules[1].centre = W._snap(np.array([14.2, 15.1, wl.z_interface - 0.6]))
+    _compare_run(wl, 40, 5e-6, 1e-5, tol_x=2e-5)
+
+
 def test_walls_channel_parity():
     wl = W.make("c4_mini")
     _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
