@@ -11,10 +11,10 @@
 //                   method:volume), one thread per triangle
 //   k_faces         Skalak (Sec. II.B, eq. method:strain) and volume
 //                   forces per triangle and corner, F = -dE/dX
-//   k_nodes         one wavefront per node: gather its triangles' corner
-//                   forces, add the wettability reaction (64 lanes = the
-//                   4x4x4 delta stencil, psi staged on a 6^3 LDS cube),
-//                   count the node into its home bin (4^3)
+//   k_nodes         sixteen lanes per node: gather its triangles' corner
+//                   forces, add the wettability reaction (lane (kx, ky)
+//                   takes a column of the 4x4x4 delta stencil, psi staged
+//                   on a 6^3 LDS cube), count the node into its home bin
 //   k_bin_scan      exclusive scan of the home-bin counts
 //   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
 //                   the 8^3 tiles the bins' stencils can reach
@@ -22,7 +22,7 @@
 //                   the virtual density in 7^3 LDS boxes (one per wavefront,
 //                   one lane per stencil point, no LDS atomics), then flush
 //                   the non-zero cells to HBM with global atomics
-//   k_interp_advect one wavefront per node: U_b = sum u delta, X += U_b
+//   k_interp_advect sixteen lanes per node: U_b = sum u delta, X += U_b
 #include "lbm_internal.h"
 
 namespace lbmx {
@@ -79,13 +79,14 @@ struct NodePos {
 };
 
 __device__ __forceinline__ NodePos node_pos(const Dev& d, int b) {
-    const CapDev& C = d.caps[d.node_cap[b]];
+    const int4 an = d.node_anc[b];
+    const int A[3] = {an.x, an.y, an.z};
     NodePos p;
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
         const float o = d.off_hi[3 * b + k];
         const float fo = floorf(o);
-        p.fl[k] = C.anchor[k] + (int)fo;
+        p.fl[k] = A[k] + (int)fo;
         p.r[k] = o - fo;
     }
     return p;
@@ -272,85 +273,107 @@ __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
     const float vfac = C.kV != 0.0f ? -(float)((double)C.kV * (d.capV[cap] - C.V0) / C.V0) * (1.0f / 6.0f) : 0.0f;
     float Fsk[3][3], F[3][3];
     face_forces<float>(X, d.fref[f], C.kS, C.C, vfac, Fsk, F);
-    float* o = d.face_F + 9 * (int64_t)f;
 #pragma unroll
-    for (int k = 0; k < 3; ++k)
+    for (int k = 0; k < 3; ++k) {
+        float* o = d.face_F + 3 * (int64_t)d.corner_slot[3 * f + k];
 #pragma unroll
-        for (int j = 0; j < 3; ++j) o[3 * k + j] = F[k][j];
+        for (int j = 0; j < 3; ++j) o[j] = F[k][j];
+    }
 }
 
+// Four nodes per wavefront, sixteen lanes per node (lane (kx, ky) takes the
+// stencil column kz = 0..3), sixteen nodes per block.
 __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __restrict__ rho_n,
                                                const float* __restrict__ cs, int n_nodes, int par) {
     constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
-    __shared__ float cube[4][CB * CB * CB];
-    const int lane = threadIdx.x & 63;
-    const int wv = wave_id();
-    const int b = blockIdx.x * 4 + wv;
-    if (b >= n_nodes) return;                   // whole wavefront; no block barrier below
-    float* cb = cube[wv];
+    constexpr int C3 = CB * CB * CB;
+    __shared__ float cube[16][C3];
+    const int lane = threadIdx.x & 63, l16 = lane & 15;
+    const int slot = wave_id() * 4 + (lane >> 4);
+    const int b = blockIdx.x * 16 + slot;
+    const bool valid = b < n_nodes;
+    float* cb = cube[slot];
     // corner forces of the incident triangles
     float gx = 0.f, gy = 0.f, gz = 0.f;
-    const int beg = d.csr_ptr[b], end = d.csr_ptr[b + 1];
-    for (int k = beg + lane; k < end; k += 64) {
-        const int e = d.csr_idx[k];
-        gx += d.face_F[3 * (int64_t)e + 0];
-        gy += d.face_F[3 * (int64_t)e + 1];
-        gz += d.face_F[3 * (int64_t)e + 2];
+    NodePos p;
+    int pw[3] = {0, 0, 0};
+    float wet = 0.0f;
+    int t = 0, rank = 0;
+    if (valid) {
+        const int beg = d.csr_ptr[b], end = d.csr_ptr[b + 1];
+        for (int k = beg + l16; k < end; k += 16) {
+            gx += d.face_F[3 * (int64_t)k + 0];
+            gy += d.face_F[3 * (int64_t)k + 1];
+            gz += d.face_F[3 * (int64_t)k + 2];
+        }
+        p = node_pos(d, b);
+        wrapped_floor(L, p, pw);
+        wet = d.node_wet[b];
+        if (l16 == 1) {
+            // count the node into its home bin (4^3) early; the rank is used last
+            t = bin_of(L, pw[0], pw[1], pw[2]);
+            rank = atomicAdd(&d.tile_count[t], 1);
+        }
     }
-    const NodePos p = node_pos(d, b);
-    int pw[3];
-    wrapped_floor(L, p, pw);
-    const float wet = d.node_wet[b];
-    if (wet != 0.0f) {
+    const bool wetting = valid && wet != 0.0f;
+    int np = 0;
+    if (wetting) {
         // reaction of the virtual density on the node:
-        // -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i
-        const int np = 1 - d.caps[d.node_cap[b]].pref;
+        // -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i;
+        // the node's sixteen lanes stage psi^np on the 6^3 cube
+        // floor(X)-2 .. floor(X)+3
+        np = 1 - d.node_anc[b].w;
         const float* rc = rho_n + (int64_t)np * L.n;
         const float sc = cs ? cs[np] : 1.0f;      // FP16 form: mass compensation of this step
-        // the wavefront stages psi^np on the 6^3 cube floor(X)-2 .. floor(X)+3
 #pragma unroll
-        for (int it = 0; it < (CB * CB * CB + 63) / 64; ++it) {
-            const int j = lane + 64 * it;
-            if (j < CB * CB * CB) {
+        for (int it = 0; it < (C3 + 15) / 16; ++it) {
+            const int j = l16 + 16 * it;
+            if (j < C3) {
                 const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
-                int gy = wrap3(pw[1] - 2 + qy, L.ny);
-                if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
-                const int gz = wrap3(pw[2] - 2 + qz, L.nz), gx = wrap3(pw[0] - 2 + qx, L.nx);
-                cb[j] = sc * rc[(uint32_t)((gz * L.ny + gy) * L.nx + gx)];
+                int gyy = wrap3(pw[1] - 2 + qy, L.ny);
+                if (L.walls) gyy = gyy == 0 ? 1 : (gyy == L.ny - 1 ? L.ny - 2 : gyy);
+                const int gzz = wrap3(pw[2] - 2 + qz, L.nz), gxx = wrap3(pw[0] - 2 + qx, L.nx);
+                cb[j] = sc * rc[(uint32_t)((gzz * L.ny + gyy) * L.nx + gxx)];
             }
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
-        const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
-        const int c0 = ((kz + 1) * CB + (ky + 1)) * CB + (kx + 1);
-        float S[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-        for (int k = 1; k < Q; k += 2) {
-            const int o = (cz(k) * CB + cy(k)) * CB + cx(k);
-            const float va = cb[c0 + o];
-            const float vb = cb[c0 - o];
-            const float dd = wgt(k) * (va - vb);
-            if (cx(k)) S[0] += cx(k) * dd;
-            if (cy(k)) S[1] += cy(k) * dd;
-            if (cz(k)) S[2] += cz(k) * dd;
-        }
-        const float s = -L.G * wet * w;
-        gx += s * S[0];
-        gy += s * S[1];
-        gz += s * S[2];
     }
-    gx = wave_sum(gx);
-    gy = wave_sum(gy);
-    gz = wave_sum(gz);
-    if (lane == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (wetting) {
+        const int kx = l16 & 3, ky = l16 >> 2;
+        const float wxy = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky);
+        const float s0 = -L.G * wet;
+#pragma unroll
+        for (int kz = 0; kz < 4; ++kz) {
+            const float w = wxy * peskin(p.r[2] + 1.0f - kz);
+            const int c0 = ((kz + 1) * CB + (ky + 1)) * CB + (kx + 1);
+            float S[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int k = 1; k < Q; k += 2) {
+                const int o = (cz(k) * CB + cy(k)) * CB + cx(k);
+                const float dd = wgt(k) * (cb[c0 + o] - cb[c0 - o]);
+                if (cx(k)) S[0] += cx(k) * dd;
+                if (cy(k)) S[1] += cy(k) * dd;
+                if (cz(k)) S[2] += cz(k) * dd;
+            }
+            const float s = s0 * w;
+            gx += s * S[0];
+            gy += s * S[1];
+            gz += s * S[2];
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        gx += __shfl_xor(gx, o, 16);
+        gy += __shfl_xor(gy, o, 16);
+        gz += __shfl_xor(gz, o, 16);
+    }
+    if (valid && l16 == 0) {
         d.node_F[3 * b + 0] = gx;
         d.node_F[3 * b + 1] = gy;
         d.node_F[3 * b + 2] = gz;
-    } else if (lane == 1) {
-        const int t = bin_of(L, pw[0], pw[1], pw[2]);
-        const int rank = atomicAdd(&d.tile_count[t], 1);
+    } else if (valid && l16 == 1) {
         d.node_tile[b] = t;
         d.node_rank[b] = rank;
         if (rank == 0) d.home[par][atomicAdd(&d.counters[CNT_HOME + par], 1)] = t;
@@ -387,34 +410,39 @@ __global__ __launch_bounds__(1024) void k_bin_scan(Dev d, int par) {
 // axis) has its stencil in [4c-1, 4c+5], so each occupied bin flags every
 // tile that range meets on each axis (at most three when an edge is not a
 // multiple of the tile).  A small superset of the exact set, from one
-// thread per bin instead of per node.
+// thread per (bin, tile combination) instead of per node.
 __global__ __launch_bounds__(256) void k_bin_scatter(Lattice L, Dev d, int n_nodes, int par) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b < n_nodes) d.sorted[d.tile_offset[d.node_tile[b]] + d.node_rank[b]] = b;
     const int nh = d.counters[CNT_HOME + par];
-    if (b >= nh) return;
-    const int h = d.home[par][b];
-    const int bc[3] = {h % L.nbx, (h / L.nbx) % L.nby, h / (L.nbx * L.nby)};
     const int nn[3] = {L.nx, L.ny, L.nz};
-    int tt[3][3], nt[3];
+    for (int it = b; it < nh * 27; it += gridDim.x * blockDim.x) {
+        const int e = it / 27, cmb = it - 27 * e;
+        const int sel[3] = {cmb % 3, (cmb / 3) % 3, cmb / 9};
+        const int h = d.home[par][e];
+        const int bc[3] = {h % L.nbx, (h / L.nbx) % L.nby, h / (L.nbx * L.nby)};
+        int tsel[3];
+        bool ok = true;
 #pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        nt[a] = 0;
+        for (int a = 0; a < 3; ++a) {
+            // the sel[a]-th distinct tile met by cells 4c-1 .. 4c+5 of axis a
+            int tt[3], nt = 0;
 #pragma unroll
-        for (int k = 0; k < BIN + 3; ++k) {
-            const int tk = wrap3(BIN * bc[a] - 1 + k, nn[a]) >> 3;
-            bool seen = false;
-            for (int q = 0; q < nt[a]; ++q) seen = seen || tt[a][q] == tk;
-            if (!seen && nt[a] < 3) tt[a][nt[a]++] = tk;
+            for (int k = 0; k < BIN + 3; ++k) {
+                const int tk = wrap3(BIN * bc[a] - 1 + k, nn[a]) >> 3;
+                bool seen = false;
+                for (int q = 0; q < nt; ++q) seen = seen || tt[q] == tk;
+                if (!seen && nt < 3) tt[nt++] = tk;
+            }
+            ok = ok && sel[a] < nt;
+            tsel[a] = tt[sel[a] < nt ? sel[a] : 0];
+        }
+        if (ok) {
+            const int t = (tsel[2] * L.nty + tsel[1]) * L.ntx + tsel[0];
+            if (atomicExch(&d.tile_flag[t], 1) == 0)
+                d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t;
         }
     }
-    for (int k = 0; k < nt[2]; ++k)
-        for (int j = 0; j < nt[1]; ++j)
-            for (int i = 0; i < nt[0]; ++i) {
-                const int t = (tt[2][k] * L.nty + tt[1][j]) * L.ntx + tt[0][i];
-                if (atomicExch(&d.tile_flag[t], 1) == 0)
-                    d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t;
-            }
 }
 
 constexpr int SPREAD_GRID = 2048;
@@ -461,7 +489,7 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
                 sf[2][threadIdx.x] = d.node_F[3 * b + 2];
                 const float wet = d.node_wet[b];
                 sf[3][threadIdx.x] = wet;
-                sfield[threadIdx.x] = wet != 0.0f ? 3 + d.caps[d.node_cap[b]].pref : -1;
+                sfield[threadIdx.x] = wet != 0.0f ? 3 + d.node_anc[b].w : -1;
                 scell[threadIdx.x] = ((pw[2] - oz) * BOX + (pw[1] - oy)) * BOX + (pw[0] - ox);
             }
             __syncthreads();
@@ -490,21 +518,36 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
     }
 }
 
+// Four nodes per wavefront, sixteen lanes per node: lane (kx, ky) of a
+// node sums its stencil column kz = 0..3, then the sixteen lanes reduce.
 __global__ __launch_bounds__(256) void k_interp_advect(Lattice L, Dev d, int n_nodes) {
     const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + wave_id();
-    if (b >= n_nodes) return;
-    const NodePos p = node_pos(d, b);
-    int pw[3];
-    wrapped_floor(L, p, pw);
-    const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
-    const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
-    const uint32_t node = (uint32_t)((wrap3(pw[2] - 1 + kz, L.nz) * L.ny + wrap3(pw[1] - 1 + ky, L.ny)) * L.nx
-                                     + wrap3(pw[0] - 1 + kx, L.nx));
-    const float ux = wave_sum(w * d.u[node]);
-    const float uy = wave_sum(w * d.u[L.n + node]);
-    const float uz = wave_sum(w * d.u[2 * L.n + node]);
-    if (lane == 0) {
+    const int q = lane >> 4, kx = lane & 3, ky = (lane >> 2) & 3;
+    const int b = (blockIdx.x * 4 + wave_id()) * 4 + q;
+    float ux = 0.f, uy = 0.f, uz = 0.f;
+    NodePos p;
+    if (b < n_nodes) {
+        p = node_pos(d, b);
+        int pw[3];
+        wrapped_floor(L, p, pw);
+        const float wxy = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky);
+        const uint32_t rxy = (uint32_t)(wrap3(pw[1] - 1 + ky, L.ny) * L.nx + wrap3(pw[0] - 1 + kx, L.nx));
+#pragma unroll
+        for (int kz = 0; kz < 4; ++kz) {
+            const float w = wxy * peskin(p.r[2] + 1.0f - kz);
+            const uint32_t node = (uint32_t)(wrap3(pw[2] - 1 + kz, L.nz) * L.ny * L.nx) + rxy;
+            ux += w * d.u[node];
+            uy += w * d.u[L.n + node];
+            uz += w * d.u[2 * L.n + node];
+        }
+    }
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        ux += __shfl_xor(ux, o, 16);
+        uy += __shfl_xor(uy, o, 16);
+        uz += __shfl_xor(uz, o, 16);
+    }
+    if (b < n_nodes && (lane & 15) == 0) {
         const float U[3] = {ux, uy, uz};
 #pragma unroll
         for (int k = 0; k < 3; ++k) {
@@ -594,7 +637,7 @@ __global__ __launch_bounds__(256) void k_spread_vec(Lattice L, Dev d, int par, c
             wrapped_floor(L, p, pw);
             const float w = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky) * peskin(p.r[2] + 1.0f - kz);
             const int cell = ((pw[2] - oz + kz) * BOX + (pw[1] - oy + ky)) * BOX + (pw[0] - ox + kx);
-            const int base = mode == 0 ? 0 : 3 * (1 - d.caps[d.node_cap[b]].pref);
+            const int base = mode == 0 ? 0 : 3 * (1 - d.node_anc[b].w);
             for (int a = 0; a < 3; ++a) mybox[(base + a) * B3 + cell] += w * val[3 * b + a];
         }
         __syncthreads();
@@ -772,12 +815,13 @@ __global__ __launch_bounds__(256) void k_adj_faces(Dev d, int n_faces) {
         }
         Dual Fsk[3][3], F[3][3];
         face_forces<Dual>(X, d.fref[f], C.kS, C.C, vfac, Fsk, F);
-        float* o = d.face_F + 9 * (int64_t)f;
-        for (int k = 0; k < 3; ++k)
+        for (int k = 0; k < 3; ++k) {
+            float* o = d.face_F + 3 * (int64_t)d.corner_slot[3 * f + k];
             for (int j = 0; j < 3; ++j) {
-                o[3 * k + j] = F[k][j].e;
+                o[j] = F[k][j].e;
                 gk += (double)l[k][j] * Fsk[k][j].v;
             }
+        }
         gk /= (double)C.kS;
     }
     sh[threadIdx.x] = gk;
@@ -795,10 +839,8 @@ __global__ __launch_bounds__(256) void k_adj_node_update(Dev d, int n_nodes) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= n_nodes) return;
     float g[3] = {d.lam_Xg[3 * b], d.lam_Xg[3 * b + 1], d.lam_Xg[3 * b + 2]};
-    for (int k = d.csr_ptr[b]; k < d.csr_ptr[b + 1]; ++k) {
-        const int e = d.csr_idx[k];
-        for (int a = 0; a < 3; ++a) g[a] += d.face_F[3 * (int64_t)e + a];
-    }
+    for (int k = d.csr_ptr[b]; k < d.csr_ptr[b + 1]; ++k)
+        for (int a = 0; a < 3; ++a) g[a] += d.face_F[3 * (int64_t)k + a];
     for (int a = 0; a < 3; ++a) d.lam_X[3 * b + a] += g[a];
 }
 
@@ -850,7 +892,7 @@ void launch_faces(const Dev& d, int n_faces, hipStream_t s) {
 void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes, int par,
                   hipStream_t s) {
     if (n_nodes > 0)
-        hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 3) / 4), dim3(256), 0, s, L, d, rho_n, cs, n_nodes, par);
+        hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 15) / 16), dim3(256), 0, s, L, d, rho_n, cs, n_nodes, par);
 }
 void launch_bin_scan(const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, d, par);
@@ -864,7 +906,7 @@ void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
 }
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s) {
     if (n_nodes > 0)
-        hipLaunchKernelGGL(k_interp_advect, dim3((n_nodes + 3) / 4), dim3(256), 0, s, L, d, n_nodes);
+        hipLaunchKernelGGL(k_interp_advect, dim3((n_nodes + 15) / 16), dim3(256), 0, s, L, d, n_nodes);
 }
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s) {
     if (n_caps > 0) hipLaunchKernelGGL(k_cap_moments, dim3(n_caps), dim3(256), 0, s, d);

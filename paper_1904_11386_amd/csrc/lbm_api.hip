@@ -25,7 +25,7 @@ struct Layout {
     size_t f[2], rho[2], fib, u;
     size_t tile_flag, tile_count, tile_offset, home_start, touched[2], home[2], counters;
     int64_t bins;
-    size_t off_hi, off_lo, node_cap, node_wet, node_F, node_tile, node_rank, sorted, csr_ptr, csr_idx,
+    size_t off_hi, off_lo, node_cap, node_anc, node_wet, node_F, node_tile, node_rank, sorted, csr_ptr, corner_slot,
         dbg_bins;
     size_t tri, fref, face_cap, face_F;
     size_t caps, capV, cap_mom, red, cscale, dpart, dmass;
@@ -76,13 +76,14 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     l.off_hi = take(c, 3 * nb * 4);
     l.off_lo = take(c, 3 * nb * 4);
     l.node_cap = take(c, nb * 4);
+    l.node_anc = take(c, nb * 16);
     l.node_wet = take(c, nb * 4);
     l.node_F = take(c, 3 * nb * 4);
     l.node_tile = take(c, nb * 4);
     l.node_rank = take(c, nb * 4);
     l.sorted = take(c, nb * 4);
     l.csr_ptr = take(c, (nb + 1) * 4);
-    l.csr_idx = take(c, 3 * nf * 4);
+    l.corner_slot = take(c, 3 * nf * 4);
     l.dbg_bins = take(c, 4 * nb * 4);
     l.tri = take(c, 3 * nf * 4);
     l.fref = take(c, nf * sizeof(FaceRef));
@@ -297,13 +298,14 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     d.off_hi = (float*)(w + lay.off_hi);
     d.off_lo = (float*)(w + lay.off_lo);
     d.node_cap = (int*)(w + lay.node_cap);
+    d.node_anc = (int4*)(w + lay.node_anc);
     d.node_wet = (float*)(w + lay.node_wet);
     d.node_F = (float*)(w + lay.node_F);
     d.node_tile = (int*)(w + lay.node_tile);
     d.node_rank = (int*)(w + lay.node_rank);
     d.sorted = (int*)(w + lay.sorted);
     d.csr_ptr = (int*)(w + lay.csr_ptr);
-    d.csr_idx = (int*)(w + lay.csr_idx);
+    d.corner_slot = (int*)(w + lay.corner_slot);
     d.dbg_bins = (int*)(w + lay.dbg_bins);
     d.tri = (int*)(w + lay.tri);
     d.fref = (FaceRef*)(w + lay.fref);
@@ -471,14 +473,22 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
         nofs += nn;
         fofs += nf;
     }
-    // node -> (face, corner) adjacency, in face order
-    std::vector<int> ptr(c->n_nodes + 1, 0), idx(3 * (size_t)c->n_faces);
+    // node -> (face, corner) adjacency: the corners of node b, in face
+    // order, own slots ptr[b] .. ptr[b+1]-1, where the face kernels store
+    // their corner forces
+    std::vector<int> ptr(c->n_nodes + 1, 0), slot(3 * (size_t)c->n_faces);
     for (int f = 0; f < c->n_faces; ++f)
         for (int j = 0; j < 3; ++j) ptr[c->tri_global[3 * f + j] + 1]++;
     for (int b = 0; b < c->n_nodes; ++b) ptr[b + 1] += ptr[b];
     std::vector<int> fill(ptr.begin(), ptr.end() - 1);
     for (int f = 0; f < c->n_faces; ++f)
-        for (int j = 0; j < 3; ++j) idx[fill[c->tri_global[3 * f + j]]++] = 3 * f + j;
+        for (int j = 0; j < 3; ++j) slot[3 * f + j] = fill[c->tri_global[3 * f + j]]++;
+    std::vector<int> anc(4 * (size_t)c->n_nodes);
+    for (int b = 0; b < c->n_nodes; ++b) {
+        const CapDev& cd = c->caps[c->node_cap[b]];
+        for (int j = 0; j < 3; ++j) anc[4 * b + j] = cd.anchor[j];
+        anc[4 * b + 3] = cd.pref;
+    }
     Dev& d = c->d;
     hipStream_t s = c->stream;
     const size_t nb = c->n_nodes, nf = c->n_faces;
@@ -489,7 +499,8 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
     HIPCHK(c, hipMemcpyAsync(d.node_wet, c->node_wet.data(), nb * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.node_area, c->node_area.data(), nb * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.csr_ptr, ptr.data(), (nb + 1) * 4, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(d.csr_idx, idx.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.corner_slot, slot.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.node_anc, anc.data(), nb * 16, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.tri, c->tri_global.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.fref, c->fref.data(), nf * sizeof(FaceRef), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.face_cap, c->face_cap.data(), nf * 4, hipMemcpyHostToDevice, s));

@@ -100,19 +100,20 @@ struct Dev {
     float* off_hi;        // [nodes][3]
     float* off_lo;        // [nodes][3]
     int* node_cap;        // [nodes]
+    int4* node_anc;       // [nodes] the capsule's anchor (x, y, z) and preferred component (w)
     float* node_wet;      // [nodes] |rho_v| A_b
     float* node_F;        // [nodes][3]
     int* node_tile;       // [nodes]
     int* node_rank;       // [nodes]
     int* sorted;          // [nodes]
-    int* csr_ptr;         // [nodes + 1]
-    int* csr_idx;         // [3 faces] face*3 + corner
+    int* csr_ptr;         // [nodes + 1] corners of node b: slots csr_ptr[b] .. csr_ptr[b+1]-1
+    int* corner_slot;     // [faces][3] slot of corner (face, k), in node order
     int* dbg_bins;        // [nodes][4] debug binning output
     // faces
     int* tri;             // [faces][3] global node indices
     FaceRef* fref;        // [faces]
     int* face_cap;        // [faces]
-    float* face_F;        // [faces][9]
+    float* face_F;        // [3 faces][3] corner forces, stored at the corners' slots
     // capsules
     CapDev* caps;         // [max caps]
     double* capV;         // [max caps]
