@@ -71,6 +71,13 @@ __device__ __forceinline__ T* ptrx(T* row, uint32_t x) {
     return (T*)((char*)row + x * (uint32_t)sizeof(T));
 }
 
+// Quotients of the collision: correctly rounded, or (FAST, the FP16 form,
+// whose storage rounding is far coarser) the hardware reciprocal, ~1 ulp.
+template <bool FAST>
+__device__ __forceinline__ float qdiv(float a, float b) {
+    return FAST ? a * __builtin_amdgcn_rcpf(b) : a / b;
+}
+
 template <typename T>
 __device__ __forceinline__ void store_pop(T* p, T v) {
 #if LBM_NT_STORE
@@ -217,14 +224,16 @@ template <bool WALLS, bool HALF, int I, typename EncAt>
 __device__ __forceinline__ void decode_one(const Lattice& L, int y, const Raw<HALF>& R, float ra_prev, float rb_prev,
                                            const EncAt& enc, Pulled& A, Pulled& B) {
     const PopT<HALF> v = R.v[I];
+    // FP16: f = rho_enc (w + g), as rho_enc g + rho_enc w (one mixed-precision
+    // FMA that reads the binary16 value directly)
     if (WALLS && ((cy(I) == 1 && y == 1) || (cy(I) == -1 && y == L.ny - 2))) {
-        A.f[I] = (HALF ? ra_prev * (wgt(opp(I)) + (float)v.x) : (float)v.x) + wall_term<I>(L, ra_prev);
-        B.f[I] = (HALF ? rb_prev * (wgt(opp(I)) + (float)v.y) : (float)v.y) + wall_term<I>(L, rb_prev);
+        A.f[I] = (HALF ? fmaf(ra_prev, (float)v.x, ra_prev * wgt(opp(I))) : (float)v.x) + wall_term<I>(L, ra_prev);
+        B.f[I] = (HALF ? fmaf(rb_prev, (float)v.y, rb_prev * wgt(opp(I))) : (float)v.y) + wall_term<I>(L, rb_prev);
     } else if (HALF) {
         float ea, eb;
         enc(cx(I), cy(I), cz(I), ea, eb);
-        A.f[I] = ea * (wgt(I) + (float)v.x);
-        B.f[I] = eb * (wgt(I) + (float)v.y);
+        A.f[I] = fmaf(ea, (float)v.x, ea * wgt(I));
+        B.f[I] = fmaf(eb, (float)v.y, eb * wgt(I));
     } else {
         A.f[I] = (float)v.x;
         B.f[I] = (float)v.y;
@@ -521,12 +530,18 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
     const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
-    float cpv[2] = {1.0f, 1.0f}, ccu[2] = {1.0f, 1.0f};
+    // FP16: cpv scales the stored densities to the decode densities of the
+    // writing step; ccu is this step's FP64 mass compensation, applied to
+    // the decoded populations through the staged decode densities
+    // (cdec = cpv ccu; decoding is linear in them, the wall term included)
+    float cpv[2] = {1.0f, 1.0f}, ccu[2] = {1.0f, 1.0f}, cdec[2] = {1.0f, 1.0f};
     if (HALF) {
         cpv[0] = cscale[2 * par_prev];
         cpv[1] = cscale[2 * par_prev + 1];
         ccu[0] = cscale[2 * par_cur];
         ccu[1] = cscale[2 * par_cur + 1];
+        cdec[0] = cpv[0] * ccu[0];
+        cdec[1] = cpv[1] * ccu[1];
     }
 
     // Does any tile that the block's column or its halo overlaps carry
@@ -553,7 +568,7 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
             stage_load<true, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
         else
             stage_load<false, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
-        if (HALF) stage_load<false, NE>(ne, P, zz, tid, rho_p, cpv, nullptr, nullptr, L);
+        if (HALF) stage_load<false, NE>(ne, P, zz, tid, rho_p, cdec, nullptr, nullptr, L);
     };
     auto store_plane = [&](int zz) {
         stage_store<2>(sp, np, zz, z0, tid);
@@ -584,12 +599,6 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                     b = se.v[sl][NE - 1][ty + 1 - ey][tx + 1 - ex];
                 };
                 decode<WALLS, true>(L, y, rcur, se.v[s0][0][ty + 1][tx + 1], se.v[s0][NE - 1][ty + 1][tx + 1], enc, A, B);
-                // FP64 mass compensation of this step
-#pragma unroll
-                for (int i = 0; i < Q; ++i) {
-                    A.f[i] *= ccu[0];
-                    B.f[i] *= ccu[1];
-                }
             } else {
                 auto none = [](int, int, int, float&, float&) {};
                 const float rpa = WALLS ? ldx(rho_p + row, xo) : 0.0f;
@@ -627,7 +636,7 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                 flagged = tile_flag[t] != 0;
                 if (flagged) {
                     // immersed-boundary force shared by mass fraction
-                    const float fa = ra / rsum, fb = rb / rsum;
+                    const float fa = qdiv<HALF>(ra, rsum), fb = qdiv<HALF>(rb, rsum);
 #pragma unroll
                     for (int d = 0; d < 3; ++d) {
                         const float Fi = ldx(fib + d * N + row, xo);
@@ -638,12 +647,12 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
             }
             // common velocity u' and the shifted equilibrium velocities
             const float wa = L.omega[0], wb = L.omega[1];
-            const float den = 1.0f / (ra * wa + rb * wb);
+            const float den = qdiv<HALF>(1.0f, ra * wa + rb * wb);
             const float upx = (jax * wa + jbx * wb) * den;
             const float upy = (jay * wa + jby * wb) * den;
             const float upz = (jaz * wa + jbz * wb) * den;
             if (MACRO || (IBM && flagged)) {
-                const float ir = 1.0f / rsum;
+                const float ir = qdiv<HALF>(1.0f, rsum);
                 *ptrx(u_out + row, xo) = (jax + jbx + 0.5f * (Fa[0] + Fb[0])) * ir;
                 *ptrx(u_out + N + row, xo) = (jay + jby + 0.5f * (Fa[1] + Fb[1])) * ir;
                 *ptrx(u_out + 2 * N + row, xo) = (jaz + jbz + 0.5f * (Fa[2] + Fb[2])) * ir;
@@ -654,14 +663,14 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
                     const float* F = c == 0 ? Fa : Fb;
-                    const float ts = L.tau[c] / r2[c];
+                    const float ts = qdiv<HALF>(L.tau[c], r2[c]);
                     ux[c] = upx + ts * F[0];
                     uy[c] = upy + ts * F[1];
                     uz[c] = upz + ts * F[2];
                     base[c] = r2[c] * (1.0f - 1.5f * (ux[c] * ux[c] + uy[c] * uy[c] + uz[c] * uz[c]));
                     // FP16: encode relative to this node's compensated density,
                     // bit-identical to what the next step's decoder stages
-                    inv[c] = HALF ? 1.0f / (ccu[c] * ldx(rho_n + c * N + row, xo)) : 1.0f;
+                    inv[c] = HALF ? qdiv<true>(1.0f, ccu[c] * ldx(rho_n + c * N + row, xo)) : 1.0f;
                     rest[c] = r2[c];
                 }
                 PopT<HALF>* fo = fout + row;
