@@ -66,6 +66,17 @@ template <typename T>
 __device__ __forceinline__ T ldx(const T* __restrict__ row, uint32_t x) {
     return *(const T*)((const char*)row + x * (uint32_t)sizeof(T));
 }
+// Cache policy of the population streams (every population is read once
+// and written once per pass).  A lattice whose population buffer fits the
+// caches' reach well (CACHED) loads populations non-temporally and stores
+// them normally; a larger one does the opposite.  Each was measured the
+// faster on its side (a 128^3 and a 512^3 lattice).
+template <bool NT, typename T>
+__device__ __forceinline__ T ldpop(const T* __restrict__ row, uint32_t x) {
+    const T* p = (const T*)((const char*)row + x * (uint32_t)sizeof(T));
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
 template <typename T>
 __device__ __forceinline__ T* ptrx(T* row, uint32_t x) {
     return (T*)((char*)row + x * (uint32_t)sizeof(T));
@@ -78,13 +89,10 @@ __device__ __forceinline__ float qdiv(float a, float b) {
     return FAST ? a * __builtin_amdgcn_rcpf(b) : a / b;
 }
 
-template <typename T>
+template <bool NT, typename T>
 __device__ __forceinline__ void store_pop(T* p, T v) {
-#if LBM_NT_STORE
-    __builtin_nontemporal_store(v, p);
-#else
-    *p = v;
-#endif
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
 }
 
 // Populations of the two components for one direction and node sit side by
@@ -126,11 +134,11 @@ struct PullCtx {
 // the decode densities of the source node x - c (FP16 form only); ra_prev,
 // rb_prev are the node's own previous densities (wall term, and the decode
 // density of its own reflected population).
-template <bool WALLS, bool HALF, int I, typename EncAt>
+template <bool WALLS, bool HALF, bool NTL, int I, typename EncAt>
 __device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                          float ra_prev, float rb_prev, const EncAt& enc, Pulled& A, Pulled& B) {
     if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
-        const PopT<HALF> v = ldx(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
+        const PopT<HALF> v = ldpop<NTL>(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
         A.f[I] = (HALF ? ra_prev * (wgt(opp(I)) + (float)v.x) : (float)v.x) + wall_term<I>(L, ra_prev);
         B.f[I] = (HALF ? rb_prev * (wgt(opp(I)) + (float)v.y) : (float)v.y) + wall_term<I>(L, rb_prev);
     } else {
@@ -138,7 +146,7 @@ __device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const
         const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
         const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
         const uint32_t srow = (uint32_t)((sz * L.ny + sy) * L.nx);
-        const PopT<HALF> v = ldx(f + (int64_t)I * L.n + srow, (uint32_t)sx);
+        const PopT<HALF> v = ldpop<NTL>(f + (int64_t)I * L.n + srow, (uint32_t)sx);
         if (HALF) {
             float ea, eb;
             enc(cx(I), cy(I), cz(I), ea, eb);
@@ -151,14 +159,14 @@ __device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const
     }
 }
 
-template <bool WALLS, bool HALF, typename EncAt, int... Is>
+template <bool WALLS, bool HALF, bool NTL, typename EncAt, int... Is>
 __device__ __forceinline__ void pull_all(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                          float ra_prev, float rb_prev, const EncAt& enc, Pulled& A, Pulled& B,
                                          std::integer_sequence<int, Is...>) {
-    (pull_one<WALLS, HALF, Is>(f, L, c, ra_prev, rb_prev, enc, A, B), ...);
+    (pull_one<WALLS, HALF, NTL, Is>(f, L, c, ra_prev, rb_prev, enc, A, B), ...);
 }
 
-template <bool WALLS, bool HALF, typename EncAt>
+template <bool WALLS, bool HALF, bool NTL = false, typename EncAt>
 __device__ __forceinline__ void pull(const PopT<HALF>* __restrict__ f, const Lattice& L, int64_t node, int x,
                                      int y, int z, float ra_prev, float rb_prev, const EncAt& enc, Pulled& A,
                                      Pulled& B) {
@@ -168,7 +176,7 @@ __device__ __forceinline__ void pull(const PopT<HALF>* __restrict__ f, const Lat
     c.xm = x == 0 ? L.nx - 1 : x - 1; c.xp = x == L.nx - 1 ? 0 : x + 1;
     c.ym = y == 0 ? L.ny - 1 : y - 1; c.yp = y == L.ny - 1 ? 0 : y + 1;
     c.zm = z == 0 ? L.nz - 1 : z - 1; c.zp = z == L.nz - 1 ? 0 : z + 1;
-    pull_all<WALLS, HALF>(f, L, c, ra_prev, rb_prev, enc, A, B, std::make_integer_sequence<int, Q>{});
+    pull_all<WALLS, HALF, NTL>(f, L, c, ra_prev, rb_prev, enc, A, B, std::make_integer_sequence<int, Q>{});
 }
 
 // The same pull in two phases, so that a z-marching kernel can issue the
@@ -180,24 +188,24 @@ struct Raw {
     PopT<HALF> v[Q];
 };
 
-template <bool WALLS, bool HALF, int I>
+template <bool WALLS, bool HALF, bool NTL, int I>
 __device__ __forceinline__ void load_raw_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                              Raw<HALF>& R) {
     if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
-        R.v[I] = ldx(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
+        R.v[I] = ldpop<NTL>(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
     } else {
         const int sx = cx(I) == 1 ? c.xm : (cx(I) == -1 ? c.xp : c.x);
         const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
         const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
         const uint32_t srow = (uint32_t)((sz * L.ny + sy) * L.nx);
-        R.v[I] = ldx(f + (int64_t)I * L.n + srow, (uint32_t)sx);
+        R.v[I] = ldpop<NTL>(f + (int64_t)I * L.n + srow, (uint32_t)sx);
     }
 }
 
-template <bool WALLS, bool HALF, int... Is>
+template <bool WALLS, bool HALF, bool NTL, int... Is>
 __device__ __forceinline__ void load_raw_all(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                              Raw<HALF>& R, std::integer_sequence<int, Is...>) {
-    (load_raw_one<WALLS, HALF, Is>(f, L, c, R), ...);
+    (load_raw_one<WALLS, HALF, NTL, Is>(f, L, c, R), ...);
 }
 
 __device__ __forceinline__ PullCtx pull_ctx(const Lattice& L, int64_t node, int x, int y, int z) {
@@ -214,10 +222,10 @@ __device__ __forceinline__ PullCtx pull_ctx(const Lattice& L, int64_t node, int 
     return c;
 }
 
-template <bool WALLS, bool HALF>
+template <bool WALLS, bool HALF, bool NTL = false>
 __device__ __forceinline__ void load_raw(const PopT<HALF>* __restrict__ f, const Lattice& L, int64_t node, int x,
                                          int y, int z, Raw<HALF>& R) {
-    load_raw_all<WALLS, HALF>(f, L, pull_ctx(L, node, x, y, z), R, std::make_integer_sequence<int, Q>{});
+    load_raw_all<WALLS, HALF, NTL>(f, L, pull_ctx(L, node, x, y, z), R, std::make_integer_sequence<int, Q>{});
 }
 
 template <bool WALLS, bool HALF, int I, typename EncAt>
@@ -391,7 +399,7 @@ __device__ __forceinline__ void stage_store(Ring<NR>& R, const StageRegs<NC>& S,
 
 // ---------------------------------------------------------------------------
 // Density pass, FP32: one thread per node.
-template <bool WALLS>
+template <bool WALLS, bool CACHED>
 __global__ __launch_bounds__(256) void k_density(const pf2* __restrict__ fin,
                                                  const float* __restrict__ rho_prev,
                                                  float* __restrict__ rho_out, Lattice L) {
@@ -408,14 +416,14 @@ __global__ __launch_bounds__(256) void k_density(const pf2* __restrict__ fin,
     Pulled A, B;
     const float rpa = WALLS ? ldx(rho_prev + row, (uint32_t)x) : 0.0f;
     const float rpb = WALLS ? ldx(rho_prev + L.n + row, (uint32_t)x) : 0.0f;
-    pull<WALLS, false>(fin, L, node, x, y, z, rpa, rpb, none, A, B);
+    pull<WALLS, false, CACHED>(fin, L, node, x, y, z, rpa, rpb, none, A, B);
     *ptrx(rho_out + row, (uint32_t)x) = sum_pop(A);
     *ptrx(rho_out + L.n + row, (uint32_t)x) = sum_pop(B);
 }
 
 // Density pass, FP16: z-marching column with the decode densities
 // cscale(prev) * rho^{n-1} staged in LDS, plus FP64 block sums of rho^n.
-template <bool WALLS>
+template <bool WALLS, bool CACHED>
 __global__ __launch_bounds__(256) void k_density_half(const ph2* __restrict__ fin,
                                                       const float* __restrict__ rho_prev,
                                                       const float* __restrict__ cscale, int par_prev,
@@ -444,7 +452,7 @@ __global__ __launch_bounds__(256) void k_density_half(const ph2* __restrict__ fi
         stage_load<false, 2>(st, P, z + 1, tid, rho_prev, cp, nullptr, nullptr, L);
         stage_store<2>(ring, st, z + 1, z0, tid);
         __syncthreads();
-        if (active) load_raw<WALLS, true>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
+        if (active) load_raw<WALLS, true, CACHED>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
         if (active) {
             const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx);
             const int s0 = (z - z0 + 1) % 3;
@@ -512,7 +520,7 @@ __global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Fused pull + force + collide.  MACRO: recompute the velocity of this
 // collision without storing populations (field read-back).
-template <bool WALLS, bool IBM, bool MACRO, bool HALF>
+template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED>
 __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
@@ -587,7 +595,7 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
         load_plane(z + 1);
         store_plane(z + 1);
         __syncthreads();
-        if (active) load_raw<WALLS, HALF>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
+        if (active) load_raw<WALLS, HALF, CACHED>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
         if (active) {
             const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx), xo = (uint32_t)x;
             const int s0 = (z - z0 + 1) % 3;
@@ -686,13 +694,13 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                         rest[c] -= fs[c];
                         if (HALF) fs[c] = fs[c] * inv[c] - wgt(i);
                     }
-                    store_pop(ptrx(fo + (int64_t)i * N, xo), pack<HALF>(fs[0], fs[1]));
+                    store_pop<!CACHED>(ptrx(fo + (int64_t)i * N, xo), pack<HALF>(fs[0], fs[1]));
                 }
                 // rest populations close the node's mass
                 if (HALF)
-                    store_pop(ptrx(fo, xo), pack<HALF>(rest[0] * inv[0] - wgt(0), rest[1] * inv[1] - wgt(0)));
+                    store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(rest[0] * inv[0] - wgt(0), rest[1] * inv[1] - wgt(0)));
                 else
-                    store_pop(ptrx(fo, xo), pack<HALF>(rest[0], rest[1]));
+                    store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(rest[0], rest[1]));
             }
         } else if (MACRO && x < L.nx && y < L.ny) {
             const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
@@ -1138,19 +1146,20 @@ void launch_density(const Lattice& L, const void* fin, const float* rho_prev, fl
                     const float* cscale, int par_prev, double* partial, hipStream_t s) {
     const dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, half ? (L.nz + L.zc - 1) / L.zc : L.nz);
     const dim3 block(BX, BY);
+#define LD_H(W, C)                                                                                            \
+    hipLaunchKernelGGL((k_density_half<W, C>), grid, block, 0, s, (const ph2*)fin, rho_prev, cscale, par_prev, \
+                       rho_out, partial, L)
+#define LD_F(W, C) hipLaunchKernelGGL((k_density<W, C>), grid, block, 0, s, (const pf2*)fin, rho_prev, rho_out, L)
+    const bool w = L.walls != 0, c = L.cached != 0;
     if (half) {
-        if (L.walls)
-            hipLaunchKernelGGL(k_density_half<true>, grid, block, 0, s, (const ph2*)fin, rho_prev, cscale,
-                               par_prev, rho_out, partial, L);
-        else
-            hipLaunchKernelGGL(k_density_half<false>, grid, block, 0, s, (const ph2*)fin, rho_prev, cscale,
-                               par_prev, rho_out, partial, L);
+        if (w) { if (c) LD_H(true, true); else LD_H(true, false); }
+        else { if (c) LD_H(false, true); else LD_H(false, false); }
     } else {
-        if (L.walls)
-            hipLaunchKernelGGL(k_density<true>, grid, block, 0, s, (const pf2*)fin, rho_prev, rho_out, L);
-        else
-            hipLaunchKernelGGL(k_density<false>, grid, block, 0, s, (const pf2*)fin, rho_prev, rho_out, L);
+        if (w) { if (c) LD_F(true, true); else LD_F(true, false); }
+        else { if (c) LD_F(false, true); else LD_F(false, false); }
     }
+#undef LD_F
+#undef LD_H
 }
 
 void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale, int par_cur,
@@ -1165,8 +1174,16 @@ static void launch_collide_t(const Lattice& L, const void* fin, void* fout, cons
                              const float* cscale, int par_prev, int par_cur, hipStream_t s) {
     dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc);
     dim3 block(BX, BY);
-    hipLaunchKernelGGL((k_collide<W, I, M, H>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout, rho_n,
-                       rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+    // the velocity read-back (M) writes no populations; it runs in one policy
+    if constexpr (!M) {
+        if (L.cached) {
+            hipLaunchKernelGGL((k_collide<W, I, M, H, true>), grid, block, 0, s, (const PopT<H>*)fin,
+                               (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+            return;
+        }
+    }
+    hipLaunchKernelGGL((k_collide<W, I, M, H, false>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout,
+                       rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
 }
 
 void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,

@@ -274,6 +274,9 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     L.nbx = (p->nx + BIN - 1) / BIN; L.nby = (p->ny + BIN - 1) / BIN; L.nbz = (p->nz + BIN - 1) / BIN;
     L.n = N;
     L.zc = zc_for(p);
+    // a population buffer of at most 512 MiB (128^3 in FP32) streams with
+    // non-temporal loads and cached stores, a larger one the other way round
+    L.cached = (int64_t)N * 2 * Q * (p->precision == LBM_FP16 ? 2 : 4) <= ((int64_t)512 << 20) ? 1 : 0;
     L.walls = p->walls;
     L.G = (float)p->G;
     for (int k = 0; k < 2; ++k) { L.tau[k] = (float)p->tau[k]; L.omega[k] = (float)(1.0 / p->tau[k]); }

@@ -43,9 +43,6 @@ constexpr int BOX = BIN + 3;   // spreading box edge: stencil reach of one bin's
 #ifndef LBM_XCD_REMAP
 #define LBM_XCD_REMAP 0
 #endif
-#ifndef LBM_NT_STORE
-#define LBM_NT_STORE 1
-#endif
 constexpr int BX = LBM_BX;     // lattice blocks: x extent (a multiple of the wavefront)
 constexpr int BY = LBM_BY;     // lattice blocks: y extent
 constexpr int ZC = LBM_ZC;     // lattice blocks: fewest z planes marched per block
@@ -56,6 +53,7 @@ struct Lattice {
     int ntx, nty, ntz;     // tile counts (TILE)
     int nbx, nby, nbz;     // bin counts (BIN)
     int zc;                // z planes marched per lattice block (a multiple of ZC)
+    int cached;            // population streams: non-temporal loads, cached stores (1) or the reverse
     int64_t n;             // nx*ny*nz
     int walls;
     float G;
