@@ -148,6 +148,62 @@ def adjoint_leg(torch, steps=2000, every=100):
             "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3)}
 
 
+def precision_study(torch, steps):
+    """The FP16 g-storage form beside the FP32 form on the 256^3 droplet
+    workload (B droplet of radius 60 in A, 64 capsules of 642 nodes on a
+    shell of radius 66, angles in [45, 135] deg): per-component FP64 mass
+    drift, droplet radius, density difference and capsule heights after
+    `steps` steps, and each form's MLUPS.  (Against the FP64 oracle the same
+    forms are checked on the 64^3 copy by the GPU tests.)"""
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
+    wl = workloads.make("c3")
+    m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
+
+    def radius(rb):
+        v = ((np.asarray(rb, dtype=np.float64) - workloads.RHO_MIN) / (workloads.RHO_MAJ - workloads.RHO_MIN)).sum()
+        return float((3.0 * v / (4.0 * np.pi)) ** (1.0 / 3.0))
+
+    out, kept = {"workload": "256^3 periodic box, B droplet R=60 in A, %d capsules R=6 (642 nodes) on a shell "
+                             "of radius 66, theta~U[45,135] deg" % len(wl.capsules), "steps": steps}, {}
+    # a second FP32 run is the control: spreading sums with float atomics,
+    # so two runs of one form differ by rounding order, and after many steps
+    # the capsules' trajectories separate on their own
+    for name, prec in (("fp32", LBM_FP32), ("fp32_rerun", LBM_FP32), ("fp16", LBM_FP16)):
+        print("bench: precision study, %s form, %d steps" % (name, steps), file=sys.stderr, flush=True)
+        sim = sim_from_workload(wl, precision=prec)
+        t0 = time.perf_counter()
+        done = 0
+        while done < steps:
+            k = min(2000, steps - done)
+            sim.step(k)
+            sim.synchronize()
+            done += k
+            print("bench: precision study, %s form, %d / %d steps" % (name, done, steps), file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t0
+        ra, rb, _ = sim.fields()
+        obs = sim.observables()
+        kept[name] = (ra, rb, [c["height"] for c in obs["caps"]])
+        out[name] = {"mlups": round(wl.n_lattice * steps / wall / 1e6, 1),
+                     "mass_drift": [float(v) for v in (obs["mass"] / m0 - 1)],
+                     "droplet_radius": round(radius(rb), 5)}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    a32, b32, h32 = kept["fp32"]
+
+    def diff(other):
+        a, b, h = kept[other]
+        return {"rho_rel_max": [float(np.abs(a - a32).max() / np.abs(a32).max()),
+                                float(np.abs(b - b32).max() / np.abs(b32).max())],
+                "droplet_radius_diff": round(out[other]["droplet_radius"] - out["fp32"]["droplet_radius"], 6),
+                "capsule_height_diff_max": float(np.abs(np.array(h) - np.array(h32)).max())}
+    out["fp16_vs_fp32"] = diff("fp16")
+    out["fp16_vs_fp32"]["mlups_ratio"] = round(out["fp16"]["mlups"] / out["fp32"]["mlups"], 3)
+    out["fp32_rerun_vs_fp32"] = diff("fp32_rerun")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +214,8 @@ def main():
     ap.add_argument("--no-fp16-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="also run the FP16/FP32 precision study on the 256^3 droplet for STEPS steps")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -242,6 +300,8 @@ def main():
         torch.cuda.empty_cache()
     if args.precision == "fp32" and not args.no_adjoint_leg:
         out["adjoint"] = adjoint_leg(torch)
+    if args.precision_study > 0:
+        out["precision_study"] = precision_study(torch, args.precision_study)
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
