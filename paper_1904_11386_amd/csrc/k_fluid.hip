@@ -38,15 +38,25 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Block coordinates, optionally in an XCD-aware order: workgroups are dealt
-// to the 8 dies round-robin, so linear id b runs on die b % 8; the remap
-// gives each die a contiguous run of the (x, y, z)-ordered block grid.
+// Block coordinates, optionally in an XCD-aware order.  Workgroups are dealt
+// to the 8 dies round-robin (linear id b runs on die b % 8).  Mode 1 gives
+// each die a contiguous run of the (x, y, z)-ordered grid; mode 2 gives each
+// die a contiguous strip of block rows in y through every z, so that blocks
+// sharing halo rows share an L2 while every die still meets the capsules.
 __device__ __forceinline__ void block_xyz(int& bx, int& by, int& bz) {
     const int gx = gridDim.x, gy = gridDim.y;
     int b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
-#if LBM_XCD_REMAP
+#if LBM_XCD_REMAP == 1
     const int nb = gx * gy * gridDim.z;
     if (nb % NXCD == 0) b = (b % NXCD) * (nb / NXCD) + b / NXCD;
+#elif LBM_XCD_REMAP == 2
+    if (gy % NXCD == 0) {
+        const int die = b % NXCD, slot = b / NXCD, R = gy / NXCD;
+        bx = slot % gx;
+        by = die * R + (slot / gx) % R;
+        bz = slot / (gx * R);
+        return;
+    }
 #endif
     bx = b % gx;
     by = (b / gx) % gy;

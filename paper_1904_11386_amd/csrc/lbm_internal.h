@@ -41,7 +41,7 @@ constexpr int BOX = BIN + 3;   // spreading box edge: stencil reach of one bin's
 #define LBM_ZC 8
 #endif
 #ifndef LBM_XCD_REMAP
-#define LBM_XCD_REMAP 0
+#define LBM_XCD_REMAP 2
 #endif
 constexpr int BX = LBM_BX;     // lattice blocks: x extent (a multiple of the wavefront)
 constexpr int BY = LBM_BY;     // lattice blocks: y extent
