@@ -87,7 +87,15 @@ typedef struct lbm_params {
                                of Sec. II.D as written                           */
     int32_t ring_len;       /* > 0: room for the adjoint (FP32 only), with a
                                recompute ring of ring_len states                 */
-    int32_t reserved2;
+    int32_t stream_policy;  /* cache policy of the population streams:
+                               0 chosen by size (1 up to 512 MiB of populations,
+                               else 2); 1 non-temporal loads, cached stores;
+                               2 cached loads, non-temporal stores. Results do
+                               not depend on it.                                 */
+    int32_t zchunk;         /* z planes marched per lattice block: 0 chosen by
+                               storage form and grid size, else a multiple of 8
+                               up to 64. Results do not depend on it.            */
+    int32_t reserved[3];    /* zero                                              */
 } lbm_params;
 
 typedef struct lbm_obs {

@@ -29,7 +29,8 @@ class Params(C.Structure):
                 ("rho_maj", C.c_double), ("rho_min", C.c_double),
                 ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
                 ("z_interface", C.c_double), ("mass_tol", C.c_double), ("wet_scale", C.c_double),
-                ("ring_len", C.c_int32), ("reserved2", C.c_int32)]
+                ("ring_len", C.c_int32), ("stream_policy", C.c_int32), ("zchunk", C.c_int32),
+                ("reserved", C.c_int32 * 3)]
 
 
 class Obs(C.Structure):
@@ -103,7 +104,8 @@ def _ptr(a, ctype):
 
 def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
-                check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0):
+                check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0, stream_policy=0,
+                zchunk=0):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -121,6 +123,8 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.wet_scale = wet_scale
     p.use_graphs = use_graphs
     p.ring_len = ring_len
+    p.stream_policy = stream_policy
+    p.zchunk = zchunk
     return p
 
 
@@ -273,13 +277,15 @@ class Sim:
             pass
 
 
-def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1, ring_len=0):
+def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1, ring_len=0,
+                      stream_policy=0, zchunk=0):
     """Build a Sim for a seeded workload (paper_1904_11386_amd.workloads)."""
     npc, fpc, xyz, tri = wl.meshes()
     p = make_params(wl.nx, wl.ny, wl.nz, tau=wl.tau, G=wl.G, walls=wl.walls, wall_u_lo=wl.wall_u_lo,
                     wall_u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
-                    check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len)
+                    check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len,
+                    stream_policy=stream_policy, zchunk=zchunk)
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()

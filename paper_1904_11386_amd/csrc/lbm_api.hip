@@ -160,6 +160,9 @@ std::string validate(const lbm_params* p) {
     if (p->use_graphs != 0 && p->use_graphs != 1) return "use_graphs must be 0 or 1";
     if (p->ring_len < 0 || p->ring_len > 100000) return "ring_len out of range";
     if (p->ring_len > 0 && p->precision != LBM_FP32) return "the adjoint needs FP32 storage";
+    if (p->stream_policy < 0 || p->stream_policy > 2) return "stream_policy must be 0, 1 or 2";
+    if (p->zchunk != 0 && (p->zchunk % ZC != 0 || p->zchunk > 8 * ZC)) return "zchunk must be 0 or a multiple of 8 up to 64";
+    if (p->reserved[0] || p->reserved[1] || p->reserved[2]) return "reserved fields must be zero";
     return "";
 }
 
@@ -273,10 +276,13 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     L.ntx = (p->nx + TILE - 1) / TILE; L.nty = (p->ny + TILE - 1) / TILE; L.ntz = (p->nz + TILE - 1) / TILE;
     L.nbx = (p->nx + BIN - 1) / BIN; L.nby = (p->ny + BIN - 1) / BIN; L.nbz = (p->nz + BIN - 1) / BIN;
     L.n = N;
-    L.zc = zc_for(p);
+    L.zc = p->zchunk ? p->zchunk : zc_for(p);
     // a population buffer of at most 512 MiB (128^3 in FP32) streams with
     // non-temporal loads and cached stores, a larger one the other way round
-    L.cached = (int64_t)N * 2 * Q * (p->precision == LBM_FP16 ? 2 : 4) <= ((int64_t)512 << 20) ? 1 : 0;
+    if (p->stream_policy == 0)
+        L.cached = (int64_t)N * 2 * Q * (p->precision == LBM_FP16 ? 2 : 4) <= ((int64_t)512 << 20) ? 1 : 0;
+    else
+        L.cached = p->stream_policy == 1 ? 1 : 0;
     L.walls = p->walls;
     L.G = (float)p->G;
     for (int k = 0; k < 2; ++k) { L.tau[k] = (float)p->tau[k]; L.omega[k] = (float)(1.0 / p->tau[k]); }

@@ -42,11 +42,18 @@ def test_workspace_bytes_and_validation():
     assert B.workspace_bytes(p2, 0, 0) > n0
     lib = B.load()
     out = C.c_int64()
-    for bad in (dict(tau=(0.5, 1.0)), dict(G=-1.0), dict(walls=3), dict(precision=7)):
+    for bad in (dict(tau=(0.5, 1.0)), dict(G=-1.0), dict(walls=3), dict(precision=7), dict(stream_policy=3),
+                dict(zchunk=12), dict(zchunk=72), dict(ring_len=4, precision=B.LBM_FP16)):
         pb = B.make_params(16, 16, 16, **bad)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
         assert lib.lbm_last_error(None)
     pb = B.make_params(3, 16, 16)
+    assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
+    pb = B.make_params(16, 16, 16)
+    pb.reserved[1] = 1
+    assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
+    # more than 2^30 nodes cannot be addressed with 32-bit offsets
+    pb = B.make_params(1024, 1024, 1025)
     assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
     # init rejects a bad tau before touching the (bogus) workspace pointer
     pb = B.make_params(16, 16, 16, tau=(0.4, 1.0))

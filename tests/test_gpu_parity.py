@@ -108,6 +108,32 @@ def test_capsule_across_one_cell_partial_tiles():
     _compare_run(wl, 40, 5e-6, 1e-5, tol_x=2e-5)
 
 
+@pytest.mark.parametrize("precision,policy,zchunk,walls", [("fp32", 2, 16, 0), ("fp16", 2, 16, 0), ("fp16", 1, 24, 0),
+                                                            ("fp32", 1, 8, 0), ("fp32", 2, 16, 1), ("fp16", 2, 8, 1)])
+def test_stream_policy_and_zchunk(precision, policy, zchunk, walls):
+    """The population cache policy and the z planes per block are chosen by
+    lattice size; forcing each choice on a small ragged lattice or the walled
+    channel (so every kernel variant meets the oracle) must not change the
+    results."""
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32
+    wl = W.make("c4_mini") if walls else W.small(nx=40, ny=36, nz=44, ncap=2, theta=(70.0, 115.0))
+    steps = 40
+    prec = LBM_FP16 if precision == "fp16" else LBM_FP32
+    _say("case", wl.name, precision, "policy", policy, "zchunk", zchunk, "steps", steps)
+    g = _sim(wl, precision=prec, stream_policy=policy, zchunk=zchunk)
+    g.step(steps)
+    o = from_workload(wl).run(steps)
+    ra, rb, _ = g.fields()
+    fm = _fluid(wl)
+    ea = _rel(ra[:, fm], o.rho_last[0].numpy()[:, fm])
+    eb = _rel(rb[:, fm], o.rho_last[1].numpy()[:, fm])
+    dx = float(np.abs(g.nodes() - torch.cat(o.X, 0).numpy()).max())
+    _say("  rho rel err %.3e %.3e  node position err %.3e lu" % (ea, eb, dx))
+    tol = 1e-3 if precision == "fp16" else 5e-6
+    assert ea <= tol and eb <= tol
+    assert dx <= (1e-3 if precision == "fp16" else 2e-5)
+
+
 def test_walls_channel_parity():
     wl = W.make("c4_mini")
     _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
