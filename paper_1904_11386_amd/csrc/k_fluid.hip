@@ -38,26 +38,21 @@ __device__ __forceinline__ int wrapi(int v, int n) {
     return v < 0 ? v + n : v;
 }
 
-// Block coordinates, optionally in an XCD-aware order.  Workgroups are dealt
-// to the 8 dies round-robin (linear id b runs on die b % 8).  Mode 1 gives
-// each die a contiguous run of the (x, y, z)-ordered grid; mode 2 gives each
-// die a contiguous strip of block rows in y through every z, so that blocks
-// sharing halo rows share an L2 while every die still meets the capsules.
-__device__ __forceinline__ void block_xyz(int& bx, int& by, int& bz) {
+// Block coordinates in an XCD-aware order.  Workgroups are dealt to the 8
+// dies round-robin (linear id b runs on die b % 8).  With ystrips each die
+// takes a contiguous strip of block rows in y through every z, so blocks that
+// share halo rows share an L2 while every die still meets the capsules;
+// without, the grid is walked in (x, y, z) order.
+__device__ __forceinline__ void block_xyz(int& bx, int& by, int& bz, bool ystrips = true) {
     const int gx = gridDim.x, gy = gridDim.y;
-    int b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
-#if LBM_XCD_REMAP == 1
-    const int nb = gx * gy * gridDim.z;
-    if (nb % NXCD == 0) b = (b % NXCD) * (nb / NXCD) + b / NXCD;
-#elif LBM_XCD_REMAP == 2
-    if (gy % NXCD == 0) {
+    const int b = (blockIdx.z * gy + blockIdx.y) * gx + blockIdx.x;
+    if (ystrips && gy % NXCD == 0) {
         const int die = b % NXCD, slot = b / NXCD, R = gy / NXCD;
         bx = slot % gx;
         by = die * R + (slot / gx) % R;
         bz = slot / (gx * R);
         return;
     }
-#endif
     bx = b % gx;
     by = (b / gx) % gy;
     bz = b / (gx * gy);
@@ -544,7 +539,9 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
     const int tx = threadIdx.x, ty = uniform_ty();
     const int tid = ty * BX + tx;
     int bx, by, bz;
-    block_xyz(bx, by, bz);
+    // y-strips on cache-sized lattices; on larger ones the plain order
+    // measured faster for this kernel (the density passes gain either way)
+    block_xyz(bx, by, bz, CACHED);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
     const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;

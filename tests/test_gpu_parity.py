@@ -233,7 +233,8 @@ def test_graph_replay_matches_eager():
         ra_e, rb_e, u_e = ge.fields()
         ra_g, rb_g, u_g = gg.fields()
         assert np.abs(ra_e - ra_g).max() < 1e-6 and np.abs(rb_e - rb_g).max() < 1e-6
-        assert np.abs(u_e - u_g).max() < 1e-7
+        # a few FP32 ulps of |u| (a missing or reordered kernel shows as 1e-3 or more)
+        assert np.abs(u_e - u_g).max() < 1e-5 * max(np.abs(u_e).max(), 1e-3)
         assert np.abs(ge.nodes() - gg.nodes()).max() < 1e-6
         assert np.allclose(oe["mass"], og["mass"], rtol=1e-7)
 
