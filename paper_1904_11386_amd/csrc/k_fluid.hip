@@ -132,6 +132,7 @@ struct Pulled {
 struct PullCtx {
     int x, xm, xp, y, ym, yp, z, zm, zp;
     int64_t node;
+    int64_t n;          // direction stride (a per-plane copy of L.n)
     uint32_t row;
 };
 
@@ -143,7 +144,7 @@ template <bool WALLS, bool HALF, bool NTL, int I, typename EncAt>
 __device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                          float ra_prev, float rb_prev, const EncAt& enc, Pulled& A, Pulled& B) {
     if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
-        const PopT<HALF> v = ldpop<NTL>(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
+        const PopT<HALF> v = ldpop<NTL>(f + opp(I) * c.n + c.row, (uint32_t)c.x);
         A.f[I] = (HALF ? ra_prev * (wgt(opp(I)) + (float)v.x) : (float)v.x) + wall_term<I>(L, ra_prev);
         B.f[I] = (HALF ? rb_prev * (wgt(opp(I)) + (float)v.y) : (float)v.y) + wall_term<I>(L, rb_prev);
     } else {
@@ -151,7 +152,7 @@ __device__ __forceinline__ void pull_one(const PopT<HALF>* __restrict__ f, const
         const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
         const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
         const uint32_t srow = (uint32_t)((sz * L.ny + sy) * L.nx);
-        const PopT<HALF> v = ldpop<NTL>(f + (int64_t)I * L.n + srow, (uint32_t)sx);
+        const PopT<HALF> v = ldpop<NTL>(f + I * c.n + srow, (uint32_t)sx);
         if (HALF) {
             float ea, eb;
             enc(cx(I), cy(I), cz(I), ea, eb);
@@ -176,7 +177,7 @@ __device__ __forceinline__ void pull(const PopT<HALF>* __restrict__ f, const Lat
                                      int y, int z, float ra_prev, float rb_prev, const EncAt& enc, Pulled& A,
                                      Pulled& B) {
     PullCtx c;
-    c.x = x; c.y = y; c.z = z; c.node = node;
+    c.x = x; c.y = y; c.z = z; c.node = node; c.n = L.n;
     c.row = (uint32_t)((z * L.ny + y) * L.nx);
     c.xm = x == 0 ? L.nx - 1 : x - 1; c.xp = x == L.nx - 1 ? 0 : x + 1;
     c.ym = y == 0 ? L.ny - 1 : y - 1; c.yp = y == L.ny - 1 ? 0 : y + 1;
@@ -197,13 +198,13 @@ template <bool WALLS, bool HALF, bool NTL, int I>
 __device__ __forceinline__ void load_raw_one(const PopT<HALF>* __restrict__ f, const Lattice& L, const PullCtx& c,
                                              Raw<HALF>& R) {
     if (WALLS && ((cy(I) == 1 && c.y == 1) || (cy(I) == -1 && c.y == L.ny - 2))) {
-        R.v[I] = ldpop<NTL>(f + (int64_t)opp(I) * L.n + c.row, (uint32_t)c.x);
+        R.v[I] = ldpop<NTL>(f + opp(I) * c.n + c.row, (uint32_t)c.x);
     } else {
         const int sx = cx(I) == 1 ? c.xm : (cx(I) == -1 ? c.xp : c.x);
         const int sy = cy(I) == 1 ? c.ym : (cy(I) == -1 ? c.yp : c.y);
         const int sz = cz(I) == 1 ? c.zm : (cz(I) == -1 ? c.zp : c.z);
         const uint32_t srow = (uint32_t)((sz * L.ny + sy) * L.nx);
-        R.v[I] = ldpop<NTL>(f + (int64_t)I * L.n + srow, (uint32_t)sx);
+        R.v[I] = ldpop<NTL>(f + I * c.n + srow, (uint32_t)sx);
     }
 }
 
@@ -220,10 +221,12 @@ __device__ __forceinline__ PullCtx pull_ctx(const Lattice& L, int64_t node, int 
     c.xm = x == 0 ? L.nx - 1 : x - 1; c.xp = x == L.nx - 1 ? 0 : x + 1;
     c.ym = y == 0 ? L.ny - 1 : y - 1; c.yp = y == L.ny - 1 ? 0 : y + 1;
     c.zm = z == 0 ? L.nz - 1 : z - 1; c.zp = z == L.nz - 1 ? 0 : z + 1;
-    // Fresh lane offsets for every plane: each load is then a scalar row
-    // base plus one of three 32-bit x offsets, instead of one 64-bit
-    // pointer per direction held in registers across the march.
-    asm volatile("" : "+v"(c.xm), "+v"(c.x), "+v"(c.xp));
+    // Fresh lane offsets and direction stride for every plane: each load is
+    // then a scalar row base plus one of three 32-bit x offsets, rebuilt in a
+    // few scalar instructions, instead of a pointer per direction held in
+    // (vector, or spilled scalar) registers across the march.
+    c.n = L.n;
+    asm volatile("" : "+v"(c.xm), "+v"(c.x), "+v"(c.xp), "+s"(c.n));
     return c;
 }
 
@@ -405,7 +408,7 @@ __device__ __forceinline__ void stage_store(Ring<NR>& R, const StageRegs<NC>& S,
 // ---------------------------------------------------------------------------
 // Density pass, FP32: one thread per node.
 template <bool WALLS, bool CACHED>
-__global__ __launch_bounds__(256) void k_density(const pf2* __restrict__ fin,
+__global__ __launch_bounds__(BX * BY) void k_density(const pf2* __restrict__ fin,
                                                  const float* __restrict__ rho_prev,
                                                  float* __restrict__ rho_out, Lattice L) {
     int bx, by, bz;
@@ -429,7 +432,7 @@ __global__ __launch_bounds__(256) void k_density(const pf2* __restrict__ fin,
 // Density pass, FP16: z-marching column with the decode densities
 // cscale(prev) * rho^{n-1} staged in LDS, plus FP64 block sums of rho^n.
 template <bool WALLS, bool CACHED>
-__global__ __launch_bounds__(256) void k_density_half(const ph2* __restrict__ fin,
+__global__ __launch_bounds__(BX * BY) void k_density_half(const ph2* __restrict__ fin,
                                                       const float* __restrict__ rho_prev,
                                                       const float* __restrict__ cscale, int par_prev,
                                                       float* __restrict__ rho_out, double* __restrict__ partial,
@@ -526,7 +529,7 @@ __global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ 
 // Fused pull + force + collide.  MACRO: recompute the velocity of this
 // collision without storing populations (field read-back).
 template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED>
-__global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
+__global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
                                                  const float* __restrict__ fib,
@@ -689,25 +692,52 @@ __global__ __launch_bounds__(256) void k_collide(const PopT<HALF>* __restrict__ 
                     rest[c] = r2[c];
                 }
                 PopT<HALF>* fo = fout + row;
-#pragma unroll
-                for (int i = 1; i < Q; ++i) {
-                    float fs[2];
+                int64_t Ns = N;                    // direction stride, rebuilt per plane
+                asm volatile("" : "+s"(Ns));
+                if constexpr (HALF) {
+                    // BGK and the encode in one step, g_i = f*_i / rho_enc - w_i
+                    //   = (1 - omega) inv f_i + omega inv w_i t_i - w_i
+                    // with feq_i = w_i t_i, t_i = base + rho (c.u)(3 + 4.5 c.u);
+                    // the rest population closes the mass in g units:
+                    // g_0 = rho inv - 1 - sum_{i>0} g_i.
+                    float a1[2], bo[2], gs[2] = {0.f, 0.f};
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
-                        const Pulled& P = c == 0 ? A : B;
-                        const float cu = cx(i) * ux[c] + cy(i) * uy[c] + cz(i) * uz[c];
-                        const float feq = wgt(i) * (base[c] + r2[c] * cu * (3.0f + 4.5f * cu));
-                        fs[c] = P.f[i] + L.omega[c] * (feq - P.f[i]);
-                        rest[c] -= fs[c];
-                        if (HALF) fs[c] = fs[c] * inv[c] - wgt(i);
+                        a1[c] = (1.0f - L.omega[c]) * inv[c];
+                        bo[c] = L.omega[c] * inv[c];
                     }
-                    store_pop<!CACHED>(ptrx(fo + (int64_t)i * N, xo), pack<HALF>(fs[0], fs[1]));
-                }
-                // rest populations close the node's mass
-                if (HALF)
-                    store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(rest[0] * inv[0] - wgt(0), rest[1] * inv[1] - wgt(0)));
-                else
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) {
+                        float g[2];
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const Pulled& Pp = c == 0 ? A : B;
+                            const float cu = cx(i) * ux[c] + cy(i) * uy[c] + cz(i) * uz[c];
+                            const float t = fmaf(r2[c] * cu, fmaf(4.5f, cu, 3.0f), base[c]);
+                            g[c] = fmaf(a1[c], Pp.f[i], fmaf(bo[c] * wgt(i), t, -wgt(i)));
+                            gs[c] += g[c];
+                        }
+                        store_pop<!CACHED>(ptrx(fo + i * Ns, xo), pack<HALF>(g[0], g[1]));
+                    }
+                    store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(fmaf(r2[0], inv[0], -1.0f) - gs[0],
+                                                                fmaf(r2[1], inv[1], -1.0f) - gs[1]));
+                } else {
+#pragma unroll
+                    for (int i = 1; i < Q; ++i) {
+                        float fs[2];
+#pragma unroll
+                        for (int c = 0; c < 2; ++c) {
+                            const Pulled& P = c == 0 ? A : B;
+                            const float cu = cx(i) * ux[c] + cy(i) * uy[c] + cz(i) * uz[c];
+                            const float feq = wgt(i) * (base[c] + r2[c] * cu * (3.0f + 4.5f * cu));
+                            fs[c] = P.f[i] + L.omega[c] * (feq - P.f[i]);
+                            rest[c] -= fs[c];
+                        }
+                        store_pop<!CACHED>(ptrx(fo + i * Ns, xo), pack<HALF>(fs[0], fs[1]));
+                    }
+                    // rest populations close the node's mass
                     store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(rest[0], rest[1]));
+                }
             }
         } else if (MACRO && x < L.nx && y < L.ny) {
             const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
@@ -790,7 +820,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh, int tid, int
 }
 
 template <bool WALLS, bool IBM>
-__global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin, const float* __restrict__ rho_n,
+__global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__ fin, const float* __restrict__ rho_n,
                                                      const float* __restrict__ rho_p, const float* __restrict__ fib,
                                                      const int* __restrict__ tile_flag, const pf2* __restrict__ lam_in,
                                                      const float* __restrict__ lam_u, float* __restrict__ lam_rho,
@@ -981,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_adj_collide(const pf2* __restrict__ fin
 // first and last fluid rows also collect what their solid-row copies
 // received.
 template <bool WALLS>
-__global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ lam_S, float* __restrict__ lam_rho,
+__global__ __launch_bounds__(BX * BY) void k_adj_gather(const float* __restrict__ lam_S, float* __restrict__ lam_rho,
                                                     Lattice L) {
     __shared__ Ring<6> sr;
     const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
@@ -1048,7 +1078,7 @@ __global__ __launch_bounds__(256) void k_adj_gather(const float* __restrict__ la
 }
 
 template <bool WALLS>
-__global__ __launch_bounds__(256) void k_adj_push(const pf2* __restrict__ lam_in, const float* __restrict__ lam_rho,
+__global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ lam_in, const float* __restrict__ lam_rho,
                                                   const float* __restrict__ lam_j, pf2* __restrict__ lam_out,
                                                   Lattice L) {
     __shared__ Ring<8> rj;

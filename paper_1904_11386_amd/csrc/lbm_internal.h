@@ -40,6 +40,9 @@ constexpr int BOX = BIN + 3;   // spreading box edge: stencil reach of one bin's
 #ifndef LBM_ZC
 #define LBM_ZC 8
 #endif
+#ifndef LBM_COLLIDE_ATTR
+#define LBM_COLLIDE_ATTR
+#endif
 constexpr int BX = LBM_BX;     // lattice blocks: x extent (a multiple of the wavefront)
 constexpr int BY = LBM_BY;     // lattice blocks: y extent
 constexpr int ZC = LBM_ZC;     // lattice blocks: fewest z planes marched per block
