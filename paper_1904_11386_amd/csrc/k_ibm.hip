@@ -15,7 +15,8 @@
 //                   forces, add the wettability reaction (lane (kx, ky)
 //                   takes a column of the 4x4x4 delta stencil, psi staged
 //                   on a 6^3 LDS cube), count the node into its home bin
-//   k_bin_scan      exclusive scan of the home-bin counts
+//   k_bin_alloc     disjoint slot runs for the occupied bins (wavefront scan
+//                   plus one global atomic per wavefront)
 //   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
 //                   the 8^3 tiles the bins' stencils can reach
 //   k_spread        one workgroup per occupied bin: accumulate F_b delta and
@@ -31,6 +32,7 @@ namespace {
 
 constexpr int CNT_TOUCHED = 0;   // counters[0..1]
 constexpr int CNT_HOME = 2;      // counters[2..3]
+constexpr int CNT_ALLOC = 4;     // counters[4..5]
 
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
@@ -107,22 +109,27 @@ __device__ __forceinline__ int bin_of(const Lattice& L, int x, int y, int z) {
     return ((z / BIN) * L.nby + (y / BIN)) * L.nbx + (x / BIN);
 }
 
+// One workgroup per touched tile of the previous step (tile coordinates are
+// wave-uniform): zero its immersed-boundary fields and flag; then the
+// previous step's bin counts, this step's counters and capsule volumes.
 __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, int pc, int n_caps) {
     const int nt = d.counters[CNT_TOUCHED + pp];
     const int nh = d.counters[CNT_HOME + pp];
     const int64_t N = L.n;
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (int64_t)nt * 512;
-         k += (int64_t)gridDim.x * blockDim.x) {
-        const int e = (int)(k >> 9), c = (int)(k & 511);
+    for (int e = blockIdx.x; e < nt; e += gridDim.x) {
         const int t = d.touched[pp][e];
         const int tx = t % L.ntx, ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
-        const int x = tx * TILE + (c & 7), y = ty * TILE + ((c >> 3) & 7), z = tz * TILE + (c >> 6);
-        if (x < L.nx && y < L.ny && z < L.nz) {
-            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+        for (int c = threadIdx.x; c < TILE * TILE * TILE; c += blockDim.x) {
+            const int x = tx * TILE + (c & 7), y = ty * TILE + ((c >> 3) & 7), z = tz * TILE + (c >> 6);
+            if (x < L.nx && y < L.ny && z < L.nz) {
+                const uint32_t node = (uint32_t)((z * L.ny + y) * L.nx + x);
 #pragma unroll
-            for (int f = 0; f < 5; ++f) d.fib[f * N + node] = 0.0f;
+                for (int f = 0; f < 5; ++f) d.fib[f * N + node] = 0.0f;
+                if (d.lam_u)   // the adjoint velocity field lives in the same tiles
+                    for (int f = 0; f < 3; ++f) d.lam_u[f * N + node] = 0.0f;
+            }
         }
-        if (c == 0) d.tile_flag[t] = 0;
+        if (threadIdx.x == 0) d.tile_flag[t] = 0;
     }
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nh;
          k += (int64_t)gridDim.x * blockDim.x)
@@ -131,24 +138,11 @@ __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, i
         if (threadIdx.x == 0) {
             d.counters[CNT_TOUCHED + pc] = 0;
             d.counters[CNT_HOME + pc] = 0;
+            d.counters[CNT_ALLOC + pc] = 0;
         }
         for (int k = threadIdx.x; k < n_caps; k += blockDim.x) {
             d.capV[k] = 0.0;
             if (d.capdV) d.capdV[k] = 0.0;
-        }
-    }
-    if (d.lam_u) {
-        // adjoint velocity field lives in the same tiles
-        for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < (int64_t)nt * 512;
-             k += (int64_t)gridDim.x * blockDim.x) {
-            const int e = (int)(k >> 9), c = (int)(k & 511);
-            const int t = d.touched[pp][e];
-            const int tx = t % L.ntx, ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
-            const int x = tx * TILE + (c & 7), y = ty * TILE + ((c >> 3) & 7), z = tz * TILE + (c >> 6);
-            if (x < L.nx && y < L.ny && z < L.nz) {
-                const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
-                for (int f = 0; f < 3; ++f) d.lam_u[f * N + node] = 0.0f;
-            }
         }
     }
 }
@@ -380,28 +374,32 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
     }
 }
 
-__global__ __launch_bounds__(1024) void k_bin_scan(Dev d, int par) {
-    __shared__ int sh[1024];
+// Segments of the counting sort: each occupied bin gets a disjoint run of
+// slots.  A wavefront scans its 64 bins' counts and takes one run for all
+// of them from a global counter (segment order is immaterial to the sort).
+__global__ __launch_bounds__(256) void k_bin_alloc(Dev d, int par) {
     const int nh = d.counters[CNT_HOME + par];
-    int carry = 0;
-    for (int base = 0; base < nh; base += 1024) {
-        const int k = base + (int)threadIdx.x;
-        const int v = k < nh ? d.tile_count[d.home[par][k]] : 0;
-        sh[threadIdx.x] = v;
-        __syncthreads();
-        for (int o = 1; o < 1024; o <<= 1) {
-            const int add = (int)threadIdx.x >= o ? sh[threadIdx.x - o] : 0;
-            __syncthreads();
-            sh[threadIdx.x] += add;
-            __syncthreads();
-        }
-        if (k < nh) {
-            const int start = carry + sh[threadIdx.x] - v;
-            d.home_start[k] = start;
-            d.tile_offset[d.home[par][k]] = start;
-        }
-        carry += sh[1023];
-        __syncthreads();
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int lane = threadIdx.x & 63;
+    int h = 0, cnt = 0;
+    if (e < nh) {
+        h = d.home[par][e];
+        cnt = d.tile_count[h];
+    }
+    int v = cnt;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int u = __shfl_up(v, o, 64);
+        if (lane >= o) v += u;
+    }
+    const int total = __shfl(v, 63, 64);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(&d.counters[CNT_ALLOC + par], total);
+    base = __shfl(base, 63, 64);
+    if (e < nh) {
+        const int start = base + v - cnt;
+        d.home_start[e] = start;
+        d.tile_offset[h] = start;
     }
 }
 
@@ -881,7 +879,7 @@ __global__ __launch_bounds__(256) void k_debug_bins(Lattice L, Dev d, int n_node
 }  // namespace
 
 void launch_clear_tiles(const Lattice& L, Dev& d, int pp, int pc, int n_caps, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_tiles, dim3(1024), dim3(256), 0, s, L, d, pp, pc, n_caps);
+    hipLaunchKernelGGL(k_clear_tiles, dim3(2048), dim3(256), 0, s, L, d, pp, pc, n_caps);
 }
 void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s) {
     if (n_faces > 0) hipLaunchKernelGGL(k_cap_volume, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
@@ -894,8 +892,8 @@ void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const floa
     if (n_nodes > 0)
         hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 15) / 16), dim3(256), 0, s, L, d, rho_n, cs, n_nodes, par);
 }
-void launch_bin_scan(const Dev& d, int par, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_scan, dim3(1), dim3(1024), 0, s, d, par);
+void launch_bin_scan(const Dev& d, int n_nodes, int par, hipStream_t s) {
+    if (n_nodes > 0) hipLaunchKernelGGL(k_bin_alloc, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, par);
 }
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0)

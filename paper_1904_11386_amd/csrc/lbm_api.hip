@@ -562,7 +562,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_NODES);
     if (ibm) launch_nodes(L, d, rho_n, half ? d.cscale + 2 * cur : nullptr, c->n_nodes, par, s);
     mark(LBM_K_SCAN);
-    if (ibm) launch_bin_scan(d, par, s);
+    if (ibm) launch_bin_scan(d, c->n_nodes, par, s);
     mark(LBM_K_SCATTER);
     if (ibm) launch_bin_scatter(L, d, c->n_nodes, par, s);
     mark(LBM_K_SPREAD);

@@ -158,7 +158,7 @@ void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s);
 void launch_faces(const Dev& d, int n_faces, hipStream_t s);
 void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
                   int parity, hipStream_t s);
-void launch_bin_scan(const Dev& d, int parity, hipStream_t s);
+void launch_bin_scan(const Dev& d, int n_nodes, int parity, hipStream_t s);
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s);
 void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
