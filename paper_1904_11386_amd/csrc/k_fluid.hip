@@ -318,6 +318,12 @@ struct Ring {
     static constexpr int SW = BX + 2, SH = BY + 2;
     float v[3][NC][SH][SW];
 };
+// The same for a pair of components read together (both fluid components
+// at one cell): one 8-byte LDS access per neighbour instead of two.
+struct Ring2 {
+    static constexpr int SW = BX + 2, SH = BY + 2;
+    float2 v[3][SH][SW];
+};
 
 // Staging a plane of the ring.  stage_positions fixes, once per block, the
 // plane positions a thread stages (they do not depend on z; with WALLS the
@@ -339,8 +345,15 @@ struct StageRegs {
 };
 
 // Position k = ly * SW + lx of the plane is also its offset within one
-// component plane of the ring.
+// component plane of the ring (and its cell in a Ring2 plane).
 __device__ __forceinline__ bool stage_has(int tid, int it) { return tid + it * BX * BY < StagePos::POS; }
+
+__device__ __forceinline__ void stage_store2(Ring2& R, const StageRegs<2>& S, int zz, int z0, int tid) {
+    const int slot = (zz - z0 + 1) % 3;
+#pragma unroll
+    for (int it = 0; it < StagePos::NIT; ++it)
+        if (stage_has(tid, it)) (&R.v[slot][0][0])[tid + it * BX * BY] = make_float2(S.v[it][0], S.v[it][1]);
+}
 
 template <bool WALLS>
 __device__ __forceinline__ StagePos stage_positions(int x0, int y0, int tid, const Lattice& L) {
@@ -437,7 +450,7 @@ __global__ __launch_bounds__(BX * BY) void k_density_half(const ph2* __restrict_
                                                       const float* __restrict__ cscale, int par_prev,
                                                       float* __restrict__ rho_out, double* __restrict__ partial,
                                                       Lattice L) {
-    __shared__ Ring<2> ring;
+    __shared__ Ring2 ring;
     __shared__ double red[2][BX * BY];
     const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
@@ -448,9 +461,9 @@ __global__ __launch_bounds__(BX * BY) void k_density_half(const ph2* __restrict_
     const StagePos P = stage_positions<WALLS>(x0, y0, tid, L);
     StageRegs<2> st;
     stage_load<false, 2>(st, P, z0 - 1, tid, rho_prev, cp, nullptr, nullptr, L);
-    stage_store<2>(ring, st, z0 - 1, z0, tid);
+    stage_store2(ring, st, z0 - 1, z0, tid);
     stage_load<false, 2>(st, P, z0, tid, rho_prev, cp, nullptr, nullptr, L);
-    stage_store<2>(ring, st, z0, z0, tid);
+    stage_store2(ring, st, z0, z0, tid);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
     double acc[2] = {0.0, 0.0};
@@ -458,7 +471,7 @@ __global__ __launch_bounds__(BX * BY) void k_density_half(const ph2* __restrict_
 #pragma unroll 1
     for (int z = z0; z < z1; ++z) {
         stage_load<false, 2>(st, P, z + 1, tid, rho_prev, cp, nullptr, nullptr, L);
-        stage_store<2>(ring, st, z + 1, z0, tid);
+        stage_store2(ring, st, z + 1, z0, tid);
         __syncthreads();
         if (active) load_raw<WALLS, true, CACHED>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
         if (active) {
@@ -466,11 +479,13 @@ __global__ __launch_bounds__(BX * BY) void k_density_half(const ph2* __restrict_
             const int s0 = (z - z0 + 1) % 3;
             auto enc = [&](int ex, int ey, int ez, float& a, float& b) {
                 const int sl = (s0 - ez + 3) % 3;
-                a = ring.v[sl][0][ty + 1 - ey][tx + 1 - ex];
-                b = ring.v[sl][1][ty + 1 - ey][tx + 1 - ex];
+                const float2 e = ring.v[sl][ty + 1 - ey][tx + 1 - ex];
+                a = e.x;
+                b = e.y;
             };
             Pulled A, B;
-            decode<WALLS, true>(L, y, rcur, ring.v[s0][0][ty + 1][tx + 1], ring.v[s0][1][ty + 1][tx + 1], enc, A, B);
+            const float2 e0 = ring.v[s0][ty + 1][tx + 1];
+            decode<WALLS, true>(L, y, rcur, e0.x, e0.y, enc, A, B);
             const float ra = sum_pop(A), rb = sum_pop(B);
             *ptrx(rho_out + row, (uint32_t)x) = ra;
             *ptrx(rho_out + L.n + row, (uint32_t)x) = rb;
@@ -536,9 +551,8 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                                                  const int* __restrict__ tile_flag,
                                                  float* __restrict__ u_out, const float* __restrict__ cscale,
                                                  int par_prev, int par_cur, Lattice L) {
-    constexpr int NE = HALF ? 2 : 1;
-    __shared__ Ring<2> sp;                       // psi + phi at time n
-    __shared__ Ring<NE> se;                      // decode densities rho_enc^{n-1} (FP16)
+    __shared__ Ring2 sp;                         // psi + phi at time n (A, B)
+    __shared__ Ring2 se;                         // decode densities rho_enc^{n-1} (FP16)
     const int tx = threadIdx.x, ty = uniform_ty();
     const int tid = ty * BX + tx;
     int bx, by, bz;
@@ -580,17 +594,17 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
     }
     const StagePos P = stage_positions<WALLS>(x0, y0, tid, L);
     StageRegs<2> np;
-    StageRegs<NE> ne;
+    StageRegs<2> ne;
     auto load_plane = [&](int zz) {
         if (IBM && near_ibm)
             stage_load<true, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
         else
             stage_load<false, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
-        if (HALF) stage_load<false, NE>(ne, P, zz, tid, rho_p, cdec, nullptr, nullptr, L);
+        if constexpr (HALF) stage_load<false, 2>(ne, P, zz, tid, rho_p, cdec, nullptr, nullptr, L);
     };
     auto store_plane = [&](int zz) {
-        stage_store<2>(sp, np, zz, z0, tid);
-        if (HALF) stage_store<NE>(se, ne, zz, z0, tid);
+        stage_store2(sp, np, zz, z0, tid);
+        if constexpr (HALF) stage_store2(se, ne, zz, z0, tid);
     };
 
     load_plane(z0 - 1);
@@ -613,10 +627,12 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
             if constexpr (HALF) {
                 auto enc = [&](int ex, int ey, int ez, float& a, float& b) {
                     const int sl = (s0 - ez + 3) % 3;
-                    a = se.v[sl][0][ty + 1 - ey][tx + 1 - ex];
-                    b = se.v[sl][NE - 1][ty + 1 - ey][tx + 1 - ex];
+                    const float2 e = se.v[sl][ty + 1 - ey][tx + 1 - ex];
+                    a = e.x;
+                    b = e.y;
                 };
-                decode<WALLS, true>(L, y, rcur, se.v[s0][0][ty + 1][tx + 1], se.v[s0][NE - 1][ty + 1][tx + 1], enc, A, B);
+                const float2 e0 = se.v[s0][ty + 1][tx + 1];
+                decode<WALLS, true>(L, y, rcur, e0.x, e0.y, enc, A, B);
             } else {
                 auto none = [](int, int, int, float&, float&) {};
                 const float rpa = WALLS ? ldx(rho_p + row, xo) : 0.0f;
@@ -634,8 +650,8 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
             for (int k = 1; k < Q; k += 2) {
                 const int sP = (s0 + cz(k) + 3) % 3, sM = (s0 - cz(k) + 3) % 3;
                 const int ly = ty + 1, lx = tx + 1;
-                const float da = sp.v[sP][0][ly + cy(k)][lx + cx(k)] - sp.v[sM][0][ly - cy(k)][lx - cx(k)];
-                const float db = sp.v[sP][1][ly + cy(k)][lx + cx(k)] - sp.v[sM][1][ly - cy(k)][lx - cx(k)];
+                const float2 vp = sp.v[sP][ly + cy(k)][lx + cx(k)], vm = sp.v[sM][ly - cy(k)][lx - cx(k)];
+                const float da = vp.x - vm.x, db = vp.y - vm.y;
                 const float w = wgt(k);
                 if (cx(k) != 0) { sa[0] += w * cx(k) * da; sb[0] += w * cx(k) * db; }
                 if (cy(k) != 0) { sa[1] += w * cy(k) * da; sb[1] += w * cy(k) * db; }
@@ -827,7 +843,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
                                                      float* __restrict__ lam_j, float* __restrict__ lam_S,
                                                      float* __restrict__ lam_Fib, float* __restrict__ u_out,
                                                      double* __restrict__ grads, Lattice L) {
-    __shared__ Ring<2> sp;
+    __shared__ Ring2 sp;
     __shared__ double red[BX * BY];
     const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
@@ -855,7 +871,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
             stage_load<true, 2>(np, P, zz, tid, rho_n, nullptr, fib, tile_flag, L);
         else
             stage_load<false, 2>(np, P, zz, tid, rho_n, nullptr, nullptr, nullptr, L);
-        stage_store<2>(sp, np, zz, z0, tid);
+        stage_store2(sp, np, zz, z0, tid);
     };
     stage(z0 - 1);
     stage(z0);
@@ -884,8 +900,8 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
             for (int k = 1; k < Q; k += 2) {
                 const int sP = (s0 + cz(k) + 3) % 3, sM = (s0 - cz(k) + 3) % 3;
                 const int ly = ty + 1, lx = tx + 1;
-                const float da = sp.v[sP][0][ly + cy(k)][lx + cx(k)] - sp.v[sM][0][ly - cy(k)][lx - cx(k)];
-                const float db = sp.v[sP][1][ly + cy(k)][lx + cx(k)] - sp.v[sM][1][ly - cy(k)][lx - cx(k)];
+                const float2 vp = sp.v[sP][ly + cy(k)][lx + cx(k)], vm = sp.v[sM][ly - cy(k)][lx - cx(k)];
+                const float da = vp.x - vm.x, db = vp.y - vm.y;
                 const float w = wgt(k);
                 if (cx(k) != 0) { sa[0] += w * cx(k) * da; sb[0] += w * cx(k) * db; }
                 if (cy(k) != 0) { sa[1] += w * cy(k) * da; sb[1] += w * cy(k) * db; }
