@@ -148,6 +148,37 @@ def adjoint_leg(torch, steps=2000, every=100):
             "backward_s": round(t_bwd, 4), "backward_over_forward": round(t_bwd / t_plain, 3)}
 
 
+def scale_leg(torch, warmup=100, steps=200):
+    """The throughput-at-scale configuration: 512^3 periodic box, flat
+    interface at z=256, 512 capsules (thirds of 162/642/2562 nodes, radii
+    4/6/10), angles in [60, 120] deg; both storage forms, `steps` graph-replayed
+    steps after `warmup`, with the collide kernel's algorithmic HBM rate."""
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
+    wl = workloads.make("c5")
+    N = wl.n_lattice
+    out = {"workload": "512^3 periodic two-component box, interface at z=256, 512 capsules (162/642/2562 nodes, "
+                       "R=4/6/10), theta~U[60,120] deg", "warmup": warmup, "steps": steps}
+    for name, prec in (("fp32", LBM_FP32), ("fp16", LBM_FP16)):
+        print("bench: 512^3 leg, %s form" % name, file=sys.stderr, flush=True)
+        sim = sim_from_workload(wl, precision=prec)
+        sim.step(warmup)
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        wall = time.perf_counter() - t0
+        k = sim.step_timed(20)
+        t_col = k["collide"] / 20 * 1e-3
+        out[name] = {"mlups": round(N * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4),
+                     "collide_gbs": round(COLLIDE_BYTES_PER_LUP[name] * N / t_col / 1e9, 1)}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["fp16_over_fp32"] = round(out["fp16"]["mlups"] / out["fp32"]["mlups"], 3)
+    return out
+
+
 def precision_study(torch, steps):
     """The FP16 g-storage form beside the FP32 form on the 256^3 droplet
     workload (B droplet of radius 60 in A, 64 capsules of 642 nodes on a
@@ -214,6 +245,7 @@ def main():
     ap.add_argument("--no-fp16-leg", action="store_true")
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-scale-leg", action="store_true", help="skip the 512^3 FP32/FP16 leg")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="also run the FP16/FP32 precision study on the 256^3 droplet for STEPS steps")
     args = ap.parse_args()
@@ -300,6 +332,8 @@ def main():
         torch.cuda.empty_cache()
     if args.precision == "fp32" and not args.no_adjoint_leg:
         out["adjoint"] = adjoint_leg(torch)
+    if args.precision == "fp32" and not args.no_scale_leg:
+        out["scale_512"] = scale_leg(torch)
     if args.precision_study > 0:
         out["precision_study"] = precision_study(torch, args.precision_study)
     if not args.no_cpu_baseline:
