@@ -99,6 +99,24 @@ __device__ __forceinline__ void store_pop(T* p, T v) {
     if constexpr (NT) __builtin_nontemporal_store(v, p);
     else *p = v;
 }
+// A global-memory pointer kept in scalar registers: the population stores
+// walk the 19 directions by adding the direction stride to it, so each
+// store is this base plus the lane's 32-bit x offset.  The empty asm keeps
+// LLVM from folding the x offset into a 64-bit per-lane address.
+template <typename T>
+using GPtr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ __forceinline__ GPtr<T> gstep(GPtr<T> p, int64_t stride) {
+    p += stride;
+    asm volatile("" : "+s"(p));
+    return p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void store_popx(GPtr<T> row, uint32_t x, T v) {
+    GPtr<T> p = (GPtr<T>)((__attribute__((address_space(1))) char*)row + x * (uint32_t)sizeof(T));
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
 
 // Populations of the two components for one direction and node sit side by
 // side: f[i][z][y][x][c], so one pull is one 8-byte (FP32) or 4-byte (FP16)
@@ -115,13 +133,32 @@ __device__ __forceinline__ PopT<HALF> pack(float a, float b) {
     return v;
 }
 
+// c_i . v with only the non-zero terms: IEEE rules keep a product by a zero
+// coefficient (and the load feeding it), so the plain dot product would cost
+// three operations for every direction.
+__device__ __forceinline__ float cdot(int i, float vx, float vy, float vz) {
+    if (cx(i) == 0 && cy(i) == 0 && cz(i) == 0) return 0.0f;
+    float s = cx(i) > 0 ? vx : -vx;
+    bool have = cx(i) != 0;
+    if (cy(i) != 0) {
+        const float t = cy(i) > 0 ? vy : -vy;
+        s = have ? s + t : t;
+        have = true;
+    }
+    if (cz(i) != 0) {
+        const float t = cz(i) > 0 ? vz : -vz;
+        s = have ? s + t : t;
+    }
+    return s;
+}
+
 // Moving-wall half-way bounce-back (Sec. II.C, eq. method:SBB): the
 // population entering a fluid node from a solid row is the node's own
 // opposite post-collision population plus 2 w_i rho (c_i . u_w) / c_s^2.
 template <int I>
 __device__ __forceinline__ float wall_term(const Lattice& L, float rho_prev_node) {
     const float* uw = cy(I) == 1 ? L.uw_lo : L.uw_hi;
-    const float cu = cx(I) * uw[0] + cy(I) * uw[1] + cz(I) * uw[2];
+    const float cu = cdot(I, uw[0], uw[1], uw[2]);
     return 2.0f * wgt(I) * rho_prev_node * cu * 3.0f;
 }
 
@@ -692,7 +729,7 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                 *ptrx(u_out + 2 * N + row, xo) = (jaz + jbz + 0.5f * (Fa[2] + Fb[2])) * ir;
             }
             if (!MACRO) {
-                float ux[2], uy[2], uz[2], base[2], inv[2], rest[2];
+                float ux[2], uy[2], uz[2], base[2], inv[2];
                 const float r2[2] = {ra, rb};
 #pragma unroll
                 for (int c = 0; c < 2; ++c) {
@@ -705,54 +742,86 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                     // FP16: encode relative to this node's compensated density,
                     // bit-identical to what the next step's decoder stages
                     inv[c] = HALF ? qdiv<true>(1.0f, ccu[c] * ldx(rho_n + c * N + row, xo)) : 1.0f;
-                    rest[c] = r2[c];
                 }
-                PopT<HALF>* fo = fout + row;
+                // direction bases advance by the stride in scalar registers,
+                // so each store is a scalar base plus the lane's x offset
+                const GPtr<PopT<HALF>> fo = (GPtr<PopT<HALF>>)(fout + row);
+                GPtr<PopT<HALF>> fi = fo;
                 int64_t Ns = N;                    // direction stride, rebuilt per plane
-                asm volatile("" : "+s"(Ns));
+                uint32_t xs = xo;                  // 32-bit lane offset, per plane
+                asm volatile("" : "+s"(Ns), "+v"(xs));
                 if constexpr (HALF) {
-                    // BGK and the encode in one step, g_i = f*_i / rho_enc - w_i
-                    //   = (1 - omega) inv f_i + omega inv w_i t_i - w_i
-                    // with feq_i = w_i t_i, t_i = base + rho (c.u)(3 + 4.5 c.u);
-                    // the rest population closes the mass in g units:
-                    // g_0 = rho inv - 1 - sum_{i>0} g_i.
-                    float a1[2], bo[2], gs[2] = {0.f, 0.f};
+                    // BGK and the encode in one step, per opposite pair
+                    // (c_{k+1} = -c_k, equal weights).  With feq_i = w_i t_i,
+                    // t_i = base + rho (c.u)(3 + 4.5 c.u), the stored
+                    // g_i = f*_i / rho_enc - w_i = a1 f_i + bo w_i t_i - w_i
+                    // (a1 = (1 - omega) inv, bo = omega inv, inv = 1/rho_enc)
+                    // splits into a part even in c.u,
+                    // P = bo w (base + 4.5 rho (c.u)^2) - w, and an odd part,
+                    // H = 3 bo w rho (c.u):
+                    //   g_k = a1 f_k + P + H,  g_{k+1} = a1 f_{k+1} + P - H.
+                    // The rest population closes the mass in g units,
+                    // g_0 = rho inv - 1 - sum_{i>0} g_i, with
+                    // sum_{i>0} g_i = a1 (rho - f_0) + 2 sum P.  Constants of the
+                    // diagonal class (w = 1/36) are half the axis class's (1/18).
+                    float a1[2], B1[2][2], K45[2][2], K3[2][2], sumP[2] = {0.f, 0.f};
 #pragma unroll
                     for (int c = 0; c < 2; ++c) {
                         a1[c] = (1.0f - L.omega[c]) * inv[c];
-                        bo[c] = L.omega[c] * inv[c];
+                        const float bw = L.omega[c] * inv[c] * (1.0f / 18.0f);
+                        B1[0][c] = fmaf(bw, base[c], -1.0f / 18.0f);
+                        K3[0][c] = (3.0f * bw) * r2[c];
+                        K45[0][c] = 1.5f * K3[0][c];
+                        B1[1][c] = 0.5f * B1[0][c];
+                        K3[1][c] = 0.5f * K3[0][c];
+                        K45[1][c] = 0.5f * K45[0][c];
                     }
 #pragma unroll
-                    for (int i = 1; i < Q; ++i) {
-                        float g[2];
+                    for (int k = 1; k < Q; k += 2) {
+                        const int cls = k <= 6 ? 0 : 1;
+                        float g1[2], g2[2];
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
                             const Pulled& Pp = c == 0 ? A : B;
-                            const float cu = cx(i) * ux[c] + cy(i) * uy[c] + cz(i) * uz[c];
-                            const float t = fmaf(r2[c] * cu, fmaf(4.5f, cu, 3.0f), base[c]);
-                            g[c] = fmaf(a1[c], Pp.f[i], fmaf(bo[c] * wgt(i), t, -wgt(i)));
-                            gs[c] += g[c];
+                            const float cu = cdot(k, ux[c], uy[c], uz[c]);
+                            const float Pe = fmaf(K45[cls][c], cu * cu, B1[cls][c]);
+                            const float Ho = K3[cls][c] * cu;
+                            g1[c] = fmaf(a1[c], Pp.f[k], Pe + Ho);
+                            g2[c] = fmaf(a1[c], Pp.f[k + 1], Pe - Ho);
+                            sumP[c] += Pe;
                         }
-                        store_pop<!CACHED>(ptrx(fo + i * Ns, xo), pack<HALF>(g[0], g[1]));
+                        fi = gstep(fi, Ns);
+                        store_popx<!CACHED>(fi, xs, pack<HALF>(g1[0], g1[1]));
+                        fi = gstep(fi, Ns);
+                        store_popx<!CACHED>(fi, xs, pack<HALF>(g2[0], g2[1]));
                     }
-                    store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(fmaf(r2[0], inv[0], -1.0f) - gs[0],
-                                                                fmaf(r2[1], inv[1], -1.0f) - gs[1]));
+                    float g0[2];
+#pragma unroll
+                    for (int c = 0; c < 2; ++c) {
+                        const Pulled& Pp = c == 0 ? A : B;
+                        g0[c] = fmaf(r2[c], inv[c], -1.0f) - fmaf(a1[c], r2[c] - Pp.f[0], 2.0f * sumP[c]);
+                    }
+                    store_popx<!CACHED>(fo, xs, pack<HALF>(g0[0], g0[1]));
                 } else {
+                    // (per direction: the pairwise form above costs this
+                    // HBM-bound path a wave of occupancy)
+                    float rest[2] = {r2[0], r2[1]};
 #pragma unroll
                     for (int i = 1; i < Q; ++i) {
                         float fs[2];
 #pragma unroll
                         for (int c = 0; c < 2; ++c) {
                             const Pulled& P = c == 0 ? A : B;
-                            const float cu = cx(i) * ux[c] + cy(i) * uy[c] + cz(i) * uz[c];
+                            const float cu = cdot(i, ux[c], uy[c], uz[c]);
                             const float feq = wgt(i) * (base[c] + r2[c] * cu * (3.0f + 4.5f * cu));
                             fs[c] = P.f[i] + L.omega[c] * (feq - P.f[i]);
                             rest[c] -= fs[c];
                         }
-                        store_pop<!CACHED>(ptrx(fo + i * Ns, xo), pack<HALF>(fs[0], fs[1]));
+                        fi = gstep(fi, Ns);
+                        store_popx<!CACHED>(fi, xs, pack<HALF>(fs[0], fs[1]));
                     }
                     // rest populations close the node's mass
-                    store_pop<!CACHED>(ptrx(fo, xo), pack<HALF>(rest[0], rest[1]));
+                    store_popx<!CACHED>(fo, xs, pack<HALF>(rest[0], rest[1]));
                 }
             }
         } else if (MACRO && x < L.nx && y < L.ny) {
@@ -959,7 +1028,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
                 for (int i = 0; i < Q; ++i) {
                     const pf2 lv = ldx(lam_in + (int64_t)i * N + row, xo);
                     const float mu = om * (c == 0 ? lv.x : lv.y);
-                    const float eu = cx(i) * ue[c][0] + cy(i) * ue[c][1] + cz(i) * ue[c][2];
+                    const float eu = cdot(i, ue[c][0], ue[c][1], ue[c][2]);
                     lrf += mu * wgt(i) * (1.0f + 3.0f * eu + 4.5f * eu * eu - 1.5f * usq);
                     const float co = mu * wgt(i) * r;
                     const float ce = co * (3.0f + 9.0f * eu);
@@ -1137,8 +1206,8 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
             auto own_lf = [&](int i, int c) {
                 const pf2 lv = ldx(lam_in + (int64_t)i * N + row, xo);
                 const float ls = c == 0 ? lv.x : lv.y;
-                const float lj = cx(i) * rj.v[s0][2 + 3 * c][ly][lx] + cy(i) * rj.v[s0][3 + 3 * c][ly][lx] +
-                                 cz(i) * rj.v[s0][4 + 3 * c][ly][lx];
+                const float lj = cdot(i, rj.v[s0][2 + 3 * c][ly][lx], rj.v[s0][3 + 3 * c][ly][lx],
+                                      rj.v[s0][4 + 3 * c][ly][lx]);
                 return (1.0f - L.omega[c]) * ls + rj.v[s0][c][ly][lx] + lj;
             };
             float wall_extra[2] = {0.f, 0.f};
@@ -1147,10 +1216,14 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
                 for (int i = 1; i < Q; ++i) {
                     if (cy(i) != sgn) continue;
                     const float* uw = sgn == 1 ? L.uw_lo : L.uw_hi;
-                    const float cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
+                    const float cu = cdot(i, uw[0], uw[1], uw[2]);
                     for (int c = 0; c < 2; ++c) wall_extra[c] += own_lf(i, c) * 2.0f * wgt(i) * cu * 3.0f;
                 }
             }
+            GPtr<pf2> lo = (GPtr<pf2>)(lam_out + row);      // direction base, scalar
+            int64_t Ns = N;
+            uint32_t xs = xo;
+            asm volatile("" : "+s"(Ns), "+v"(xs));
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 float out[2];
@@ -1165,12 +1238,13 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
                     const pf2 lv = ldx(lam_in + (int64_t)k * N + (uint32_t)((sz * L.ny + sy) * L.nx), (uint32_t)sx);
                     const int sl = (s0 + cz(k) + 3) % 3, qy = ly + cy(k), qx = lx + cx(k);
                     for (int c = 0; c < 2; ++c) {
-                        const float lj = cx(k) * rj.v[sl][2 + 3 * c][qy][qx] + cy(k) * rj.v[sl][3 + 3 * c][qy][qx] +
-                                         cz(k) * rj.v[sl][4 + 3 * c][qy][qx];
+                        const float lj = cdot(k, rj.v[sl][2 + 3 * c][qy][qx], rj.v[sl][3 + 3 * c][qy][qx],
+                                              rj.v[sl][4 + 3 * c][qy][qx]);
                         out[c] = (1.0f - L.omega[c]) * (c == 0 ? lv.x : lv.y) + rj.v[sl][c][qy][qx] + lj;
                     }
                 }
-                *ptrx(lam_out + (int64_t)k * N + row, xo) = pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]);
+                store_popx<false>(lo, xs, pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]));
+                if (k + 1 < Q) lo = gstep(lo, Ns);
             }
         } else if (inside) {
             const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx);
