@@ -302,20 +302,25 @@ def main():
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-scale-leg", action="store_true", help="skip the 512^3 FP32/FP16 leg")
+    ap.add_argument("--scale-only", action="store_true",
+                    help="run only the 512^3 FP32/FP16 leg and print it (for profiling that configuration)")
     ap.add_argument("--adjoint-fd-sweep", action="store_true",
                     help="also check the full-size adjoint against FP32 central differences over a sweep of h")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="also run the FP16/FP32 precision study on the 256^3 droplet for STEPS steps")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the step would shard by z-slabs; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path "
+              "(the step would shard by z-slabs, one per GPU, with one halo exchange per step).", file=sys.stderr)
         sys.exit(2)
 
     import torch
     from paper_1904_11386_amd import workloads
     from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
 
+    if args.scale_only:
+        print(json.dumps({"scale_512": scale_leg(torch, warmup=args.warmup, steps=args.steps)}), flush=True)
+        return
     wl = workloads.make(args.workload)
     print("bench: workload %s %dx%dx%d, %d capsules, %d nodes" %
           (args.workload, wl.nx, wl.ny, wl.nz, len(wl.capsules), int(wl.meshes()[0].sum())),

@@ -1220,10 +1220,6 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
                     for (int c = 0; c < 2; ++c) wall_extra[c] += own_lf(i, c) * 2.0f * wgt(i) * cu * 3.0f;
                 }
             }
-            GPtr<pf2> lo = (GPtr<pf2>)(lam_out + row);      // direction base, scalar
-            int64_t Ns = N;
-            uint32_t xs = xo;
-            asm volatile("" : "+s"(Ns), "+v"(xs));
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
                 float out[2];
@@ -1243,8 +1239,7 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
                         out[c] = (1.0f - L.omega[c]) * (c == 0 ? lv.x : lv.y) + rj.v[sl][c][qy][qx] + lj;
                     }
                 }
-                store_popx<false>(lo, xs, pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]));
-                if (k + 1 < Q) lo = gstep(lo, Ns);
+                *ptrx(lam_out + (int64_t)k * N + row, xo) = pack<false>(out[0] + wall_extra[0], out[1] + wall_extra[1]);
             }
         } else if (inside) {
             const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx);
