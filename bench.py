@@ -105,10 +105,18 @@ def cpu_baseline(wl, budget_s=20.0):
         el = time.perf_counter() - t0
         if el > budget_s * 0.5 or n >= 50:
             break
-    return {"value": wl.n_lattice * n / el / 1e6, "unit": "MLUPS", "cores": torch.get_num_threads(),
-            "kind": "oracle",
+    used = torch.get_num_threads()
+    # one more step on a single thread, for the per-core rate
+    torch.set_num_threads(1)
+    t1 = time.perf_counter()
+    o.step()
+    el1 = time.perf_counter() - t1
+    torch.set_num_threads(used)
+    return {"value": wl.n_lattice * n / el / 1e6, "unit": "MLUPS", "cores": used,
+            "kind": "oracle", "value_1_thread": wl.n_lattice / el1 / 1e6,
             "sample": "%d FP64 oracle steps of the benchmark workload (%dx%dx%d, %d capsules) after one "
-                      "untimed step, %.1f s" % (n, wl.nx, wl.ny, wl.nz, len(wl.capsules), el)}
+                      "untimed step, %.1f s; then one step on one thread, %.1f s"
+                      % (n, wl.nx, wl.ny, wl.nz, len(wl.capsules), el, el1)}
 
 
 def adjoint_leg(torch, steps=2000, every=100):
