@@ -274,6 +274,109 @@ def test_full_size_c2_first_steps_parity():
     assert all(np.isfinite(c["height"]) for c in ob["caps"])
 
 
+def _crop_plan(wl, x0, y0, wc, z0, wz, margin):
+    """A box of the lattice (periodic in x and y) for the oracle: the capsules
+    lying wholly inside it with room for their stencils, the capsules cut by
+    its faces (left out of the oracle's copy), and the nodes and capsules whose
+    first steps cannot feel either the box faces or a left-out capsule within
+    `margin` cells."""
+    n = np.array([wl.nx, wl.ny], np.float64)
+    C = np.array([c.centre for c in wl.capsules])
+    R = np.array([c.radius for c in wl.capsules])
+    rel = C - np.array([x0, y0, z0], np.float64)
+    rel[:, :2] = np.mod(rel[:, :2] + n / 2 - np.array([wc, wc]) / 2, n) - n / 2 + np.array([wc, wc]) / 2
+    lo, hi = R + 4, wc - 1 - R - 4
+    kept = ((rel[:, 0] >= lo) & (rel[:, 0] <= hi) & (rel[:, 1] >= lo) & (rel[:, 1] <= hi)
+            & (rel[:, 2] >= R + 4) & (rel[:, 2] <= wz - 1 - R - 4))
+    near = ((rel[:, 0] > -R - margin) & (rel[:, 0] < wc + R + margin) & (rel[:, 1] > -R - margin)
+            & (rel[:, 1] < wc + R + margin))
+    cut = near & ~kept
+    Z, Y, X = np.meshgrid(np.arange(wz), np.arange(wc), np.arange(wc), indexing="ij")
+    mask = ((X >= margin) & (X < wc - margin) & (Y >= margin) & (Y < wc - margin)
+            & (Z >= margin) & (Z < wz - margin))
+    for j in np.nonzero(cut)[0]:
+        mask &= (X - rel[j, 0]) ** 2 + (Y - rel[j, 1]) ** 2 + (Z - rel[j, 2]) ** 2 >= (R[j] + margin) ** 2
+    compared = []
+    for k in np.nonzero(kept)[0]:
+        ok = (rel[k, :2] >= R[k] + margin).all() and (rel[k, :2] <= wc - 1 - R[k] - margin).all()
+        ok = ok and all(np.linalg.norm(rel[k] - rel[j]) >= R[k] + R[j] + margin for j in np.nonzero(cut)[0])
+        if ok:
+            compared.append(int(k))
+    return rel, np.nonzero(kept)[0], mask, compared
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp32", "fp16"])
+def test_full_size_512_sampled_parity(precision):
+    """The 512^3 workload with 512 capsules, in the launch configuration the
+    benchmark times (graph-replayed steps, the large-lattice cache policy):
+    two steps on the GPU, then the oracle on a 176 x 176 x 60 box of the same
+    initial state that straddles the periodic seam in x and y.  A node's
+    first two steps depend on the lattice within a few cells (the pull, the
+    Shan-Chen neighbours, the delta stencil) and on whole capsules (volume
+    and Skalak forces), so every node and capsule at least 14 cells from the
+    box faces and from the capsules the box cuts is the oracle's to rounding.
+    FP32 bounds as for the 128^3 first steps; FP16: density 1e-3, and the
+    binary16 rounding of g (2^-11 relative, |g| <~ 0.05, about ten populations
+    per velocity component) bounds |du| near 1e-4 lu/step, asserted at 1e-3,
+    with node positions within 1e-3 lu."""
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32
+    wl = W.make("c5")
+    x0, y0, wc, z0, wz, margin = 430, 430, 176, 226, 60, 14
+    rel, kept, mask, compared = _crop_plan(wl, x0, y0, wc, z0, wz, margin)
+    _say("case c5 512^3", precision, "crop", (x0, y0, z0, wc, wz), "kept caps", len(kept),
+         "compared nodes", int(mask.sum()), "compared caps", len(compared))
+    assert mask.sum() > 300000 and len(compared) >= 10
+    g = _sim(wl, precision=LBM_FP16 if precision == "fp16" else LBM_FP32)
+    g.step(2)
+    ra, rb, u = g.fields()
+    Xg = g.nodes()
+    g.close()
+    del g
+    torch.cuda.empty_cache()
+    xs = (x0 + np.arange(wc)) % wl.nx
+    ys = (y0 + np.arange(wc)) % wl.ny
+    zs = z0 + np.arange(wz)
+    sel = np.ix_(zs, ys, xs)
+    ga, gb, gu = ra[sel], rb[sel], u[(slice(None),) + sel]
+    del ra, rb, u
+    caps = []
+    for k in kept:
+        c = wl.capsules[k]
+        caps.append(W.Capsule(rel[k].copy(), c.radius, c.freq, c.kS, c.C, c.kV, c.theta_deg))
+    crop = W.Workload("c5_crop", wc, wc, wz, wl.rhoA[sel].copy(), wl.rhoB[sel].copy(), caps,
+                      tau=wl.tau, G=wl.G, z_interface=wl.z_interface - z0)
+    torch.set_num_threads(max(1, min(16, os.cpu_count() or 1)))
+    o = from_workload(crop)
+    umax = 0.0
+    for _ in range(2):
+        o.step()
+        umax = max(umax, float(o.u_last.abs().numpy()[:, mask].max()))
+    oa, ob_ = o.rho_last[0].numpy(), o.rho_last[1].numpy()
+    ou = o.u_last.numpy()
+    ea = _rel(ga[mask], oa[mask])
+    eb = _rel(gb[mask], ob_[mask])
+    du = float(np.abs(gu[:, mask] - ou[:, mask]).max())
+    # node positions of the compared capsules, nearest periodic image
+    first = np.concatenate([[0], np.cumsum([10 * c.freq ** 2 + 2 for c in wl.capsules])])
+    dx = 0.0
+    for i, k in enumerate(kept):
+        if k not in compared:
+            continue
+        d = Xg[first[k]:first[k + 1]] - np.array([x0, y0, z0], np.float64) - o.X[i].numpy()
+        d[:, :2] = np.mod(d[:, :2] + wl.nx / 2, wl.nx) - wl.nx / 2
+        dx = max(dx, float(np.abs(d).max()))
+    _say("  rho rel err %.3e %.3e  |du| %.3e  U %.3e  node err %.3e lu" % (ea, eb, du, umax, dx))
+    if precision == "fp32":
+        assert ea <= 2e-6 and eb <= 2e-6
+        assert du <= 1e-5 * umax
+        assert dx <= 1e-6
+    else:
+        assert ea <= 1e-3 and eb <= 1e-3
+        assert du <= 1e-3
+        assert dx <= 1e-3
+
+
 # ---- FP16 population storage ------------------------------------------------
 
 def _droplet_workload(n=48, R=12.0, ncap=6, seed=5):
