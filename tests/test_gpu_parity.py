@@ -274,6 +274,57 @@ def test_full_size_c2_first_steps_parity():
     assert all(np.isfinite(c["height"]) for c in ob["caps"])
 
 
+@pytest.mark.timeout(600)
+def test_full_size_channel_parity():
+    """The 192 x 96 x 96 sheared channel (walls at y = 0 and 95 moving -+0.01,
+    one 2562-node capsule) at its full size: ten graph-replayed steps against
+    the oracle on the whole lattice, bounds as for the 48 x 24 x 24 copy."""
+    wl = W.make("c4")
+    torch.set_num_threads(max(1, min(16, os.cpu_count() or 1)))
+    _compare_run(wl, 10, 5e-6, 1e-5, tol_x=2e-5)
+
+
+@pytest.mark.timeout(900)
+def test_full_size_256_droplet_parity():
+    """The 256^3 precision workload (B droplet R60, 64 capsules on a shell)
+    at its full size, both storage forms: two graph-replayed steps against two
+    oracle steps on the whole lattice.  FP32 bounds as for the 128^3 first
+    steps; FP16 as for the 512^3 sampled check."""
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32
+    wl = W.make("c3")
+    res = {}
+    for name, prec in (("fp32", LBM_FP32), ("fp16", LBM_FP16)):
+        _say("case c3 256^3", name, "caps", len(wl.capsules), "steps 2")
+        g = _sim(wl, precision=prec)
+        g.step(2)
+        res[name] = g.fields() + (g.nodes(),)
+        g.close()
+        del g
+        torch.cuda.empty_cache()
+    torch.set_num_threads(max(1, min(16, os.cpu_count() or 1)))
+    o = from_workload(wl)
+    umax = 0.0
+    for _ in range(2):
+        o.step()
+        umax = max(umax, float(o.u_last.abs().max()))
+    oa, ob_ = o.rho_last[0].numpy(), o.rho_last[1].numpy()
+    ou = o.u_last.numpy()
+    Xo = torch.cat(o.X, 0).numpy()
+    for name, (ra, rb, u, X) in res.items():
+        ea, eb = _rel(ra, oa), _rel(rb, ob_)
+        du = float(np.abs(u - ou).max())
+        dx = float(np.abs(X - Xo).max())
+        _say("  %s rho rel err %.3e %.3e  |du| %.3e  U %.3e  node err %.3e lu" % (name, ea, eb, du, umax, dx))
+        if name == "fp32":
+            assert ea <= 2e-6 and eb <= 2e-6
+            assert du <= 1e-5 * umax
+            assert dx <= 1e-6
+        else:
+            assert ea <= 1e-3 and eb <= 1e-3
+            assert du <= 1e-3
+            assert dx <= 1e-3
+
+
 def _crop_plan(wl, x0, y0, wc, z0, wz, margin):
     """A box of the lattice (periodic in x and y) for the oracle: the capsules
     lying wholly inside it with room for their stencils, the capsules cut by
