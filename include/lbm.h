@@ -95,7 +95,15 @@ typedef struct lbm_params {
     int32_t zchunk;         /* z planes marched per lattice block: 0 chosen by
                                storage form and grid size, else a multiple of 8
                                up to 64. Results do not depend on it.            */
-    int32_t reserved[3];    /* zero                                              */
+    int32_t reserved[1];    /* zero                                              */
+    double rep_eps;         /* particle-particle repulsion (Sec. III.E): node
+                               pairs of different capsules at separation
+                               d < rep_d0 repel along their separation with
+                               rep_eps (rep_d0 - d)^{3/2}; 0 = off (the paper
+                               uses 0.5). Finite, >= 0; with the adjoint
+                               (ring_len > 0) it must be 0.                      */
+    double rep_d0;          /* its cut-off, in (0, 2] when rep_eps > 0 (the
+                               paper uses 1.25)                                  */
 } lbm_params;
 
 typedef struct lbm_obs {
@@ -164,10 +172,11 @@ enum {
     LBM_K_NODES = 4,    /* node gather, wettability reaction, binning      */
     LBM_K_SCAN = 5,     /* scan of the tile bins                           */
     LBM_K_SCATTER = 6,  /* counting-sort scatter                           */
-    LBM_K_SPREAD = 7,   /* LDS-binned spreading                            */
-    LBM_K_COLLIDE = 8,  /* fused pull + force + collide over the lattice   */
-    LBM_K_INTERP = 9,   /* interpolation and node advection                */
-    LBM_NK = 10
+    LBM_K_REPULSE = 7,  /* particle-particle repulsion (rep_eps > 0)       */
+    LBM_K_SPREAD = 8,   /* LDS-binned spreading                            */
+    LBM_K_COLLIDE = 9,  /* fused pull + force + collide over the lattice   */
+    LBM_K_INTERP = 10,  /* interpolation and node advection                */
+    LBM_NK = 11
 };
 
 /* As lbm_step (without the mass check), and synchronises: HIP events are

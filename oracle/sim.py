@@ -20,6 +20,8 @@ positions X^n.  The step, in this order:
         R_b = -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i
     (np = the non-preferred component), which keeps fluid plus membrane
     momentum conserved, as Sec. II.D requires of the cross-boundary force;
+    when enabled, the particle-particle repulsion of Sec. III.E between
+    nodes of different capsules (contact.py);
  4. spreading F_ib(x) = sum_b F_b delta(x - X_b) and the phi fields;
  5. fluid force F^c = -psi^c G sum_i w_i (psi^c' + phi^c')(x + c_i) c_i
     + (rho^c / rho) F_ib (Sec. II.D eq. method:shanchen; the body force is
@@ -40,7 +42,7 @@ import math
 
 import torch
 
-from . import ibm, lattice, membrane
+from . import contact, ibm, lattice, membrane
 
 DT = torch.float64
 
@@ -67,7 +69,8 @@ class OracleSim:
 
     def __init__(self, rhoA, rhoB, caps=(), tau=(1.0, 1.0), G=3.6, walls=0,
                  u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0), rho_maj=0.7,
-                 rho_min=0.04, z_interface=0.0, wet_scale=1.0, differentiable=False):
+                 rho_min=0.04, z_interface=0.0, wet_scale=1.0, differentiable=False,
+                 rep_eps=0.0, rep_d0=1.25):
         rhoA = torch.as_tensor(rhoA, dtype=DT)
         rhoB = torch.as_tensor(rhoB, dtype=DT)
         self.nz, self.ny, self.nx = rhoA.shape
@@ -80,6 +83,8 @@ class OracleSim:
         self.rho_maj = float(rho_maj)
         self.rho_min = float(rho_min)
         self.wet_scale = float(wet_scale)
+        self.rep_eps = float(rep_eps)
+        self.rep_d0 = float(rep_d0)
         self.z_interface = float(z_interface)
         self.diff = differentiable
         self.fpost = lattice.rest_populations(rhoA, rhoB)
@@ -139,6 +144,10 @@ class OracleSim:
             pb = a if pref == 1 else torch.zeros_like(a)
             Fb.append(F)
             phiw.append(torch.stack([pa, pb], 1))
+        if self.rep_eps > 0.0:
+            # particle-particle repulsion at X^n (Sec. III.E)
+            R = contact.repulsion_forces(self.X, self.dims, self.rep_eps, self.rep_d0, w)
+            Fb = [F + Rk for F, Rk in zip(Fb, R)]
         return Fb, phiw
 
     def step(self):
@@ -209,7 +218,8 @@ def from_workload(wl, differentiable=False, **over):
         caps.append(dict(xyz=xyz, tri=tri, kS=c.kS, C=c.C, kV=c.kV, theta=c.theta_deg))
     kw = dict(tau=wl.tau, G=wl.G, walls=wl.walls, u_lo=wl.wall_u_lo, u_hi=wl.wall_u_hi,
               rho_maj=wl.rho_maj, rho_min=wl.rho_min, z_interface=wl.z_interface,
-              wet_scale=wl.wet_scale, differentiable=differentiable)
+              wet_scale=wl.wet_scale, differentiable=differentiable,
+              rep_eps=getattr(wl, "rep_eps", 0.0), rep_d0=getattr(wl, "rep_d0", 1.25))
     kw.update(over)
     return OracleSim(wl.rhoA.astype("float64"), wl.rhoB.astype("float64"), caps, **kw)
 

@@ -30,7 +30,7 @@ class Params(C.Structure):
                 ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
                 ("z_interface", C.c_double), ("mass_tol", C.c_double), ("wet_scale", C.c_double),
                 ("ring_len", C.c_int32), ("stream_policy", C.c_int32), ("zchunk", C.c_int32),
-                ("reserved", C.c_int32 * 3)]
+                ("reserved", C.c_int32 * 1), ("rep_eps", C.c_double), ("rep_d0", C.c_double)]
 
 
 class Obs(C.Structure):
@@ -105,7 +105,7 @@ def _ptr(a, ctype):
 def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
                 check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0, stream_policy=0,
-                zchunk=0):
+                zchunk=0, rep_eps=0.0, rep_d0=1.25):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -125,6 +125,8 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.ring_len = ring_len
     p.stream_policy = stream_policy
     p.zchunk = zchunk
+    p.rep_eps = rep_eps
+    p.rep_d0 = rep_d0
     return p
 
 
@@ -188,7 +190,7 @@ class Sim:
     def step(self, n=1):
         self._check(self.lib.lbm_step(self.ctx, int(n)))
 
-    KERNELS = ["clear", "density", "volume", "faces", "nodes", "scan", "scatter", "spread",
+    KERNELS = ["clear", "density", "volume", "faces", "nodes", "scan", "scatter", "repulse", "spread",
                "collide", "interp"]
 
     def step_timed(self, n):
@@ -285,7 +287,7 @@ def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="
                     wall_u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
                     check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len,
-                    stream_policy=stream_policy, zchunk=zchunk)
+                    stream_policy=stream_policy, zchunk=zchunk, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0)
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()

@@ -19,6 +19,8 @@
 //                   plus one global atomic per wavefront)
 //   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
 //                   the 8^3 tiles the bins' stencils can reach
+//   k_repulse       (when enabled) particle-particle repulsion between nodes
+//                   of different capsules, searched through the bins
 //   k_spread        one workgroup per occupied bin: accumulate F_b delta and
 //                   the virtual density in 7^3 LDS boxes (one per wavefront,
 //                   one lane per stencil point, no LDS atomics), then flush
@@ -441,6 +443,87 @@ __global__ __launch_bounds__(256) void k_bin_scatter(Lattice L, Dev d, int n_nod
                 d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t;
         }
     }
+}
+
+// Particle-particle repulsion (Sec. III.E): a node pair of different
+// capsules at separation d < d0 repels along the separation with
+// eps (d0 - d)^{3/2}.  One thread per node searches this step's 4^3 bins
+// that its d0-ball meets and sums its own pairs; the two nodes of a pair
+// compute the same d from negated differences, so their forces are exact
+// negatives.  Positions are anchor + (hi + lo) offsets, separations
+// minimum-image on the periodic axes.  The search range is widened by 1e-3
+// so that the bins (taken from the hi offsets alone) cover every pair.
+__global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, float eps, float d0) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    const NodePos p = node_pos(d, b);
+    int pw[3];
+    wrapped_floor(L, p, pw);
+    const int4 an = d.node_anc[b];
+    const int cap = d.node_cap[b];
+    const int A[3] = {an.x, an.y, an.z};
+    float oh[3], ol[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        oh[k] = d.off_hi[3 * b + k];
+        ol[k] = d.off_lo[3 * b + k];
+    }
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    const float reach = d0 + 1e-3f;
+    // distinct bins met by the cells floor(X - reach) .. floor(X + reach) per axis
+    int bins[3][4], nb[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        nb[a] = 0;
+        const int c0 = pw[a] + (int)floorf(p.r[a] - reach), c1 = pw[a] + (int)floorf(p.r[a] + reach);
+        for (int c = c0; c <= c1; ++c) {
+            int cw = c;
+            if (a == 1 && L.walls) {
+                if (c < 0 || c >= nn[a]) continue;
+            } else {
+                cw = wrap3(c, nn[a]);
+            }
+            const int bb = cw / BIN;
+            bool seen = false;
+            for (int q = 0; q < nb[a]; ++q) seen = seen || bins[a][q] == bb;
+            if (!seen && nb[a] < 4) bins[a][nb[a]++] = bb;
+        }
+    }
+    const float d02 = d0 * d0;
+    float F[3] = {0.f, 0.f, 0.f};
+    for (int iz = 0; iz < nb[2]; ++iz)
+        for (int iy = 0; iy < nb[1]; ++iy)
+            for (int ix = 0; ix < nb[0]; ++ix) {
+                const int t = (bins[2][iz] * L.nby + bins[1][iy]) * L.nbx + bins[0][ix];
+                const int cnt = d.tile_count[t];
+                const int start = cnt > 0 ? d.tile_offset[t] : 0;
+                for (int k = 0; k < cnt; ++k) {
+                    const int e = d.sorted[start + k];
+                    if (d.node_cap[e] == cap) continue;
+                    const int4 ae = d.node_anc[e];
+                    const int Ae[3] = {ae.x, ae.y, ae.z};
+                    float dx[3];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        float v = (float)(A[a] - Ae[a]) + ((oh[a] - d.off_hi[3 * e + a]) + (ol[a] - d.off_lo[3 * e + a]));
+                        if (!(a == 1 && L.walls)) {
+                            const float nf = (float)nn[a];
+                            v -= nf * rintf(v / nf);
+                        }
+                        dx[a] = v;
+                    }
+                    const float r2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
+                    if (r2 < d02 && r2 > 0.0f) {
+                        const float r = sqrtf(r2), g = d0 - r;
+                        const float m = eps * g * sqrtf(g) / r;
+                        F[0] += m * dx[0];
+                        F[1] += m * dx[1];
+                        F[2] += m * dx[2];
+                    }
+                }
+            }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] += F[a];
 }
 
 constexpr int SPREAD_GRID = 2048;
@@ -898,6 +981,10 @@ void launch_bin_scan(const Dev& d, int n_nodes, int par, hipStream_t s) {
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0)
         hipLaunchKernelGGL(k_bin_scatter, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, par);
+}
+void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
+    if (n_nodes > 0)
+        hipLaunchKernelGGL(k_repulse, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, eps, d0);
 }
 void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_spread, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);

@@ -162,7 +162,10 @@ std::string validate(const lbm_params* p) {
     if (p->ring_len > 0 && p->precision != LBM_FP32) return "the adjoint needs FP32 storage";
     if (p->stream_policy < 0 || p->stream_policy > 2) return "stream_policy must be 0, 1 or 2";
     if (p->zchunk != 0 && (p->zchunk % ZC != 0 || p->zchunk > 8 * ZC)) return "zchunk must be 0 or a multiple of 8 up to 64";
-    if (p->reserved[0] || p->reserved[1] || p->reserved[2]) return "reserved fields must be zero";
+    if (p->reserved[0]) return "reserved fields must be zero";
+    if (!(p->rep_eps >= 0.0) || !isfinite(p->rep_eps)) return "rep_eps must be finite and >= 0";
+    if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
+    if (p->rep_eps > 0.0 && p->ring_len > 0) return "the adjoint does not differentiate the repulsion: rep_eps must be 0";
     return "";
 }
 
@@ -565,6 +568,9 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     if (ibm) launch_bin_scan(d, c->n_nodes, par, s);
     mark(LBM_K_SCATTER);
     if (ibm) launch_bin_scatter(L, d, c->n_nodes, par, s);
+    mark(LBM_K_REPULSE);
+    if (ibm && c->p.rep_eps > 0.0 && ncap > 1)
+        launch_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
     mark(LBM_K_SPREAD);
     if (ibm) launch_spread(L, d, par, s);
     mark(LBM_K_COLLIDE);

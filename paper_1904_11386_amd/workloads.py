@@ -26,6 +26,8 @@ Workloads (sizes as stated, seeds numpy.random.default_rng(1904 + k)):
   c4      192x96x96 channel, walls y = 0 / 95 at -+0.01, interface z = 48
   c4_mini 48x24x24 channel, walls y = 0 / 23, one R = 4 (162-node) capsule
   c5      512^3 periodic, 512 capsules of 162 / 642 / 2562 nodes (R 4 / 6 / 10)
+  pressed 37x30x33, four R = 4 capsules pressed together in pairs (one pair
+          across the periodic x boundary), particle-particle repulsion on
 """
 
 from __future__ import annotations
@@ -176,6 +178,8 @@ class Workload:
     rho_maj: float = float(RHO_MAJ)
     rho_min: float = float(RHO_MIN)
     wet_scale: float = WET_SCALE
+    rep_eps: float = 0.0        # particle-particle repulsion strength (0 = off)
+    rep_d0: float = 1.25        # and its cut-off
     note: str = ""
 
     @property
@@ -324,6 +328,26 @@ def make(name: str, kV: Optional[float] = None) -> Workload:
         return Workload("c5", n, n, n, rhoA, rhoB, caps, z_interface=n / 2 - 0.5,
                         steps=300)
     raise KeyError(name)
+
+
+def pressed(nx=37, ny=30, nz=33, radius=4.0, freq=4, gap=0.6, rep_eps=0.5, rep_d0=1.25, walls=0,
+            theta=(70.0, 115.0, 100.0, 65.0), kS=0.01, G=3.6, wall_u=0.01) -> Workload:
+    """Capsules pressed together for the particle-particle repulsion: one
+    pair side by side in x in the middle of the box and one pair facing each
+    other across the periodic x boundary, surfaces `gap` apart (< rep_d0), on
+    a flat interface.  Odd box edges make the last tiles and bins partial."""
+    zs = nz // 2
+    rhoA, rhoB = layered(nx, ny, nz, zs)
+    h = radius + 0.5 * gap
+    yc, zc = ny / 2.0 + 0.3, zs - 0.4
+    centres = [(nx / 2.0 - h, yc, zc), (nx / 2.0 + h, yc, zc),
+               (h - 0.25, yc - 0.7, zc + 0.2), (nx - h - 0.25, yc - 0.7, zc + 0.2)]
+    caps = [Capsule(_snap(np.array(c)), radius, freq, kS, 0.0, KV_DEFAULT, theta[k % len(theta)])
+            for k, c in enumerate(centres)]
+    return Workload("pressed", nx, ny, nz, rhoA, rhoB, caps, G=G, walls=walls,
+                    wall_u_lo=(-wall_u, 0, 0) if walls else (0, 0, 0),
+                    wall_u_hi=(wall_u, 0, 0) if walls else (0, 0, 0),
+                    z_interface=zs - 0.5, steps=20, rep_eps=rep_eps, rep_d0=rep_d0)
 
 
 def small(nx=40, ny=36, nz=44, ncap=2, freq=4, radius=4.0, theta=(70.0, 115.0),

@@ -159,6 +159,43 @@ def test_first_step_node_forces_and_spread():
     assert np.allclose(phi.sum((1, 2, 3), dtype=np.float64), o.phi_last.sum((1, 2, 3)).numpy(), rtol=1e-5)
 
 
+@pytest.mark.parametrize("walls", [0, 1])
+def test_repulsion_first_step_node_forces(walls):
+    """Particle-particle repulsion (Sec. III.E) between four capsules pressed
+    together in pairs, one pair across the periodic x boundary, on an odd box
+    (partial last bins): the node forces of the first step, repulsion
+    included, against the oracle's; and the repulsion itself against the
+    same step without it."""
+    wl = W.pressed(walls=walls)
+    o = from_workload(wl)
+    o.step()
+    Fo = torch.cat(o.Fb_last, 0).numpy()
+    off = from_workload(wl, rep_eps=0.0)
+    off.step()
+    Ro = Fo - torch.cat(off.Fb_last, 0).numpy()
+    g = _sim(wl)
+    g.step(1)
+    F = g.node_forces()
+    import dataclasses
+    g0 = _sim(dataclasses.replace(wl, rep_eps=0.0))
+    g0.step(1)
+    R = F - g0.node_forces()
+    e = float(np.abs(F - Fo).max() / np.abs(Fo).max())
+    er = float(np.abs(R - Ro).max() / np.abs(Ro).max())
+    _say("pressed walls=%d: node force rel err %.3e, repulsion rel err %.3e (max %.3e), pairs' net force %.2e"
+         % (walls, e, er, np.abs(Ro).max(), float(np.abs(R.sum(0)).max())))
+    assert np.abs(Ro).max() > 1e-2
+    assert e < 1e-4 and er < 1e-4
+    # equal and opposite pair forces: the repulsion has no net force
+    assert float(np.abs(R.astype(np.float64).sum(0)).max()) <= 1e-5 * np.abs(Ro).max()
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_repulsion_pressed_capsules_100_steps(walls):
+    wl = W.pressed(walls=walls)
+    _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
+
+
 def test_bins_and_stencil_base_bit_exact():
     wl = W.small(nx=40, ny=36, nz=44, ncap=3, radius=4.0)
     # put one capsule across the periodic corner so floor() and wrapping are exercised
