@@ -19,6 +19,8 @@
  *     the same delta and scaled by wet_scale;
  *   - planar half-way bounce-back walls that may move (Sec. II.C,
  *     eq. method:SBB);
+ *   - optionally, the short-range particle-particle repulsion between
+ *     boundary nodes of different capsules (Sec. III.E);
  *   - observables: component masses, capsule centre of mass and height
  *     above the interface (Sec. III.D, eq. interface:contactangle), Taylor
  *     deformation (Sec. III.A, eq. results:taylorparameter).

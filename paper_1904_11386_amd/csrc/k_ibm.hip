@@ -460,7 +460,10 @@ __global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, 
     int pw[3];
     wrapped_floor(L, p, pw);
     const int4 an = d.node_anc[b];
-    const int cap = d.node_cap[b];
+    // a capsule's nodes have consecutive ids: same-capsule candidates are
+    // skipped by a range test, without loading anything of theirs
+    const CapDev& C = d.caps[d.node_cap[b]];
+    const unsigned own0 = (unsigned)C.node_start, own_n = (unsigned)C.node_count;
     const int A[3] = {an.x, an.y, an.z};
     float oh[3], ol[3];
 #pragma unroll
@@ -499,7 +502,7 @@ __global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, 
                 const int start = cnt > 0 ? d.tile_offset[t] : 0;
                 for (int k = 0; k < cnt; ++k) {
                     const int e = d.sorted[start + k];
-                    if (d.node_cap[e] == cap) continue;
+                    if ((unsigned)e - own0 < own_n) continue;
                     const int4 ae = d.node_anc[e];
                     const int Ae[3] = {ae.x, ae.y, ae.z};
                     float dx[3];
