@@ -102,8 +102,8 @@ typedef struct lbm_params {
                                pairs of different capsules at separation
                                d < rep_d0 repel along their separation with
                                rep_eps (rep_d0 - d)^{3/2}; 0 = off (the paper
-                               uses 0.5). Finite, >= 0; with the adjoint
-                               (ring_len > 0) it must be 0.                      */
+                               uses 0.5). Finite, >= 0; the adjoint
+                               differentiates it.                                */
     double rep_d0;          /* its cut-off, in (0, 2] when rep_eps > 0 (the
                                paper uses 1.25)                                  */
 } lbm_params;

@@ -447,21 +447,22 @@ __global__ __launch_bounds__(256) void k_bin_scatter(Lattice L, Dev d, int n_nod
 
 // Particle-particle repulsion (Sec. III.E): a node pair of different
 // capsules at separation d < d0 repels along the separation with
-// eps (d0 - d)^{3/2}.  One thread per node searches this step's 4^3 bins
-// that its d0-ball meets and sums its own pairs; the two nodes of a pair
-// compute the same d from negated differences, so their forces are exact
-// negatives.  Positions are anchor + (hi + lo) offsets, separations
-// minimum-image on the periodic axes.  The search range is widened by 1e-3
-// so that the bins (taken from the hi offsets alone) cover every pair.
-__global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, float eps, float d0) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_nodes) return;
+// eps (d0 - d)^{3/2}.
+//
+// for_each_contact calls fn(e, v, r2) for every node e of another capsule
+// with |v|^2 = r2 < d0^2, v = X_b - X_e on the nearest periodic image:
+// node b searches this step's 4^3 bins that its d0-ball meets.  Positions
+// are anchor + (hi + lo) offsets; both nodes of a pair compute the same
+// separation from negated differences.  The search range is widened by
+// 1e-3 so that the bins (taken from the hi offsets alone) cover every pair.
+// A capsule's nodes have consecutive ids, so same-capsule candidates are
+// skipped by a range test without loading anything of theirs.
+template <typename Fn>
+__device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d, int b, float d0, Fn&& fn) {
     const NodePos p = node_pos(d, b);
     int pw[3];
     wrapped_floor(L, p, pw);
     const int4 an = d.node_anc[b];
-    // a capsule's nodes have consecutive ids: same-capsule candidates are
-    // skipped by a range test, without loading anything of theirs
     const CapDev& C = d.caps[d.node_cap[b]];
     const unsigned own0 = (unsigned)C.node_start, own_n = (unsigned)C.node_count;
     const int A[3] = {an.x, an.y, an.z};
@@ -493,7 +494,6 @@ __global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, 
         }
     }
     const float d02 = d0 * d0;
-    float F[3] = {0.f, 0.f, 0.f};
     for (int iz = 0; iz < nb[2]; ++iz)
         for (int iy = 0; iy < nb[1]; ++iy)
             for (int ix = 0; ix < nb[0]; ++ix) {
@@ -505,28 +505,59 @@ __global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, 
                     if ((unsigned)e - own0 < own_n) continue;
                     const int4 ae = d.node_anc[e];
                     const int Ae[3] = {ae.x, ae.y, ae.z};
-                    float dx[3];
+                    float v[3];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        float v = (float)(A[a] - Ae[a]) + ((oh[a] - d.off_hi[3 * e + a]) + (ol[a] - d.off_lo[3 * e + a]));
+                        float x = (float)(A[a] - Ae[a]) + ((oh[a] - d.off_hi[3 * e + a]) + (ol[a] - d.off_lo[3 * e + a]));
                         if (!(a == 1 && L.walls)) {
                             const float nf = (float)nn[a];
-                            v -= nf * rintf(v / nf);
+                            x -= nf * rintf(x / nf);
                         }
-                        dx[a] = v;
+                        v[a] = x;
                     }
-                    const float r2 = dx[0] * dx[0] + dx[1] * dx[1] + dx[2] * dx[2];
-                    if (r2 < d02 && r2 > 0.0f) {
-                        const float r = sqrtf(r2), g = d0 - r;
-                        const float m = eps * g * sqrtf(g) / r;
-                        F[0] += m * dx[0];
-                        F[1] += m * dx[1];
-                        F[2] += m * dx[2];
-                    }
+                    const float r2 = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+                    if (r2 < d02 && r2 > 0.0f) fn(e, v, r2);
                 }
             }
+}
+
+// Forward: node b's repulsion, f_b = sum_e m(d) (X_b - X_e) with
+// m(d) = eps (d0 - d)^{3/2} / d, added to its force at X^n.
+__global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, float eps, float d0) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    float F[3] = {0.f, 0.f, 0.f};
+    for_each_contact(L, d, b, d0, [&](int, const float* v, float r2) {
+        const float r = sqrtf(r2), g = d0 - r;
+        const float m = eps * g * sqrtf(g) / r;
+        F[0] += m * v[0];
+        F[1] += m * v[1];
+        F[2] += m * v[2];
+    });
 #pragma unroll
     for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] += F[a];
+}
+
+// Adjoint: with J = dF_b/dX_b = m I + (m'(d) / d) v v^T (symmetric) and
+// dF_e/dX_b = -J for the partner, lambda_X_b += sum_e J (lambda_F_b -
+// lambda_F_e), where m'(d) = -eps (1.5 (d0 - d)^{1/2} / d + (d0 - d)^{3/2} / d^2).
+__global__ __launch_bounds__(256) void k_adj_repulse(Lattice L, Dev d, int n_nodes, float eps, float d0) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    const float lb[3] = {d.lam_Fb[3 * b], d.lam_Fb[3 * b + 1], d.lam_Fb[3 * b + 2]};
+    float acc[3] = {0.f, 0.f, 0.f};
+    for_each_contact(L, d, b, d0, [&](int e, const float* v, float r2) {
+        const float r = sqrtf(r2), g = d0 - r, sg = sqrtf(g);
+        const float m = eps * g * sg / r;
+        const float mp = -eps * (1.5f * sg / r + g * sg / r2);
+        const float w[3] = {lb[0] - d.lam_Fb[3 * e], lb[1] - d.lam_Fb[3 * e + 1], lb[2] - d.lam_Fb[3 * e + 2]};
+        const float vw = (v[0] * w[0] + v[1] * w[1] + v[2] * w[2]) * (mp / r);
+        acc[0] += m * w[0] + vw * v[0];
+        acc[1] += m * w[1] + vw * v[1];
+        acc[2] += m * w[2] + vw * v[2];
+    });
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d.lam_X[3 * b + a] += acc[a];
 }
 
 constexpr int SPREAD_GRID = 2048;
@@ -988,6 +1019,10 @@ void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hi
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
     if (n_nodes > 0)
         hipLaunchKernelGGL(k_repulse, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, eps, d0);
+}
+void launch_adj_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
+    if (n_nodes > 0)
+        hipLaunchKernelGGL(k_adj_repulse, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, eps, d0);
 }
 void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_spread, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);

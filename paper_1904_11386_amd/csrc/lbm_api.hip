@@ -165,7 +165,6 @@ std::string validate(const lbm_params* p) {
     if (p->reserved[0]) return "reserved fields must be zero";
     if (!(p->rep_eps >= 0.0) || !isfinite(p->rep_eps)) return "rep_eps must be finite and >= 0";
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
-    if (p->rep_eps > 0.0 && p->ring_len > 0) return "the adjoint does not differentiate the repulsion: rep_eps must be 0";
     return "";
 }
 
@@ -1102,6 +1101,8 @@ int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
             launch_adj_collide(L, fin, rho_n, rho_p, d.fib, d.tile_flag, d.lam[p], d.lam_u, d.lam_rho, d.lam_j,
                                d.lam_S, d.lam_Fib, d.u, d.grads, s);
             launch_adj_nodes(L, d, rho_n, c->n_nodes, s);
+            if (c->p.rep_eps > 0.0 && c->caps.size() > 1)
+                launch_adj_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
             launch_adj_membrane(d, c->n_nodes, c->n_faces, s);
             launch_spread_vec(L, d, par, d.lam_q, d.lam_S, 1, s);
             launch_adj_gather(L, d.lam_S, d.lam_rho, s);

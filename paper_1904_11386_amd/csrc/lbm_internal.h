@@ -170,6 +170,7 @@ void launch_spread_vec(const Lattice& L, const Dev& d, int parity, const float* 
                        hipStream_t s);
 void launch_adj_nodes(const Lattice& L, const Dev& d, const float* rho_n, int n_nodes, hipStream_t s);
 void launch_adj_membrane(const Dev& d, int n_nodes, int n_faces, hipStream_t s);
+void launch_adj_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s);
 // adjoint (k_fluid.hip)
 void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
                         const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
