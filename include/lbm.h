@@ -19,8 +19,9 @@
  *     the same delta and scaled by wet_scale;
  *   - planar half-way bounce-back walls that may move (Sec. II.C,
  *     eq. method:SBB);
- *   - optionally, the short-range particle-particle repulsion between
- *     boundary nodes of different capsules (Sec. III.E);
+ *   - optionally, Helfrich bending of the membranes (Sec. II.B) and the
+ *     short-range particle-particle repulsion between boundary nodes of
+ *     different capsules (Sec. III.E);
  *   - observables: component masses, capsule centre of mass and height
  *     above the interface (Sec. III.D, eq. interface:contactangle), Taylor
  *     deformation (Sec. III.A, eq. results:taylorparameter).
@@ -157,6 +158,18 @@ int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
                      const int32_t* tri, const double* kS, const double* C,
                      const double* kV, const double* theta_deg, int32_t* first_id);
 
+/* Helfrich bending (Sec. II.B, eqs. method:curvature and surf_dens, zero
+ * spontaneous curvature): bending moduli kB[n_caps] (finite, >= 0; 0 = none,
+ * the default) of the capsules first_id .. first_id + n_caps - 1.  Each node
+ * of a capsule with kB > 0 gets F = 2 kB [2 H (H^2 - K) + Lap_s H] n A, with
+ * the mean curvature H, Gaussian curvature K, Laplace-Beltrami operator,
+ * outward normal n and mixed area A of the discrete operators of Meyer et
+ * al. (2003) on the current mesh.  Only before the first lbm_step (else
+ * LBM_ESTATE); LBM_EINVAL for a range outside the capsules added, a bad kB,
+ * or kB > 0 on a context with the adjoint (ring_len > 0), which does not
+ * differentiate it. */
+int lbm_capsules_bending(lbm_ctx* ctx, int32_t first_id, int32_t n_caps, const double* kB);
+
 /* Advance nsteps >= 0 time steps, asynchronously on the stream.  With
  * use_graphs, pairs of steps are replayed from HIP graphs captured on the
  * first call (kernels only, no memory-set nodes).  With
@@ -175,10 +188,11 @@ enum {
     LBM_K_SCAN = 5,     /* scan of the tile bins                           */
     LBM_K_SCATTER = 6,  /* counting-sort scatter                           */
     LBM_K_REPULSE = 7,  /* particle-particle repulsion (rep_eps > 0)       */
-    LBM_K_SPREAD = 8,   /* LDS-binned spreading                            */
-    LBM_K_COLLIDE = 9,  /* fused pull + force + collide over the lattice   */
-    LBM_K_INTERP = 10,  /* interpolation and node advection                */
-    LBM_NK = 11
+    LBM_K_BEND = 8,     /* Helfrich bending forces (some kB > 0)           */
+    LBM_K_SPREAD = 9,   /* LDS-binned spreading                            */
+    LBM_K_COLLIDE = 10, /* fused pull + force + collide over the lattice   */
+    LBM_K_INTERP = 11,  /* interpolation and node advection                */
+    LBM_NK = 12
 };
 
 /* As lbm_step (without the mass check), and synchronises: HIP events are

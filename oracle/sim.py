@@ -20,8 +20,9 @@ positions X^n.  The step, in this order:
         R_b = -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i
     (np = the non-preferred component), which keeps fluid plus membrane
     momentum conserved, as Sec. II.D requires of the cross-boundary force;
-    when enabled, the particle-particle repulsion of Sec. III.E between
-    nodes of different capsules (contact.py);
+    when enabled, Helfrich bending (Sec. II.B, bending.py) and the
+    particle-particle repulsion of Sec. III.E between nodes of different
+    capsules (contact.py);
  4. spreading F_ib(x) = sum_b F_b delta(x - X_b) and the phi fields;
  5. fluid force F^c = -psi^c G sum_i w_i (psi^c' + phi^c')(x + c_i) c_i
     + (rho^c / rho) F_ib (Sec. II.D eq. method:shanchen; the body force is
@@ -42,7 +43,7 @@ import math
 
 import torch
 
-from . import contact, ibm, lattice, membrane
+from . import bending, contact, ibm, lattice, membrane
 
 DT = torch.float64
 
@@ -93,7 +94,7 @@ class OracleSim:
         for c in caps:
             mesh = membrane.Mesh(c["xyz"], c["tri"])
             self.caps.append(dict(mesh=mesh, kS=c["kS"], C=float(c["C"]),
-                                  kV=float(c["kV"]), theta=c["theta"]))
+                                  kV=float(c["kV"]), theta=c["theta"], kB=float(c.get("kB", 0.0))))
         self.X = [torch.as_tensor(c["xyz"], dtype=DT).clone() for c in caps]
         self.n = 0
         self.fluid_mask = torch.ones(self.ny, dtype=torch.bool)
@@ -131,6 +132,9 @@ class OracleSim:
             X = self.X[k]
             F = membrane.elastic_forces(cap["mesh"], X, cap["kS"], cap["C"],
                                         cap["kV"], create_graph=self.diff)
+            if cap["kB"] > 0.0:
+                # Helfrich bending (Sec. II.B, eq. surf_dens)
+                F = F + bending.bending_forces(X, cap["mesh"].tri, cap["kB"])
             rv, pref = self.colour(k)
             is_zero = (not isinstance(rv, torch.Tensor)) and rv == 0.0
             a = cap["mesh"].node_area * (rv.abs() if isinstance(rv, torch.Tensor) else abs(rv))
@@ -215,7 +219,8 @@ def from_workload(wl, differentiable=False, **over):
     caps = []
     for c in wl.capsules:
         xyz, tri = c.mesh()
-        caps.append(dict(xyz=xyz, tri=tri, kS=c.kS, C=c.C, kV=c.kV, theta=c.theta_deg))
+        caps.append(dict(xyz=xyz, tri=tri, kS=c.kS, C=c.C, kV=c.kV, theta=c.theta_deg,
+                         kB=getattr(c, "kB", 0.0)))
     kw = dict(tau=wl.tau, G=wl.G, walls=wl.walls, u_lo=wl.wall_u_lo, u_hi=wl.wall_u_hi,
               rho_maj=wl.rho_maj, rho_min=wl.rho_min, z_interface=wl.z_interface,
               wet_scale=wl.wet_scale, differentiable=differentiable,

@@ -44,7 +44,7 @@ class CapObs(C.Structure):
 
 _lib = None
 
-EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_step", "lbm_step_timed", "lbm_observables",
+EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_bending", "lbm_step", "lbm_step_timed", "lbm_observables",
            "lbm_get_fields", "lbm_get_nodes", "lbm_get_node_forces", "lbm_get_spread",
            "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_adjoint_forward", "lbm_adjoint_backward",
            "lbm_destroy", "lbm_last_error"]
@@ -68,6 +68,7 @@ def load(path: str = None):
         "lbm_workspace_bytes": ([P(Params), i64, i64, P(i64)], C.c_int),
         "lbm_init": ([P(Params), P(C.c_float), P(C.c_float), vp, i64, i64, i64, vp, P(vp)], C.c_int),
         "lbm_capsules_add": ([vp, i32, P(i32), P(i32), P(d), P(i32), P(d), P(d), P(d), P(d), P(i32)], C.c_int),
+        "lbm_capsules_bending": ([vp, i32, i32, P(d)], C.c_int),
         "lbm_step": ([vp, i32], C.c_int),
         "lbm_step_timed": ([vp, i32, P(d)], C.c_int),
         "lbm_observables": ([vp, P(Obs), P(CapObs)], C.c_int),
@@ -187,10 +188,15 @@ class Sim:
         self.n_caps += len(npc)
         return first.value
 
+    def set_bending(self, first_id, kB):
+        """Helfrich bending moduli of the capsules first_id .. first_id + len(kB) - 1."""
+        kB = np.ascontiguousarray(kB, dtype=np.float64)
+        self._check(self.lib.lbm_capsules_bending(self.ctx, int(first_id), len(kB), _ptr(kB, C.c_double)))
+
     def step(self, n=1):
         self._check(self.lib.lbm_step(self.ctx, int(n)))
 
-    KERNELS = ["clear", "density", "volume", "faces", "nodes", "scan", "scatter", "repulse", "spread",
+    KERNELS = ["clear", "density", "volume", "faces", "nodes", "scan", "scatter", "repulse", "bend", "spread",
                "collide", "interp"]
 
     def step_timed(self, n):
@@ -291,5 +297,8 @@ def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()
-        s.add_capsules(npc, fpc, xyz, tri, kS, Cs, kV, th)
+        first = s.add_capsules(npc, fpc, xyz, tri, kS, Cs, kV, th)
+        kB = np.array([c.kB for c in wl.capsules], np.float64)
+        if (kB > 0).any():
+            s.set_bending(first, kB)
     return s

@@ -19,6 +19,8 @@
 //                   plus one global atomic per wavefront)
 //   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
 //                   the 8^3 tiles the bins' stencils can reach
+//   k_bend_geo, k_bend_force  (when enabled) Helfrich bending: discrete
+//                   curvatures per node, then the cot Laplacian and the force
 //   k_repulse       (when enabled) particle-particle repulsion between nodes
 //                   of different capsules, searched through the bins
 //   k_spread        one workgroup per occupied bin: accumulate F_b delta and
@@ -560,6 +562,110 @@ __global__ __launch_bounds__(256) void k_adj_repulse(Lattice L, Dev d, int n_nod
     for (int a = 0; a < 3; ++a) d.lam_X[3 * b + a] += acc[a];
 }
 
+// Helfrich bending (Sec. II.B, eq. surf_dens with zero spontaneous
+// curvature): F_i = 2 kB [2 H (H^2 - K) + Lap_s H] n A at each node of a
+// capsule with kB > 0, from the discrete operators of Meyer et al. (2003)
+// on the current mesh.  Per triangle (i, j, k) seen from node i: the cot of
+// the angle at a corner is (dot of its two edges) / |cross|; the mixed area
+// is the Voronoi part (|x_ij|^2 cot_k + |x_ik|^2 cot_j) / 8 for a triangle
+// without an obtuse angle, else area / 2 (obtuse at i) or area / 4; the
+// mean curvature normal sums cot_k (x_i - x_j) + cot_j (x_i - x_k) over
+// 2 A; the Gaussian curvature is the angle deficit over A; n is the
+// normalised sum of the triangles' area normals, H = (K_vec . n) / 2.
+// Two passes, one thread per node walking its corners: the geometry, then
+// the cot Laplacian of H (which needs the neighbours' H) and the force.
+// Positions are the capsule-relative hi + lo offsets (one anchor per capsule).
+__device__ __forceinline__ void bend_pos(const Dev& d, int b, float x[3]) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) x[a] = d.off_hi[3 * b + a] + d.off_lo[3 * b + a];
+}
+
+struct BendCorner {
+    int j, k;                 // the other two nodes, in the triangle's cyclic order after i
+    float eij[3], eik[3];     // x_j - x_i, x_k - x_i
+    float cn;                 // |e_ij x e_ik| (twice the area)
+    float cr[3];              // e_ij x e_ik (outward area normal, doubled)
+    float di, cot_j, cot_k;   // dot at i, cots at j and k
+};
+
+__device__ __forceinline__ BendCorner bend_corner(const Dev& d, int sc, const float xi[3]) {
+    BendCorner q;
+    const int f = sc / 3, c = sc - 3 * f;
+    q.j = d.tri[3 * f + (c + 1) % 3];
+    q.k = d.tri[3 * f + (c + 2) % 3];
+    float xj[3], xk[3];
+    bend_pos(d, q.j, xj);
+    bend_pos(d, q.k, xk);
+    float ejk[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        q.eij[a] = xj[a] - xi[a];
+        q.eik[a] = xk[a] - xi[a];
+        ejk[a] = xk[a] - xj[a];
+    }
+    q.cr[0] = q.eij[1] * q.eik[2] - q.eij[2] * q.eik[1];
+    q.cr[1] = q.eij[2] * q.eik[0] - q.eij[0] * q.eik[2];
+    q.cr[2] = q.eij[0] * q.eik[1] - q.eij[1] * q.eik[0];
+    q.cn = sqrtf(q.cr[0] * q.cr[0] + q.cr[1] * q.cr[1] + q.cr[2] * q.cr[2]);
+    q.di = q.eij[0] * q.eik[0] + q.eij[1] * q.eik[1] + q.eij[2] * q.eik[2];
+    const float dj = -(q.eij[0] * ejk[0] + q.eij[1] * ejk[1] + q.eij[2] * ejk[2]);
+    const float dk = q.eik[0] * ejk[0] + q.eik[1] * ejk[1] + q.eik[2] * ejk[2];
+    q.cot_j = dj / q.cn;
+    q.cot_k = dk / q.cn;
+    return q;
+}
+
+__global__ __launch_bounds__(256) void k_bend_geo(Dev d, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes || d.caps[d.node_cap[b]].kB == 0.0f) return;
+    float xi[3];
+    bend_pos(d, b, xi);
+    float A = 0.f, th = 0.f, Kv[3] = {0.f, 0.f, 0.f}, nr[3] = {0.f, 0.f, 0.f};
+    for (int s = d.csr_ptr[b]; s < d.csr_ptr[b + 1]; ++s) {
+        const BendCorner q = bend_corner(d, d.slot_corner[s], xi);
+        const float area = 0.5f * q.cn;
+        const float lij = q.eij[0] * q.eij[0] + q.eij[1] * q.eij[1] + q.eij[2] * q.eij[2];
+        const float lik = q.eik[0] * q.eik[0] + q.eik[1] * q.eik[1] + q.eik[2] * q.eik[2];
+        const bool obt_other = q.cot_j < 0.0f || q.cot_k < 0.0f;
+        A += q.di < 0.0f ? 0.5f * area : (obt_other ? 0.25f * area : 0.125f * (lij * q.cot_k + lik * q.cot_j));
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            Kv[a] -= q.cot_k * q.eij[a] + q.cot_j * q.eik[a];
+            nr[a] += q.cr[a];
+        }
+        th += atan2f(q.cn, q.di);
+    }
+    const float inr = 1.0f / sqrtf(nr[0] * nr[0] + nr[1] * nr[1] + nr[2] * nr[2]);
+    const float n[3] = {nr[0] * inr, nr[1] * inr, nr[2] * inr};
+    float* o = d.node_bend + 6 * (int64_t)b;
+    o[0] = 0.5f * (Kv[0] * n[0] + Kv[1] * n[1] + Kv[2] * n[2]) / (2.0f * A);
+    o[1] = (6.28318530717958648f - th) / A;
+    o[2] = A;
+    o[3] = n[0];
+    o[4] = n[1];
+    o[5] = n[2];
+}
+
+__global__ __launch_bounds__(256) void k_bend_force(Dev d, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    const float kB = d.caps[d.node_cap[b]].kB;
+    if (kB == 0.0f) return;
+    float xi[3];
+    bend_pos(d, b, xi);
+    const float* g = d.node_bend + 6 * (int64_t)b;
+    const float H = g[0], K = g[1], A = g[2];
+    float lap = 0.f;
+    for (int s = d.csr_ptr[b]; s < d.csr_ptr[b + 1]; ++s) {
+        const BendCorner q = bend_corner(d, d.slot_corner[s], xi);
+        lap += q.cot_k * (d.node_bend[6 * (int64_t)q.j] - H) + q.cot_j * (d.node_bend[6 * (int64_t)q.k] - H);
+    }
+    lap /= 2.0f * A;
+    const float sF = 2.0f * kB * (2.0f * H * (H * H - K) + lap) * A;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] += sF * g[3 + a];
+}
+
 constexpr int SPREAD_GRID = 2048;
 
 __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
@@ -1023,6 +1129,12 @@ void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, floa
 void launch_adj_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
     if (n_nodes > 0)
         hipLaunchKernelGGL(k_adj_repulse, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, eps, d0);
+}
+void launch_bending(const Dev& d, int n_nodes, hipStream_t s) {
+    if (n_nodes <= 0) return;
+    const dim3 g((n_nodes + 255) / 256);
+    hipLaunchKernelGGL(k_bend_geo, g, dim3(256), 0, s, d, n_nodes);
+    hipLaunchKernelGGL(k_bend_force, g, dim3(256), 0, s, d, n_nodes);
 }
 void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_spread, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);

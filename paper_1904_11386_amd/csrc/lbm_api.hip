@@ -26,7 +26,7 @@ struct Layout {
     size_t tile_flag, tile_count, tile_offset, home_start, touched[2], home[2], counters;
     int64_t bins;
     size_t off_hi, off_lo, node_cap, node_anc, node_wet, node_F, node_tile, node_rank, sorted, csr_ptr, corner_slot,
-        dbg_bins;
+        slot_corner, node_bend, dbg_bins;
     size_t tri, fref, face_cap, face_F;
     size_t caps, capV, cap_mom, red, cscale, dpart, dmass;
     size_t slot0, slot_bytes, fbytes;
@@ -84,6 +84,8 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     l.sorted = take(c, nb * 4);
     l.csr_ptr = take(c, (nb + 1) * 4);
     l.corner_slot = take(c, 3 * nf * 4);
+    l.slot_corner = take(c, 3 * nf * 4);
+    l.node_bend = take(c, 6 * nb * 4);
     l.dbg_bins = take(c, 4 * nb * 4);
     l.tri = take(c, 3 * nf * 4);
     l.fref = take(c, nf * sizeof(FaceRef));
@@ -199,6 +201,7 @@ struct lbm_ctx {
     int n_nodes = 0, n_faces = 0;
     hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [step parity][flip]
     bool graphs_failed = false;
+    bool bending = false;          // some capsule has a bending modulus
     std::string err;
 
     bool half() const { return p.precision == LBM_FP16; }
@@ -317,6 +320,8 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     d.sorted = (int*)(w + lay.sorted);
     d.csr_ptr = (int*)(w + lay.csr_ptr);
     d.corner_slot = (int*)(w + lay.corner_slot);
+    d.slot_corner = (int*)(w + lay.slot_corner);
+    d.node_bend = (float*)(w + lay.node_bend);
     d.dbg_bins = (int*)(w + lay.dbg_bins);
     d.tri = (int*)(w + lay.tri);
     d.fref = (FaceRef*)(w + lay.fref);
@@ -438,6 +443,7 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
         cd.kS = (float)kS[k];
         cd.C = (float)C[k];
         cd.kV = (float)kV[k];
+        cd.kB = 0.0f;
         // rest geometry in FP64, relative to the anchor
         std::vector<double> R(3 * (size_t)nn);
         for (int b = 0; b < nn; ++b)
@@ -494,6 +500,8 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
     std::vector<int> fill(ptr.begin(), ptr.end() - 1);
     for (int f = 0; f < c->n_faces; ++f)
         for (int j = 0; j < 3; ++j) slot[3 * f + j] = fill[c->tri_global[3 * f + j]]++;
+    std::vector<int> slot_corner(3 * (size_t)c->n_faces);
+    for (int64_t q = 0; q < 3 * (int64_t)c->n_faces; ++q) slot_corner[slot[q]] = (int)q;
     std::vector<int> anc(4 * (size_t)c->n_nodes);
     for (int b = 0; b < c->n_nodes; ++b) {
         const CapDev& cd = c->caps[c->node_cap[b]];
@@ -511,6 +519,7 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
     HIPCHK(c, hipMemcpyAsync(d.node_area, c->node_area.data(), nb * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.csr_ptr, ptr.data(), (nb + 1) * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.corner_slot, slot.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.slot_corner, slot_corner.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.node_anc, anc.data(), nb * 16, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.tri, c->tri_global.data(), 3 * nf * 4, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(d.fref, c->fref.data(), nf * sizeof(FaceRef), hipMemcpyHostToDevice, s));
@@ -570,6 +579,8 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_REPULSE);
     if (ibm && c->p.rep_eps > 0.0 && ncap > 1)
         launch_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
+    mark(LBM_K_BEND);
+    if (ibm && c->bending) launch_bending(d, c->n_nodes, s);
     mark(LBM_K_SPREAD);
     if (ibm) launch_spread(L, d, par, s);
     mark(LBM_K_COLLIDE);
@@ -622,6 +633,30 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
     return ex;
 }
 
+
+int lbm_capsules_bending(lbm_ctx* c, int32_t first_id, int32_t n_caps, const double* kB) {
+    if (!c) return LBM_EINVAL;
+    if (c->step != 0) return c->fail(LBM_ESTATE, "bending moduli must be set before the first step");
+    if (n_caps < 0 || first_id < 0 || (int64_t)first_id + n_caps > (int64_t)c->caps.size())
+        return c->fail(LBM_EINVAL, "capsule range outside the capsules added");
+    if (n_caps == 0) return LBM_OK;
+    if (!kB) return c->fail(LBM_EINVAL, "NULL kB");
+    bool any = false;
+    for (int k = 0; k < n_caps; ++k) {
+        if (!(kB[k] >= 0.0) || !isfinite(kB[k])) return c->fail(LBM_EINVAL, "capsule %d: kB must be finite and >= 0", first_id + k);
+        any = any || kB[k] > 0.0;
+    }
+    if (any && c->p.ring_len > 0) return c->fail(LBM_EINVAL, "the adjoint does not differentiate bending: kB must be 0");
+    for (int k = 0; k < n_caps; ++k) c->caps[first_id + k].kB = (float)kB[k];
+    bool on = false;
+    for (const CapDev& cd : c->caps) on = on || cd.kB > 0.0f;
+    c->bending = on;
+    for (auto& g : c->graph)
+        for (auto& e : g)
+            if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+    HIPCHK(c, hipMemcpyAsync(c->d.caps, c->caps.data(), c->caps.size() * sizeof(CapDev), hipMemcpyHostToDevice, c->stream));
+    return LBM_OK;
+}
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");

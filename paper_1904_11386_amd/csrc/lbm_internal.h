@@ -69,6 +69,7 @@ struct CapDev {
     float rv_abs;       // |rho_v|
     float drv;          // d|rho_v| / d theta (per radian)
     float kS, C, kV;
+    float kB;           // Helfrich bending modulus (0 = none)
     double V0;
 };
 
@@ -106,6 +107,8 @@ struct Dev {
     int* sorted;          // [nodes]
     int* csr_ptr;         // [nodes + 1] corners of node b: slots csr_ptr[b] .. csr_ptr[b+1]-1
     int* corner_slot;     // [faces][3] slot of corner (face, k), in node order
+    int* slot_corner;     // [3 faces] the inverse: 3 * face + k of each slot
+    float* node_bend;     // [nodes][6] bending geometry: H, K, mixed area, outward normal
     int* dbg_bins;        // [nodes][4] debug binning output
     // faces
     int* tri;             // [faces][3] global node indices
@@ -161,6 +164,7 @@ void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const floa
 void launch_bin_scan(const Dev& d, int n_nodes, int parity, hipStream_t s);
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s);
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s);
+void launch_bending(const Dev& d, int n_nodes, hipStream_t s);
 void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s);

@@ -28,6 +28,8 @@ Workloads (sizes as stated, seeds numpy.random.default_rng(1904 + k)):
   c5      512^3 periodic, 512 capsules of 162 / 642 / 2562 nodes (R 4 / 6 / 10)
   pressed 37x30x33, four R = 4 capsules pressed together in pairs (one pair
           across the periodic x boundary), particle-particle repulsion on
+  bent    38x34x36, two capsules with Helfrich bending (one an ellipsoid) and
+          an ellipsoid without it across the periodic x boundary
 """
 
 from __future__ import annotations
@@ -153,10 +155,12 @@ class Capsule:
     C: float
     kV: float
     theta_deg: float
+    kB: float = 0.0                         # Helfrich bending modulus (0 = none)
+    stretch: tuple = (1.0, 1.0, 1.0)        # axis scaling of the rest mesh (ellipsoids)
 
     def mesh(self):
         xyz, tri = icosphere(self.freq, self.radius)
-        return _snap(xyz + self.centre[None, :]), tri
+        return _snap(xyz * np.asarray(self.stretch, dtype=np.float64)[None, :] + self.centre[None, :]), tri
 
 
 @dataclass
@@ -328,6 +332,24 @@ def make(name: str, kV: Optional[float] = None) -> Workload:
         return Workload("c5", n, n, n, rhoA, rhoB, caps, z_interface=n / 2 - 0.5,
                         steps=300)
     raise KeyError(name)
+
+
+def bent(nx=38, ny=34, nz=36, kB=0.02, freq=4, walls=0) -> Workload:
+    """Capsules with Helfrich bending on a flat interface: an ellipsoid
+    (rest mesh stretched 1.35 / 1.0 / 0.75 from R = 5), a sphere (R = 4) and
+    a second ellipsoid across the periodic x boundary without bending.  The
+    rest shape is the stretched one, so the Skalak force starts at zero and
+    the bending force (zero spontaneous curvature) drives the ellipsoids."""
+    zs = nz // 2
+    rhoA, rhoB = layered(nx, ny, nz, zs)
+    caps = [Capsule(_snap(np.array([11.3, 10.2, zs - 0.3])), 5.0, freq, 0.01, 0.0, KV_DEFAULT, 75.0,
+                    kB=kB, stretch=(1.35, 1.0, 0.75)),
+            Capsule(_snap(np.array([25.6, 23.4, zs - 0.6])), 4.0, freq, 0.008, 0.0, KV_DEFAULT, 105.0, kB=kB),
+            Capsule(_snap(np.array([1.4, 24.1, zs + 0.2])), 4.0, freq, 0.01, 0.0, KV_DEFAULT, 95.0,
+                    stretch=(0.8, 1.2, 1.0))]
+    return Workload("bent", nx, ny, nz, rhoA, rhoB, caps, walls=walls,
+                    wall_u_lo=(-0.01, 0, 0) if walls else (0, 0, 0),
+                    wall_u_hi=(0.01, 0, 0) if walls else (0, 0, 0), z_interface=zs - 0.5, steps=20)
 
 
 def pressed(nx=37, ny=30, nz=33, radius=4.0, freq=4, gap=0.6, rep_eps=0.5, rep_d0=1.25, walls=0,

@@ -196,6 +196,54 @@ def test_repulsion_pressed_capsules_100_steps(walls):
     _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
 
 
+def test_bending_first_step_node_forces():
+    """Helfrich bending (Sec. II.B) on a stretched ellipsoid and a sphere, with
+    an unbent ellipsoid across the periodic boundary: the first step's node
+    forces against the oracle's, and the bending part alone (forces with it
+    minus without it) against the oracle's discrete-operator force."""
+    import dataclasses
+    from oracle import bending as obend
+    wl = W.bent()
+    o = from_workload(wl)
+    o.step()
+    Fo = torch.cat(o.Fb_last, 0).numpy()
+    flat = dataclasses.replace(wl, capsules=[dataclasses.replace(c, kB=0.0) for c in wl.capsules])
+    g = _sim(wl)
+    g.step(1)
+    F = g.node_forces()
+    g0 = _sim(flat)
+    g0.step(1)
+    Bg = F - g0.node_forces()
+    Bo = np.concatenate([obend.bending_forces(torch.tensor(c.mesh()[0]), torch.tensor(c.mesh()[1]), c.kB).numpy()
+                         if c.kB > 0 else np.zeros((10 * c.freq ** 2 + 2, 3)) for c in wl.capsules], 0)
+    e = float(np.abs(F - Fo).max() / np.abs(Fo).max())
+    eb = float(np.abs(Bg - Bo).max() / np.abs(Bo).max())
+    _say("bent: node force rel err %.3e, bending rel err %.3e (max %.3e)" % (e, eb, np.abs(Bo).max()))
+    assert np.abs(Bo).max() > 1e-3
+    assert e < 1e-4 and eb < 1e-3
+
+
+@pytest.mark.parametrize("walls", [0, 1])
+def test_bending_capsules_100_steps(walls):
+    wl = W.bent(walls=walls)
+    _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
+
+
+def test_bending_entry_point_validation():
+    from paper_1904_11386_amd.binding import LbmError, sim_from_workload
+    wl = W.bent()
+    g = sim_from_workload(wl)
+    for first, kB in ((3, [0.1]), (-1, [0.1]), (0, [0.1, 0.1, 0.1, 0.1]), (0, [-0.1]), (0, [float("nan")])):
+        with pytest.raises(LbmError):
+            g.set_bending(first, kB)
+    g.step(2)
+    with pytest.raises(LbmError):                # only before the first step
+        g.set_bending(0, [0.1])
+    ga = sim_from_workload(W.bent(kB=0.0), n_slots=2, ring_len=4)
+    with pytest.raises(LbmError):                # the adjoint does not differentiate bending
+        ga.set_bending(0, [0.1])
+
+
 def test_bins_and_stencil_base_bit_exact():
     wl = W.small(nx=40, ny=36, nz=44, ncap=3, radius=4.0)
     # put one capsule across the periodic corner so floor() and wrapping are exercised
