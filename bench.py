@@ -243,21 +243,24 @@ def scale_leg(torch, warmup=100, steps=200):
     return out
 
 
-def repulsion_leg(torch, warmup=100, steps=200):
-    """The 512^3 configuration with the particle-particle repulsion of
-    Sec. III.E switched on (eps 0.5, cut-off 1.25, the paper's values): both
-    storage forms, MLUPS and the repulsion kernel's share of the step.  The
-    seeded capsules start at least 2 lu apart, so this prices the bin search
-    every step pays; pairs in contact add a few flops each."""
+def membrane_extras_leg(torch, warmup=100, steps=200):
+    """The 512^3 configuration with the optional membrane terms on: Helfrich
+    bending at the paper's B = kB / (kS R0^2) = 1e-2 (Sec. II.B) and the
+    particle-particle repulsion of Sec. III.E (eps 0.5, cut-off 1.25); both
+    storage forms, MLUPS and the two terms' kernel time per step.  The seeded
+    capsules start at least 2 lu apart, so the repulsion prices the bin
+    search every step pays."""
     import dataclasses
     from paper_1904_11386_amd import workloads
     from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
-    wl = dataclasses.replace(workloads.make("c5"), rep_eps=0.5, rep_d0=1.25)
+    base = workloads.make("c5")
+    caps = [dataclasses.replace(c, kB=1e-2 * c.kS * c.radius ** 2) for c in base.capsules]
+    wl = dataclasses.replace(base, capsules=caps, rep_eps=0.5, rep_d0=1.25)
     N = wl.n_lattice
-    out = {"workload": "512^3 scale configuration with particle-particle repulsion (eps 0.5, d0 1.25)",
-           "warmup": warmup, "steps": steps}
+    out = {"workload": "512^3 scale configuration with bending (B = 1e-2) and particle-particle repulsion "
+                       "(eps 0.5, d0 1.25)", "warmup": warmup, "steps": steps}
     for name, prec in (("fp32", LBM_FP32), ("fp16", LBM_FP16)):
-        print("bench: repulsion leg, %s form" % name, file=sys.stderr, flush=True)
+        print("bench: membrane extras leg, %s form" % name, file=sys.stderr, flush=True)
         sim = sim_from_workload(wl, precision=prec)
         sim.step(warmup)
         sim.synchronize()
@@ -267,7 +270,7 @@ def repulsion_leg(torch, warmup=100, steps=200):
         wall = time.perf_counter() - t0
         k = sim.step_timed(20)
         out[name] = {"mlups": round(N * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4),
-                     "repulse_ms_per_step": round(k["repulse"] / 20, 5)}
+                     "repulse_ms_per_step": round(k["repulse"] / 20, 5), "bend_ms_per_step": round(k["bend"] / 20, 5)}
         sim.close()
         del sim
         torch.cuda.empty_cache()
@@ -343,8 +346,8 @@ def main():
     ap.add_argument("--no-scale-leg", action="store_true", help="skip the 512^3 FP32/FP16 leg")
     ap.add_argument("--scale-only", action="store_true",
                     help="run only the 512^3 FP32/FP16 leg and print it (for profiling that configuration)")
-    ap.add_argument("--repulsion-leg", action="store_true",
-                    help="also run the 512^3 configuration with particle-particle repulsion on")
+    ap.add_argument("--membrane-extras-leg", action="store_true",
+                    help="also run the 512^3 configuration with bending and particle-particle repulsion on")
     ap.add_argument("--adjoint-fd-sweep", action="store_true",
                     help="also check the full-size adjoint against FP32 central differences over a sweep of h")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
@@ -443,8 +446,8 @@ def main():
         out["adjoint"] = adjoint_leg(torch)
     if args.precision == "fp32" and not args.no_scale_leg:
         out["scale_512"] = scale_leg(torch)
-    if args.repulsion_leg:
-        out["repulsion"] = repulsion_leg(torch)
+    if args.membrane_extras_leg:
+        out["membrane_extras"] = membrane_extras_leg(torch)
     if args.adjoint_fd_sweep:
         out["adjoint_fd_sweep"] = adjoint_fd_sweep(torch)
     if args.precision_study > 0:
