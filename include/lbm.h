@@ -170,6 +170,22 @@ int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
  * differentiate it. */
 int lbm_capsules_bending(lbm_ctx* ctx, int32_t first_id, int32_t n_caps, const double* kB);
 
+/* The LBM-free reference model (Sec. III.B, eq. emulatetension): nsteps of
+ * membrane-only relaxation of every capsule, without the fluid.  Each node
+ * moves by mobility * F (the nodes are massless, so the relaxation is
+ * overdamped), with F its Skalak, volume and bending forces plus the
+ * emulated surface tension: every element gets gamma A / w, A the part of
+ * its area between the planes z_interface -+ w/2, directed horizontally and
+ * radially away from the vertical axis through its capsule's centre of mass
+ * at the start of the call, shared evenly by its three nodes.  The lattice
+ * state is not touched, nor are the wettability and repulsion terms used.
+ * Asynchronous on the stream.  LBM_EINVAL for nsteps < 0, gamma < 0, w <= 0,
+ * mobility <= 0 or non-finite values.  (Stability of the explicit update
+ * needs mobility below about 2 / the stiffest elastic mode; 0.05 is stable
+ * for kV = 20 at R = 5.) */
+int lbm_reference_relax(lbm_ctx* ctx, int32_t nsteps, double gamma, double w, double z_interface,
+                        double mobility);
+
 /* Advance nsteps >= 0 time steps, asynchronously on the stream.  With
  * use_graphs, pairs of steps are replayed from HIP graphs captured on the
  * first call (kernels only, no memory-set nodes).  With

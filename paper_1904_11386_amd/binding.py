@@ -44,7 +44,8 @@ class CapObs(C.Structure):
 
 _lib = None
 
-EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_bending", "lbm_step", "lbm_step_timed", "lbm_observables",
+EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_bending", "lbm_reference_relax",
+           "lbm_step", "lbm_step_timed", "lbm_observables",
            "lbm_get_fields", "lbm_get_nodes", "lbm_get_node_forces", "lbm_get_spread",
            "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_adjoint_forward", "lbm_adjoint_backward",
            "lbm_destroy", "lbm_last_error"]
@@ -69,6 +70,7 @@ def load(path: str = None):
         "lbm_init": ([P(Params), P(C.c_float), P(C.c_float), vp, i64, i64, i64, vp, P(vp)], C.c_int),
         "lbm_capsules_add": ([vp, i32, P(i32), P(i32), P(d), P(i32), P(d), P(d), P(d), P(d), P(i32)], C.c_int),
         "lbm_capsules_bending": ([vp, i32, i32, P(d)], C.c_int),
+        "lbm_reference_relax": ([vp, i32, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
         "lbm_step": ([vp, i32], C.c_int),
         "lbm_step_timed": ([vp, i32, P(d)], C.c_int),
         "lbm_observables": ([vp, P(Obs), P(CapObs)], C.c_int),
@@ -187,6 +189,11 @@ class Sim:
         self.n_nodes += int(npc.sum())
         self.n_caps += len(npc)
         return first.value
+
+    def reference_relax(self, nsteps, gamma, w, z_interface, mobility):
+        """Membrane-only relaxation under the emulated tension (no fluid)."""
+        self._check(self.lib.lbm_reference_relax(self.ctx, int(nsteps), float(gamma), float(w), float(z_interface),
+                                                 float(mobility)))
 
     def set_bending(self, first_id, kB):
         """Helfrich bending moduli of the capsules first_id .. first_id + len(kB) - 1."""

@@ -666,6 +666,91 @@ __global__ __launch_bounds__(256) void k_bend_force(Dev d, int n_nodes) {
     for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] += sF * g[3 + a];
 }
 
+// ---- LBM-free reference model (Sec. III.B, eq. emulatetension) ----------
+// Membrane-only relaxation: the elastic and bending forces plus the
+// emulated tension gamma A / w on the part A of each element's area inside
+// the slab |z - z_interface| <= w / 2, horizontal and radially away from the
+// vertical axis through the capsule's centre of mass at the start of the
+// relaxation (cap_mom[2..3] / node count, capsule-relative), shared evenly by
+// the element's three nodes; then X += mu F.  The slab area uses the closed
+// form of the area fraction below a plane (quadratic on each side of the
+// middle vertex height).
+
+__global__ void k_ref_zero_volume(Dev d, int n_caps) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < n_caps) d.capV[k] = 0.0;
+}
+
+__device__ __forceinline__ float frac_below(float z0, float z1, float z2, float h) {
+    // sort the three heights
+    float a = fminf(z0, fminf(z1, z2)), c = fmaxf(z0, fmaxf(z1, z2));
+    float b = z0 + z1 + z2 - a - c;
+    if (h <= a) return 0.0f;
+    if (h >= c) return 1.0f;
+    if (h <= b) return (h - a) * (h - a) / ((b - a) * (c - a));
+    return 1.0f - (c - h) * (c - h) / ((c - b) * (c - a));
+}
+
+__global__ __launch_bounds__(256) void k_ref_tension(Dev d, int n_faces, float gamma, float w, double z_interface) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_faces) return;
+    const int cap = d.face_cap[f];
+    const CapDev& C = d.caps[cap];
+    float x[3][3];
+    for (int k = 0; k < 3; ++k) {
+        const int b = d.tri[3 * f + k];
+        for (int a = 0; a < 3; ++a) x[k][a] = d.off_hi[3 * b + a] + d.off_lo[3 * b + a];
+    }
+    // the slab in capsule-relative heights
+    const float zi = (float)(z_interface - (double)C.anchor[2]);
+    const float lo = zi - 0.5f * w, hi = zi + 0.5f * w;
+    const float fb = frac_below(x[0][2], x[1][2], x[2][2], hi) - frac_below(x[0][2], x[1][2], x[2][2], lo);
+    if (fb == 0.0f) return;
+    float e1[3], e2[3];
+    for (int a = 0; a < 3; ++a) {
+        e1[a] = x[1][a] - x[0][a];
+        e2[a] = x[2][a] - x[0][a];
+    }
+    const float cx = e1[1] * e2[2] - e1[2] * e2[1], cy = e1[2] * e2[0] - e1[0] * e2[2], cz = e1[0] * e2[1] - e1[1] * e2[0];
+    const float area = 0.5f * sqrtf(cx * cx + cy * cy + cz * cz);
+    const double inv_n = 1.0 / (double)C.node_count;
+    const float ax = (float)(d.cap_mom[cap * MOM_STRIDE + 2] * inv_n), ay = (float)(d.cap_mom[cap * MOM_STRIDE + 3] * inv_n);
+    const float dx = (x[0][0] + x[1][0] + x[2][0]) * (1.0f / 3.0f) - ax;
+    const float dy = (x[0][1] + x[1][1] + x[2][1]) * (1.0f / 3.0f) - ay;
+    const float dn = sqrtf(dx * dx + dy * dy);
+    if (dn == 0.0f) return;
+    const float m = gamma * area * fb / w * (1.0f / 3.0f) / dn;
+    for (int k = 0; k < 3; ++k) {
+        const int sl = d.corner_slot[3 * f + k];
+        d.face_F[3 * (int64_t)sl + 0] += m * dx;
+        d.face_F[3 * (int64_t)sl + 1] += m * dy;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ref_gather(Dev d, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    float g[3] = {0.f, 0.f, 0.f};
+    for (int k = d.csr_ptr[b]; k < d.csr_ptr[b + 1]; ++k)
+        for (int a = 0; a < 3; ++a) g[a] += d.face_F[3 * (int64_t)k + a];
+    for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] = g[a];
+}
+
+__global__ __launch_bounds__(256) void k_ref_advance(Dev d, int n_nodes, float mu) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    for (int k = 0; k < 3; ++k) {
+        // compensated (hi, lo) += mu F, as in the coupled advection
+        const float a = d.off_hi[3 * b + k];
+        const float bb = d.off_lo[3 * b + k] + mu * d.node_F[3 * b + k];
+        const float s = a + bb;
+        const float bv = s - a;
+        const float err = (a - (s - bv)) + (bb - bv);
+        d.off_hi[3 * b + k] = s;
+        d.off_lo[3 * b + k] = err;
+    }
+}
+
 constexpr int SPREAD_GRID = 2048;
 
 __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
@@ -1135,6 +1220,17 @@ void launch_bending(const Dev& d, int n_nodes, hipStream_t s) {
     const dim3 g((n_nodes + 255) / 256);
     hipLaunchKernelGGL(k_bend_geo, g, dim3(256), 0, s, d, n_nodes);
     hipLaunchKernelGGL(k_bend_force, g, dim3(256), 0, s, d, n_nodes);
+}
+void launch_reference_step(const Dev& d, int n_nodes, int n_faces, int n_caps, bool bend, float gamma, float w,
+                           double z_interface, float mu, hipStream_t s) {
+    if (n_faces <= 0) return;
+    hipLaunchKernelGGL(k_ref_zero_volume, dim3((n_caps + 255) / 256), dim3(256), 0, s, d, n_caps);
+    launch_cap_volume(d, n_faces, s);
+    launch_faces(d, n_faces, s);
+    hipLaunchKernelGGL(k_ref_tension, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces, gamma, w, z_interface);
+    hipLaunchKernelGGL(k_ref_gather, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
+    if (bend) launch_bending(d, n_nodes, s);
+    hipLaunchKernelGGL(k_ref_advance, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes, mu);
 }
 void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
     hipLaunchKernelGGL(k_spread, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);

@@ -657,6 +657,24 @@ int lbm_capsules_bending(lbm_ctx* c, int32_t first_id, int32_t n_caps, const dou
     HIPCHK(c, hipMemcpyAsync(c->d.caps, c->caps.data(), c->caps.size() * sizeof(CapDev), hipMemcpyHostToDevice, c->stream));
     return LBM_OK;
 }
+
+int lbm_reference_relax(lbm_ctx* c, int32_t nsteps, double gamma, double w, double z_interface, double mobility) {
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");
+    if (!(gamma >= 0.0) || !isfinite(gamma)) return c->fail(LBM_EINVAL, "gamma must be finite and >= 0");
+    if (!(w > 0.0) || !isfinite(w)) return c->fail(LBM_EINVAL, "w must be finite and > 0");
+    if (!isfinite(z_interface)) return c->fail(LBM_EINVAL, "z_interface must be finite");
+    if (!(mobility > 0.0) || !isfinite(mobility)) return c->fail(LBM_EINVAL, "mobility must be finite and > 0");
+    if (c->caps.empty() || nsteps == 0) return LBM_OK;
+    Dev& d = c->d;
+    // the axes: each capsule's centre of mass now
+    launch_cap_moments(d, (int)c->caps.size(), c->stream);
+    for (int k = 0; k < nsteps; ++k)
+        launch_reference_step(d, c->n_nodes, c->n_faces, (int)c->caps.size(), c->bending, (float)gamma, (float)w,
+                              z_interface, (float)mobility, c->stream);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+}
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");

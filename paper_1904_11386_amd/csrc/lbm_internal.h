@@ -165,6 +165,8 @@ void launch_bin_scan(const Dev& d, int n_nodes, int parity, hipStream_t s);
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s);
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s);
 void launch_bending(const Dev& d, int n_nodes, hipStream_t s);
+void launch_reference_step(const Dev& d, int n_nodes, int n_faces, int n_caps, bool bend, float gamma, float w,
+                           double z_interface, float mu, hipStream_t s);
 void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s);

@@ -244,6 +244,35 @@ def test_bending_entry_point_validation():
         ga.set_bending(0, [0.1])
 
 
+@pytest.mark.parametrize("freq", [4, 8])
+def test_reference_model_relaxation(freq):
+    """The LBM-free reference model (Sec. III.B, eq. emulatetension): a
+    capsule centred on the interface plane relaxes under its Skalak, volume
+    and bending forces and the emulated tension gamma A / w (beta = 1000,
+    B = 1e-2, nu_s = 0.9, kV = 20, w = 1), 200 overdamped steps against the
+    oracle's FP64 relaxation."""
+    from oracle import reference as oref
+    R0, gamma, beta, B, mu, steps = 5.0, 0.0388, 1000.0, 1e-2, 0.05, 200
+    kB = R0 * R0 * gamma / beta
+    kS = kB / (B * R0 * R0)
+    ra, rb = W.layered(24, 24, 24, 12)
+    cap = W.Capsule(W._snap(np.array([12.3, 11.8, 12.0])), R0, freq, kS, 9.0, 20.0, 90.0, kB=kB)
+    wl = W.Workload("ref", 24, 24, 24, ra, rb, [cap], z_interface=11.5)
+    g = _sim(wl)
+    g.reference_relax(steps, gamma, 1.0, 12.0, mu)
+    X = g.nodes()
+    xyz, tri = cap.mesh()
+    Xo = oref.relax(xyz, tri, kS, 9.0, 20.0, kB, gamma, 1.0, 12.0, mu, steps).numpy()
+    dx = float(np.abs(X - Xo).max())
+    Xc = Xo - Xo.mean(0)
+    r_i, r_p = float(np.linalg.norm(Xc[:, :2], axis=1).max()), float(np.abs(Xc[:, 2]).max())
+    _say("reference model freq %d: node err %.3e lu, moved %.3e lu, r_i %.4f r_p %.4f"
+         % (freq, dx, float(np.abs(Xo - xyz).max()), r_i, r_p))
+    assert float(np.abs(Xo - xyz).max()) > 0.05
+    assert dx < 1e-4
+    assert r_i > R0 and r_p < R0
+
+
 def test_bins_and_stencil_base_bit_exact():
     wl = W.small(nx=40, ny=36, nz=44, ncap=3, radius=4.0)
     # put one capsule across the periodic corner so floor() and wrapping are exercised
