@@ -277,6 +277,40 @@ def membrane_extras_leg(torch, warmup=100, steps=200):
     return out
 
 
+def reference_model_leg(torch, steps=240000, chunk=20000):
+    """The LBM-free reference model of Sec. III.B at the paper's particle
+    size: R0 = 10 (2562-node mesh), beta = R0^2 gamma / kB = 1000,
+    B = kB / (kS R0^2) = 1e-2, nu_s = 0.9 (C = 9), kV = 20, gamma = 0.0388,
+    w = 1, overdamped with mobility 0.05.  Reports the ellipsoid half-axes
+    (from the volume second moments, the paper's 'tensor of inertia') along
+    the relaxation and the time per membrane step."""
+    import numpy as np
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import sim_from_workload
+    R0, gamma, beta, B, mu = 10.0, 0.0388, 1000.0, 1e-2, 0.05
+    kB = R0 * R0 * gamma / beta
+    kS = kB / (B * R0 * R0)
+    ra, rb = workloads.layered(32, 32, 32, 16)
+    cap = workloads.Capsule(workloads._snap(np.array([16.0, 16.0, 16.0])), R0, 16, kS, 9.0, 20.0, 90.0, kB=kB)
+    wl = workloads.Workload("reference", 32, 32, 32, ra, rb, [cap], z_interface=15.5)
+    sim = sim_from_workload(wl)
+    hist = []
+    t_run = 0.0
+    for k in range(steps // chunk):
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.reference_relax(chunk, gamma, 1.0, 16.0, mu)
+        sim.synchronize()
+        t_run += time.perf_counter() - t0
+        ax = sim.observables()["caps"][0]["axes"]
+        hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5), "r_i": round(float(ax[2]), 5)})
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"workload": "one R0=10 capsule (2562 nodes), beta 1000, B 1e-2, nu_s 0.9, kV 20, gamma 0.0388, w 1, "
+                        "mobility 0.05", "us_per_step": round(t_run / steps * 1e6, 2), "relaxation": hist}
+
+
 def precision_study(torch, steps):
     """The FP16 g-storage form beside the FP32 form on the 256^3 droplet
     workload (B droplet of radius 60 in A, 64 capsules of 642 nodes on a
@@ -346,6 +380,8 @@ def main():
     ap.add_argument("--no-scale-leg", action="store_true", help="skip the 512^3 FP32/FP16 leg")
     ap.add_argument("--scale-only", action="store_true",
                     help="run only the 512^3 FP32/FP16 leg and print it (for profiling that configuration)")
+    ap.add_argument("--reference-model-leg", action="store_true",
+                    help="also relax a capsule with the LBM-free reference model (no fluid)")
     ap.add_argument("--membrane-extras-leg", action="store_true",
                     help="also run the 512^3 configuration with bending and particle-particle repulsion on")
     ap.add_argument("--adjoint-fd-sweep", action="store_true",
@@ -446,6 +482,8 @@ def main():
         out["adjoint"] = adjoint_leg(torch)
     if args.precision == "fp32" and not args.no_scale_leg:
         out["scale_512"] = scale_leg(torch)
+    if args.reference_model_leg:
+        out["reference_model"] = reference_model_leg(torch)
     if args.membrane_extras_leg:
         out["membrane_extras"] = membrane_extras_leg(torch)
     if args.adjoint_fd_sweep:
