@@ -9,7 +9,7 @@
  *   - fluid: D3Q19 BGK (Sec. II.A, eqs. method:boltzmann, lbm:equilibrium,
  *     lbm:weights), force as an equilibrium-velocity shift (Sec. II.A), two
  *     components with the Shan-Chen interaction (Sec. II.D,
- *     eq. method:shanchen), pseudo-potential psi = rho;
+ *     eq. method:shanchen), pseudo-potential psi = rho or 1 - exp(-rho);
  *   - capsules: Skalak membrane energy (Sec. II.B, eq. method:strain) and
  *     volume penalty (Sec. II.B, eq. method:volume), node forces by virtual
  *     work, forward-Euler node motion (Sec. II.B);
@@ -98,7 +98,11 @@ typedef struct lbm_params {
     int32_t zchunk;         /* z planes marched per lattice block: 0 chosen by
                                storage form and grid size, else a multiple of 8
                                up to 64. Results do not depend on it.            */
-    int32_t reserved[1];    /* zero                                              */
+    int32_t psi_kind;       /* Shan-Chen pseudo-potential: 0 psi = rho; 1 psi =
+                               1 - exp(-rho) (Sec. II.D, rho0 = 1). The virtual
+                               density of the wettability term is added to psi
+                               either way. 1 is not available with the adjoint
+                               (ring_len > 0).                                   */
     double rep_eps;         /* particle-particle repulsion (Sec. III.E): node
                                pairs of different capsules at separation
                                d < rep_d0 repel along their separation with

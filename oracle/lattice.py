@@ -102,6 +102,15 @@ def wall_copy(a, walls):
     return a.index_select(-2, idx)
 
 
+def pseudo_potential(rho, kind=0):
+    """The Shan-Chen pseudo-potential: kind 0 psi = rho (the workloads'
+    reading), kind 1 psi = rho0 (1 - exp(-rho / rho0)) with rho0 = 1, the
+    form Sec. II.D names."""
+    if kind == 0:
+        return rho
+    return 1.0 - torch.exp(-rho)
+
+
 def sc_sum(psi):
     """S(x) = sum_{i=1..18} w_i psi(x + c_i) c_i, periodic.  This is the
     neighbour sum inside the Shan-Chen force of Sec. II.D (eq.

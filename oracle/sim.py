@@ -5,9 +5,9 @@ positions X^n.  The step, in this order:
 
  1. stream: f^n = pull(f*^{n-1}) with half-way bounce-back at walls
     (Sec. II.A; Sec. II.C eq. method:SBB);
- 2. densities rho^c = sum_i f_i^c, momenta j^c = sum_i f_i^c c_i, psi = rho
-    (Sec. II.A moments; pseudo-potential reading psi = rho for the
-    workloads, Sec. II.D names 1 - exp(-rho/rho0));
+ 2. densities rho^c = sum_i f_i^c, momenta j^c = sum_i f_i^c c_i, and the
+    pseudo-potential: psi = rho for the workloads (psi_kind 0), or the
+    1 - exp(-rho/rho0), rho0 = 1, that Sec. II.D names (psi_kind 1);
  3. node forces at X^n: Skalak plus volume (Sec. II.B) plus the wettability
     reaction.  The wettability term follows Sec. II.D: a virtual density
     offset rho_v added to the preferred component, with the particle colour
@@ -71,7 +71,7 @@ class OracleSim:
     def __init__(self, rhoA, rhoB, caps=(), tau=(1.0, 1.0), G=3.6, walls=0,
                  u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0), rho_maj=0.7,
                  rho_min=0.04, z_interface=0.0, wet_scale=1.0, differentiable=False,
-                 rep_eps=0.0, rep_d0=1.25):
+                 rep_eps=0.0, rep_d0=1.25, psi_kind=0):
         rhoA = torch.as_tensor(rhoA, dtype=DT)
         rhoB = torch.as_tensor(rhoB, dtype=DT)
         self.nz, self.ny, self.nx = rhoA.shape
@@ -84,6 +84,7 @@ class OracleSim:
         self.rho_maj = float(rho_maj)
         self.rho_min = float(rho_min)
         self.wet_scale = float(wet_scale)
+        self.psi_kind = int(psi_kind)
         self.rep_eps = float(rep_eps)
         self.rep_d0 = float(rep_d0)
         self.z_interface = float(z_interface)
@@ -140,7 +141,8 @@ class OracleSim:
             a = cap["mesh"].node_area * (rv.abs() if isinstance(rv, torch.Tensor) else abs(rv))
             if not is_zero:
                 if S_psi is None:
-                    S_psi = [lattice.sc_sum(lattice.wall_copy(rho[c], w)) for c in (0, 1)]
+                    S_psi = [lattice.sc_sum(lattice.wall_copy(lattice.pseudo_potential(rho[c], self.psi_kind), w))
+                             for c in (0, 1)]
                 npc = 1 - pref
                 interp = ibm.interpolate(S_psi[npc], X)          # [N, 3]
                 F = F - self.G * a.unsqueeze(1) * interp
@@ -170,12 +172,15 @@ class OracleSim:
             Fb = []
             Fib = torch.zeros(3, nz, ny, nx, dtype=DT)
             phi = torch.zeros(2, nz, ny, nx, dtype=DT)
-        psi_tot = [lattice.wall_copy(rho[c] + phi[c], w) for c in (0, 1)]
+        # the virtual density is a field added to the pseudo-potential (the
+        # reading under the immersed boundary; linear in phi for any psi)
+        psi = [lattice.pseudo_potential(rho[c], self.psi_kind) for c in (0, 1)]
+        psi_tot = [lattice.wall_copy(psi[c] + phi[c], w) for c in (0, 1)]
         S_tot = [lattice.sc_sum(psi_tot[c]) for c in (0, 1)]
         rsum = rho[0] + rho[1]
         F = []
         for c in (0, 1):
-            Fc = lattice.shan_chen_force(rho[c], S_tot[1 - c], self.G)
+            Fc = lattice.shan_chen_force(psi[c], S_tot[1 - c], self.G)
             Fc = Fc + (rho[c] / rsum).unsqueeze(0) * Fib
             F.append(Fc)
         F = torch.stack(F, 0)
@@ -224,7 +229,8 @@ def from_workload(wl, differentiable=False, **over):
     kw = dict(tau=wl.tau, G=wl.G, walls=wl.walls, u_lo=wl.wall_u_lo, u_hi=wl.wall_u_hi,
               rho_maj=wl.rho_maj, rho_min=wl.rho_min, z_interface=wl.z_interface,
               wet_scale=wl.wet_scale, differentiable=differentiable,
-              rep_eps=getattr(wl, "rep_eps", 0.0), rep_d0=getattr(wl, "rep_d0", 1.25))
+              rep_eps=getattr(wl, "rep_eps", 0.0), rep_d0=getattr(wl, "rep_d0", 1.25),
+              psi_kind=getattr(wl, "psi_kind", 0))
     kw.update(over)
     return OracleSim(wl.rhoA.astype("float64"), wl.rhoB.astype("float64"), caps, **kw)
 

@@ -30,7 +30,7 @@ class Params(C.Structure):
                 ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
                 ("z_interface", C.c_double), ("mass_tol", C.c_double), ("wet_scale", C.c_double),
                 ("ring_len", C.c_int32), ("stream_policy", C.c_int32), ("zchunk", C.c_int32),
-                ("reserved", C.c_int32 * 1), ("rep_eps", C.c_double), ("rep_d0", C.c_double)]
+                ("psi_kind", C.c_int32), ("rep_eps", C.c_double), ("rep_d0", C.c_double)]
 
 
 class Obs(C.Structure):
@@ -108,7 +108,7 @@ def _ptr(a, ctype):
 def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
                 check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0, stream_policy=0,
-                zchunk=0, rep_eps=0.0, rep_d0=1.25):
+                zchunk=0, rep_eps=0.0, rep_d0=1.25, psi_kind=0):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -130,6 +130,7 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.zchunk = zchunk
     p.rep_eps = rep_eps
     p.rep_d0 = rep_d0
+    p.psi_kind = psi_kind
     return p
 
 
@@ -300,7 +301,8 @@ def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="
                     wall_u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
                     check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len,
-                    stream_policy=stream_policy, zchunk=zchunk, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0)
+                    stream_policy=stream_policy, zchunk=zchunk, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0,
+                    psi_kind=wl.psi_kind)
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()

@@ -412,7 +412,10 @@ __device__ __forceinline__ StagePos stage_positions(int x0, int y0, int tid, con
     return P;
 }
 
-template <bool ADD_PHI, int NC>
+// PSI: the staged densities become the exponential Shan-Chen pseudo-potential
+// 1 - exp(-rho) before the virtual density field is added (a compile-time
+// choice: a runtime flag made the compiler specialise the whole z march).
+template <bool ADD_PHI, int NC, bool PSI = false>
 __device__ __forceinline__ void stage_load(StageRegs<NC>& S, const StagePos& P, int zz, int tid,
                                            const float* __restrict__ src, const float* scale,
                                            const float* __restrict__ fib, const int* __restrict__ tile_flag,
@@ -429,6 +432,7 @@ __device__ __forceinline__ void stage_load(StageRegs<NC>& S, const StagePos& P, 
             for (int c = 0; c < NC; ++c) {
                 float v = ldx(src + c * L.n + zoff, P.xy[it]);
                 if (scale) v *= scale[c];
+                if constexpr (PSI) v = psi_exp(v);
                 if (ADD_PHI) {
                     // the load goes out unconditionally so that no wait on
                     // the flag sits between the loads in flight
@@ -580,7 +584,7 @@ __global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ 
 // ---------------------------------------------------------------------------
 // Fused pull + force + collide.  MACRO: recompute the velocity of this
 // collision without storing populations (field read-back).
-template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED>
+template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI>
 __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
@@ -634,9 +638,9 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
     StageRegs<2> ne;
     auto load_plane = [&](int zz) {
         if (IBM && near_ibm)
-            stage_load<true, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
+            stage_load<true, 2, PSI>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
         else
-            stage_load<false, 2>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
+            stage_load<false, 2, PSI>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
         if constexpr (HALF) stage_load<false, 2>(ne, P, zz, tid, rho_p, cdec, nullptr, nullptr, L);
     };
     auto store_plane = [&](int zz) {
@@ -695,11 +699,13 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                 if (cz(k) != 0) { sa[2] += w * cz(k) * da; sb[2] += w * cz(k) * db; }
             }
             const float rsum = ra + rb;
+            // the node's own pseudo-potential
+            const float pa = PSI ? psi_exp(ra) : ra, pb = PSI ? psi_exp(rb) : rb;
             float Fa[3], Fb[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
-                Fa[d] = -L.G * ra * sb[d];
-                Fb[d] = -L.G * rb * sa[d];
+                Fa[d] = -L.G * pa * sb[d];
+                Fb[d] = -L.G * pb * sa[d];
             }
             bool flagged = false;
             if (IBM && near_ibm) {
@@ -1290,7 +1296,7 @@ void launch_compensate(const Lattice& L, const double* partial, double m0a, doub
     hipLaunchKernelGGL(k_compensate, dim3(1), dim3(1024), 0, s, partial, nb, m0a, m0b, cscale, par_cur, mass_out);
 }
 
-template <bool W, bool I, bool M, bool H>
+template <bool W, bool I, bool M, bool H, bool P>
 static void launch_collide_t(const Lattice& L, const void* fin, void* fout, const float* rho_n,
                              const float* rho_prev, const float* fib, const int* tile_flag, float* u,
                              const float* cscale, int par_prev, int par_cur, hipStream_t s) {
@@ -1299,12 +1305,12 @@ static void launch_collide_t(const Lattice& L, const void* fin, void* fout, cons
     // the velocity read-back (M) writes no populations; it runs in one policy
     if constexpr (!M) {
         if (L.cached) {
-            hipLaunchKernelGGL((k_collide<W, I, M, H, true>), grid, block, 0, s, (const PopT<H>*)fin,
+            hipLaunchKernelGGL((k_collide<W, I, M, H, true, P>), grid, block, 0, s, (const PopT<H>*)fin,
                                (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
             return;
         }
     }
-    hipLaunchKernelGGL((k_collide<W, I, M, H, false>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout,
+    hipLaunchKernelGGL((k_collide<W, I, M, H, false, P>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout,
                        rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
 }
 
@@ -1312,10 +1318,12 @@ void launch_collide(const Lattice& L, const void* fin, void* fout, const float* 
                     const float* fib, const int* tile_flag, float* u, bool has_ibm, bool macro, bool half,
                     const float* cscale, int par_prev, int par_cur, hipStream_t s) {
     const bool w = L.walls != 0;
-#define LC(W, I, M, H) \
-    launch_collide_t<W, I, M, H>(L, fin, fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, s)
+#define LC(W, I, M, H, P) \
+    launch_collide_t<W, I, M, H, P>(L, fin, fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, s)
+#define LC_P(W, I, M, H) \
+    do { if (L.psi_exp) LC(W, I, M, H, true); else LC(W, I, M, H, false); } while (0)
 #define LC_H(W, I, M) \
-    do { if (half) LC(W, I, M, true); else LC(W, I, M, false); } while (0)
+    do { if (half) LC_P(W, I, M, true); else LC_P(W, I, M, false); } while (0)
 #define LC_I(W, M) \
     do { if (has_ibm) LC_H(W, true, M); else LC_H(W, false, M); } while (0)
     if (macro) {
@@ -1325,6 +1333,7 @@ void launch_collide(const Lattice& L, const void* fin, void* fout, const float* 
     }
 #undef LC_I
 #undef LC_H
+#undef LC_P
 #undef LC
 }
 

@@ -316,7 +316,8 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
     const bool wetting = valid && wet != 0.0f;
     int np = 0;
     if (wetting) {
-        // reaction of the virtual density on the node:
+        // reaction of the virtual density on the node (it is linear in the
+        // virtual density for either pseudo-potential):
         // -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i;
         // the node's sixteen lanes stage psi^np on the 6^3 cube
         // floor(X)-2 .. floor(X)+3
@@ -331,7 +332,8 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
                 int gyy = wrap3(pw[1] - 2 + qy, L.ny);
                 if (L.walls) gyy = gyy == 0 ? 1 : (gyy == L.ny - 1 ? L.ny - 2 : gyy);
                 const int gzz = wrap3(pw[2] - 2 + qz, L.nz), gxx = wrap3(pw[0] - 2 + qx, L.nx);
-                cb[j] = sc * rc[(uint32_t)((gzz * L.ny + gyy) * L.nx + gxx)];
+                const float r = sc * rc[(uint32_t)((gzz * L.ny + gyy) * L.nx + gxx)];
+                cb[j] = L.psi_exp ? psi_exp(r) : r;     // the pseudo-potential
             }
         }
     }

@@ -164,7 +164,8 @@ std::string validate(const lbm_params* p) {
     if (p->ring_len > 0 && p->precision != LBM_FP32) return "the adjoint needs FP32 storage";
     if (p->stream_policy < 0 || p->stream_policy > 2) return "stream_policy must be 0, 1 or 2";
     if (p->zchunk != 0 && (p->zchunk % ZC != 0 || p->zchunk > 8 * ZC)) return "zchunk must be 0 or a multiple of 8 up to 64";
-    if (p->reserved[0]) return "reserved fields must be zero";
+    if (p->psi_kind != 0 && p->psi_kind != 1) return "psi_kind must be 0 or 1";
+    if (p->psi_kind == 1 && p->ring_len > 0) return "the adjoint assumes psi = rho: psi_kind must be 0 with ring_len > 0";
     if (!(p->rep_eps >= 0.0) || !isfinite(p->rep_eps)) return "rep_eps must be finite and >= 0";
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
     return "";
@@ -281,6 +282,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     L.ntx = (p->nx + TILE - 1) / TILE; L.nty = (p->ny + TILE - 1) / TILE; L.ntz = (p->nz + TILE - 1) / TILE;
     L.nbx = (p->nx + BIN - 1) / BIN; L.nby = (p->ny + BIN - 1) / BIN; L.nbz = (p->nz + BIN - 1) / BIN;
     L.n = N;
+    L.psi_exp = p->psi_kind;
     L.zc = p->zchunk ? p->zchunk : zc_for(p);
     // a population buffer of at most 512 MiB (128^3 in FP32) streams with
     // non-temporal loads and cached stores, a larger one the other way round

@@ -54,6 +54,7 @@ struct Lattice {
     int nbx, nby, nbz;     // bin counts (BIN)
     int zc;                // z planes marched per lattice block (a multiple of ZC)
     int cached;            // population streams: non-temporal loads, cached stores (1) or the reverse
+    int psi_exp;           // Shan-Chen pseudo-potential 1 - exp(-rho) (1) or rho (0)
     int64_t n;             // nx*ny*nz
     int walls;
     float G;
@@ -61,6 +62,16 @@ struct Lattice {
     float omega[2];        // 1/tau
     float uw_lo[3], uw_hi[3];
 };
+
+// The exponential Shan-Chen pseudo-potential 1 - exp(-v) (Sec. II.D, rho0 = 1),
+// branch-free: below 0.5 a degree-7 Taylor polynomial (truncation below 2e-7
+// relative), above it the direct form (the subtraction loses below 2e-7).
+__device__ __forceinline__ float psi_exp(float v) {
+    const float p = v * (1.0f + v * (-0.5f + v * (1.0f / 6.0f + v * (-1.0f / 24.0f + v * (1.0f / 120.0f +
+                    v * (-1.0f / 720.0f + v * (1.0f / 5040.0f)))))));
+    const float q = 1.0f - __expf(-v);
+    return v < 0.5f ? p : q;
+}
 
 struct CapDev {
     int anchor[3];

@@ -184,6 +184,7 @@ class Workload:
     wet_scale: float = WET_SCALE
     rep_eps: float = 0.0        # particle-particle repulsion strength (0 = off)
     rep_d0: float = 1.25        # and its cut-off
+    psi_kind: int = 0           # Shan-Chen pseudo-potential: 0 psi = rho, 1 psi = 1 - exp(-rho)
     note: str = ""
 
     @property

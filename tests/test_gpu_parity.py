@@ -273,6 +273,31 @@ def test_reference_model_relaxation(freq):
     assert r_i > R0 and r_p < R0
 
 
+@pytest.mark.parametrize("walls", [0, 1])
+def test_exponential_pseudo_potential_parity(walls):
+    """psi = 1 - exp(-rho) (Sec. II.D) with wetting capsules on a ragged box:
+    100 FP32 steps against the oracle, bounds as for psi = rho."""
+    import dataclasses
+    wl = dataclasses.replace(W.small(nx=40, ny=36, nz=44, ncap=2, theta=(60.0, 120.0), walls=walls), psi_kind=1)
+    _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
+
+
+def test_exponential_pseudo_potential_fp16():
+    """The FP16 storage form with psi = 1 - exp(-rho): density within 1e-3 of
+    the oracle and capsule heights within 0.05 lu after 200 steps."""
+    import dataclasses
+    from paper_1904_11386_amd.binding import LBM_FP16
+    wl = dataclasses.replace(W.small(nx=40, ny=36, nz=44, ncap=2, theta=(60.0, 120.0)), psi_kind=1)
+    g = _sim(wl, precision=LBM_FP16)
+    g.step(200)
+    o = from_workload(wl).run(200)
+    ra, rb, _ = g.fields()
+    ea, eb = _rel(ra, o.rho_last[0].numpy()), _rel(rb, o.rho_last[1].numpy())
+    dh = max(abs(c["height"] - float(o.capsule_obs(k)["height"])) for k, c in enumerate(g.observables()["caps"]))
+    _say("  psi exp fp16: rho rel err %.3e %.3e, max height err %.3e lu" % (ea, eb, dh))
+    assert ea <= 1e-3 and eb <= 1e-3 and dh <= 0.05
+
+
 def test_bins_and_stencil_base_bit_exact():
     wl = W.small(nx=40, ny=36, nz=44, ncap=3, radius=4.0)
     # put one capsule across the periodic corner so floor() and wrapping are exercised

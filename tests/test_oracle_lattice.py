@@ -177,3 +177,34 @@ def test_phase_separation_sign_and_static_interface_velocity():
     Fmax = float(s.F_last.abs().max())
     assert Fmax > 1e-3
     assert float(s.u_last.abs().max()) < 1e-4 * Fmax
+
+
+def test_exponential_pseudo_potential_closed_forms():
+    """psi = 1 - exp(-rho) (Sec. II.D): psi(0) = 0, slope 1 at 0, saturation at
+    1, and psi(-ln(1 - a)) = a."""
+    from oracle.lattice import pseudo_potential
+    r = torch.tensor([0.0, 1e-8, 0.7, 0.042, 50.0], dtype=torch.float64)
+    p = pseudo_potential(r, 1)
+    assert float(p[0]) == 0.0 and abs(float(p[1]) / 1e-8 - 1.0) < 1e-7
+    assert abs(float(p[4]) - 1.0) < 1e-15
+    a = torch.tensor([0.1, 0.5, 0.9], dtype=torch.float64)
+    assert torch.allclose(pseudo_potential(-torch.log1p(-a), 1), a, rtol=1e-14)
+    assert torch.equal(pseudo_potential(r, 0), r)
+
+
+def test_shan_chen_force_on_a_linear_pseudo_potential():
+    """With rho^B chosen so that psi^B = alpha + beta x exactly, the D3Q19
+    neighbour sum is beta sum_i w_i c_ix c_i = (beta / 3, 0, 0) at every node
+    away from the periodic seam, so F^A = -psi^A G beta / 3 along x."""
+    from oracle.lattice import pseudo_potential, sc_sum, shan_chen_force
+    nx, ny, nz, alpha, beta, G = 16, 4, 5, 0.05, 0.03, 3.6
+    x = torch.arange(nx, dtype=torch.float64).view(1, 1, nx).expand(nz, ny, nx)
+    rhoB = -torch.log1p(-(alpha + beta * x))
+    rhoA = 0.4 + 0.02 * torch.arange(nz, dtype=torch.float64).view(nz, 1, 1).expand(nz, ny, nx)
+    S = sc_sum(pseudo_potential(rhoB, 1))
+    inner = slice(1, nx - 1)
+    assert torch.allclose(S[0, :, :, inner], torch.full_like(S[0, :, :, inner], beta / 3.0), rtol=1e-13, atol=0)
+    assert float(S[1:, :, :, inner].abs().max()) < 1e-16
+    F = shan_chen_force(pseudo_potential(rhoA, 1), S, G)
+    ref = -G * (1.0 - torch.exp(-rhoA[:, :, inner])) * beta / 3.0
+    assert torch.allclose(F[0, :, :, inner], ref, rtol=1e-13, atol=0)
