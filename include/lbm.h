@@ -101,8 +101,7 @@ typedef struct lbm_params {
     int32_t psi_kind;       /* Shan-Chen pseudo-potential: 0 psi = rho; 1 psi =
                                1 - exp(-rho) (Sec. II.D, rho0 = 1). The virtual
                                density of the wettability term is added to psi
-                               either way. 1 is not available with the adjoint
-                               (ring_len > 0).                                   */
+                               either way.                                       */
     double rep_eps;         /* particle-particle repulsion (Sec. III.E): node
                                pairs of different capsules at separation
                                d < rep_d0 repel along their separation with

@@ -910,7 +910,7 @@ __device__ __forceinline__ double block_sum_d(double v, double* sh, int tid, int
     return r;
 }
 
-template <bool WALLS, bool IBM>
+template <bool WALLS, bool IBM, bool PSI>
 __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__ fin, const float* __restrict__ rho_n,
                                                      const float* __restrict__ rho_p, const float* __restrict__ fib,
                                                      const int* __restrict__ tile_flag, const pf2* __restrict__ lam_in,
@@ -943,9 +943,9 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
     StageRegs<2> np;
     auto stage = [&](int zz) {
         if (IBM && near_ibm)
-            stage_load<true, 2>(np, P, zz, tid, rho_n, nullptr, fib, tile_flag, L);
+            stage_load<true, 2, PSI>(np, P, zz, tid, rho_n, nullptr, fib, tile_flag, L);
         else
-            stage_load<false, 2>(np, P, zz, tid, rho_n, nullptr, nullptr, nullptr, L);
+            stage_load<false, 2, PSI>(np, P, zz, tid, rho_n, nullptr, nullptr, nullptr, L);
         stage_store2(sp, np, zz, z0, tid);
     };
     stage(z0 - 1);
@@ -992,10 +992,13 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
                     for (int d = 0; d < 3; ++d) Fib[d] = ldx(fib + d * N + row, xo);
             }
             const float ma = ra * ir, mb = rb * ir;
+            // pseudo-potentials and their slopes (exp form: d psi / d rho = 1 - psi)
+            const float pa = PSI ? psi_exp(ra) : ra, pb = PSI ? psi_exp(rb) : rb;
+            const float dpa = PSI ? 1.0f - pa : 1.0f, dpb = PSI ? 1.0f - pb : 1.0f;
             float Fa[3], Fb[3];
             for (int d = 0; d < 3; ++d) {
-                Fa[d] = -L.G * ra * sb[d] + ma * Fib[d];
-                Fb[d] = -L.G * rb * sa[d] + mb * Fib[d];
+                Fa[d] = -L.G * pa * sb[d] + ma * Fib[d];
+                Fb[d] = -L.G * pb * sa[d] + mb * Fib[d];
             }
             const float wa = L.omega[0], wb = L.omega[1];
             const float Dn = ra * wa + rb * wb, iD = 1.0f / Dn;
@@ -1065,13 +1068,13 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
             // adjoint of F^c = -G rho^c S^c' + m^c F_ib
             float lSa[3], lSb[3];
             for (int d = 0; d < 3; ++d) {
-                lSb[d] = -L.G * ra * lF[0][d];     // S of B enters the force on A
-                lSa[d] = -L.G * rb * lF[1][d];
+                lSb[d] = -L.G * pa * lF[0][d];     // S of B enters the force on A
+                lSa[d] = -L.G * pb * lF[1][d];
             }
-            lr[0] += -L.G * (lF[0][0] * sb[0] + lF[0][1] * sb[1] + lF[0][2] * sb[2]);
-            lr[1] += -L.G * (lF[1][0] * sa[0] + lF[1][1] * sa[1] + lF[1][2] * sa[2]);
-            gG += -(double)ra * (lF[0][0] * sb[0] + lF[0][1] * sb[1] + lF[0][2] * sb[2])
-                  - (double)rb * (lF[1][0] * sa[0] + lF[1][1] * sa[1] + lF[1][2] * sa[2]);
+            lr[0] += -L.G * dpa * (lF[0][0] * sb[0] + lF[0][1] * sb[1] + lF[0][2] * sb[2]);
+            lr[1] += -L.G * dpb * (lF[1][0] * sa[0] + lF[1][1] * sa[1] + lF[1][2] * sa[2]);
+            gG += -(double)pa * (lF[0][0] * sb[0] + lF[0][1] * sb[1] + lF[0][2] * sb[2])
+                  - (double)pb * (lF[1][0] * sa[0] + lF[1][1] * sa[1] + lF[1][2] * sa[2]);
             if (flagged) {
                 float lma = 0.f, lmb = 0.f;
                 for (int d = 0; d < 3; ++d) {
@@ -1101,9 +1104,9 @@ __global__ __launch_bounds__(BX * BY) void k_adj_collide(const pf2* __restrict__
 // lambda_rho^c(y) += sum_i w_i c_i . lambda_S^c(y - c_i); with walls, the
 // first and last fluid rows also collect what their solid-row copies
 // received.
-template <bool WALLS>
+template <bool WALLS, bool PSI>
 __global__ __launch_bounds__(BX * BY) void k_adj_gather(const float* __restrict__ lam_S, float* __restrict__ lam_rho,
-                                                    Lattice L) {
+                                                    const float* __restrict__ rho_n, Lattice L) {
     __shared__ Ring<6> sr;
     const int tx = threadIdx.x, ty = uniform_ty(), tid = ty * BX + tx;
     int bx, by, bz;
@@ -1160,6 +1163,12 @@ __global__ __launch_bounds__(BX * BY) void k_adj_gather(const float* __restrict_
                         acc[c] += wgt(i) * v;
                     }
                 }
+            }
+            if constexpr (PSI) {
+                // the gathered sum is the adjoint of the pseudo-potential; its
+                // density part carries d psi / d rho = exp(-rho) = 1 - psi
+                acc[0] *= 1.0f - psi_exp(ldx(rho_n + row, xo));
+                acc[1] *= 1.0f - psi_exp(ldx(rho_n + N + row, xo));
             }
             *ptrx(lam_rho + row, xo) += acc[0];
             *ptrx(lam_rho + N + row, xo) += acc[1];
@@ -1347,24 +1356,36 @@ void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const f
                            cscale, par, partial, L);
 }
 
+template <bool W, bool P>
+static void launch_adj_collide_t(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p,
+                                 const float* fib, const int* tile_flag, const void* lam_in, const float* lam_u,
+                                 float* lam_rho, float* lam_j, float* lam_S, float* lam_Fib, float* u_out,
+                                 double* grads, hipStream_t s) {
+    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc), block(BX, BY);
+    hipLaunchKernelGGL((k_adj_collide<W, true, P>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
+                       tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, u_out, grads, L);
+}
 void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
                         const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
                         float* lam_S, float* lam_Fib, float* u_out, double* grads, hipStream_t s) {
-    dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc), block(BX, BY);
-    if (L.walls)
-        hipLaunchKernelGGL((k_adj_collide<true, true>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
-                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, u_out, grads, L);
-    else
-        hipLaunchKernelGGL((k_adj_collide<false, true>), grid, block, 0, s, (const pf2*)fin, rho_n, rho_p, fib,
-                           tile_flag, (const pf2*)lam_in, lam_u, lam_rho, lam_j, lam_S, lam_Fib, u_out, grads, L);
+#define AC(W, P) launch_adj_collide_t<W, P>(L, fin, rho_n, rho_p, fib, tile_flag, lam_in, lam_u, lam_rho, lam_j, \
+                                            lam_S, lam_Fib, u_out, grads, s)
+    if (L.walls) {
+        if (L.psi_exp) AC(true, true); else AC(true, false);
+    } else {
+        if (L.psi_exp) AC(false, true); else AC(false, false);
+    }
+#undef AC
 }
-
-void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hipStream_t s) {
+void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, const float* rho_n, hipStream_t s) {
     dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc), block(BX, BY);
-    if (L.walls)
-        hipLaunchKernelGGL(k_adj_gather<true>, grid, block, 0, s, lam_S, lam_rho, L);
-    else
-        hipLaunchKernelGGL(k_adj_gather<false>, grid, block, 0, s, lam_S, lam_rho, L);
+#define AG(W, P) hipLaunchKernelGGL((k_adj_gather<W, P>), grid, block, 0, s, lam_S, lam_rho, rho_n, L)
+    if (L.walls) {
+        if (L.psi_exp) AG(true, true); else AG(true, false);
+    } else {
+        if (L.psi_exp) AG(false, true); else AG(false, false);
+    }
+#undef AG
 }
 
 void launch_adj_push(const Lattice& L, const void* lam_in, const float* lam_rho, const float* lam_j, void* lam_out,

@@ -994,8 +994,9 @@ __global__ __launch_bounds__(256) void k_adj_nodes(Lattice L, Dev d, const float
         const int64_t idx = ((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx + wrapi(p.fl[0] - 2 + qx, L.nx);
         for (int a = 0; a < 3; ++a) cube_s[wv][a][j] = d.lam_S[(3 * pref + a) * N + idx];
         if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
-        cube_r[wv][j] = rho_n[np * N + ((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx +
+        const float r = rho_n[np * N + ((int64_t)wrapi(p.fl[2] - 2 + qz, L.nz) * L.ny + gy) * L.nx +
                               wrapi(p.fl[0] - 2 + qx, L.nx)];
+        cube_r[wv][j] = L.psi_exp ? psi_exp(r) : r;     // the pseudo-potential, as in the forward
     }
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();

@@ -165,7 +165,6 @@ std::string validate(const lbm_params* p) {
     if (p->stream_policy < 0 || p->stream_policy > 2) return "stream_policy must be 0, 1 or 2";
     if (p->zchunk != 0 && (p->zchunk % ZC != 0 || p->zchunk > 8 * ZC)) return "zchunk must be 0 or a multiple of 8 up to 64";
     if (p->psi_kind != 0 && p->psi_kind != 1) return "psi_kind must be 0 or 1";
-    if (p->psi_kind == 1 && p->ring_len > 0) return "the adjoint assumes psi = rho: psi_kind must be 0 with ring_len > 0";
     if (!(p->rep_eps >= 0.0) || !isfinite(p->rep_eps)) return "rep_eps must be finite and >= 0";
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
     return "";
@@ -1160,7 +1159,7 @@ int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
                 launch_adj_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
             launch_adj_membrane(d, c->n_nodes, c->n_faces, s);
             launch_spread_vec(L, d, par, d.lam_q, d.lam_S, 1, s);
-            launch_adj_gather(L, d.lam_S, d.lam_rho, s);
+            launch_adj_gather(L, d.lam_S, d.lam_rho, rho_n, s);
             launch_adj_push(L, d.lam[p], d.lam_rho, d.lam_j, d.lam[p ^ 1], s);
             p ^= 1;
             HIPCHK(c, hipGetLastError());

@@ -192,7 +192,7 @@ void launch_adj_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, 
 void launch_adj_collide(const Lattice& L, const void* fin, const float* rho_n, const float* rho_p, const float* fib,
                         const int* tile_flag, const void* lam_in, const float* lam_u, float* lam_rho, float* lam_j,
                         float* lam_S, float* lam_Fib, float* u_out, double* grads, hipStream_t s);
-void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, hipStream_t s);
+void launch_adj_gather(const Lattice& L, const float* lam_S, float* lam_rho, const float* rho_n, hipStream_t s);
 void launch_adj_push(const Lattice& L, const void* lam_in, const float* lam_rho, const float* lam_j, void* lam_out,
                      hipStream_t s);
 

@@ -51,12 +51,12 @@ def test_workspace_bytes_and_validation():
         assert lib.lbm_last_error(None)
     pb = B.make_params(3, 16, 16)
     assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
-    for bad in (dict(psi_kind=2), dict(psi_kind=-1), dict(psi_kind=1, ring_len=4)):
+    for bad in (dict(psi_kind=2), dict(psi_kind=-1)):
         pb = B.make_params(16, 16, 16, **bad)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
     # the repulsion's cut-off only matters when it is on; the largest allowed is 2
     for good in (dict(rep_eps=0.0, rep_d0=5.0), dict(rep_eps=0.5, rep_d0=2.0), dict(rep_eps=0.5, ring_len=4),
-                 dict(psi_kind=1)):
+                 dict(psi_kind=1), dict(psi_kind=1, ring_len=4)):
         pb = B.make_params(16, 16, 16, **good)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_OK
     # more than 2^30 nodes cannot be addressed with 32-bit offsets

@@ -32,7 +32,7 @@ class OracleChannel:
         return S.OracleSim(wl.rhoA.astype(np.float64), wl.rhoB.astype(np.float64), caps, tau=wl.tau, G=G,
                            walls=wl.walls, u_lo=wl.wall_u_lo, u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj,
                            rho_min=wl.rho_min, z_interface=wl.z_interface, wet_scale=wl.wet_scale,
-                           differentiable=True, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0)
+                           differentiable=True, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0, psi_kind=wl.psi_kind)
 
 
 def _gpu_grad(wl, params, steps, every, kind):
@@ -165,3 +165,40 @@ def test_adjoint_with_repulsion_pressed_channel():
     _, g0 = _gpu_grad(dataclasses.replace(wl, rep_eps=0.0), params, steps, every, kind)
     _say("  grad without repulsion", g0.tolist())
     assert np.abs(g0 - g).max() > 1e-3 * np.abs(g).max()
+
+
+@pytest.mark.parametrize("kind", ["com_z", "taylor_D"])
+def test_adjoint_with_exponential_pseudo_potential(kind):
+    """The adjoint with psi = 1 - exp(-rho) on the 48 x 24 x 24 walled channel,
+    40 steps: against the oracle's reverse-mode gradient and FP64 central
+    differences of the oracle forward."""
+    import dataclasses
+    wl = dataclasses.replace(W.make("c4_mini"), psi_kind=1)
+    params = (75.0, 0.005, 3.6)
+    steps, every = 40, 10
+    _say("adjoint, psi = 1 - exp(-rho),", kind)
+    J, g = _gpu_grad(wl, params, steps, every, kind)
+    oc = OracleChannel(wl, params)
+    Jo, go = S.gradient(oc, steps, every, kind)
+    go = go.numpy()
+    rel = np.abs(g - go) / np.abs(go)
+    _say("  J gpu %.8e oracle %.8e" % (J, Jo))
+    _say("  grad gpu", g.tolist(), "oracle", go.tolist(), "rel", rel.tolist())
+    assert abs(J - Jo) < 1e-5 * max(1.0, abs(Jo))
+    assert np.all(rel < 1e-4), rel
+    if kind == "com_z":
+        def run(p):
+            s = oc(*p)
+            with torch.no_grad():
+                s.run(steps)
+                return float(S.objective(s, kind))
+
+        for i, h in enumerate((0.05, 1e-5, 1e-4)):
+            pp, pm = list(params), list(params)
+            pp[i] += h
+            pm[i] -= h
+            fd = (run(pp) - run(pm)) / (2 * h)
+            if i == 0:
+                fd *= 180.0 / math.pi
+            _say("  param %d gpu adjoint %.8e fp64 fd %.8e rel %.2e" % (i, g[i], fd, abs(g[i] - fd) / abs(fd)))
+            assert abs(g[i] - fd) <= 1e-4 * abs(fd)
