@@ -281,6 +281,7 @@ __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
 
 // Four nodes per wavefront, sixteen lanes per node (lane (kx, ky) takes the
 // stencil column kz = 0..3), sixteen nodes per block.
+template <bool PSI>     // the exponential pseudo-potential (a compile-time choice, as in the collide)
 __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __restrict__ rho_n,
                                                const float* __restrict__ cs, int n_nodes, int par) {
     constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
                 if (L.walls) gyy = gyy == 0 ? 1 : (gyy == L.ny - 1 ? L.ny - 2 : gyy);
                 const int gzz = wrap3(pw[2] - 2 + qz, L.nz), gxx = wrap3(pw[0] - 2 + qx, L.nx);
                 const float r = sc * rc[(uint32_t)((gzz * L.ny + gyy) * L.nx + gxx)];
-                cb[j] = L.psi_exp ? psi_exp(r) : r;     // the pseudo-potential
+                cb[j] = PSI ? psi_exp(r) : r;     // the pseudo-potential
             }
         }
     }
@@ -1200,8 +1201,12 @@ void launch_faces(const Dev& d, int n_faces, hipStream_t s) {
 }
 void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes, int par,
                   hipStream_t s) {
-    if (n_nodes > 0)
-        hipLaunchKernelGGL(k_nodes, dim3((n_nodes + 15) / 16), dim3(256), 0, s, L, d, rho_n, cs, n_nodes, par);
+    if (n_nodes <= 0) return;
+    const dim3 grid((n_nodes + 15) / 16), block(256);
+    if (L.psi_exp)
+        hipLaunchKernelGGL(k_nodes<true>, grid, block, 0, s, L, d, rho_n, cs, n_nodes, par);
+    else
+        hipLaunchKernelGGL(k_nodes<false>, grid, block, 0, s, L, d, rho_n, cs, n_nodes, par);
 }
 void launch_bin_scan(const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0) hipLaunchKernelGGL(k_bin_alloc, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, par);
