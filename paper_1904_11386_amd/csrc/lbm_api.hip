@@ -408,17 +408,43 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
         return c->fail(LBM_ENOMEM, "capsules exceed the workspace sizes given to lbm_init");
     const double rv_scale = 2.0 * (c->p.rho_maj - c->p.rho_min) * c->p.wet_scale;
     int64_t nofs = 0, fofs = 0;
-    // validate the whole batch before touching the context
+    // validate the whole batch before touching the context: indices,
+    // positions, every node on some triangle, no degenerate triangle, and a
+    // positive rest volume (outward triangles)
     for (int k = 0; k < n_caps; ++k) {
-        for (int f = 0; f < faces_per_cap[k]; ++f)
+        const int nn = nodes_per_cap[k], nf = faces_per_cap[k];
+        const double* X = xyz_rest + 3 * nofs;
+        const int32_t* T = tri + 3 * fofs;
+        std::vector<char> used(nn, 0);
+        for (int f = 0; f < nf; ++f)
             for (int j = 0; j < 3; ++j) {
-                const int v = tri[3 * (fofs + f) + j];
-                if (v < 0 || v >= nodes_per_cap[k]) return c->fail(LBM_EINVAL, "capsule %d: triangle index out of range", k);
+                const int v = T[3 * f + j];
+                if (v < 0 || v >= nn) return c->fail(LBM_EINVAL, "capsule %d: triangle index out of range", k);
+                used[v] = 1;
             }
-        for (int64_t b = 0; b < 3 * (int64_t)nodes_per_cap[k]; ++b)
-            if (!isfinite(xyz_rest[3 * nofs + b])) return c->fail(LBM_EINVAL, "capsule %d: non-finite position", k);
-        nofs += nodes_per_cap[k];
-        fofs += faces_per_cap[k];
+        for (int64_t b = 0; b < 3 * (int64_t)nn; ++b)
+            if (!isfinite(X[b])) return c->fail(LBM_EINVAL, "capsule %d: non-finite position", k);
+        for (int b = 0; b < nn; ++b)
+            if (!used[b]) return c->fail(LBM_EINVAL, "capsule %d: node %d is on no triangle", k, b);
+        double V = 0.0;
+        for (int f = 0; f < nf; ++f) {
+            const double* a = X + 3 * T[3 * f];
+            const double* bq = X + 3 * T[3 * f + 1];
+            const double* cc = X + 3 * T[3 * f + 2];
+            double e1[3], e2[3];
+            for (int j = 0; j < 3; ++j) { e1[j] = bq[j] - a[j]; e2[j] = cc[j] - a[j]; }
+            const double n0 = e1[1] * e2[2] - e1[2] * e2[1], n1 = e1[2] * e2[0] - e1[0] * e2[2],
+                         n2 = e1[0] * e2[1] - e1[1] * e2[0];
+            if (!(n0 * n0 + n1 * n1 + n2 * n2 > 0.0)) return c->fail(LBM_EINVAL, "capsule %d: degenerate triangle %d", k, f);
+            // (1/6) a . (b x c) summed: the enclosed volume, relative to the first node
+            double r1[3], r2[3], r0[3];
+            for (int j = 0; j < 3; ++j) { r0[j] = a[j] - X[j]; r1[j] = bq[j] - X[j]; r2[j] = cc[j] - X[j]; }
+            V += (r0[0] * (r1[1] * r2[2] - r1[2] * r2[1]) + r0[1] * (r1[2] * r2[0] - r1[0] * r2[2]) +
+                  r0[2] * (r1[0] * r2[1] - r1[1] * r2[0])) / 6.0;
+        }
+        if (!(V > 0.0)) return c->fail(LBM_EINVAL, "capsule %d: rest volume not positive (triangles must face outward)", k);
+        nofs += nn;
+        fofs += nf;
     }
     if (first_id) *first_id = (int32_t)c->caps.size();
     nofs = fofs = 0;

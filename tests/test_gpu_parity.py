@@ -229,6 +229,41 @@ def test_bending_capsules_100_steps(walls):
     _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
 
 
+def test_capsule_mesh_validation_leaves_context_clean():
+    """lbm_capsules_add rejects a degenerate triangle, a node on no triangle
+    and inward-facing triangles before touching the context: a valid add
+    afterwards behaves exactly like one on a fresh context."""
+    from paper_1904_11386_amd.binding import LbmError, Sim, make_params
+    wl = W.small(nx=24, ny=22, nz=26, ncap=1)
+    c = wl.capsules[0]
+    xyz, tri = c.mesh()
+    kS, Cs, kV, th = wl.cap_params()
+    n, f = xyz.shape[0], tri.shape[0]
+
+    def fresh():
+        p = make_params(wl.nx, wl.ny, wl.nz, z_interface=wl.z_interface, wet_scale=wl.wet_scale)
+        return Sim(p, wl.rhoA, wl.rhoB, max_nodes=4 * n, max_faces=4 * f)
+
+    g = fresh()
+    bad_deg = xyz.copy()
+    bad_deg[tri[0, 1]] = bad_deg[tri[0, 0]]                        # a zero-area triangle
+    extra = np.concatenate([xyz, xyz.mean(0, keepdims=True)], 0)     # a node on no triangle
+    for X, T, npc in ((bad_deg, tri, n), (extra, tri, n + 1), (xyz, tri[:, ::-1].copy(), n)):
+        with pytest.raises(LbmError):
+            g.add_capsules([npc], [f], X, T, kS, Cs, kV, th)
+    g.add_capsules([n], [f], xyz, tri, kS, Cs, kV, th)
+    ref = fresh()
+    ref.add_capsules([n], [f], xyz, tri, kS, Cs, kV, th)
+    # the first step's node forces are deterministic; later positions carry
+    # the rounding order of the spread's float atomics
+    g.step(1)
+    ref.step(1)
+    assert np.array_equal(g.node_forces(), ref.node_forces())
+    g.step(2)
+    ref.step(2)
+    assert np.abs(g.nodes() - ref.nodes()).max() < 1e-5
+
+
 def test_bending_entry_point_validation():
     from paper_1904_11386_amd.binding import LbmError, sim_from_workload
     wl = W.bent()
