@@ -119,6 +119,34 @@ def cpu_baseline(wl, budget_s=20.0):
                       % (n, wl.nx, wl.ny, wl.nz, len(wl.capsules), el, el1)}
 
 
+def oracle_timing_leg():
+    """The FP64 oracle's own rate on the small configurations, on this host:
+    the 32^3 one-capsule case in full (1000 steps) and the 64^3 crop of the
+    benchmark workload and 64^3 copy of the precision workload over 50 steps
+    each, at all cores and at one thread.  A reported baseline only."""
+    import torch
+    from oracle.sim import from_workload
+    from paper_1904_11386_amd import workloads
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(cores, 16))
+    out = {"cores": cores}
+    for name, steps in (("c1", 1000), ("c2_64", 50), ("c3_64", 50)):
+        wl = workloads.make(name)
+        row = {"steps": steps}
+        for label, threads in (("all_cores", cores), ("one_thread", 1)):
+            torch.set_num_threads(threads)
+            print("bench: oracle timing %s, %d thread(s)" % (name, threads), file=sys.stderr, flush=True)
+            o = from_workload(wl)
+            o.step()
+            t0 = time.perf_counter()
+            o.run(steps - 1)
+            el = time.perf_counter() - t0
+            row[label + "_mlups"] = round(wl.n_lattice * (steps - 1) / el / 1e6, 4)
+        out[name] = row
+    torch.set_num_threads(cores)
+    return out
+
+
 def adjoint_leg(torch, steps=2000, every=100):
     """Forward and backward wall time of the hand-written adjoint on the
     192x96x96 sheared channel (one 2562-node capsule, theta 75 deg,
@@ -380,6 +408,9 @@ def main():
     ap.add_argument("--no-scale-leg", action="store_true", help="skip the 512^3 FP32/FP16 leg")
     ap.add_argument("--scale-only", action="store_true",
                     help="run only the 512^3 FP32/FP16 leg and print it (for profiling that configuration)")
+    ap.add_argument("--oracle-timing-leg", action="store_true",
+                    help="also time the FP64 oracle on the 32^3 case (1000 steps) and the 64^3 cases (50 steps), "
+                         "all cores and one thread")
     ap.add_argument("--reference-model-leg", action="store_true",
                     help="also relax a capsule with the LBM-free reference model (no fluid)")
     ap.add_argument("--membrane-extras-leg", action="store_true",
@@ -490,6 +521,8 @@ def main():
         out["adjoint_fd_sweep"] = adjoint_fd_sweep(torch)
     if args.precision_study > 0:
         out["precision_study"] = precision_study(torch, args.precision_study)
+    if args.oracle_timing_leg:
+        out["oracle_timing"] = oracle_timing_leg()
     if not args.no_cpu_baseline:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
