@@ -11,10 +11,11 @@
 //                   method:volume), one thread per triangle
 //   k_faces         Skalak (Sec. II.B, eq. method:strain) and volume
 //                   forces per triangle and corner, F = -dE/dX
-//   k_nodes         sixteen lanes per node: gather its triangles' corner
-//                   forces, add the wettability reaction (lane (kx, ky)
-//                   takes a column of the 4x4x4 delta stencil, psi staged
-//                   on a 6^3 LDS cube), count the node into its home bin
+//   k_node_gather   sixteen lanes per node: gather its triangles' corner
+//                   forces, count the node into its home bin
+//   k_node_wet      sixteen lanes per wetting node: add the wettability
+//                   reaction (lane (kx, ky) takes a column of the 4x4x4
+//                   delta stencil, psi staged on a 6^3 LDS cube)
 //   k_bin_alloc     disjoint slot runs for the occupied bins (wavefront scan
 //                   plus one global atomic per wavefront)
 //   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
@@ -28,6 +29,8 @@
 //                   one lane per stencil point, no LDS atomics), then flush
 //                   the non-zero cells to HBM with global atomics
 //   k_interp_advect sixteen lanes per node: U_b = sum u delta, X += U_b
+// Only k_node_wet reads the densities of the step: the kernels before it
+// (after the previous step's advection) can overlap the density pass.
 #include "lbm_internal.h"
 
 namespace lbmx {
@@ -279,24 +282,16 @@ __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
     }
 }
 
-// Four nodes per wavefront, sixteen lanes per node (lane (kx, ky) takes the
-// stencil column kz = 0..3), sixteen nodes per block.
-template <bool PSI>     // the exponential pseudo-potential (a compile-time choice, as in the collide)
-__global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __restrict__ rho_n,
-                                               const float* __restrict__ cs, int n_nodes, int par) {
-    constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
-    constexpr int C3 = CB * CB * CB;
-    __shared__ float cube[16][C3];
+// Node forces in two kernels.  k_node_gather sums the corner forces of the
+// incident triangles and counts the node into its home bin (4^3); it reads
+// no density, so it can run beside the density pass.  k_node_wet adds the
+// wettability reaction, which needs this step's densities.  Four nodes per
+// wavefront, sixteen lanes per node, sixteen nodes per block.
+__global__ __launch_bounds__(256) void k_node_gather(Lattice L, Dev d, int n_nodes, int par) {
     const int lane = threadIdx.x & 63, l16 = lane & 15;
-    const int slot = wave_id() * 4 + (lane >> 4);
-    const int b = blockIdx.x * 16 + slot;
+    const int b = blockIdx.x * 16 + wave_id() * 4 + (lane >> 4);
     const bool valid = b < n_nodes;
-    float* cb = cube[slot];
-    // corner forces of the incident triangles
     float gx = 0.f, gy = 0.f, gz = 0.f;
-    NodePos p;
-    int pw[3] = {0, 0, 0};
-    float wet = 0.0f;
     int t = 0, rank = 0;
     if (valid) {
         const int beg = d.csr_ptr[b], end = d.csr_ptr[b + 1];
@@ -305,24 +300,54 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
             gy += d.face_F[3 * (int64_t)k + 1];
             gz += d.face_F[3 * (int64_t)k + 2];
         }
-        p = node_pos(d, b);
-        wrapped_floor(L, p, pw);
-        wet = d.node_wet[b];
         if (l16 == 1) {
-            // count the node into its home bin (4^3) early; the rank is used last
+            const NodePos p = node_pos(d, b);
+            int pw[3];
+            wrapped_floor(L, p, pw);
             t = bin_of(L, pw[0], pw[1], pw[2]);
             rank = atomicAdd(&d.tile_count[t], 1);
         }
     }
-    const bool wetting = valid && wet != 0.0f;
-    int np = 0;
+#pragma unroll
+    for (int o = 8; o > 0; o >>= 1) {
+        gx += __shfl_xor(gx, o, 16);
+        gy += __shfl_xor(gy, o, 16);
+        gz += __shfl_xor(gz, o, 16);
+    }
+    if (valid && l16 == 0) {
+        d.node_F[3 * b + 0] = gx;
+        d.node_F[3 * b + 1] = gy;
+        d.node_F[3 * b + 2] = gz;
+    } else if (valid && l16 == 1) {
+        d.node_tile[b] = t;
+        d.node_rank[b] = rank;
+        if (rank == 0) d.home[par][atomicAdd(&d.counters[CNT_HOME + par], 1)] = t;
+    }
+}
+
+// The reaction of the virtual density on a wetting node (linear in the
+// virtual density for either pseudo-potential):
+// -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i.
+// The node's sixteen lanes stage psi^np on the 6^3 cube floor(X)-2 ..
+// floor(X)+3; lane (kx, ky) takes the stencil column kz = 0..3.
+template <bool PSI>     // the exponential pseudo-potential (a compile-time choice, as in the collide)
+__global__ __launch_bounds__(256) void k_node_wet(Lattice L, Dev d, const float* __restrict__ rho_n,
+                                                  const float* __restrict__ cs, int n_nodes) {
+    constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
+    constexpr int C3 = CB * CB * CB;
+    __shared__ float cube[16][C3];
+    const int lane = threadIdx.x & 63, l16 = lane & 15;
+    const int slot = wave_id() * 4 + (lane >> 4);
+    const int b = blockIdx.x * 16 + slot;
+    float* cb = cube[slot];
+    const float wet = b < n_nodes ? d.node_wet[b] : 0.0f;
+    const bool wetting = wet != 0.0f;
+    NodePos p;
+    int pw[3] = {0, 0, 0};
     if (wetting) {
-        // reaction of the virtual density on the node (it is linear in the
-        // virtual density for either pseudo-potential):
-        // -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i;
-        // the node's sixteen lanes stage psi^np on the 6^3 cube
-        // floor(X)-2 .. floor(X)+3
-        np = 1 - d.node_anc[b].w;
+        p = node_pos(d, b);
+        wrapped_floor(L, p, pw);
+        const int np = 1 - d.node_anc[b].w;
         const float* rc = rho_n + (int64_t)np * L.n;
         const float sc = cs ? cs[np] : 1.0f;      // FP16 form: mass compensation of this step
 #pragma unroll
@@ -341,6 +366,7 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    float gx = 0.f, gy = 0.f, gz = 0.f;
     if (wetting) {
         const int kx = l16 & 3, ky = l16 >> 2;
         const float wxy = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky);
@@ -370,14 +396,10 @@ __global__ __launch_bounds__(256) void k_nodes(Lattice L, Dev d, const float* __
         gy += __shfl_xor(gy, o, 16);
         gz += __shfl_xor(gz, o, 16);
     }
-    if (valid && l16 == 0) {
-        d.node_F[3 * b + 0] = gx;
-        d.node_F[3 * b + 1] = gy;
-        d.node_F[3 * b + 2] = gz;
-    } else if (valid && l16 == 1) {
-        d.node_tile[b] = t;
-        d.node_rank[b] = rank;
-        if (rank == 0) d.home[par][atomicAdd(&d.counters[CNT_HOME + par], 1)] = t;
+    if (wetting && l16 == 0) {
+        d.node_F[3 * b + 0] += gx;
+        d.node_F[3 * b + 1] += gy;
+        d.node_F[3 * b + 2] += gz;
     }
 }
 
@@ -1199,14 +1221,17 @@ void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s) {
 void launch_faces(const Dev& d, int n_faces, hipStream_t s) {
     if (n_faces > 0) hipLaunchKernelGGL(k_faces, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
 }
-void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes, int par,
-                  hipStream_t s) {
+void launch_node_gather(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s) {
+    if (n_nodes > 0) hipLaunchKernelGGL(k_node_gather, dim3((n_nodes + 15) / 16), dim3(256), 0, s, L, d, n_nodes, par);
+}
+void launch_node_wet(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
+                     hipStream_t s) {
     if (n_nodes <= 0) return;
     const dim3 grid((n_nodes + 15) / 16), block(256);
     if (L.psi_exp)
-        hipLaunchKernelGGL(k_nodes<true>, grid, block, 0, s, L, d, rho_n, cs, n_nodes, par);
+        hipLaunchKernelGGL(k_node_wet<true>, grid, block, 0, s, L, d, rho_n, cs, n_nodes);
     else
-        hipLaunchKernelGGL(k_nodes<false>, grid, block, 0, s, L, d, rho_n, cs, n_nodes, par);
+        hipLaunchKernelGGL(k_node_wet<false>, grid, block, 0, s, L, d, rho_n, cs, n_nodes);
 }
 void launch_bin_scan(const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0) hipLaunchKernelGGL(k_bin_alloc, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, par);

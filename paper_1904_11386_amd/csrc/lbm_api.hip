@@ -181,6 +181,11 @@ struct lbm_ctx {
     Layout lay;
     char* ws = nullptr;
     hipStream_t stream = nullptr;
+    // the membrane kernels that read no density of the step run on a second
+    // stream beside the density pass, forked from and joined to `stream`
+    hipStream_t side = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+    bool interp_pending = false;   // the last step's advection is still to launch
     int64_t max_nodes = 0, max_faces = 0;
     int64_t step = 0;
     int flip = 0;                  // parity of the immersed-boundary tile lists
@@ -210,6 +215,9 @@ struct lbm_ctx {
         for (auto& row : graph)
             for (auto& g : row)
                 if (g) (void)hipGraphExecDestroy(g);
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
+        if (side) (void)hipStreamDestroy(side);
     }
 
     int fail(int code, const char* fmt, ...) {
@@ -374,6 +382,12 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     if ((er = hipMemsetAsync(d.tile_flag, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_count, 0, lay.bins * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.counters, 0, 8 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess)
+        return bad(er, "hipStreamCreateWithFlags");
+    if ((er = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess)
+        return bad(er, "hipEventCreateWithFlags");
+    if ((er = hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming)) != hipSuccess)
+        return bad(er, "hipEventCreateWithFlags");
     if (lay.adjoint) {
         if ((er = hipMemsetAsync(d.lam_u, 0, 3 * N * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
         if ((er = hipMemsetAsync(d.capdV, 0, lay.max_caps * 8, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
@@ -577,8 +591,16 @@ static int check_mass(lbm_ctx* c) {
 // NULL) receives LBM_NK + 1 events: ev[k] is recorded before kernel group k
 // and ev[LBM_NK] after the last.  advect = false leaves the nodes in place
 // (the adjoint's recompute of a step's intermediates).
+// One step.  With `ev` the kernels run in order on one stream with an event
+// before each group (the per-kernel timing).  Otherwise the membrane kernels
+// that read no density of this step (the previous step's advection when it
+// was deferred, tile clearing, volumes, triangle forces, the node gather and
+// the bin sort) run on the side stream beside the density pass and join
+// before the wettability reaction.  With `defer_interp` this step's
+// advection is left to the next step's side branch; the caller's last step
+// leaves it off, so that no call returns with an advection pending.
 static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, const float* rho_p, bool advect,
-                         hipEvent_t* ev) {
+                         hipEvent_t* ev, bool defer_interp = false) {
     const Lattice& L = c->L;
     Dev& d = c->d;
     hipStream_t s = c->stream;
@@ -587,22 +609,47 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     const int cur = (int)(c->step & 1), nxt = cur ^ 1;
     const int par = c->flip;
     const bool half = c->half();
+    const float* cs = half ? d.cscale + 2 * cur : nullptr;
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
+    const bool fork = !ev && fout && ibm;
+    hipStream_t m = fork ? c->side : s;       // the membrane kernels' stream up to the join
+    if (fork) {
+        (void)hipEventRecord(c->ev_fork, s);
+        (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
+    }
+    if (c->interp_pending) {
+        launch_interp_advect(L, d, c->n_nodes, m);
+        c->interp_pending = false;
+    }
     mark(LBM_K_CLEAR);
-    if (ibm) launch_clear_tiles(L, d, par ^ 1, par, ncap, s);
+    if (ibm) launch_clear_tiles(L, d, par ^ 1, par, ncap, m);
+    if (fork) {
+        launch_cap_volume(d, c->n_faces, m);
+        launch_faces(d, c->n_faces, m);
+        launch_node_gather(L, d, c->n_nodes, par, m);
+        launch_bin_scan(d, c->n_nodes, par, m);
+        launch_bin_scatter(L, d, c->n_nodes, par, m);
+        (void)hipEventRecord(c->ev_join, m);
+    }
     mark(LBM_K_DENSITY);
     if (fout) launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
     if (half && fout) launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
-    mark(LBM_K_VOLUME);
-    if (ibm) launch_cap_volume(d, c->n_faces, s);
-    mark(LBM_K_FACES);
-    if (ibm) launch_faces(d, c->n_faces, s);
-    mark(LBM_K_NODES);
-    if (ibm) launch_nodes(L, d, rho_n, half ? d.cscale + 2 * cur : nullptr, c->n_nodes, par, s);
-    mark(LBM_K_SCAN);
-    if (ibm) launch_bin_scan(d, c->n_nodes, par, s);
-    mark(LBM_K_SCATTER);
-    if (ibm) launch_bin_scatter(L, d, c->n_nodes, par, s);
+    if (fork) {
+        (void)hipStreamWaitEvent(s, c->ev_join, 0);
+        launch_node_wet(L, d, rho_n, cs, c->n_nodes, s);
+    } else {
+        mark(LBM_K_VOLUME);
+        if (ibm) launch_cap_volume(d, c->n_faces, s);
+        mark(LBM_K_FACES);
+        if (ibm) launch_faces(d, c->n_faces, s);
+        mark(LBM_K_NODES);
+        if (ibm) launch_node_gather(L, d, c->n_nodes, par, s);
+        if (ibm) launch_node_wet(L, d, rho_n, cs, c->n_nodes, s);
+        mark(LBM_K_SCAN);
+        if (ibm) launch_bin_scan(d, c->n_nodes, par, s);
+        mark(LBM_K_SCATTER);
+        if (ibm) launch_bin_scatter(L, d, c->n_nodes, par, s);
+    }
     mark(LBM_K_REPULSE);
     if (ibm && c->p.rep_eps > 0.0 && ncap > 1)
         launch_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
@@ -618,15 +665,20 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     }
     launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ibm, false, half, d.cscale, nxt, cur, s);
     mark(LBM_K_INTERP);
-    if (ibm && advect) launch_interp_advect(L, d, c->n_nodes, s);
+    if (ibm && advect) {
+        if (defer_interp && fork)
+            c->interp_pending = true;
+        else
+            launch_interp_advect(L, d, c->n_nodes, s);
+    }
     mark(LBM_NK);
     c->step++;
     c->flip ^= 1;
 }
 
-static void enqueue_step(lbm_ctx* c, hipEvent_t* ev) {
+static void enqueue_step(lbm_ctx* c, hipEvent_t* ev, bool defer_interp = false) {
     const int cur = (int)(c->step & 1), nxt = cur ^ 1;
-    enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev);
+    enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev, defer_interp);
 }
 
 // Two steps captured as one graph.  The launch arguments depend only on the
@@ -643,7 +695,7 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
         (void)hipGetLastError();
         return nullptr;
     }
-    enqueue_step(c, nullptr);
+    enqueue_step(c, nullptr, true);
     enqueue_step(c, nullptr);
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     c->step = step0;
@@ -717,7 +769,7 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
             c->step += 2;
             chunk -= 2;
         }
-        for (; chunk > 0; --chunk) enqueue_step(c, nullptr);
+        for (; chunk > 0; --chunk) enqueue_step(c, nullptr, chunk > 1);
         HIPCHK(c, hipGetLastError());
         if (c->p.check_every > 0 && c->step % c->p.check_every == 0) {
             const int r = check_mass(c);

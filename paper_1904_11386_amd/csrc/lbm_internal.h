@@ -170,8 +170,9 @@ void launch_clear_tiles(const Lattice& L, Dev& d, int parity_prev, int parity_cu
                         hipStream_t s);
 void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s);
 void launch_faces(const Dev& d, int n_faces, hipStream_t s);
-void launch_nodes(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
-                  int parity, hipStream_t s);
+void launch_node_gather(const Lattice& L, const Dev& d, int n_nodes, int parity, hipStream_t s);
+void launch_node_wet(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
+                     hipStream_t s);
 void launch_bin_scan(const Dev& d, int n_nodes, int parity, hipStream_t s);
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s);
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s);
