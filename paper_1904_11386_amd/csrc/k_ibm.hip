@@ -40,6 +40,10 @@ namespace {
 constexpr int CNT_TOUCHED = 0;   // counters[0..1]
 constexpr int CNT_HOME = 2;      // counters[2..3]
 constexpr int CNT_ALLOC = 4;     // counters[4..5]
+#ifndef LBM_CLEAR_GRID
+#define LBM_CLEAR_GRID 2048
+#endif
+constexpr int CLEAR_GRID = LBM_CLEAR_GRID;   // blocks of the tile clearing (a grid-stride loop over the tiles)
 
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
@@ -119,11 +123,13 @@ __device__ __forceinline__ int bin_of(const Lattice& L, int x, int y, int z) {
 // One workgroup per touched tile of the previous step (tile coordinates are
 // wave-uniform): zero its immersed-boundary fields and flag; then the
 // previous step's bin counts, this step's counters and capsule volumes.
-__global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, int pc, int n_caps) {
+// (blk of nblk blocks: the kernel also runs as a part of k_advect_clear)
+__device__ __forceinline__ void clear_tiles(const Lattice& L, const Dev& d, int pp, int pc, int n_caps, int blk,
+                                            int nblk) {
     const int nt = d.counters[CNT_TOUCHED + pp];
     const int nh = d.counters[CNT_HOME + pp];
     const int64_t N = L.n;
-    for (int e = blockIdx.x; e < nt; e += gridDim.x) {
+    for (int e = blk; e < nt; e += nblk) {
         const int t = d.touched[pp][e];
         const int tx = t % L.ntx, ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
         for (int c = threadIdx.x; c < TILE * TILE * TILE; c += blockDim.x) {
@@ -138,10 +144,9 @@ __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, i
         }
         if (threadIdx.x == 0) d.tile_flag[t] = 0;
     }
-    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < nh;
-         k += (int64_t)gridDim.x * blockDim.x)
+    for (int64_t k = blk * (int64_t)blockDim.x + threadIdx.x; k < nh; k += (int64_t)nblk * blockDim.x)
         d.tile_count[d.home[pp][k]] = 0;
-    if (blockIdx.x == 0) {
+    if (blk == 0) {
         if (threadIdx.x == 0) {
             d.counters[CNT_TOUCHED + pc] = 0;
             d.counters[CNT_HOME + pc] = 0;
@@ -152,6 +157,10 @@ __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, i
             if (d.capdV) d.capdV[k] = 0.0;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, int pc, int n_caps) {
+    clear_tiles(L, d, pp, pc, n_caps, blockIdx.x, gridDim.x);
 }
 
 // FP64 enclosed volume per capsule, V = (1/6) sum_T X1 . (X2 x X3) over
@@ -851,10 +860,10 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
 
 // Four nodes per wavefront, sixteen lanes per node: lane (kx, ky) of a
 // node sums its stencil column kz = 0..3, then the sixteen lanes reduce.
-__global__ __launch_bounds__(256) void k_interp_advect(Lattice L, Dev d, int n_nodes) {
+__device__ __forceinline__ void interp_advect(const Lattice& L, const Dev& d, int n_nodes, int blk) {
     const int lane = threadIdx.x & 63;
     const int q = lane >> 4, kx = lane & 3, ky = (lane >> 2) & 3;
-    const int b = (blockIdx.x * 4 + wave_id()) * 4 + q;
+    const int b = (blk * 4 + wave_id()) * 4 + q;
     float ux = 0.f, uy = 0.f, uz = 0.f;
     NodePos p;
     if (b < n_nodes) {
@@ -892,6 +901,20 @@ __global__ __launch_bounds__(256) void k_interp_advect(Lattice L, Dev d, int n_n
             d.off_lo[3 * b + k] = err;
         }
     }
+}
+
+__global__ __launch_bounds__(256) void k_interp_advect(Lattice L, Dev d, int n_nodes) {
+    interp_advect(L, d, n_nodes, blockIdx.x);
+}
+
+// The previous step's advection and this step's tile clearing in one launch
+// (they touch disjoint data): the first n_ib blocks advect, the rest clear.
+__global__ __launch_bounds__(256) void k_advect_clear(Lattice L, Dev d, int n_nodes, int n_ib, int pp, int pc,
+                                                      int n_caps) {
+    if ((int)blockIdx.x < n_ib)
+        interp_advect(L, d, n_nodes, blockIdx.x);
+    else
+        clear_tiles(L, d, pp, pc, n_caps, blockIdx.x - n_ib, gridDim.x - n_ib);
 }
 
 // FP64 shape moments per capsule, origin at the anchor:
@@ -1213,7 +1236,11 @@ __global__ __launch_bounds__(256) void k_debug_bins(Lattice L, Dev d, int n_node
 }  // namespace
 
 void launch_clear_tiles(const Lattice& L, Dev& d, int pp, int pc, int n_caps, hipStream_t s) {
-    hipLaunchKernelGGL(k_clear_tiles, dim3(2048), dim3(256), 0, s, L, d, pp, pc, n_caps);
+    hipLaunchKernelGGL(k_clear_tiles, dim3(CLEAR_GRID), dim3(256), 0, s, L, d, pp, pc, n_caps);
+}
+void launch_advect_clear(const Lattice& L, Dev& d, int n_nodes, int pp, int pc, int n_caps, hipStream_t s) {
+    const int n_ib = (n_nodes + 15) / 16;
+    hipLaunchKernelGGL(k_advect_clear, dim3(n_ib + CLEAR_GRID), dim3(256), 0, s, L, d, n_nodes, n_ib, pp, pc, n_caps);
 }
 void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s) {
     if (n_faces > 0) hipLaunchKernelGGL(k_cap_volume, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);

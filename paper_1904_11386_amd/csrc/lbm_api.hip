@@ -592,7 +592,8 @@ static int check_mass(lbm_ctx* c) {
 // and ev[LBM_NK] after the last.  advect = false leaves the nodes in place
 // (the adjoint's recompute of a step's intermediates).
 // One step.  With `ev` the kernels run in order on one stream with an event
-// before each group (the per-kernel timing).  Otherwise the membrane kernels
+// before each group (the per-kernel timing), and so they do without
+// `overlap` (the adjoint's recompute).  Otherwise the membrane kernels
 // that read no density of this step (the previous step's advection when it
 // was deferred, tile clearing, volumes, triangle forces, the node gather and
 // the bin sort) run on the side stream beside the density pass and join
@@ -600,7 +601,7 @@ static int check_mass(lbm_ctx* c) {
 // advection is left to the next step's side branch; the caller's last step
 // leaves it off, so that no call returns with an advection pending.
 static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, const float* rho_p, bool advect,
-                         hipEvent_t* ev, bool defer_interp = false) {
+                         hipEvent_t* ev, bool overlap = false, bool defer_interp = false) {
     const Lattice& L = c->L;
     Dev& d = c->d;
     hipStream_t s = c->stream;
@@ -611,18 +612,20 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     const bool half = c->half();
     const float* cs = half ? d.cscale + 2 * cur : nullptr;
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
-    const bool fork = !ev && fout && ibm;
+    const bool fork = overlap && !ev && fout && ibm;
     hipStream_t m = fork ? c->side : s;       // the membrane kernels' stream up to the join
     if (fork) {
         (void)hipEventRecord(c->ev_fork, s);
         (void)hipStreamWaitEvent(c->side, c->ev_fork, 0);
     }
-    if (c->interp_pending) {
-        launch_interp_advect(L, d, c->n_nodes, m);
-        c->interp_pending = false;
-    }
     mark(LBM_K_CLEAR);
-    if (ibm) launch_clear_tiles(L, d, par ^ 1, par, ncap, m);
+    if (c->interp_pending) {
+        // the previous step's advection and this step's clearing, one launch
+        launch_advect_clear(L, d, c->n_nodes, par ^ 1, par, ncap, m);
+        c->interp_pending = false;
+    } else if (ibm) {
+        launch_clear_tiles(L, d, par ^ 1, par, ncap, m);
+    }
     if (fork) {
         launch_cap_volume(d, c->n_faces, m);
         launch_faces(d, c->n_faces, m);
@@ -678,7 +681,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
 
 static void enqueue_step(lbm_ctx* c, hipEvent_t* ev, bool defer_interp = false) {
     const int cur = (int)(c->step & 1), nxt = cur ^ 1;
-    enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev, defer_interp);
+    enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev, true, defer_interp);
 }
 
 // Two steps captured as one graph.  The launch arguments depend only on the

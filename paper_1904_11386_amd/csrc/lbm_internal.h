@@ -168,6 +168,8 @@ void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const f
 // ---- launchers (k_ibm.hip) ---------------------------------------------
 void launch_clear_tiles(const Lattice& L, Dev& d, int parity_prev, int parity_cur, int n_caps,
                         hipStream_t s);
+void launch_advect_clear(const Lattice& L, Dev& d, int n_nodes, int parity_prev, int parity_cur, int n_caps,
+                         hipStream_t s);
 void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s);
 void launch_faces(const Dev& d, int n_faces, hipStream_t s);
 void launch_node_gather(const Lattice& L, const Dev& d, int n_nodes, int parity, hipStream_t s);
