@@ -204,7 +204,7 @@ struct lbm_ctx {
     std::vector<FaceRef> fref;
     std::vector<int> face_cap;
     int n_nodes = 0, n_faces = 0;
-    hipGraphExec_t graph[2][2] = {{nullptr, nullptr}, {nullptr, nullptr}};  // [step parity][flip]
+    hipGraphExec_t graph[2][2][2] = {};  // [step parity][flip][advection pending at the start]
     bool graphs_failed = false;
     bool bending = false;          // some capsule has a bending modulus
     std::string err;
@@ -212,9 +212,10 @@ struct lbm_ctx {
     bool half() const { return p.precision == LBM_FP16; }
 
     ~lbm_ctx() {
-        for (auto& row : graph)
-            for (auto& g : row)
-                if (g) (void)hipGraphExecDestroy(g);
+        for (auto& plane : graph)
+            for (auto& row : plane)
+                for (auto& g : row)
+                    if (g) (void)hipGraphExecDestroy(g);
         if (ev_fork) (void)hipEventDestroy(ev_fork);
         if (ev_join) (void)hipEventDestroy(ev_join);
         if (side) (void)hipStreamDestroy(side);
@@ -598,8 +599,8 @@ static int check_mass(lbm_ctx* c) {
 // was deferred, tile clearing, volumes, triangle forces, the node gather and
 // the bin sort) run on the side stream beside the density pass and join
 // before the wettability reaction.  With `defer_interp` this step's
-// advection is left to the next step's side branch; the caller's last step
-// leaves it off, so that no call returns with an advection pending.
+// advection is left to the next step's side branch; the caller launches the
+// last one pending before it returns.
 static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, const float* rho_p, bool advect,
                          hipEvent_t* ev, bool overlap = false, bool defer_interp = false) {
     const Lattice& L = c->L;
@@ -684,11 +685,13 @@ static void enqueue_step(lbm_ctx* c, hipEvent_t* ev, bool defer_interp = false) 
     enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev, true, defer_interp);
 }
 
-// Two steps captured as one graph.  The launch arguments depend only on the
+// Two steps captured as one graph; both leave their advection to the next
+// step, so a graph ends with one pending, and its first step takes over the
+// one pending before it, if any.  The launch arguments depend only on the
 // step parity and the tile-list parity, so four graphs cover every state.
 static hipGraphExec_t two_step_graph(lbm_ctx* c) {
-    const int sp = (int)(c->step & 1), fp = c->flip;
-    if (c->graph[sp][fp]) return c->graph[sp][fp];
+    const int sp = (int)(c->step & 1), fp = c->flip, pin = c->interp_pending ? 1 : 0;
+    if (c->graph[sp][fp][pin]) return c->graph[sp][fp][pin];
     if (c->graphs_failed || c->stream == nullptr) return nullptr;
     const int64_t step0 = c->step;
     const int flip0 = c->flip;
@@ -699,10 +702,11 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
         return nullptr;
     }
     enqueue_step(c, nullptr, true);
-    enqueue_step(c, nullptr);
+    enqueue_step(c, nullptr, true);
     const hipError_t e = hipStreamEndCapture(c->stream, &g);
     c->step = step0;
     c->flip = flip0;
+    c->interp_pending = pin != 0;
     hipGraphExec_t ex = nullptr;
     if (e != hipSuccess || !g || hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
         c->graphs_failed = true;
@@ -711,7 +715,7 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
         return nullptr;
     }
     (void)hipGraphDestroy(g);
-    c->graph[sp][fp] = ex;
+    c->graph[sp][fp][pin] = ex;
     return ex;
 }
 
@@ -733,9 +737,10 @@ int lbm_capsules_bending(lbm_ctx* c, int32_t first_id, int32_t n_caps, const dou
     bool on = false;
     for (const CapDev& cd : c->caps) on = on || cd.kB > 0.0f;
     c->bending = on;
-    for (auto& g : c->graph)
-        for (auto& e : g)
-            if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
+    for (auto& plane : c->graph)
+        for (auto& row : plane)
+            for (auto& e : row)
+                if (e) { (void)hipGraphExecDestroy(e); e = nullptr; }
     HIPCHK(c, hipMemcpyAsync(c->d.caps, c->caps.data(), c->caps.size() * sizeof(CapDev), hipMemcpyHostToDevice, c->stream));
     return LBM_OK;
 }
@@ -770,9 +775,15 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
             if (!ex) break;
             HIPCHK(c, hipGraphLaunch(ex, c->stream));
             c->step += 2;
+            c->interp_pending = c->n_nodes > 0;
             chunk -= 2;
         }
-        for (; chunk > 0; --chunk) enqueue_step(c, nullptr, chunk > 1);
+        for (; chunk > 0; --chunk) enqueue_step(c, nullptr, true);
+        // the last advection, so that the call leaves the nodes moved
+        if (c->interp_pending) {
+            launch_interp_advect(c->L, c->d, c->n_nodes, c->stream);
+            c->interp_pending = false;
+        }
         HIPCHK(c, hipGetLastError());
         if (c->p.check_every > 0 && c->step % c->p.check_every == 0) {
             const int r = check_mass(c);
