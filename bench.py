@@ -305,11 +305,11 @@ def membrane_extras_leg(torch, warmup=100, steps=200):
     return out
 
 
-def reference_model_leg(torch, steps=240000, chunk=20000):
+def reference_model_leg(torch, steps=240000, chunk=20000, kV=20.0):
     """The LBM-free reference model of Sec. III.B at the paper's particle
     size: R0 = 10 (2562-node mesh), beta = R0^2 gamma / kB = 1000,
-    B = kB / (kS R0^2) = 1e-2, nu_s = 0.9 (C = 9), kV = 20, gamma = 0.0388,
-    w = 1, overdamped with mobility 0.05.  Reports the ellipsoid half-axes
+    B = kB / (kS R0^2) = 1e-2, nu_s = 0.9 (C = 9), volume modulus kV (20),
+    gamma = 0.0388, w = 1, overdamped with mobility 0.05.  Reports the ellipsoid half-axes
     (from the volume second moments, the paper's 'tensor of inertia') along
     the relaxation and the time per membrane step."""
     import numpy as np
@@ -319,7 +319,7 @@ def reference_model_leg(torch, steps=240000, chunk=20000):
     kB = R0 * R0 * gamma / beta
     kS = kB / (B * R0 * R0)
     ra, rb = workloads.layered(32, 32, 32, 16)
-    cap = workloads.Capsule(workloads._snap(np.array([16.0, 16.0, 16.0])), R0, 16, kS, 9.0, 20.0, 90.0, kB=kB)
+    cap = workloads.Capsule(workloads._snap(np.array([16.0, 16.0, 16.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
     wl = workloads.Workload("reference", 32, 32, 32, ra, rb, [cap], z_interface=15.5)
     sim = sim_from_workload(wl)
     hist = []
@@ -331,12 +331,54 @@ def reference_model_leg(torch, steps=240000, chunk=20000):
         sim.synchronize()
         t_run += time.perf_counter() - t0
         ax = sim.observables()["caps"][0]["axes"]
-        hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5), "r_i": round(float(ax[2]), 5)})
+        hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5), "r_i": round(float(ax[2]), 5),
+                     "r_i_mean": round(0.5 * float(ax[1] + ax[2]), 5)})
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return {"workload": "one R0=10 capsule (2562 nodes), beta 1000, B 1e-2, nu_s 0.9, kV 20, gamma 0.0388, w 1, "
-                        "mobility 0.05", "us_per_step": round(t_run / steps * 1e6, 2), "relaxation": hist}
+    return {"workload": "one R0=10 capsule (2562 nodes), beta 1000, B 1e-2, nu_s 0.9, kV %g, gamma 0.0388, w 1, "
+                        "mobility 0.05" % kV, "us_per_step": round(t_run / steps * 1e6, 2), "relaxation": hist}
+
+
+def shape_error_leg(torch, steps=40000, chunk=5000, kV=2.0):
+    """The shape errors of Sec. III.B (eq. interface:error) between the
+    reference model and the coupled simulation of the same capsule (R0 = 10,
+    2562 nodes, beta 1000, B 1e-2, nu_s 0.9), here immersed-boundary coupled
+    at the flat interface of a 64x64x48 two-component box (G 3.6, theta
+    90 deg) and run to equilibrium.  Delta_p = (r_p^ref - r_p^sim) / R0 and
+    Delta_i = (r_i^ref - r_i^sim) / R0 with r_p the half-axis normal to the
+    interface and r_i the mean of the two in-plane half-axes, both from the
+    volume second moments.  Both sides use the volume modulus kV = 2 (the
+    explicit coupling diverges within 250 steps at kV = 20)."""
+    ref = reference_model_leg(torch, kV=kV)
+    import numpy as np
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import sim_from_workload
+    R0, gamma, beta, B = 10.0, 0.0388, 1000.0, 1e-2
+    kB = R0 * R0 * gamma / beta
+    kS = kB / (B * R0 * R0)
+    ra, rb = workloads.layered(64, 64, 48, 24)
+    cap = workloads.Capsule(workloads._snap(np.array([32.0, 32.0, 24.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
+    wl = workloads.Workload("shape_error", 64, 64, 48, ra, rb, [cap], z_interface=23.5)
+    sim = sim_from_workload(wl)
+    hist = []
+    t0 = time.perf_counter()
+    for k in range(steps // chunk):
+        sim.step(chunk)
+        ax = sim.observables()["caps"][0]["axes"]
+        hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5),
+                     "r_i_mean": round(0.5 * float(ax[1] + ax[2]), 5)})
+    sim.synchronize()
+    wall = time.perf_counter() - t0
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    fin, rf = hist[-1], ref["relaxation"][-1]
+    return {"workload": "64x64x48 box, interface z=23.5, one R0=10 capsule (2562 nodes), beta 1000, B 1e-2, "
+                        "nu_s 0.9, kV %g, theta 90 deg, G 3.6" % kV,
+            "steps": steps, "wall_s": round(wall, 2), "coupled": hist, "reference": ref["relaxation"][-1],
+            "delta_p": round((rf["r_p"] - fin["r_p"]) / R0, 5),
+            "delta_i": round((rf["r_i_mean"] - fin["r_i_mean"]) / R0, 5)}
 
 
 def precision_study(torch, steps):
@@ -411,6 +453,9 @@ def main():
     ap.add_argument("--oracle-timing-leg", action="store_true",
                     help="also time the FP64 oracle on the 32^3 case (1000 steps) and the 64^3 cases (50 steps), "
                          "all cores and one thread")
+    ap.add_argument("--shape-error-leg", action="store_true",
+                    help="also relax a capsule with the reference model and couple the same capsule at a fluid "
+                         "interface, and report the shape errors between the two")
     ap.add_argument("--reference-model-leg", action="store_true",
                     help="also relax a capsule with the LBM-free reference model (no fluid)")
     ap.add_argument("--membrane-extras-leg", action="store_true",
@@ -515,6 +560,8 @@ def main():
         out["scale_512"] = scale_leg(torch)
     if args.reference_model_leg:
         out["reference_model"] = reference_model_leg(torch)
+    if args.shape_error_leg:
+        out["shape_error"] = shape_error_leg(torch)
     if args.membrane_extras_leg:
         out["membrane_extras"] = membrane_extras_leg(torch)
     if args.adjoint_fd_sweep:
