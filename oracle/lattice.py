@@ -10,7 +10,10 @@ Pins (tests/test_oracle_lattice.py): equilibrium moments (mass, momentum,
 momentum flux) exactly; shear-wave decay against the closed form with
 nu = c_s^2 (tau - 1/2); half-way bounce-back Couette profile; Shan-Chen
 force sums to zero in a periodic box; flat interface stays flat; bulk
-densities move toward the mean-field coexistence values.
+densities move toward the mean-field coexistence values; the on-site
+velocity closure gives the boundary node the wall velocity exactly, keeps
+a fluid at rest at rest, and its steady Couette profile is the exact
+linear one between the boundary rows (tests/test_oracle_onsite.py).
 """
 
 import torch
@@ -61,6 +64,9 @@ def stream(fpost, walls=0, u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0)):
     """Pull streaming f_i(x) = f*_i(x - c_i), periodic in every direction
     (Sec. II.A, left-hand side of eq. method:boltzmann).
 
+    walls = 2: on-site velocity boundaries on the rows y = 0 and
+    y = ny - 1, which are fluid (onsite_closure).
+
     walls = 1: rows y = 0 and y = ny - 1 are solid.  A fluid population
     whose source node is solid is reflected half-way with the moving-wall
     term of Sec. II.C (eq. method:SBB):
@@ -74,6 +80,8 @@ def stream(fpost, walls=0, u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0)):
         cx, cy, cz = (int(v) for v in C[i])
         out.append(torch.roll(fpost[:, i], shifts=(cz, cy, cx), dims=(1, 2, 3)))
     f = torch.stack(out, 1)
+    if walls == 2:
+        return onsite_closure(f, u_lo, u_hi)
     if walls:
         ny = f.shape[3]
         f = f.clone()
@@ -90,10 +98,45 @@ def stream(fpost, walls=0, u_lo=(0.0, 0.0, 0.0), u_hi=(0.0, 0.0, 0.0)):
     return f
 
 
+def onsite_closure(f, u_lo, u_hi):
+    """On-site velocity boundaries on the rows y = 0 and y = ny - 1 (the
+    boundaries the paper's shear-flow case names; Zou and He, in the D3Q19
+    form of Hecht and Harting).  After streaming, the populations that would
+    have come from outside the box (c_y = +1 at y = 0, c_y = -1 at
+    y = ny - 1) are unknown.  With s the sign of c_y of the unknowns and u
+    the wall velocity, mass and normal momentum give the node density
+        rho = (Z + 2 O) / (1 - s u_y),
+    Z the sum of the populations with c_y = 0 and O of those with c_y = -s;
+    each unknown is its opposite plus the equilibrium difference, with a
+    transverse correction that makes the tangential momentum rho u exactly:
+        f_i = f_opp(i) + 6 w_i rho (c_i . u) - c_ix N_x - c_iz N_z,
+        N_x = (1/2) sum_{c_y = 0} f c_x - rho u_x / 3 (and N_z alike).
+    f: [c, 19, z, y, x] after streaming; returns a copy with the unknowns set."""
+    f = f.clone()
+    ny = f.shape[3]
+    for yb, s, uw in ((0, 1, u_lo), (ny - 1, -1, u_hi)):
+        g = f[:, :, :, yb, :].clone()               # [c, 19, z, x]
+        cy = C[:, 1]
+        Z = g[:, cy == 0].sum(1)
+        O = g[:, cy == -s].sum(1)
+        rho = (Z + 2.0 * O) / (1.0 - s * uw[1])
+        flat = cy == 0
+        Nx = 0.5 * (g[:, flat] * CF[flat, 0].view(1, -1, 1, 1)).sum(1) - rho * uw[0] / 3.0
+        Nz = 0.5 * (g[:, flat] * CF[flat, 2].view(1, -1, 1, 1)).sum(1) - rho * uw[2] / 3.0
+        for i in range(19):
+            if int(C[i][1]) != s:
+                continue
+            cu = float(C[i][0]) * uw[0] + float(C[i][1]) * uw[1] + float(C[i][2]) * uw[2]
+            f[:, i, :, yb, :] = (g[:, OPP[i]] + 6.0 * float(W[i]) * rho * cu
+                                 - float(C[i][0]) * Nx - float(C[i][2]) * Nz)
+    return f
+
+
 def wall_copy(a, walls):
     """Solid rows take the value of the adjacent fluid row (a neutral wall for
-    the pseudo-potential).  a: [..., z, y, x]."""
-    if not walls:
+    the pseudo-potential).  a: [..., z, y, x].  (With on-site boundaries every
+    row is fluid; sc_sum then clamps its neighbours at the box instead.)"""
+    if walls != 1:
         return a
     ny = a.shape[-2]
     idx = torch.arange(ny)
@@ -111,15 +154,22 @@ def pseudo_potential(rho, kind=0):
     return 1.0 - torch.exp(-rho)
 
 
-def sc_sum(psi):
+def sc_sum(psi, walls=0):
     """S(x) = sum_{i=1..18} w_i psi(x + c_i) c_i, periodic.  This is the
     neighbour sum inside the Shan-Chen force of Sec. II.D (eq.
-    method:shanchen).  psi: [z, y, x] -> [3, z, y, x]."""
+    method:shanchen).  psi: [z, y, x] -> [3, z, y, x].  walls = 2 (on-site
+    boundaries): a neighbour beyond the rows y = 0 or y = ny - 1 takes the
+    boundary row's value (a neutral wall), not the periodic image."""
     s = torch.zeros((3,) + tuple(psi.shape), dtype=psi.dtype)
     acc = []
+    ny = psi.shape[1]
     for i in range(1, 19):
         cx, cy, cz = (int(v) for v in C[i])
-        nb = torch.roll(psi, shifts=(-cz, -cy, -cx), dims=(0, 1, 2))
+        if walls == 2:
+            iy = torch.clamp(torch.arange(ny) + cy, 0, ny - 1)
+            nb = torch.roll(psi.index_select(1, iy), shifts=(-cz, -cx), dims=(0, 2))
+        else:
+            nb = torch.roll(psi, shifts=(-cz, -cy, -cx), dims=(0, 1, 2))
         acc.append(float(W[i]) * nb.unsqueeze(0) * CF[i].view(3, 1, 1, 1))
     for a in acc:
         s = s + a

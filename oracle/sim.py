@@ -4,7 +4,8 @@ State at the start of step n: post-collision populations f*^{n-1} and node
 positions X^n.  The step, in this order:
 
  1. stream: f^n = pull(f*^{n-1}) with half-way bounce-back at walls
-    (Sec. II.A; Sec. II.C eq. method:SBB);
+    (Sec. II.A; Sec. II.C eq. method:SBB), or with on-site velocity
+    boundaries on the rows y = 0 and y = ny - 1 (walls = 2);
  2. densities rho^c = sum_i f_i^c, momenta j^c = sum_i f_i^c c_i, and the
     pseudo-potential: psi = rho for the workloads (psi_kind 0), or the
     1 - exp(-rho/rho0), rho0 = 1, that Sec. II.D names (psi_kind 1);
@@ -99,7 +100,7 @@ class OracleSim:
         self.X = [torch.as_tensor(c["xyz"], dtype=DT).clone() for c in caps]
         self.n = 0
         self.fluid_mask = torch.ones(self.ny, dtype=torch.bool)
-        if self.walls:
+        if self.walls == 1:
             self.fluid_mask[0] = False
             self.fluid_mask[self.ny - 1] = False
         self.rho_last = self.u_last = self.Fib_last = self.phi_last = None
@@ -107,7 +108,7 @@ class OracleSim:
 
     # ---- pieces -------------------------------------------------------
     def _reset_solid(self, f):
-        if not self.walls:
+        if self.walls != 1:
             return f
         f = f.clone()
         f[:, :, :, 0, :] = self.f_solid[:, :, :, 0, :]
@@ -141,7 +142,7 @@ class OracleSim:
             a = cap["mesh"].node_area * (rv.abs() if isinstance(rv, torch.Tensor) else abs(rv))
             if not is_zero:
                 if S_psi is None:
-                    S_psi = [lattice.sc_sum(lattice.wall_copy(lattice.pseudo_potential(rho[c], self.psi_kind), w))
+                    S_psi = [lattice.sc_sum(lattice.wall_copy(lattice.pseudo_potential(rho[c], self.psi_kind), w), w)
                              for c in (0, 1)]
                 npc = 1 - pref
                 interp = ibm.interpolate(S_psi[npc], X)          # [N, 3]
@@ -176,7 +177,7 @@ class OracleSim:
         # reading under the immersed boundary; linear in phi for any psi)
         psi = [lattice.pseudo_potential(rho[c], self.psi_kind) for c in (0, 1)]
         psi_tot = [lattice.wall_copy(psi[c] + phi[c], w) for c in (0, 1)]
-        S_tot = [lattice.sc_sum(psi_tot[c]) for c in (0, 1)]
+        S_tot = [lattice.sc_sum(psi_tot[c], w) for c in (0, 1)]
         rsum = rho[0] + rho[1]
         F = []
         for c in (0, 1):
