@@ -381,6 +381,36 @@ def shape_error_leg(torch, steps=40000, chunk=5000, kV=2.0):
             "delta_i": round((rf["r_i_mean"] - fin["r_i_mean"]) / R0, 5)}
 
 
+def shear_leg(torch, cas=(0.0125, 0.025, 0.05, 0.1, 0.2), steps=100000, every=10000):
+    """The capsule-in-shear workload of Sec. III.A: a 48^3 box between
+    on-site velocity boundaries moving at -+rate (n - 1) / 2 (shear rate
+    1e-4), one fluid of density 1 (both components at 0.5, G = 0), one
+    R0 = 7.64 capsule (2562 nodes) with C = 1 and kS = rho nu rate R0 / Ca.
+    Reports the Taylor deformation D along each run and its final value per
+    capillary number, and the time per step."""
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import sim_from_workload
+    out = {"workload": "48^3, on-site boundaries y=0/47 at -+2.35e-3, rho 1, G 0, one R0=7.64 capsule "
+                       "(2562 nodes), C 1, kS = rho nu rate R0 / Ca", "steps": steps, "runs": []}
+    for ca in cas:
+        print("bench: capsule in shear, Ca %g" % ca, file=sys.stderr, flush=True)
+        wl = workloads.shear(ca)
+        sim = sim_from_workload(wl)
+        hist = []
+        t0 = time.perf_counter()
+        for k in range(steps // every):
+            sim.step(every)
+            hist.append(round(float(sim.observables()["caps"][0]["D"]), 5))
+        sim.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        out["runs"].append({"Ca": ca, "kS": round(wl.capsules[0].kS, 7), "D": hist[-1], "D_over_Ca": round(hist[-1] / ca, 3),
+                            "D_every_%d" % every: hist, "us_per_step": round(wall / steps * 1e6, 2)})
+    return out
+
+
 def precision_study(torch, steps):
     """The FP16 g-storage form beside the FP32 form on the 256^3 droplet
     workload (B droplet of radius 60 in A, 64 capsules of 642 nodes on a
@@ -453,6 +483,8 @@ def main():
     ap.add_argument("--oracle-timing-leg", action="store_true",
                     help="also time the FP64 oracle on the 32^3 case (1000 steps) and the 64^3 cases (50 steps), "
                          "all cores and one thread")
+    ap.add_argument("--shear-leg", action="store_true",
+                    help="also run the capsule-in-shear workload (on-site boundaries) at five capillary numbers")
     ap.add_argument("--shape-error-leg", action="store_true",
                     help="also relax a capsule with the reference model and couple the same capsule at a fluid "
                          "interface, and report the shape errors between the two")
@@ -562,6 +594,8 @@ def main():
         out["reference_model"] = reference_model_leg(torch)
     if args.shape_error_leg:
         out["shape_error"] = shape_error_leg(torch)
+    if args.shear_leg:
+        out["shear"] = shear_leg(torch)
     if args.membrane_extras_leg:
         out["membrane_extras"] = membrane_extras_leg(torch)
     if args.adjoint_fd_sweep:

@@ -18,7 +18,9 @@
  *     (Sec. III.D, eq. results:anglescaling), spread over the membrane with
  *     the same delta and scaled by wet_scale;
  *   - planar half-way bounce-back walls that may move (Sec. II.C,
- *     eq. method:SBB);
+ *     eq. method:SBB), or on-site velocity boundaries (Zou and He, in the
+ *     D3Q19 form of Hecht and Harting), the boundaries of the paper's
+ *     shear-flow case (Sec. III.A), FP32 storage and forward runs only;
  *   - optionally, Helfrich bending of the membranes (Sec. II.B) and the
  *     short-range particle-particle repulsion between boundary nodes of
  *     different capsules (Sec. III.E);
@@ -73,7 +75,12 @@ enum { LBM_OBJ_COM_Z = 0, LBM_OBJ_TAYLOR_D = 1 };
 typedef struct lbm_params {
     int32_t nx, ny, nz;     /* lattice size, each >= 4, nx*ny*nz <= 2^30        */
     int32_t precision;      /* LBM_FP32, or LBM_FP16 population storage         */
-    int32_t walls;          /* 0 periodic; 1 solid rows y = 0 and y = ny - 1   */
+    int32_t walls;          /* 0 periodic; 1 solid rows y = 0 and y = ny - 1
+                               (half-way bounce-back, ny >= 5); 2 on-site
+                               velocity boundaries on the fluid rows y = 0
+                               and y = ny - 1 (FP32, ring_len 0).  Both move
+                               at wall_u_lo / wall_u_hi; capsules keep their
+                               stencils off the boundary rows              */
     int32_t n_slots;        /* checkpoint slots carved from the workspace       */
     int32_t check_every;    /* FP64 mass check period in steps, 0 = never       */
     int32_t use_graphs;     /* 1: lbm_step replays captured two-step HIP graphs

@@ -366,6 +366,8 @@ __global__ __launch_bounds__(256) void k_node_wet(Lattice L, Dev d, const float*
                 const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
                 int gyy = wrap3(pw[1] - 2 + qy, L.ny);
                 if (L.walls) gyy = gyy == 0 ? 1 : (gyy == L.ny - 1 ? L.ny - 2 : gyy);
+                // on-site boundaries: beyond the box is the boundary row
+                if (L.onsite) gyy = min(max(pw[1] - 2 + qy, 0), L.ny - 1);
                 const int gzz = wrap3(pw[2] - 2 + qz, L.nz), gxx = wrap3(pw[0] - 2 + qx, L.nx);
                 const float r = sc * rc[(uint32_t)((gzz * L.ny + gyy) * L.nx + gxx)];
                 cb[j] = PSI ? psi_exp(r) : r;     // the pseudo-potential
@@ -518,7 +520,7 @@ __device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d,
         const int c0 = pw[a] + (int)floorf(p.r[a] - reach), c1 = pw[a] + (int)floorf(p.r[a] + reach);
         for (int c = c0; c <= c1; ++c) {
             int cw = c;
-            if (a == 1 && L.walls) {
+            if (a == 1 && (L.walls || L.onsite)) {
                 if (c < 0 || c >= nn[a]) continue;
             } else {
                 cw = wrap3(c, nn[a]);
@@ -545,7 +547,7 @@ __device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d,
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         float x = (float)(A[a] - Ae[a]) + ((oh[a] - d.off_hi[3 * e + a]) + (ol[a] - d.off_lo[3 * e + a]));
-                        if (!(a == 1 && L.walls)) {
+                        if (!(a == 1 && (L.walls || L.onsite))) {
                             const float nf = (float)nn[a];
                             x -= nf * rintf(x / nf);
                         }

@@ -148,8 +148,10 @@ std::string validate(const lbm_params* p) {
     // kernels address one component of one direction with 32-bit offsets
     if ((int64_t)p->nx * p->ny * p->nz > ((int64_t)1 << 30)) return "lattice too large (more than 2^30 nodes)";
     if (p->precision != LBM_FP32 && p->precision != LBM_FP16) return "precision must be LBM_FP32 or LBM_FP16";
-    if (p->walls != 0 && p->walls != 1) return "walls must be 0 or 1";
-    if (p->walls && p->ny < 5) return "walls need ny >= 5";
+    if (p->walls < 0 || p->walls > 2) return "walls must be 0, 1 or 2";
+    if (p->walls == 1 && p->ny < 5) return "walls need ny >= 5";
+    if (p->walls == 2 && p->precision != LBM_FP32) return "on-site velocity boundaries (walls = 2) need FP32 storage";
+    if (p->walls == 2 && p->ring_len > 0) return "the adjoint does not cover on-site velocity boundaries (walls = 2)";
     for (int c = 0; c < 2; ++c)
         if (!(p->tau[c] > 0.5) || !isfinite(p->tau[c])) return "tau must be finite and > 0.5";
     if (!(p->G >= 0.0) || !isfinite(p->G)) return "G must be finite and >= 0";
@@ -266,7 +268,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     double m[2] = {0, 0};
     for (int64_t k = 0; k < N; ++k) {
         const int y = (int)((k / p->nx) % p->ny);
-        const bool fluid = !p->walls || (y > 0 && y < p->ny - 1);
+        const bool fluid = p->walls != 1 || (y > 0 && y < p->ny - 1);
         if (!fluid) continue;
         if (!(rhoA[k] > 0.0f) || !(rhoB[k] > 0.0f) || !isfinite(rhoA[k]) || !isfinite(rhoB[k])) {
             g_init_error = "initial densities must be finite and > 0 on fluid nodes";
@@ -298,7 +300,8 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
         L.cached = (int64_t)N * 2 * Q * (p->precision == LBM_FP16 ? 2 : 4) <= ((int64_t)512 << 20) ? 1 : 0;
     else
         L.cached = p->stream_policy == 1 ? 1 : 0;
-    L.walls = p->walls;
+    L.walls = p->walls == 1 ? 1 : 0;
+    L.onsite = p->walls == 2 ? 1 : 0;
     L.G = (float)p->G;
     for (int k = 0; k < 2; ++k) { L.tau[k] = (float)p->tau[k]; L.omega[k] = (float)(1.0 / p->tau[k]); }
     for (int k = 0; k < 3; ++k) { L.uw_lo[k] = (float)p->wall_u_lo[k]; L.uw_hi[k] = (float)p->wall_u_hi[k]; }
@@ -376,6 +379,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     }
     const bool half = p->precision == LBM_FP16;
     launch_init_rest(L, d.f[0], d.rho[0], d.rho[0] + N, half, s);
+    if (L.onsite) launch_onsite(L, d.f[0], s);
     static const float ones[4] = {1.0f, 1.0f, 1.0f, 1.0f};
     if ((er = hipMemcpyAsync(d.cscale, ones, sizeof ones, hipMemcpyHostToDevice, s)) != hipSuccess)
         return bad(er, "hipMemcpyAsync");
@@ -668,6 +672,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         return;
     }
     launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ibm, false, half, d.cscale, nxt, cur, s);
+    if (L.onsite) launch_onsite(L, fout, s);
     mark(LBM_K_INTERP);
     if (ibm && advect) {
         if (defer_interp && fork)

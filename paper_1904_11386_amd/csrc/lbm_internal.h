@@ -56,7 +56,8 @@ struct Lattice {
     int cached;            // population streams: non-temporal loads, cached stores (1) or the reverse
     int psi_exp;           // Shan-Chen pseudo-potential 1 - exp(-rho) (1) or rho (0)
     int64_t n;             // nx*ny*nz
-    int walls;
+    int walls;             // half-way bounce-back walls: solid rows y = 0 and ny - 1
+    int onsite;            // on-site velocity boundaries on the fluid rows y = 0 and ny - 1
     float G;
     float tau[2];
     float omega[2];        // 1/tau
@@ -162,6 +163,7 @@ void launch_compensate(const Lattice& L, const double* partial, double m0a, doub
 void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,
                     const float* fib, const int* tile_flag, float* u, bool has_ibm, bool macro, bool half,
                     const float* cscale, int par_prev, int par_cur, hipStream_t s);
+void launch_onsite(const Lattice& L, void* f, hipStream_t s);
 void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const float* renc,
                          const float* cscale, int par, double* partial, hipStream_t s);
 

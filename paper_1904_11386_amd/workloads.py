@@ -30,6 +30,12 @@ Workloads (sizes as stated, seeds numpy.random.default_rng(1904 + k)):
           across the periodic x boundary), particle-particle repulsion on
   bent    38x34x36, two capsules with Helfrich bending (one an ellipsoid) and
           an ellipsoid without it across the periodic x boundary
+  onsite_mini  40x20x24 channel with on-site velocity boundaries on the rows
+          y = 0 / 19 moving at -+0.01, interface z = 12, one R = 4 capsule
+  shear   48^3 capsule in shear (Sec. III.A): on-site boundaries y = 0 / 47
+          moving so that the shear rate is 1e-4, A and B both 0.5
+          everywhere, G = 0, one R0 = 7.64 (2562-node) capsule, C = 1, kS
+          from the capillary number Ca = rho nu rate R0 / kS
 """
 
 from __future__ import annotations
@@ -333,6 +339,34 @@ def make(name: str, kV: Optional[float] = None) -> Workload:
         return Workload("c5", n, n, n, rhoA, rhoB, caps, z_interface=n / 2 - 0.5,
                         steps=300)
     raise KeyError(name)
+
+
+def onsite_mini(nx=40, ny=20, nz=24, theta=75.0) -> Workload:
+    """A small channel between on-site velocity boundaries (walls = 2) on the
+    rows y = 0 and y = ny - 1, moving at -+0.01 in x, with the flat
+    interface z = nz / 2 meeting them and one R = 4 (162-node) capsule in
+    the middle of the channel."""
+    rhoA, rhoB = layered(nx, ny, nz, nz // 2)
+    cap = Capsule(_snap(np.array([nx / 2, (ny - 1) / 2.0, nz / 2])), 4.0, 4, 0.005, 0.0, KV_DEFAULT, theta)
+    return Workload("onsite_mini", nx, ny, nz, rhoA, rhoB, [cap], walls=2,
+                    wall_u_lo=(-0.01, 0.0, 0.0), wall_u_hi=(0.01, 0.0, 0.0), z_interface=nz / 2 - 0.5,
+                    steps=100)
+
+
+def shear(Ca, n=48, R0=7.64, rate=1e-4, C=1.0, freq=16, tau=1.0) -> Workload:
+    """A capsule in simple shear between on-site velocity boundaries (Sec.
+    III.A): an n^3 box whose rows y = 0 and y = n - 1 move at -+rate (n - 1) / 2
+    in x, both components at 0.5 everywhere with G = 0 (one fluid of density
+    1), one capsule of radius R0 in the centre with the Skalak parameter C and
+    kS = rho nu rate R0 / Ca (nu = (tau - 1/2) / 3, rho = 1)."""
+    nu = (tau - 0.5) / 3.0
+    kS = 1.0 * nu * rate * R0 / Ca
+    rho = np.full((n, n, n), 0.5, np.float32)
+    u = rate * (n - 1) / 2.0
+    cap = Capsule(_snap(np.array([n / 2, (n - 1) / 2.0, n / 2])), R0, freq, kS, C, KV_DEFAULT, 90.0)
+    return Workload("shear", n, n, n, rho, rho.copy(), [cap], tau=(tau, tau), G=0.0, walls=2,
+                    wall_u_lo=(-u, 0.0, 0.0), wall_u_hi=(u, 0.0, 0.0), z_interface=n / 2 - 0.5,
+                    steps=100000)
 
 
 def bent(nx=38, ny=34, nz=36, kB=0.02, freq=4, walls=0) -> Workload:

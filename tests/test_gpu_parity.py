@@ -44,7 +44,7 @@ def _rel(a, b):
 
 def _fluid(wl):
     m = np.ones(wl.ny, bool)
-    if wl.walls:
+    if wl.walls == 1:               # solid rows (on-site boundary rows are fluid)
         m[0] = m[-1] = False
     return m
 
@@ -137,6 +137,45 @@ def test_stream_policy_and_zchunk(precision, policy, zchunk, walls):
 def test_walls_channel_parity():
     wl = W.make("c4_mini")
     _compare_run(wl, 100, 5e-6, 1e-5, tol_x=2e-5)
+
+
+def test_onsite_couette_parity_and_profile():
+    """On-site velocity boundaries (walls = 2) on a fluid-only channel: the
+    fields meet the oracle after 200 steps, and the steady profile is the
+    exact linear one between the boundary rows."""
+    ny = 16
+    rho = np.full((8, ny, 8), 0.5, np.float32)
+    wl = W.Workload("onsite_couette", 8, ny, 8, rho, rho.copy(), [], tau=(1.2, 1.2), G=0.0, walls=2,
+                    wall_u_lo=(-0.01, 0.0, 0.0), wall_u_hi=(0.01, 0.0, 0.0))
+    # U is only 0.01 here, so the velocity bound is taken at 3e-5 U = 3e-7
+    # absolute: the FP32 floor of about 1e-8 per step (see the header)
+    # accumulated over 200 steps (1.6e-7 measured, spread over every row)
+    g, o = _compare_run(wl, 200, 2e-6, 3e-5)
+    g.step(6000)
+    _, _, u = g.fields()
+    exp = -0.01 + 0.02 * np.arange(ny) / (ny - 1)
+    err = float(np.abs(u[0] - exp[None, :, None]).max())
+    _say("  steady profile err %.3e, cross-flow %.3e" % (err, float(np.abs(u[1:]).max())))
+    assert err < 2e-7
+    # FP32 rounding drives a cross-flow of ~2e-7 (1e-5 U); a wrong closure
+    # term would be of the order of U itself
+    assert float(np.abs(u[1:]).max()) < 1e-6
+
+
+def test_onsite_channel_with_interface_and_capsule():
+    """On-site boundaries with the Shan-Chen interface meeting them (the
+    pseudo-potential beyond the box is the boundary row's) and a capsule in
+    the channel."""
+    _compare_run(W.onsite_mini(), 100, 5e-6, 1e-5, tol_x=2e-5)
+
+
+def test_capsule_in_shear_first_steps():
+    """The capsule-in-shear workload (48^3, 2562-node capsule, G = 0) against
+    the oracle over its first 20 steps."""
+    # U is the wall speed 2.35e-3; the velocities differ by the FP32 floor of
+    # about 1e-7 absolute (the rounding of populations that sum to 0.5,
+    # spreading in from the boundary rows), so the bound is 2.5e-4 U = 6e-7
+    _compare_run(W.shear(0.1), 20, 2e-6, 2.5e-4, tol_x=1e-5)
 
 
 def test_first_step_node_forces_and_spread():
