@@ -178,6 +178,38 @@ def test_capsule_in_shear_first_steps():
     _compare_run(W.shear(0.1), 20, 2e-6, 2.5e-4, tol_x=1e-5)
 
 
+def test_graph_eager_and_chunked_stepping_agree():
+    """Replayed graphs (whose steps leave each advection to the next step's
+    side branch), eager steps, odd call sizes, mass-check chunks and a timed
+    stretch in between give the same state: a lost or repeated advection
+    would move the nodes by a whole step's displacement."""
+    wl = W.small(nx=40, ny=36, nz=44, ncap=2, theta=(70.0, 115.0))
+    runs = {}
+    for name, kw, calls in (("graphs", {}, (5, 1, 2, 29)), ("eager", dict(use_graphs=0), (37,)),
+                            ("chunked", dict(check_every=7), (37,)), ("timed", {}, (4, "t3", 30))):
+        _say("case", name, calls)
+        g = _sim(wl, **kw)
+        for c in calls:
+            if isinstance(c, str):
+                g.step_timed(int(c[1:]))
+            else:
+                g.step(c)
+        ra, _, _ = g.fields()
+        runs[name] = (g.nodes(), ra, g.observables()["step"])
+        g.close()
+    X0, r0, s0 = runs["graphs"]
+    o = from_workload(wl).run(37)
+    Xo = torch.cat(o.X, 0).numpy()
+    for name, (X, r, st) in runs.items():
+        dx = float(np.abs(X - X0).max())
+        dxo = float(np.abs(X - Xo).max())
+        _say("  %s: step %d, |X - X_graphs| %.3e lu, |X - X_oracle| %.3e lu, rho %.3e"
+             % (name, st, dx, dxo, _rel(r, r0)))
+        assert st == 37
+        assert dx < 1e-5 and dxo < 2e-5
+        assert _rel(r, r0) < 1e-5
+
+
 def test_first_step_node_forces_and_spread():
     wl = W.small(nx=40, ny=36, nz=44, ncap=2, theta=(55.0, 130.0), wet_scale=1.0)
     g = _sim(wl)
