@@ -20,7 +20,7 @@
  *   - planar half-way bounce-back walls that may move (Sec. II.C,
  *     eq. method:SBB), or on-site velocity boundaries (Zou and He, in the
  *     D3Q19 form of Hecht and Harting), the boundaries of the paper's
- *     shear-flow case (Sec. III.A), FP32 storage and forward runs only;
+ *     shear-flow case (Sec. III.A), forward runs only;
  *   - optionally, Helfrich bending of the membranes (Sec. II.B) and the
  *     short-range particle-particle repulsion between boundary nodes of
  *     different capsules (Sec. III.E);
@@ -78,9 +78,13 @@ typedef struct lbm_params {
     int32_t walls;          /* 0 periodic; 1 solid rows y = 0 and y = ny - 1
                                (half-way bounce-back, ny >= 5); 2 on-site
                                velocity boundaries on the fluid rows y = 0
-                               and y = ny - 1 (FP32, ring_len 0).  Both move
+                               and y = ny - 1 (ring_len 0).  Both move
                                at wall_u_lo / wall_u_hi; capsules keep their
-                               stencils off the boundary rows              */
+                               stencils off the boundary rows.  On-site
+                               boundaries exchange mass with the outside:
+                               the FP16 form then runs without mass
+                               compensation and the mass check tests
+                               finiteness only                              */
     int32_t n_slots;        /* checkpoint slots carved from the workspace       */
     int32_t check_every;    /* FP64 mass check period in steps, 0 = never       */
     int32_t use_graphs;     /* 1: lbm_step replays captured two-step HIP graphs
@@ -201,7 +205,8 @@ int lbm_reference_relax(lbm_ctx* ctx, int32_t nsteps, double gamma, double w, do
  * first call (kernels only, no memory-set nodes).  With
  * check_every > 0 the FP64 mass check runs every check_every steps and
  * synchronises; it returns LBM_EUNSTABLE when a component mass is not
- * finite or has drifted by more than mass_tol relative to its start. */
+ * finite or (except with walls = 2) has drifted by more than mass_tol
+ * relative to its start. */
 int lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* Kernel groups of one step, in launch order (for lbm_step_timed). */

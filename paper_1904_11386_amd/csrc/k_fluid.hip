@@ -1269,12 +1269,12 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
 }  // namespace
 
 // On-site velocity boundaries on the rows y = 0 and y = ny - 1 (Zou and He,
-// in the D3Q19 form of Hecht and Harting), FP32 storage.  One thread per
-// boundary node, after the collide (and once after initialisation).  The
-// next pull brings each boundary node its unknown populations (c_y = +1 at
-// y = 0, c_y = -1 at y = ny - 1) from the opposite boundary row through the
-// periodic addressing; those slots hold populations that leave the box and
-// that nothing else reads, so the closure is stored there:
+// in the D3Q19 form of Hecht and Harting).  One thread per boundary node,
+// after the collide (and once after initialisation).  The next pull brings
+// each boundary node its unknown populations (c_y = +1 at y = 0, c_y = -1 at
+// y = ny - 1) from the opposite boundary row through the periodic
+// addressing; those slots hold populations that leave the box and that
+// nothing else reads, so the closure is stored there:
 //   rho = (Z + 2 O) / (1 - s u_y),   s = c_y of the unknowns,
 //   f_i = f_opp(i) + 6 w_i rho (c_i . u) - c_ix N_x - c_iz N_z,
 //   N_x = (1/2) sum_{c_y = 0} f c_x - rho u_x / 3 (N_z alike),
@@ -1282,7 +1282,14 @@ __global__ __launch_bounds__(BX * BY) void k_adj_push(const pf2* __restrict__ la
 // c_y = -s, all as the pull will deliver them.  The slots read (rows 0 and 1,
 // ny - 2 and ny - 1, directions with c_y != s) and the slots written (c_y =
 // +1 in row ny - 1, c_y = -1 in row 0) are disjoint.
-__global__ __launch_bounds__(256) void k_onsite(pf2* __restrict__ f, Lattice L) {
+// FP16 form: a pulled value decodes with its source node's compensated
+// density cs * rho_enc, as in the lattice kernels; the decoders stage the
+// densities of a source beyond the box from the boundary row itself (the
+// clamp that also serves the Shan-Chen neighbours), so the unknowns are
+// encoded with the density of the boundary node x - c at the same row.
+template <bool HALF>
+__global__ __launch_bounds__(256) void k_onsite(PopT<HALF>* __restrict__ f, const float* __restrict__ rho_enc,
+                                                const float* __restrict__ cs, Lattice L) {
     const int64_t per = (int64_t)L.nx * L.nz;
     const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (t >= 2 * per) return;
@@ -1293,44 +1300,60 @@ __global__ __launch_bounds__(256) void k_onsite(pf2* __restrict__ f, Lattice L) 
     const int s = top ? -1 : 1;
     const float uw[3] = {top ? L.uw_hi[0] : L.uw_lo[0], top ? L.uw_hi[1] : L.uw_lo[1],
                          top ? L.uw_hi[2] : L.uw_lo[2]};
-    pf2 fk[Q];
-    pf2 Z = {0.f, 0.f}, O = Z, X0 = Z, Z0 = Z;
+    const float sca = HALF ? cs[0] : 1.0f, scb = HALF ? cs[1] : 1.0f;
+    float fa[Q], fb[Q];
+    float Za = 0.f, Zb = 0.f, Oa = 0.f, Ob = 0.f, Xa = 0.f, Xb = 0.f, Wa = 0.f, Wb = 0.f;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        fk[i] = pf2{0.f, 0.f};
+        fa[i] = fb[i] = 0.0f;
         if (cy(i) == s) continue;
         const int sx = wrapi(x - cx(i), L.nx), sy = yb - cy(i), sz = wrapi(z - cz(i), L.nz);
-        const pf2 v = f[i * L.n + ((int64_t)sz * L.ny + sy) * L.nx + sx];
-        fk[i] = v;
-        if (cy(i) == 0) {
-            Z.x += v.x; Z.y += v.y;
-            X0.x += cx(i) * v.x; X0.y += cx(i) * v.y;
-            Z0.x += cz(i) * v.x; Z0.y += cz(i) * v.y;
+        const int64_t node = ((int64_t)sz * L.ny + sy) * L.nx + sx;
+        const PopT<HALF> v = f[i * L.n + node];
+        if (HALF) {
+            const float ea = sca * rho_enc[node], eb = scb * rho_enc[L.n + node];
+            fa[i] = fmaf(ea, (float)v.x, ea * wgt(i));
+            fb[i] = fmaf(eb, (float)v.y, eb * wgt(i));
         } else {
-            O.x += v.x; O.y += v.y;
+            fa[i] = (float)v.x;
+            fb[i] = (float)v.y;
+        }
+        if (cy(i) == 0) {
+            Za += fa[i]; Zb += fb[i];
+            Xa += cx(i) * fa[i]; Xb += cx(i) * fb[i];
+            Wa += cz(i) * fa[i]; Wb += cz(i) * fb[i];
+        } else {
+            Oa += fa[i]; Ob += fb[i];
         }
     }
     const float inv = 1.0f / (1.0f - s * uw[1]);
-    const float ra = (Z.x + 2.0f * O.x) * inv, rb = (Z.y + 2.0f * O.y) * inv;
-    const float nxa = 0.5f * X0.x - ra * uw[0] / 3.0f, nxb = 0.5f * X0.y - rb * uw[0] / 3.0f;
-    const float nza = 0.5f * Z0.x - ra * uw[2] / 3.0f, nzb = 0.5f * Z0.y - rb * uw[2] / 3.0f;
+    const float ra = (Za + 2.0f * Oa) * inv, rb = (Zb + 2.0f * Ob) * inv;
+    const float nxa = 0.5f * Xa - ra * uw[0] / 3.0f, nxb = 0.5f * Xb - rb * uw[0] / 3.0f;
+    const float nza = 0.5f * Wa - ra * uw[2] / 3.0f, nzb = 0.5f * Wb - rb * uw[2] / 3.0f;
     const int yd = top ? 0 : L.ny - 1;          // the row the unknowns are pulled from
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         if (cy(i) != s) continue;
         const float cu = cx(i) * uw[0] + cy(i) * uw[1] + cz(i) * uw[2];
-        const pf2 o = fk[opp(i)];
-        pf2 v;
-        v.x = o.x + 6.0f * wgt(i) * ra * cu - cx(i) * nxa - cz(i) * nza;
-        v.y = o.y + 6.0f * wgt(i) * rb * cu - cx(i) * nxb - cz(i) * nzb;
+        float va = fa[opp(i)] + 6.0f * wgt(i) * ra * cu - cx(i) * nxa - cz(i) * nza;
+        float vb = fb[opp(i)] + 6.0f * wgt(i) * rb * cu - cx(i) * nxb - cz(i) * nzb;
         const int sx = wrapi(x - cx(i), L.nx), sz = wrapi(z - cz(i), L.nz);
-        f[i * L.n + ((int64_t)sz * L.ny + yd) * L.nx + sx] = v;
+        if (HALF) {
+            const int64_t enc = ((int64_t)sz * L.ny + yb) * L.nx + sx;
+            va = va / (sca * rho_enc[enc]) - wgt(i);
+            vb = vb / (scb * rho_enc[L.n + enc]) - wgt(i);
+        }
+        f[i * L.n + ((int64_t)sz * L.ny + yd) * L.nx + sx] = pack<HALF>(va, vb);
     }
 }
 
-void launch_onsite(const Lattice& L, void* f, hipStream_t s) {
+void launch_onsite(const Lattice& L, void* f, bool half, const float* rho_enc, const float* cs, hipStream_t s) {
     const int64_t n = 2 * (int64_t)L.nx * L.nz;
-    hipLaunchKernelGGL(k_onsite, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, (pf2*)f, L);
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    if (half)
+        hipLaunchKernelGGL(k_onsite<true>, grid, block, 0, s, (ph2*)f, rho_enc, cs, L);
+    else
+        hipLaunchKernelGGL(k_onsite<false>, grid, block, 0, s, (pf2*)f, rho_enc, cs, L);
 }
 
 void launch_init_rest(const Lattice& L, void* f, const float* rhoA, const float* rhoB, bool half,

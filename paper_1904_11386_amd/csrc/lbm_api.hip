@@ -150,7 +150,6 @@ std::string validate(const lbm_params* p) {
     if (p->precision != LBM_FP32 && p->precision != LBM_FP16) return "precision must be LBM_FP32 or LBM_FP16";
     if (p->walls < 0 || p->walls > 2) return "walls must be 0, 1 or 2";
     if (p->walls == 1 && p->ny < 5) return "walls need ny >= 5";
-    if (p->walls == 2 && p->precision != LBM_FP32) return "on-site velocity boundaries (walls = 2) need FP32 storage";
     if (p->walls == 2 && p->ring_len > 0) return "the adjoint does not cover on-site velocity boundaries (walls = 2)";
     for (int c = 0; c < 2; ++c)
         if (!(p->tau[c] > 0.5) || !isfinite(p->tau[c])) return "tau must be finite and > 0.5";
@@ -379,10 +378,11 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     }
     const bool half = p->precision == LBM_FP16;
     launch_init_rest(L, d.f[0], d.rho[0], d.rho[0] + N, half, s);
-    if (L.onsite) launch_onsite(L, d.f[0], s);
     static const float ones[4] = {1.0f, 1.0f, 1.0f, 1.0f};
     if ((er = hipMemcpyAsync(d.cscale, ones, sizeof ones, hipMemcpyHostToDevice, s)) != hipSuccess)
         return bad(er, "hipMemcpyAsync");
+    // (the first step decodes with the initial densities and unit compensation)
+    if (L.onsite) launch_onsite(L, d.f[0], half, d.rho[1], d.cscale + 2, s);
     if ((er = hipMemsetAsync(d.fib, 0, 5 * N * sizeof(float), s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_flag, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_count, 0, lay.bins * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
@@ -585,7 +585,8 @@ static int check_mass(lbm_ctx* c) {
     for (int comp = 0; comp < 2; ++comp) {
         double m = 0.0;
         for (int b = 0; b < RED_BLOCKS; ++b) m += part[b * 8 + comp];
-        if (!isfinite(m) || fabs(m - c->mass0[comp]) > c->p.mass_tol * fabs(c->mass0[comp]))
+        // (on-site boundaries exchange mass with the outside: finiteness only)
+        if (!isfinite(m) || (!c->L.onsite && fabs(m - c->mass0[comp]) > c->p.mass_tol * fabs(c->mass0[comp])))
             return c->fail(LBM_EUNSTABLE, "step %lld: mass of component %d is %.17g (start %.17g)",
                            (long long)c->step, comp, m, c->mass0[comp]);
     }
@@ -641,7 +642,10 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     }
     mark(LBM_K_DENSITY);
     if (fout) launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
-    if (half && fout) launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
+    // (on-site boundaries exchange mass with the outside, so there is no
+    // fixed total to restore: their FP16 form keeps unit compensation)
+    if (half && fout && !L.onsite)
+        launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
     if (fork) {
         (void)hipStreamWaitEvent(s, c->ev_join, 0);
         launch_node_wet(L, d, rho_n, cs, c->n_nodes, s);
@@ -672,7 +676,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         return;
     }
     launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ibm, false, half, d.cscale, nxt, cur, s);
-    if (L.onsite) launch_onsite(L, fout, s);
+    if (L.onsite) launch_onsite(L, fout, half, rho_n, d.cscale + 2 * cur, s);
     mark(LBM_K_INTERP);
     if (ibm && advect) {
         if (defer_interp && fork)

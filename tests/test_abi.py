@@ -45,7 +45,7 @@ def test_workspace_bytes_and_validation():
     for bad in (dict(tau=(0.5, 1.0)), dict(G=-1.0), dict(walls=3), dict(precision=7), dict(stream_policy=3),
                 dict(zchunk=12), dict(zchunk=72), dict(ring_len=4, precision=B.LBM_FP16),
                 dict(rep_eps=-0.1), dict(rep_eps=float("nan")), dict(rep_eps=0.5, rep_d0=0.0),
-                dict(rep_eps=0.5, rep_d0=2.5), dict(walls=2, precision=B.LBM_FP16), dict(walls=2, ring_len=4),
+                dict(rep_eps=0.5, rep_d0=2.5), dict(walls=2, ring_len=4),
                 dict(walls=-1)):
         pb = B.make_params(16, 16, 16, **bad)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
@@ -57,7 +57,8 @@ def test_workspace_bytes_and_validation():
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
     # the repulsion's cut-off only matters when it is on; the largest allowed is 2
     for good in (dict(rep_eps=0.0, rep_d0=5.0), dict(rep_eps=0.5, rep_d0=2.0), dict(rep_eps=0.5, ring_len=4),
-                 dict(psi_kind=1), dict(psi_kind=1, ring_len=4), dict(walls=2), dict(walls=1)):
+                 dict(psi_kind=1), dict(psi_kind=1, ring_len=4), dict(walls=2), dict(walls=1),
+                 dict(walls=2, precision=B.LBM_FP16)):
         pb = B.make_params(16, 16, 16, **good)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_OK
     # more than 2^30 nodes cannot be addressed with 32-bit offsets

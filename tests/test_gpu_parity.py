@@ -169,6 +169,26 @@ def test_onsite_channel_with_interface_and_capsule():
     _compare_run(W.onsite_mini(), 100, 5e-6, 1e-5, tol_x=2e-5)
 
 
+def test_onsite_channel_fp16_form():
+    """The FP16 storage form with on-site boundaries: the closure decodes
+    and encodes the populations it reads and writes like the lattice kernels."""
+    from paper_1904_11386_amd.binding import LBM_FP16
+    wl = W.onsite_mini()
+    steps = 100
+    _say("case", wl.name, "fp16", "steps", steps)
+    g = _sim(wl, precision=LBM_FP16)
+    g.step(steps)
+    o = from_workload(wl).run(steps)
+    ra, rb, u = g.fields()
+    ea = _rel(ra, o.rho_last[0].numpy())
+    eb = _rel(rb, o.rho_last[1].numpy())
+    du = float(np.abs(u - o.u_last.numpy()).max())
+    dx = float(np.abs(g.nodes() - torch.cat(o.X, 0).numpy()).max())
+    _say("  rho rel err %.3e %.3e  |du| %.3e  node position err %.3e lu" % (ea, eb, du, dx))
+    assert ea <= 1e-3 and eb <= 1e-3
+    assert du <= 1e-3 and dx <= 1e-3
+
+
 def test_capsule_in_shear_first_steps():
     """The capsule-in-shear workload (48^3, 2562-node capsule, G = 0) against
     the oracle over its first 20 steps."""
