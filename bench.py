@@ -305,7 +305,7 @@ def membrane_extras_leg(torch, warmup=100, steps=200):
     return out
 
 
-def reference_model_leg(torch, steps=240000, chunk=20000, kV=20.0):
+def reference_model_leg(torch, steps=240000, chunk=20000, kV=20.0, beta=1000.0, C=9.0, w=1.0):
     """The LBM-free reference model of Sec. III.B at the paper's particle
     size: R0 = 10 (2562-node mesh), beta = R0^2 gamma / kB = 1000,
     B = kB / (kS R0^2) = 1e-2, nu_s = 0.9 (C = 9), volume modulus kV (20),
@@ -315,11 +315,11 @@ def reference_model_leg(torch, steps=240000, chunk=20000, kV=20.0):
     import numpy as np
     from paper_1904_11386_amd import workloads
     from paper_1904_11386_amd.binding import sim_from_workload
-    R0, gamma, beta, B, mu = 10.0, 0.0388, 1000.0, 1e-2, 0.05
+    R0, gamma, B, mu = 10.0, 0.0388, 1e-2, 0.05
     kB = R0 * R0 * gamma / beta
     kS = kB / (B * R0 * R0)
     ra, rb = workloads.layered(32, 32, 32, 16)
-    cap = workloads.Capsule(workloads._snap(np.array([16.0, 16.0, 16.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
+    cap = workloads.Capsule(workloads._snap(np.array([16.0, 16.0, 16.0])), R0, 16, kS, C, kV, 90.0, kB=kB)
     wl = workloads.Workload("reference", 32, 32, 32, ra, rb, [cap], z_interface=15.5)
     sim = sim_from_workload(wl)
     hist = []
@@ -327,7 +327,7 @@ def reference_model_leg(torch, steps=240000, chunk=20000, kV=20.0):
     for k in range(steps // chunk):
         sim.synchronize()
         t0 = time.perf_counter()
-        sim.reference_relax(chunk, gamma, 1.0, 16.0, mu)
+        sim.reference_relax(chunk, gamma, w, 16.0, mu)
         sim.synchronize()
         t_run += time.perf_counter() - t0
         ax = sim.observables()["caps"][0]["axes"]
@@ -336,8 +336,29 @@ def reference_model_leg(torch, steps=240000, chunk=20000, kV=20.0):
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    return {"workload": "one R0=10 capsule (2562 nodes), beta 1000, B 1e-2, nu_s 0.9, kV %g, gamma 0.0388, w 1, "
-                        "mobility 0.05" % kV, "us_per_step": round(t_run / steps * 1e6, 2), "relaxation": hist}
+    return {"workload": "one R0=10 capsule (2562 nodes), beta %g, B 1e-2, C %g (nu_s %.2f), kV %g, gamma 0.0388, "
+                        "w %g, mobility 0.05" % (beta, C, C / (1.0 + C), kV, w),
+            "us_per_step": round(t_run / steps * 1e6, 2), "relaxation": hist}
+
+
+def reference_sweep_leg(torch, betas=(10.0, 100.0, 1000.0), nus=(0.5, 0.9), ws=(1.0, 4.0), steps=240000):
+    """The reference model's equilibrium over the softness beta, the surface
+    Poisson ratio nu_s (C = nu_s / (1 - nu_s)) and the emulated interface
+    width w (the membrane-only part of the paper's comparison, Sec. III.B):
+    final half-axes r_p and mean r_i, and their change over the last 20 000
+    steps as a convergence measure."""
+    out = []
+    for beta in betas:
+        for nu in nus:
+            for w in ws:
+                print("bench: reference sweep beta %g nu_s %g w %g" % (beta, nu, w), file=sys.stderr, flush=True)
+                r = reference_model_leg(torch, steps=steps, kV=20.0, beta=beta, C=nu / (1.0 - nu), w=w)
+                a, b = r["relaxation"][-2], r["relaxation"][-1]
+                out.append({"beta": beta, "nu_s": nu, "w": w, "r_p": b["r_p"], "r_i": b["r_i_mean"],
+                            "ratio": round(b["r_i_mean"] / b["r_p"], 4),
+                            "last_change": round(max(abs(b["r_p"] - a["r_p"]), abs(b["r_i_mean"] - a["r_i_mean"])), 5)})
+    return {"workload": "one R0=10 capsule (2562 nodes), B 1e-2, kV 20, gamma 0.0388, mobility 0.05, %d steps" % steps,
+            "runs": out}
 
 
 def shape_error_leg(torch, steps=40000, chunk=5000, kV=2.0):
@@ -483,6 +504,8 @@ def main():
     ap.add_argument("--oracle-timing-leg", action="store_true",
                     help="also time the FP64 oracle on the 32^3 case (1000 steps) and the 64^3 cases (50 steps), "
                          "all cores and one thread")
+    ap.add_argument("--reference-sweep-leg", action="store_true",
+                    help="also sweep the reference model over softness, surface Poisson ratio and interface width")
     ap.add_argument("--shear-leg", action="store_true",
                     help="also run the capsule-in-shear workload (on-site boundaries) at five capillary numbers")
     ap.add_argument("--shape-error-leg", action="store_true",
@@ -596,6 +619,8 @@ def main():
         out["shape_error"] = shape_error_leg(torch)
     if args.shear_leg:
         out["shear"] = shear_leg(torch)
+    if args.reference_sweep_leg:
+        out["reference_sweep"] = reference_sweep_leg(torch)
     if args.membrane_extras_leg:
         out["membrane_extras"] = membrane_extras_leg(torch)
     if args.adjoint_fd_sweep:
