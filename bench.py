@@ -361,45 +361,48 @@ def reference_sweep_leg(torch, betas=(10.0, 100.0, 1000.0), nus=(0.5, 0.9), ws=(
             "runs": out}
 
 
-def shape_error_leg(torch, steps=40000, chunk=5000, kV=2.0):
+def shape_error_leg(torch, betas=(100.0, 1000.0), steps=40000, chunk=5000, kV=2.0):
     """The shape errors of Sec. III.B (eq. interface:error) between the
     reference model and the coupled simulation of the same capsule (R0 = 10,
-    2562 nodes, beta 1000, B 1e-2, nu_s 0.9), here immersed-boundary coupled
-    at the flat interface of a 64x64x48 two-component box (G 3.6, theta
-    90 deg) and run to equilibrium.  Delta_p = (r_p^ref - r_p^sim) / R0 and
-    Delta_i = (r_i^ref - r_i^sim) / R0 with r_p the half-axis normal to the
-    interface and r_i the mean of the two in-plane half-axes, both from the
-    volume second moments.  Both sides use the volume modulus kV = 2 (the
+    2562 nodes, B 1e-2, nu_s 0.9, softness beta), here immersed-boundary
+    coupled at the flat interface of a 64x64x48 two-component box (G 3.6,
+    theta 90 deg) and run to equilibrium.  Delta_p = (r_p^ref - r_p^sim) / R0
+    and Delta_i = (r_i^ref - r_i^sim) / R0 with r_p the half-axis normal to
+    the interface and r_i the mean of the two in-plane half-axes, both from
+    the volume second moments.  Both sides use the volume modulus kV = 2 (the
     explicit coupling diverges within 250 steps at kV = 20)."""
-    ref = reference_model_leg(torch, kV=kV)
     import numpy as np
     from paper_1904_11386_amd import workloads
     from paper_1904_11386_amd.binding import sim_from_workload
-    R0, gamma, beta, B = 10.0, 0.0388, 1000.0, 1e-2
-    kB = R0 * R0 * gamma / beta
-    kS = kB / (B * R0 * R0)
-    ra, rb = workloads.layered(64, 64, 48, 24)
-    cap = workloads.Capsule(workloads._snap(np.array([32.0, 32.0, 24.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
-    wl = workloads.Workload("shape_error", 64, 64, 48, ra, rb, [cap], z_interface=23.5)
-    sim = sim_from_workload(wl)
-    hist = []
-    t0 = time.perf_counter()
-    for k in range(steps // chunk):
-        sim.step(chunk)
-        ax = sim.observables()["caps"][0]["axes"]
-        hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5),
-                     "r_i_mean": round(0.5 * float(ax[1] + ax[2]), 5)})
-    sim.synchronize()
-    wall = time.perf_counter() - t0
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
-    fin, rf = hist[-1], ref["relaxation"][-1]
-    return {"workload": "64x64x48 box, interface z=23.5, one R0=10 capsule (2562 nodes), beta 1000, B 1e-2, "
-                        "nu_s 0.9, kV %g, theta 90 deg, G 3.6" % kV,
-            "steps": steps, "wall_s": round(wall, 2), "coupled": hist, "reference": ref["relaxation"][-1],
-            "delta_p": round((rf["r_p"] - fin["r_p"]) / R0, 5),
-            "delta_i": round((rf["r_i_mean"] - fin["r_i_mean"]) / R0, 5)}
+    R0, gamma, B = 10.0, 0.0388, 1e-2
+    out = {"workload": "64x64x48 box, interface z=23.5, one R0=10 capsule (2562 nodes), B 1e-2, nu_s 0.9, kV %g, "
+                       "theta 90 deg, G 3.6" % kV, "steps": steps, "runs": []}
+    for beta in betas:
+        print("bench: shape errors, beta %g" % beta, file=sys.stderr, flush=True)
+        ref = reference_model_leg(torch, kV=kV, beta=beta)
+        kB = R0 * R0 * gamma / beta
+        kS = kB / (B * R0 * R0)
+        ra, rb = workloads.layered(64, 64, 48, 24)
+        cap = workloads.Capsule(workloads._snap(np.array([32.0, 32.0, 24.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
+        wl = workloads.Workload("shape_error", 64, 64, 48, ra, rb, [cap], z_interface=23.5)
+        sim = sim_from_workload(wl)
+        hist = []
+        t0 = time.perf_counter()
+        for k in range(steps // chunk):
+            sim.step(chunk)
+            ax = sim.observables()["caps"][0]["axes"]
+            hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5),
+                         "r_i_mean": round(0.5 * float(ax[1] + ax[2]), 5)})
+        sim.synchronize()
+        wall = time.perf_counter() - t0
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+        fin, rf = hist[-1], ref["relaxation"][-1]
+        out["runs"].append({"beta": beta, "wall_s": round(wall, 2), "coupled": hist, "reference": rf,
+                            "delta_p": round((rf["r_p"] - fin["r_p"]) / R0, 5),
+                            "delta_i": round((rf["r_i_mean"] - fin["r_i_mean"]) / R0, 5)})
+    return out
 
 
 def shear_leg(torch, cas=(0.0125, 0.025, 0.05, 0.1, 0.2), steps=100000, every=10000):
