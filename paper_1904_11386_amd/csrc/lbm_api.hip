@@ -597,9 +597,9 @@ static int check_mass(lbm_ctx* c) {
 // NULL) receives LBM_NK + 1 events: ev[k] is recorded before kernel group k
 // and ev[LBM_NK] after the last.  advect = false leaves the nodes in place
 // (the adjoint's recompute of a step's intermediates).
-// One step.  With `ev` the kernels run in order on one stream with an event
-// before each group (the per-kernel timing), and so they do without
-// `overlap` (the adjoint's recompute).  Otherwise the membrane kernels
+// With `ev` the kernels run in order on one stream with an event before
+// each group (the per-kernel timing), and so they do without `overlap` (the
+// adjoint's recompute).  Otherwise the membrane kernels
 // that read no density of this step (the previous step's advection when it
 // was deferred, tile clearing, volumes, triangle forces, the node gather and
 // the bin sort) run on the side stream beside the density pass and join
@@ -697,7 +697,8 @@ static void enqueue_step(lbm_ctx* c, hipEvent_t* ev, bool defer_interp = false) 
 // Two steps captured as one graph; both leave their advection to the next
 // step, so a graph ends with one pending, and its first step takes over the
 // one pending before it, if any.  The launch arguments depend only on the
-// step parity and the tile-list parity, so four graphs cover every state.
+// step parity, the tile-list parity and that pending advection, so eight
+// graphs cover every state.
 static hipGraphExec_t two_step_graph(lbm_ctx* c) {
     const int sp = (int)(c->step & 1), fp = c->flip, pin = c->interp_pending ? 1 : 0;
     if (c->graph[sp][fp][pin]) return c->graph[sp][fp][pin];
