@@ -13,9 +13,6 @@
 //                   forces per triangle and corner, F = -dE/dX
 //   k_node_gather   sixteen lanes per node: gather its triangles' corner
 //                   forces, count the node into its home bin
-//   k_node_wet      sixteen lanes per wetting node: add the wettability
-//                   reaction (lane (kx, ky) takes a column of the 4x4x4
-//                   delta stencil, psi staged on a 6^3 LDS cube)
 //   k_bin_alloc     disjoint slot runs for the occupied bins (wavefront scan
 //                   plus one global atomic per wavefront)
 //   k_bin_scatter   counting-sort scatter of node ids into the bins; flag
@@ -24,12 +21,14 @@
 //                   curvatures per node, then the cot Laplacian and the force
 //   k_repulse       (when enabled) particle-particle repulsion between nodes
 //                   of different capsules, searched through the bins
-//   k_spread        one workgroup per occupied bin: accumulate F_b delta and
+//   k_spread        one workgroup per occupied bin: add the wettability
+//                   reaction of its nodes (psi staged on a 9^3 LDS cube,
+//                   sixteen lanes per node), accumulate F_b delta and
 //                   the virtual density in 7^3 LDS boxes (one per wavefront,
 //                   one lane per stencil point, no LDS atomics), then flush
 //                   the non-zero cells to HBM with global atomics
 //   k_interp_advect sixteen lanes per node: U_b = sum u delta, X += U_b
-// Only k_node_wet reads the densities of the step: the kernels before it
+// Only k_spread reads the densities of the step: the kernels before it
 // (after the previous step's advection) can overlap the density pass.
 #include "lbm_internal.h"
 
@@ -291,11 +290,11 @@ __global__ __launch_bounds__(256) void k_faces(Dev d, int n_faces) {
     }
 }
 
-// Node forces in two kernels.  k_node_gather sums the corner forces of the
-// incident triangles and counts the node into its home bin (4^3); it reads
-// no density, so it can run beside the density pass.  k_node_wet adds the
-// wettability reaction, which needs this step's densities.  Four nodes per
-// wavefront, sixteen lanes per node, sixteen nodes per block.
+// Node forces: the sum of the corner forces of the incident triangles, and
+// the node's count into its home bin (4^3).  It reads no density, so it can
+// run beside the density pass; the wettability reaction, which needs this
+// step's densities, is added in k_spread.  Four nodes per wavefront, sixteen
+// lanes per node, sixteen nodes per block.
 __global__ __launch_bounds__(256) void k_node_gather(Lattice L, Dev d, int n_nodes, int par) {
     const int lane = threadIdx.x & 63, l16 = lane & 15;
     const int b = blockIdx.x * 16 + wave_id() * 4 + (lane >> 4);
@@ -331,86 +330,6 @@ __global__ __launch_bounds__(256) void k_node_gather(Lattice L, Dev d, int n_nod
         d.node_tile[b] = t;
         d.node_rank[b] = rank;
         if (rank == 0) d.home[par][atomicAdd(&d.counters[CNT_HOME + par], 1)] = t;
-    }
-}
-
-// The reaction of the virtual density on a wetting node (linear in the
-// virtual density for either pseudo-potential):
-// -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i.
-// The node's sixteen lanes stage psi^np on the 6^3 cube floor(X)-2 ..
-// floor(X)+3; lane (kx, ky) takes the stencil column kz = 0..3.
-template <bool PSI>     // the exponential pseudo-potential (a compile-time choice, as in the collide)
-__global__ __launch_bounds__(256) void k_node_wet(Lattice L, Dev d, const float* __restrict__ rho_n,
-                                                  const float* __restrict__ cs, int n_nodes) {
-    constexpr int CB = 6;                       // psi cube edge: stencil plus one-node halo
-    constexpr int C3 = CB * CB * CB;
-    __shared__ float cube[16][C3];
-    const int lane = threadIdx.x & 63, l16 = lane & 15;
-    const int slot = wave_id() * 4 + (lane >> 4);
-    const int b = blockIdx.x * 16 + slot;
-    float* cb = cube[slot];
-    const float wet = b < n_nodes ? d.node_wet[b] : 0.0f;
-    const bool wetting = wet != 0.0f;
-    NodePos p;
-    int pw[3] = {0, 0, 0};
-    if (wetting) {
-        p = node_pos(d, b);
-        wrapped_floor(L, p, pw);
-        const int np = 1 - d.node_anc[b].w;
-        const float* rc = rho_n + (int64_t)np * L.n;
-        const float sc = cs ? cs[np] : 1.0f;      // FP16 form: mass compensation of this step
-#pragma unroll
-        for (int it = 0; it < (C3 + 15) / 16; ++it) {
-            const int j = l16 + 16 * it;
-            if (j < C3) {
-                const int qz = j / (CB * CB), qy = (j / CB) % CB, qx = j % CB;
-                int gyy = wrap3(pw[1] - 2 + qy, L.ny);
-                if (L.walls) gyy = gyy == 0 ? 1 : (gyy == L.ny - 1 ? L.ny - 2 : gyy);
-                // on-site boundaries: beyond the box is the boundary row
-                if (L.onsite) gyy = min(max(pw[1] - 2 + qy, 0), L.ny - 1);
-                const int gzz = wrap3(pw[2] - 2 + qz, L.nz), gxx = wrap3(pw[0] - 2 + qx, L.nx);
-                const float r = sc * rc[(uint32_t)((gzz * L.ny + gyy) * L.nx + gxx)];
-                cb[j] = PSI ? psi_exp(r) : r;     // the pseudo-potential
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    float gx = 0.f, gy = 0.f, gz = 0.f;
-    if (wetting) {
-        const int kx = l16 & 3, ky = l16 >> 2;
-        const float wxy = peskin(p.r[0] + 1.0f - kx) * peskin(p.r[1] + 1.0f - ky);
-        const float s0 = -L.G * wet;
-#pragma unroll
-        for (int kz = 0; kz < 4; ++kz) {
-            const float w = wxy * peskin(p.r[2] + 1.0f - kz);
-            const int c0 = ((kz + 1) * CB + (ky + 1)) * CB + (kx + 1);
-            float S[3] = {0.f, 0.f, 0.f};
-#pragma unroll
-            for (int k = 1; k < Q; k += 2) {
-                const int o = (cz(k) * CB + cy(k)) * CB + cx(k);
-                const float dd = wgt(k) * (cb[c0 + o] - cb[c0 - o]);
-                if (cx(k)) S[0] += cx(k) * dd;
-                if (cy(k)) S[1] += cy(k) * dd;
-                if (cz(k)) S[2] += cz(k) * dd;
-            }
-            const float s = s0 * w;
-            gx += s * S[0];
-            gy += s * S[1];
-            gz += s * S[2];
-        }
-    }
-#pragma unroll
-    for (int o = 8; o > 0; o >>= 1) {
-        gx += __shfl_xor(gx, o, 16);
-        gy += __shfl_xor(gy, o, 16);
-        gz += __shfl_xor(gz, o, 16);
-    }
-    if (wetting && l16 == 0) {
-        d.node_F[3 * b + 0] += gx;
-        d.node_F[3 * b + 1] += gy;
-        d.node_F[3 * b + 2] += gz;
     }
 }
 
@@ -789,25 +708,41 @@ __global__ __launch_bounds__(256) void k_ref_advance(Dev d, int n_nodes, float m
 
 constexpr int SPREAD_GRID = 2048;
 
-__global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
+// Spreading, with the wettability reaction of the wetting nodes added first
+// (it needs this step's densities; the rest of the node force does not).
+// Per occupied bin: stage the bin's nodes; stage the pseudo-potential of both
+// components on the 9^3 cube that the stencils of the bin's nodes and their
+// lattice neighbours reach; add each wetting node's reaction
+// -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i, sixteen
+// nodes at a time with sixteen lanes each (lane (kx, ky) takes the stencil
+// column kz = 0..3), storing the node's total force back; then accumulate
+// F_b delta and the virtual density in the boxes and flush them.
+template <bool PSI>     // the exponential pseudo-potential (a compile-time choice, as in the collide)
+__global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par, const float* __restrict__ rho_n,
+                                                const float* __restrict__ cs) {
     constexpr int B3 = BOX * BOX * BOX;
+    constexpr int WC = BIN + 5;                 // psi cube edge: bin cells -2 .. +6
+    constexpr int W3 = WC * WC * WC;
     constexpr int CH = 128;                     // nodes staged per round
     // one box per wavefront: a wavefront adds its nodes one after another
     // with plain LDS read-modify-writes (the 64 lanes of one node hit
     // distinct cells), which is far cheaper than LDS float atomics; the
     // flush sums the four boxes
     __shared__ float box[4][5][B3];
+    __shared__ float psi[2][W3];
     // the bin's nodes, staged by one thread each: per-axis delta weights,
-    // force, virtual-density weight, the box cell of the stencil origin and
-    // the field the virtual density goes to
+    // force, virtual-density weight, the box and cube cells of the stencil
+    // origin, the field the virtual density goes to and the node id
     __shared__ float sw[12][CH];
     __shared__ float sf[4][CH];
-    __shared__ int scell[CH], sfield[CH];
+    __shared__ int scell[CH], swc[CH], sfield[CH], sid[CH];
     const int nh = d.counters[CNT_HOME + par];
     const int lane = threadIdx.x & 63, wave = wave_id();
     const int kx = lane & 3, ky = (lane >> 2) & 3, kz = lane >> 4;
+    const int l16 = lane & 15, q16 = threadIdx.x >> 4;       // wettability: node slot and lane
     const int64_t N = L.n;
     float* mybox = &box[wave][0][0];
+    const float sc[2] = {cs ? cs[0] : 1.0f, cs ? cs[1] : 1.0f};   // FP16 form: this step's mass compensation
     for (int e = blockIdx.x; e < nh; e += gridDim.x) {
         const int t = d.home[par][e];
         const int start = d.home_start[e], cnt = d.tile_count[t];
@@ -817,6 +752,7 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
         // (the barrier after staging also orders the zeroing above)
         for (int c0 = 0; c0 < cnt; c0 += CH) {
             const int m = min(cnt - c0, CH);
+            int need0 = 0, need1 = 0;           // components whose psi a wetting node reads
             if ((int)threadIdx.x < m) {
                 const int b = d.sorted[start + c0 + threadIdx.x];
                 const NodePos p = node_pos(d, b);
@@ -830,11 +766,72 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par) {
                 sf[1][threadIdx.x] = d.node_F[3 * b + 1];
                 sf[2][threadIdx.x] = d.node_F[3 * b + 2];
                 const float wet = d.node_wet[b];
+                const int pref = d.node_anc[b].w;
+                need0 = wet != 0.0f && pref == 1;   // it reads the component it does not prefer
+                need1 = wet != 0.0f && pref == 0;
                 sf[3][threadIdx.x] = wet;
-                sfield[threadIdx.x] = wet != 0.0f ? 3 + d.node_anc[b].w : -1;
+                sfield[threadIdx.x] = wet != 0.0f ? 3 + pref : -1;
                 scell[threadIdx.x] = ((pw[2] - oz) * BOX + (pw[1] - oy)) * BOX + (pw[0] - ox);
+                swc[threadIdx.x] = ((pw[2] - oz + 1) * WC + (pw[1] - oy + 1)) * WC + (pw[0] - ox + 1);
+                sid[threadIdx.x] = b;
             }
-            __syncthreads();
+            const int n0 = __syncthreads_or(need0) != 0, n1 = __syncthreads_or(need1) != 0;
+            if (n0 || n1) {
+                // (most bins meet one capsule, so one component)
+                for (int k = threadIdx.x; k < (n0 + n1) * W3; k += 256) {
+                    const int c = (k >= W3 || !n0) ? 1 : 0, cell = k >= W3 ? k - W3 : k;
+                    const int iz = cell / (WC * WC), iy = (cell / WC) % WC, ix = cell % WC;
+                    int gy = wrap3(oy - 2 + iy, L.ny);
+                    if (L.walls) gy = gy == 0 ? 1 : (gy == L.ny - 1 ? L.ny - 2 : gy);
+                    if (L.onsite) gy = min(max(oy - 2 + iy, 0), L.ny - 1);
+                    const int gx = wrap3(ox - 2 + ix, L.nx), gz = wrap3(oz - 2 + iz, L.nz);
+                    const float r = sc[c] * rho_n[c * N + (uint32_t)((gz * L.ny + gy) * L.nx + gx)];
+                    psi[c][cell] = PSI ? psi_exp(r) : r;
+                }
+                __syncthreads();
+                for (int j0 = 0; j0 < m; j0 += 16) {
+                    const int j = j0 + q16;
+                    const bool on = j < m && sfield[min(j, m - 1)] >= 0;      // (uniform per sixteen lanes)
+                    const int jj = on ? j : 0;
+                    // an idle group reads from the origin of a node at bin cell
+                    // (1, 1, 1), inside the cube, with zero weight
+                    const int base = on ? swc[jj] : ((2 * WC) + 2) * WC + 2;
+                    const float* qp = psi[on ? 4 - sfield[jj] : 0];        // component np = 1 - (field - 3)
+                    const int qx = l16 & 3, qy = l16 >> 2;
+                    const float wxy = on ? sw[qx][jj] * sw[4 + qy][jj] : 0.0f;
+                    float S[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                    for (int qz = 0; qz < 4; ++qz) {
+                        const float w = wxy * sw[8 + qz][jj];
+                        const int y0 = base + (qz * WC + qy) * WC + qx;
+                        float T[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+                        for (int k = 1; k < Q; k += 2) {
+                            const int o = (cz(k) * WC + cy(k)) * WC + cx(k);
+                            const float dd = wgt(k) * (qp[y0 + o] - qp[y0 - o]);
+                            if (cx(k)) T[0] += cx(k) * dd;
+                            if (cy(k)) T[1] += cy(k) * dd;
+                            if (cz(k)) T[2] += cz(k) * dd;
+                        }
+                        S[0] += w * T[0];
+                        S[1] += w * T[1];
+                        S[2] += w * T[2];
+                    }
+#pragma unroll
+                    for (int o = 8; o > 0; o >>= 1) {
+                        S[0] += __shfl_xor(S[0], o, 16);
+                        S[1] += __shfl_xor(S[1], o, 16);
+                        S[2] += __shfl_xor(S[2], o, 16);
+                    }
+                    if (on && l16 < 3) {
+                        const float s0 = -L.G * sf[3][jj];
+                        const float F = sf[l16][jj] + s0 * (l16 == 0 ? S[0] : (l16 == 1 ? S[1] : S[2]));
+                        sf[l16][jj] = F;
+                        d.node_F[3 * sid[jj] + l16] = F;
+                    }
+                }
+                __syncthreads();
+            }
             for (int j = wave; j < m; j += 4) {
                 const float w = sw[kx][j] * sw[4 + ky][j] * sw[8 + kz][j];
                 const int cell = scell[j] + (kz * BOX + ky) * BOX + kx;
@@ -1253,15 +1250,7 @@ void launch_faces(const Dev& d, int n_faces, hipStream_t s) {
 void launch_node_gather(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0) hipLaunchKernelGGL(k_node_gather, dim3((n_nodes + 15) / 16), dim3(256), 0, s, L, d, n_nodes, par);
 }
-void launch_node_wet(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
-                     hipStream_t s) {
-    if (n_nodes <= 0) return;
-    const dim3 grid((n_nodes + 15) / 16), block(256);
-    if (L.psi_exp)
-        hipLaunchKernelGGL(k_node_wet<true>, grid, block, 0, s, L, d, rho_n, cs, n_nodes);
-    else
-        hipLaunchKernelGGL(k_node_wet<false>, grid, block, 0, s, L, d, rho_n, cs, n_nodes);
-}
+
 void launch_bin_scan(const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0) hipLaunchKernelGGL(k_bin_alloc, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, par);
 }
@@ -1294,8 +1283,11 @@ void launch_reference_step(const Dev& d, int n_nodes, int n_faces, int n_caps, b
     if (bend) launch_bending(d, n_nodes, s);
     hipLaunchKernelGGL(k_ref_advance, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes, mu);
 }
-void launch_spread(const Lattice& L, const Dev& d, int par, hipStream_t s) {
-    hipLaunchKernelGGL(k_spread, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);
+void launch_spread(const Lattice& L, const Dev& d, int par, const float* rho_n, const float* cs, hipStream_t s) {
+    if (L.psi_exp)
+        hipLaunchKernelGGL(k_spread<true>, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par, rho_n, cs);
+    else
+        hipLaunchKernelGGL(k_spread<false>, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par, rho_n, cs);
 }
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s) {
     if (n_nodes > 0)

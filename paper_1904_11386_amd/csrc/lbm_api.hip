@@ -603,7 +603,9 @@ static int check_mass(lbm_ctx* c) {
 // that read no density of this step (the previous step's advection when it
 // was deferred, tile clearing, volumes, triangle forces, the node gather and
 // the bin sort) run on the side stream beside the density pass and join
-// before the wettability reaction.  With `defer_interp` this step's
+// before the optional node terms and the spreading, which adds the
+// wettability reaction (the one membrane term that reads the step's
+// densities).  With `defer_interp` this step's
 // advection is left to the next step's side branch; the caller launches the
 // last one pending before it returns.
 static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, const float* rho_p, bool advect,
@@ -648,7 +650,6 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         launch_compensate(L, d.dpart, c->mass0[0], c->mass0[1], d.cscale, cur, d.dmass, s);
     if (fork) {
         (void)hipStreamWaitEvent(s, c->ev_join, 0);
-        launch_node_wet(L, d, rho_n, cs, c->n_nodes, s);
     } else {
         mark(LBM_K_VOLUME);
         if (ibm) launch_cap_volume(d, c->n_faces, s);
@@ -656,7 +657,6 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         if (ibm) launch_faces(d, c->n_faces, s);
         mark(LBM_K_NODES);
         if (ibm) launch_node_gather(L, d, c->n_nodes, par, s);
-        if (ibm) launch_node_wet(L, d, rho_n, cs, c->n_nodes, s);
         mark(LBM_K_SCAN);
         if (ibm) launch_bin_scan(d, c->n_nodes, par, s);
         mark(LBM_K_SCATTER);
@@ -668,7 +668,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_BEND);
     if (ibm && c->bending) launch_bending(d, c->n_nodes, s);
     mark(LBM_K_SPREAD);
-    if (ibm) launch_spread(L, d, par, s);
+    if (ibm) launch_spread(L, d, par, rho_n, cs, s);
     mark(LBM_K_COLLIDE);
     if (!fout) {
         // the adjoint's recompute stops here: intermediates of the step only

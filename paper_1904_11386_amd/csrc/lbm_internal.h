@@ -175,15 +175,13 @@ void launch_advect_clear(const Lattice& L, Dev& d, int n_nodes, int parity_prev,
 void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s);
 void launch_faces(const Dev& d, int n_faces, hipStream_t s);
 void launch_node_gather(const Lattice& L, const Dev& d, int n_nodes, int parity, hipStream_t s);
-void launch_node_wet(const Lattice& L, const Dev& d, const float* rho_n, const float* cs, int n_nodes,
-                     hipStream_t s);
 void launch_bin_scan(const Dev& d, int n_nodes, int parity, hipStream_t s);
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s);
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s);
 void launch_bending(const Dev& d, int n_nodes, hipStream_t s);
 void launch_reference_step(const Dev& d, int n_nodes, int n_faces, int n_caps, bool bend, float gamma, float w,
                            double z_interface, float mu, hipStream_t s);
-void launch_spread(const Lattice& L, const Dev& d, int parity, hipStream_t s);
+void launch_spread(const Lattice& L, const Dev& d, int parity, const float* rho_n, const float* cs, hipStream_t s);
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s);
 void launch_debug_bins(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
