@@ -198,6 +198,26 @@ def test_capsule_in_shear_first_steps():
     _compare_run(W.shear(0.1), 20, 2e-6, 2.5e-4, tol_x=1e-5)
 
 
+def test_capsule_in_shear_small_deformation_is_linear_in_ca():
+    """In the small-deformation limit the Taylor deformation of a capsule in
+    shear is proportional to the capillary number: at Ca = 0.0125 and 0.025
+    (30 000 steps, three shear times, past the capsule's relaxation time of
+    about 1 000 steps) D / Ca agrees within 5%, and D is small."""
+    ratios = []
+    for ca in (0.0125, 0.025):
+        g = _sim(W.shear(ca))
+        g.step(30000)
+        D = float(g.observables()["caps"][0]["D"])
+        com = g.observables()["caps"][0]["com"]
+        g.close()
+        _say("  Ca %g: D %.5f, D/Ca %.3f, centre %s" % (ca, D, D / ca, np.round(com, 3)))
+        ratios.append(D / ca)
+        # the capsule stays on the centre line of the shear flow
+        assert abs(com[1] - 23.5) < 0.05
+    assert 0.0 < ratios[0] * 0.025 < 0.1
+    assert abs(ratios[0] - ratios[1]) < 0.05 * ratios[0]
+
+
 def test_graph_eager_and_chunked_stepping_agree():
     """Replayed graphs (whose steps leave each advection to the next step's
     side branch), eager steps, odd call sizes, mass-check chunks and a timed
