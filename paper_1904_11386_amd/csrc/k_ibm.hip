@@ -710,8 +710,9 @@ constexpr int SPREAD_GRID = 2048;
 
 // Spreading, with the wettability reaction of the wetting nodes added first
 // (it needs this step's densities; the rest of the node force does not).
-// Per occupied bin: stage the bin's nodes; stage the pseudo-potential of both
-// components on the 9^3 cube that the stencils of the bin's nodes and their
+// Per occupied bin: stage the bin's nodes; stage the pseudo-potential of the
+// components its wetting nodes read (usually one: most bins meet one
+// capsule) on the 9^3 cube that the stencils of the bin's nodes and their
 // lattice neighbours reach; add each wetting node's reaction
 // -G |rho_v| A_b sum_y delta(y - X_b) sum_i w_i psi^np(y + c_i) c_i, sixteen
 // nodes at a time with sixteen lanes each (lane (kx, ky) takes the stencil
