@@ -435,6 +435,37 @@ def shear_leg(torch, cas=(0.0125, 0.025, 0.05, 0.1, 0.2), steps=100000, every=10
     return out
 
 
+def extras_leg(torch, steps=2000):
+    """Short runs of the paths outside the benchmark step, for timing and
+    kernel profiles: the capsule in shear between on-site boundaries (48^3,
+    Ca 0.1, both storage forms), the reference model (20 000 membrane steps),
+    capsules with Helfrich bending (bent, 38x34x36) and with the
+    particle-particle repulsion (pressed, 37x30x33); microseconds per step
+    of each and the per-kernel split of 20 event-timed steps."""
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
+    out = {"steps": steps}
+    runs = (("shear_fp32", workloads.shear(0.1), LBM_FP32), ("shear_fp16", workloads.shear(0.1), LBM_FP16),
+            ("bent", workloads.bent(), LBM_FP32), ("pressed", workloads.pressed(), LBM_FP32))
+    for name, wl, prec in runs:
+        print("bench: extras leg, %s" % name, file=sys.stderr, flush=True)
+        sim = sim_from_workload(wl, precision=prec)
+        sim.step(100)
+        sim.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        wall = time.perf_counter() - t0
+        k = sim.step_timed(20)
+        out[name] = {"us_per_step": round(wall / steps * 1e6, 2),
+                     "kernels_us_per_step": {kk: round(v / 20 * 1e3, 2) for kk, v in k.items() if v > 0}}
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    out["reference"] = reference_model_leg(torch, steps=20000, chunk=10000)["us_per_step"]
+    return out
+
+
 def precision_study(torch, steps):
     """The FP16 g-storage form beside the FP32 form on the 256^3 droplet
     workload (B droplet of radius 60 in A, 64 capsules of 642 nodes on a
@@ -509,6 +540,8 @@ def main():
                          "all cores and one thread")
     ap.add_argument("--reference-sweep-leg", action="store_true",
                     help="also sweep the reference model over softness, surface Poisson ratio and interface width")
+    ap.add_argument("--extras-leg", action="store_true",
+                    help="also time short runs of the on-site boundaries, reference model, bending and repulsion")
     ap.add_argument("--shear-leg", action="store_true",
                     help="also run the capsule-in-shear workload (on-site boundaries) at five capillary numbers")
     ap.add_argument("--shape-error-leg", action="store_true",
@@ -622,6 +655,8 @@ def main():
         out["shape_error"] = shape_error_leg(torch)
     if args.shear_leg:
         out["shear"] = shear_leg(torch)
+    if args.extras_leg:
+        out["extras"] = extras_leg(torch)
     if args.reference_sweep_leg:
         out["reference_sweep"] = reference_sweep_leg(torch)
     if args.membrane_extras_leg:
