@@ -215,13 +215,14 @@ enum {
     LBM_K_DENSITY = 1,  /* density pass over the lattice                   */
     LBM_K_VOLUME = 2,   /* FP64 capsule volumes                            */
     LBM_K_FACES = 3,    /* Skalak + volume forces per triangle             */
-    LBM_K_NODES = 4,    /* node gather, wettability reaction, binning      */
+    LBM_K_NODES = 4,    /* node force gather and home-bin counts           */
     LBM_K_SCAN = 5,     /* scan of the tile bins                           */
     LBM_K_SCATTER = 6,  /* counting-sort scatter                           */
     LBM_K_REPULSE = 7,  /* particle-particle repulsion (rep_eps > 0)       */
     LBM_K_BEND = 8,     /* Helfrich bending forces (some kB > 0)           */
-    LBM_K_SPREAD = 9,   /* LDS-binned spreading                            */
-    LBM_K_COLLIDE = 10, /* fused pull + force + collide over the lattice   */
+    LBM_K_SPREAD = 9,   /* wettability reaction and LDS-binned spreading   */
+    LBM_K_COLLIDE = 10, /* fused pull + force + collide over the lattice,
+                           and the on-site boundary closure (walls = 2)    */
     LBM_K_INTERP = 11,  /* interpolation and node advection                */
     LBM_NK = 12
 };
