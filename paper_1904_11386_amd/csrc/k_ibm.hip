@@ -413,9 +413,12 @@ __global__ __launch_bounds__(256) void k_bin_scatter(Lattice L, Dev d, int n_nod
 // separation from negated differences.  The search range is widened by
 // 1e-3 so that the bins (taken from the hi offsets alone) cover every pair.
 // A capsule's nodes have consecutive ids, so same-capsule candidates are
-// skipped by a range test without loading anything of theirs.
+// skipped by a range test without loading anything of theirs.  The caller
+// takes the candidates sub, sub + nsub, ... of each bin (several lanes
+// sharing one node's search).
 template <typename Fn>
-__device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d, int b, float d0, Fn&& fn) {
+__device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d, int b, float d0, int sub, int nsub,
+                                                 Fn&& fn) {
     const NodePos p = node_pos(d, b);
     int pw[3];
     wrapped_floor(L, p, pw);
@@ -457,7 +460,7 @@ __device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d,
                 const int t = (bins[2][iz] * L.nby + bins[1][iy]) * L.nbx + bins[0][ix];
                 const int cnt = d.tile_count[t];
                 const int start = cnt > 0 ? d.tile_offset[t] : 0;
-                for (int k = 0; k < cnt; ++k) {
+                for (int k = sub; k < cnt; k += nsub) {
                     const int e = d.sorted[start + k];
                     if ((unsigned)e - own0 < own_n) continue;
                     const int4 ae = d.node_anc[e];
@@ -480,19 +483,32 @@ __device__ __forceinline__ void for_each_contact(const Lattice& L, const Dev& d,
 
 // Forward: node b's repulsion, f_b = sum_e m(d) (X_b - X_e) with
 // m(d) = eps (d0 - d)^{3/2} / d, added to its force at X^n.
+// REP_LANES lanes per node, each taking every REP_LANES-th candidate of a
+// bin: crowded contacts (pressed capsules) split over the lanes, while a
+// sparse suspension does not pay the bin search many times over.
+constexpr int REP_LANES = 4;
 __global__ __launch_bounds__(256) void k_repulse(Lattice L, Dev d, int n_nodes, float eps, float d0) {
-    const int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_nodes) return;
+    const int sl = threadIdx.x & (REP_LANES - 1);
+    const int b = blockIdx.x * (256 / REP_LANES) + (int)(threadIdx.x / REP_LANES);
     float F[3] = {0.f, 0.f, 0.f};
-    for_each_contact(L, d, b, d0, [&](int, const float* v, float r2) {
-        const float r = sqrtf(r2), g = d0 - r;
-        const float m = eps * g * sqrtf(g) / r;
-        F[0] += m * v[0];
-        F[1] += m * v[1];
-        F[2] += m * v[2];
-    });
+    if (b < n_nodes)
+        for_each_contact(L, d, b, d0, sl, REP_LANES, [&](int, const float* v, float r2) {
+            const float r = sqrtf(r2), g = d0 - r;
+            const float m = eps * g * sqrtf(g) / r;
+            F[0] += m * v[0];
+            F[1] += m * v[1];
+            F[2] += m * v[2];
+        });
 #pragma unroll
-    for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] += F[a];
+    for (int o = REP_LANES / 2; o > 0; o >>= 1) {
+        F[0] += __shfl_xor(F[0], o, REP_LANES);
+        F[1] += __shfl_xor(F[1], o, REP_LANES);
+        F[2] += __shfl_xor(F[2], o, REP_LANES);
+    }
+    if (b < n_nodes && sl == 0) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d.node_F[3 * b + a] += F[a];
+    }
 }
 
 // Adjoint: with J = dF_b/dX_b = m I + (m'(d) / d) v v^T (symmetric) and
@@ -503,7 +519,7 @@ __global__ __launch_bounds__(256) void k_adj_repulse(Lattice L, Dev d, int n_nod
     if (b >= n_nodes) return;
     const float lb[3] = {d.lam_Fb[3 * b], d.lam_Fb[3 * b + 1], d.lam_Fb[3 * b + 2]};
     float acc[3] = {0.f, 0.f, 0.f};
-    for_each_contact(L, d, b, d0, [&](int e, const float* v, float r2) {
+    for_each_contact(L, d, b, d0, 0, 1, [&](int e, const float* v, float r2) {
         const float r = sqrtf(r2), g = d0 - r, sg = sqrtf(g);
         const float m = eps * g * sg / r;
         const float mp = -eps * (1.5f * sg / r + g * sg / r2);
@@ -1261,7 +1277,8 @@ void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hi
 }
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
     if (n_nodes > 0)
-        hipLaunchKernelGGL(k_repulse, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, eps, d0);
+        hipLaunchKernelGGL(k_repulse, dim3((n_nodes + 256 / REP_LANES - 1) / (256 / REP_LANES)), dim3(256), 0, s, L, d,
+                           n_nodes, eps, d0);
 }
 void launch_adj_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
     if (n_nodes > 0)
