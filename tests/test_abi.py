@@ -88,3 +88,33 @@ def test_no_cpu_fallback_when_library_missing(tmp_path):
     from paper_1904_11386_amd import binding as B
     with pytest.raises(RuntimeError, match="not built"):
         B.load(str(tmp_path / "liblbm.so"))
+
+
+def test_every_entry_point_rejects_a_null_context():
+    """Each call that takes a context returns LBM_EINVAL for NULL before it
+    touches anything (no device work), and destroying NULL is a no-op."""
+    from paper_1904_11386_amd import binding as B
+    lib = B.load()
+    null = None
+    calls = {
+        "lbm_capsules_add": (null, 0, None, None, None, None, None, None, None, None, None),
+        "lbm_capsules_bending": (null, 0, 0, None),
+        "lbm_reference_relax": (null, 1, 0.01, 1.0, 0.0, 0.05),
+        "lbm_step": (null, 1),
+        "lbm_step_timed": (null, 1, None),
+        "lbm_observables": (null, None, None),
+        "lbm_get_fields": (null, None, None, None),
+        "lbm_get_nodes": (null, None),
+        "lbm_get_node_forces": (null, None),
+        "lbm_get_spread": (null, None, None),
+        "lbm_debug_bins": (null, None, None),
+        "lbm_state_save": (null, 0),
+        "lbm_state_load": (null, 0),
+        "lbm_adjoint_forward": (null, 1, 1, 0, 0, None),
+        "lbm_adjoint_backward": (null, None),
+    }
+    for name, args in calls.items():
+        assert getattr(lib, name)(*args) == B.LBM_EINVAL, name
+    lib.lbm_destroy(None)
+    assert lib.lbm_last_error(None) is not None
+
