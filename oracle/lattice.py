@@ -9,7 +9,11 @@ adjacent pairs.  The paper fixes only the three groups and their weights
 Pins (tests/test_oracle_lattice.py): equilibrium moments (mass, momentum,
 momentum flux) exactly; shear-wave decay against the closed form with
 nu = c_s^2 (tau - 1/2); half-way bounce-back Couette profile; Shan-Chen
-force sums to zero in a periodic box; flat interface stays flat; bulk
+force sums to zero in a periodic box; with two relaxation times the
+collision's momentum change summed over the components equals the summed
+force exactly, and without force the total momentum is conserved (which
+fixes the tau-weighted common velocity and the tau_c in the shift);
+flat interface stays flat; bulk
 densities move toward the mean-field coexistence values; the on-site
 velocity closure gives the boundary node the wall velocity exactly, keeps
 a fluid at rest at rest, and its steady Couette profile is the exact

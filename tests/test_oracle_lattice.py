@@ -208,3 +208,56 @@ def test_shan_chen_force_on_a_linear_pseudo_potential():
     F = shan_chen_force(pseudo_potential(rhoA, 1), S, G)
     ref = -G * (1.0 - torch.exp(-rhoA[:, :, inner])) * beta / 3.0
     assert torch.allclose(F[0, :, :, inner], ref, rtol=1e-13, atol=0)
+
+
+def test_unequal_tau_collision_momentum_change_equals_force():
+    """Force as a shift of the equilibrium velocity with two relaxation
+    times (Sec. II.A; Sec. II.D, eq. method:shanchen): the collision keeps
+    each component's mass, and the momentum it adds, summed over the
+    components, is exactly the summed force sum_c F^c, for any tau_c.  The
+    common velocity u' must be the tau-weighted one and the shift of each
+    component must carry its own tau_c for this to hold: with tau_c left out
+    of the shift the change is sum_c F^c / tau_c, and with an unweighted u'
+    an extra sum_c (rho^c u' - j^c) / tau_c appears."""
+    g = torch.Generator().manual_seed(11)
+    shp = (2, 19, 3, 4, 5)
+    f = 0.002 + 0.05 * torch.rand(shp, generator=g, dtype=DT)
+    rho, j = L.moments(f)
+    F = 1e-3 * (torch.rand(2, 3, 3, 4, 5, generator=g, dtype=DT) - 0.5)
+    for tau in ((0.7, 1.3), (0.8, 1.3), (1.3, 0.55)):
+        fs = L.collide(f, rho, j, F, tau)
+        assert torch.allclose(fs.sum(1), rho, rtol=1e-14, atol=0)
+        dp = torch.einsum("id,cizyx->dzyx", L.CF, fs - f)
+        ref = F[0] + F[1]
+        err = float((dp - ref).abs().max())
+        # rounding acts on the momenta themselves (|j| ~ 0.1 here, |F| ~ 5e-4)
+        scale = float(j.abs().max()) + float(ref.abs().max())
+        assert err < 1e-14 * scale, (tau, err)
+        # each component alone does not receive its own force: the shares
+        # are exchanged through u' when the densities differ
+        dpa = torch.einsum("id,izyx->dzyx", L.CF, fs[0] - f[0])
+        assert float((dpa - F[0]).abs().max()) > 1e-6
+
+
+def test_unequal_tau_without_force_conserves_total_momentum():
+    """With G = 0 and no capsules the two components exchange momentum only
+    through the common velocity u' of Sec. II.A, so with tau_A != tau_B the
+    total momentum of a periodic box is conserved exactly (to rounding) only
+    when u' is the tau-weighted mean sum_c (j^c / tau_c) / sum_c (rho^c / tau_c);
+    each component's own momentum does change."""
+    g = torch.Generator().manual_seed(12)
+    nz, ny, nx = 5, 4, 6
+    ra = 0.05 + 0.7 * torch.rand(nz, ny, nx, generator=g, dtype=DT)
+    rb = 0.05 + 0.7 * torch.rand(nz, ny, nx, generator=g, dtype=DT)
+    ua = 0.02 * (torch.rand(3, nz, ny, nx, generator=g, dtype=DT) - 0.5)
+    ub = 0.02 * (torch.rand(3, nz, ny, nx, generator=g, dtype=DT) - 0.5)
+    s = OracleSim(ra, rb, [], tau=(0.7, 1.3), G=0.0)
+    s.fpost = torch.stack([L.equilibrium(ra, ua), L.equilibrium(rb, ub)], 0)
+    p0 = s.momentum().clone()
+    pa0 = torch.einsum("id,izyx->d", L.CF, s.fpost[0]).clone()
+    s.run(30)
+    scale = float(s.fpost.sum())
+    assert float((s.momentum() - p0).abs().max()) < 1e-15 * scale
+    pa = torch.einsum("id,izyx->d", L.CF, s.fpost[0])
+    assert float((pa - pa0).abs().max()) > 1e-4 * float(p0.abs().max() + 1e-30) or \
+        float((pa - pa0).abs().max()) > 1e-6
