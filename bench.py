@@ -1,11 +1,16 @@
 """Benchmark of the coupled capsule lattice Boltzmann step on one MI355X.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--gpus 1]
+    python bench.py [--steps K] [--warmup W] [--workload c5] [--gpus 1]
 
 Prints one JSON line.  A step is one full coupled time step (density pass,
 membrane forces, binning, spreading, fused collide-stream, interpolation and
-advection) over the whole lattice.  `value` is MLUPS = lattice nodes x
-steps / wall time of the timed region, with all state resident in HBM.
+advection) over the whole lattice.  The headline workload is the largest
+configuration, the 512^3 periodic box with 512 capsules; `value` is its
+MLUPS in FP32 storage = lattice nodes x steps / wall time of the timed
+region, with all state resident in HBM.  The FP16-storage form runs on the
+same workload (`fp16_form`); legs follow on the 256^3 droplet (FP16/FP32
+ratio), the 128^3 box, the sheared channel (adjoint cost and its check
+against central differences) and the FP64 oracle on the host.
 
 roofline: the fused collide-stream kernel dominates; its achieved bandwidth
 is the algorithmic bytes per launch (152 B population reads + 152 B
@@ -13,7 +18,8 @@ population writes + 8 B density reads per lattice node, FP32) over its
 average duration from HIP events recorded on the library's stream around
 each launch, in a second timed region of the same number of steps run
 right after the first (the first replays HIP graphs, which carry no
-per-kernel events).
+per-kernel events).  traffic: HBM bytes per launch from the committed
+rocprofv3 counter summary of the same kernel and workload.
 
 cpu_baseline: the FP64 oracle (test infrastructure) timed on this host on a
 bounded sample of the same workload.
@@ -44,28 +50,38 @@ WORKLOAD_TEXT = {
     "c5": "512^3 periodic two-component box, flat interface at z=256, 512 capsules of 162/642/2562 "
           "nodes (R 4/6/10), theta~U[60,120] deg, tau=1, G=3.6",
     "c1": "32^3 periodic box, flat interface, one R=6 capsule (642 nodes)",
+    "c3": "256^3 periodic box, B droplet R=60 in A, 64 capsules R=6 (642 nodes) on a shell of radius 66, "
+          "theta~U[45,135] deg, tau=1, G=3.6",
 }
 
 
-def measured_traffic():
-    """HBM bytes per k_collide launch (FP32, c2) from the committed rocprofv3
-    PMC summary, or None when the kernel source changed since it was taken."""
-    import hashlib
-    path = os.path.join(ROOT, "profiles", "k_collide_c2_pmc.md")
+def measured_traffic(workload, form):
+    """HBM bytes per k_collide launch of one storage form on one workload from
+    the committed rocprofv3 counter summary profiles/k_collide_<workload>_pmc.md,
+    or None when there is none or the lattice kernel sources changed since
+    the counters were taken."""
+
+    path = os.path.join(ROOT, "profiles", "k_collide_%s_pmc.md" % workload)
     if not os.path.exists(path):
         return None
     rec = {}
     for line in open(path):
-        if line.startswith("traffic_bytes_per_launch k_collide:"):
+        if line.startswith("traffic_bytes_per_launch k_collide %s:" % form):
             rec["bytes"] = float(line.split(":")[1])
         if line.startswith("source_sha256_16:"):
             rec["sha"] = line.split(":")[1].strip()
+    if rec.get("sha") != lattice_source_hash():
+        return None
+    return rec.get("bytes")
+
+
+def lattice_source_hash():
+    """First 16 hex digits of the SHA-256 of the lattice kernels' sources."""
+    import hashlib
     h = hashlib.sha256()
     for f in ("paper_1904_11386_amd/csrc/k_fluid.hip", "paper_1904_11386_amd/csrc/lbm_internal.h"):
         h.update(open(os.path.join(ROOT, f), "rb").read())
-    if rec.get("sha") != h.hexdigest()[:16]:
-        return None
-    return rec.get("bytes")
+    return h.hexdigest()[:16]
 
 
 def copy_ceiling(torch, nbytes=1 << 30, reps=10):
@@ -88,14 +104,29 @@ def copy_ceiling(torch, nbytes=1 << 30, reps=10):
     return gbs
 
 
+def host_threads():
+    """Threads the oracle runs on: torch's default, which follows the
+    environment's OpenMP setting (the host cores given to this job), and the
+    number of cores this process may run on."""
+    import torch
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    return torch.get_num_threads(), aff
+
+
 def cpu_baseline(wl, budget_s=20.0):
-    """Time the FP64 oracle on a bounded sample of the same workload."""
+    """Time the FP64 oracle on a bounded sample of the same workload: the
+    whole lattice when it has at most 128^3 nodes, else a 128 x 128 x 64 box
+    of its initial state around the interface with the capsules that lie
+    wholly inside it."""
     import torch
     from oracle.sim import from_workload
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    cores = max(1, min(cores, 16))
-    torch.set_num_threads(cores)
-    o = from_workload(wl)
+    from paper_1904_11386_amd import workloads
+    sample = wl
+    if wl.n_lattice > 128 ** 3:
+        z0 = int(min(max(wl.z_interface - 31.5, 0), wl.nz - 64))
+        sample = workloads.crop(wl, 0, 0, z0, 128, 128, 64)
+    threads, aff = host_threads()
+    o = from_workload(sample)
     o.step()                    # first step pays allocation
     t0 = time.perf_counter()
     n = 0
@@ -112,11 +143,11 @@ def cpu_baseline(wl, budget_s=20.0):
     o.step()
     el1 = time.perf_counter() - t1
     torch.set_num_threads(used)
-    return {"value": wl.n_lattice * n / el / 1e6, "unit": "MLUPS", "cores": used,
-            "kind": "oracle", "value_1_thread": wl.n_lattice / el1 / 1e6,
-            "sample": "%d FP64 oracle steps of the benchmark workload (%dx%dx%d, %d capsules) after one "
-                      "untimed step, %.1f s; then one step on one thread, %.1f s"
-                      % (n, wl.nx, wl.ny, wl.nz, len(wl.capsules), el, el1)}
+    return {"value": sample.n_lattice * n / el / 1e6, "unit": "MLUPS", "cores": used, "affinity_cores": aff,
+            "kind": "oracle", "value_1_thread": sample.n_lattice / el1 / 1e6,
+            "sample": "%d FP64 oracle steps of a %dx%dx%d box of the benchmark workload (%d capsules wholly "
+                      "inside) after one untimed step, %.1f s; then one step on one thread, %.1f s"
+                      % (n, sample.nx, sample.ny, sample.nz, len(sample.capsules), el, el1)}
 
 
 def oracle_timing_leg():
@@ -127,9 +158,8 @@ def oracle_timing_leg():
     import torch
     from oracle.sim import from_workload
     from paper_1904_11386_amd import workloads
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    cores = max(1, min(cores, 16))
-    out = {"cores": cores}
+    cores, aff = host_threads()
+    out = {"cores": cores, "affinity_cores": aff}
     for name, steps in (("c1", 1000), ("c2_64", 50), ("c3_64", 50)):
         wl = workloads.make(name)
         row = {"steps": steps}
@@ -233,41 +263,6 @@ def adjoint_fd_sweep(torch, steps=2000, every=100):
                          "noise_rel": math.sqrt(2.0) * noise / (2 * h) / abs(fd)})
         best = min(rows, key=lambda r: r["rel_diff"])
         out[name] = {"sweep": rows, "plateau_rel_diff": best["rel_diff"], "plateau_h": best["h"]}
-    return out
-
-
-def scale_leg(torch, warmup=100, steps=200):
-    """The throughput-at-scale configuration: 512^3 periodic box, flat
-    interface at z=256, 512 capsules (thirds of 162/642/2562 nodes, radii
-    4/6/10), angles in [60, 120] deg; both storage forms, `steps` graph-replayed
-    steps after `warmup`, with the collide kernel's algorithmic HBM rate."""
-    from paper_1904_11386_amd import workloads
-    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
-    wl = workloads.make("c5")
-    N = wl.n_lattice
-    out = {"workload": "512^3 periodic two-component box, interface at z=256, 512 capsules (162/642/2562 nodes, "
-                       "R=4/6/10), theta~U[60,120] deg", "warmup": warmup, "steps": steps}
-    for name, prec in (("fp32", LBM_FP32), ("fp16", LBM_FP16)):
-        print("bench: 512^3 leg, %s form" % name, file=sys.stderr, flush=True)
-        sim = sim_from_workload(wl, precision=prec)
-        sim.step(warmup)
-        sim.synchronize()
-        t0 = time.perf_counter()
-        sim.step(steps)
-        sim.synchronize()
-        wall = time.perf_counter() - t0
-        k = sim.step_timed(20)
-        t_col = k["collide"] / 20 * 1e-3
-        m = N * steps / wall / 1e6
-        out[name] = {"mlups": round(m, 1), "ms_per_step": round(wall / steps * 1e3, 4),
-                     "collide_gbs": round(COLLIDE_BYTES_PER_LUP[name] * N / t_col / 1e9, 1),
-                     "effective_hbm_frac": round(m * 1e6 * (COLLIDE_BYTES_PER_LUP[name] + DENSITY_BYTES_PER_LUP[name])
-                                                 / 1e9 / HBM_PEAK_GBS, 4),
-                     "kernels_ms_per_step": {kk: round(v / 20, 5) for kk, v in k.items()}}
-        sim.close()
-        del sim
-        torch.cuda.empty_cache()
-    out["fp16_over_fp32"] = round(out["fp16"]["mlups"] / out["fp32"]["mlups"], 3)
     return out
 
 
@@ -522,22 +517,84 @@ def precision_study(torch, steps):
     return out
 
 
+def run_form(torch, wl, form, warmup, steps, traffic=None):
+    """`steps` graph-replayed whole steps of one storage form after `warmup`,
+    then the same number of event-timed steps for the per-kernel split.
+    Returns MLUPS, ms per step, per-kernel ms per step, and the roofline block
+    of the fused collide kernel: its algorithmic bytes per launch over its
+    average launch duration (HIP events on the library's stream)."""
+    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
+    N = wl.n_lattice
+    sim = sim_from_workload(wl, precision=LBM_FP16 if form == "fp16" else LBM_FP32)
+    sim.step(warmup)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kms = sim.step_timed(steps)
+    obs = sim.observables()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    mlups = N * steps / wall / 1e6
+    t_col = kms["collide"] / steps * 1e-3
+    t_den = kms["density"] / steps * 1e-3
+    bpl = COLLIDE_BYTES_PER_LUP[form]
+    achieved = bpl * N / t_col / 1e9
+    m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
+    return {
+        "mlups": round(mlups, 2), "ms_per_step": round(wall / steps * 1e3, 5), "wall_s": wall,
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                     "kernel": "k_collide (%s storage)" % form, "bytes_per_launch": bpl * N,
+                     "bytes_per_lup": bpl, "avg_launch_ms": round(t_col * 1e3, 5)},
+        "density_pass_gbs": round(DENSITY_BYTES_PER_LUP[form] * N / t_den / 1e9, 1),
+        # whole step: MLUPS times the two lattice passes' algorithmic bytes, over the peak
+        "effective_hbm_frac": round(mlups * 1e6 * (bpl + DENSITY_BYTES_PER_LUP[form]) / 1e9 / HBM_PEAK_GBS, 4),
+        "fp64_mass_drift": float(np.abs(obs["mass"] / m0 - 1).max()),
+        "kernels_ms_per_step": {k: round(v / steps, 5) for k, v in kms.items()},
+    }
+
+
+def ratio_leg(torch, name, warmup, steps):
+    """Both storage forms of one workload, same step counts: MLUPS, collide
+    bandwidth and the FP16/FP32 ratio."""
+    from paper_1904_11386_amd import workloads
+    wl = workloads.make(name)
+    out = {"workload": WORKLOAD_TEXT.get(name, name), "lattice": [wl.nx, wl.ny, wl.nz],
+           "capsules": len(wl.capsules), "warmup": warmup, "steps": steps}
+    for form in ("fp32", "fp16"):
+        print("bench: %s leg, %s form" % (name, form), file=sys.stderr, flush=True)
+        r = run_form(torch, wl, form, warmup, steps)
+        out[form] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
+                     "collide_gbs": r["roofline"]["achieved"], "collide_frac": r["roofline"]["frac"],
+                     "effective_hbm_frac": r["effective_hbm_frac"], "kernels_ms_per_step": r["kernels_ms_per_step"]}
+    out["fp16_over_fp32"] = round(out["fp16"]["mlups"] / out["fp32"]["mlups"], 3)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=300)
-    ap.add_argument("--warmup", type=int, default=30)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp16"])
-    ap.add_argument("--no-fp16-leg", action="store_true")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="c5",
+                    help="headline workload (default: the 512^3 throughput-at-scale configuration)")
+    ap.add_argument("--forms", default="both", choices=["both", "fp32", "fp16"],
+                    help="storage forms of the headline workload (fp32 alone for counter runs of one kernel)")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline workload's storage forms (for profiling that configuration)")
+    ap.add_argument("--no-c3-leg", action="store_true", help="skip the 256^3 FP16/FP32 leg")
+    ap.add_argument("--no-c2-leg", action="store_true", help="skip the 128^3 leg")
     ap.add_argument("--no-adjoint-leg", action="store_true")
+    ap.add_argument("--no-fd-sweep", action="store_true",
+                    help="skip the full-size adjoint check against FP32 central differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-scale-leg", action="store_true", help="skip the 512^3 FP32/FP16 leg")
-    ap.add_argument("--scale-only", action="store_true",
-                    help="run only the 512^3 FP32/FP16 leg and print it (for profiling that configuration)")
     ap.add_argument("--oracle-timing-leg", action="store_true",
-                    help="also time the FP64 oracle on the 32^3 case (1000 steps) and the 64^3 cases (50 steps), "
-                         "all cores and one thread")
+                    help="also time the FP64 oracle on the 32^3 case (1000 steps) and the 64^3 cases (50 steps)")
     ap.add_argument("--reference-sweep-leg", action="store_true",
                     help="also sweep the reference model over softness, surface Poisson ratio and interface width")
     ap.add_argument("--extras-leg", action="store_true",
@@ -551,8 +608,6 @@ def main():
                     help="also relax a capsule with the LBM-free reference model (no fluid)")
     ap.add_argument("--membrane-extras-leg", action="store_true",
                     help="also run the 512^3 configuration with bending and particle-particle repulsion on")
-    ap.add_argument("--adjoint-fd-sweep", action="store_true",
-                    help="also check the full-size adjoint against FP32 central differences over a sweep of h")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="also run the FP16/FP32 precision study on the 256^3 droplet for STEPS steps")
     args = ap.parse_args()
@@ -563,92 +618,54 @@ def main():
 
     import torch
     from paper_1904_11386_amd import workloads
-    from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
 
-    if args.scale_only:
-        print(json.dumps({"scale_512": scale_leg(torch, warmup=args.warmup, steps=args.steps)}), flush=True)
-        return
     wl = workloads.make(args.workload)
     print("bench: workload %s %dx%dx%d, %d capsules, %d nodes" %
           (args.workload, wl.nx, wl.ny, wl.nz, len(wl.capsules), int(wl.meshes()[0].sum())),
           file=sys.stderr, flush=True)
     copy_gbs = copy_ceiling(torch)
-    prec = LBM_FP16 if args.precision == "fp16" else LBM_FP32
-    sim = sim_from_workload(wl, precision=prec)
-    sim.step(args.warmup)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    # timed region: K whole steps as the library runs them (graph replay)
-    t0 = time.perf_counter()
-    sim.step(args.steps)
-    sim.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    # second timed region of the same length: HIP events on the library's
-    # stream around every kernel launch give each kernel's average duration
-    kms = sim.step_timed(args.steps)
-    N = wl.n_lattice
-    mlups = N * args.steps / wall / 1e6
-    obs = sim.observables()
-    m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
-    mass_drift = float(np.abs(obs["mass"] / m0 - 1).max())
-
-    t_col = kms["collide"] / args.steps * 1e-3
-    t_den = kms["density"] / args.steps * 1e-3
-    bpl = COLLIDE_BYTES_PER_LUP[args.precision]
-    achieved = bpl * N / t_col / 1e9
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic() if (args.workload == "c2" and args.precision == "fp32") else None,
-            "kernel": "k_collide", "bytes_per_launch": bpl * N, "avg_launch_ms": round(t_col * 1e3, 5)}
+    forms = ("fp32", "fp16") if args.forms == "both" else (args.forms,)
+    res = {}
+    for form in forms:
+        print("bench: %s, %s form, %d warm-up + %d timed steps" % (args.workload, form, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        res[form] = run_form(torch, wl, form, args.warmup, args.steps,
+                             traffic=measured_traffic(args.workload, form))
+    head = res[forms[0]]
     out = {
-        "metric": METRIC, "value": round(mlups, 2), "unit": "MLUPS", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall / args.steps * 1e3, 5),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "storage": "f16 (g = f/rho - w)" if args.precision == "fp16" else "f32",
+        "metric": METRIC, "value": head["mlups"], "unit": "MLUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "storage": "f16 (g = f/rho - w)" if forms[0] == "fp16" else "f32",
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
                    "lattice": [wl.nx, wl.ny, wl.nz], "capsules": len(wl.capsules),
-                   "membrane_nodes": int(wl.meshes()[0].sum()), "precision": args.precision},
-        "roofline": roof,
-        "kernels_ms_per_step": {k: round(v / args.steps, 5) for k, v in kms.items()},
-        "density_pass_gbs": round(DENSITY_BYTES_PER_LUP[args.precision] * N / t_den / 1e9, 1),
+                   "membrane_nodes": int(wl.meshes()[0].sum()), "storage": forms[0]},
+        "roofline": head["roofline"],
+        "kernels_ms_per_step": head["kernels_ms_per_step"],
+        "density_pass_gbs": head["density_pass_gbs"],
         "copy_ceiling_gbs": round(copy_gbs, 1),
-        "collide_frac_of_copy": round(achieved / copy_gbs, 4),
-        # whole step: MLUPS times the two lattice passes' algorithmic bytes, over the peak
-        "effective_hbm_frac": round(mlups * 1e6 * (bpl + DENSITY_BYTES_PER_LUP[args.precision]) / 1e9 / HBM_PEAK_GBS, 4),
-        "fp64_mass_drift": mass_drift,
+        "collide_frac_of_copy": round(head["roofline"]["achieved"] / copy_gbs, 4),
+        "effective_hbm_frac": head["effective_hbm_frac"],
+        "fp64_mass_drift": head["fp64_mass_drift"],
     }
-    sim.close()
-    del sim
-    torch.cuda.empty_cache()
-    if args.precision == "fp32" and not args.no_fp16_leg:
-        # the FP16-storage form on the same workload, same step count
-        s16 = sim_from_workload(wl, precision=LBM_FP16)
-        s16.step(args.warmup)
-        s16.synchronize()
-        t0 = time.perf_counter()
-        s16.step(args.steps)
-        s16.synchronize()
-        w16 = time.perf_counter() - t0
-        k16 = s16.step_timed(args.steps)
-        t16 = k16["collide"] / args.steps * 1e-3
-        a16 = COLLIDE_BYTES_PER_LUP["fp16"] * N / t16 / 1e9
-        m16 = N * args.steps / w16 / 1e6
-        out["fp16_form"] = {"value": round(m16, 2), "unit": "MLUPS",
-                            "effective_hbm_frac": round(m16 * 1e6 * (COLLIDE_BYTES_PER_LUP["fp16"] + DENSITY_BYTES_PER_LUP["fp16"])
-                                                        / 1e9 / HBM_PEAK_GBS, 4),
-                            "ms_per_step": round(w16 / args.steps * 1e3, 5),
-                            "ratio_vs_fp32": round(wall / w16, 3),
-                            "collide_gbs": round(a16, 1), "collide_frac": round(a16 / HBM_PEAK_GBS, 4),
-                            "kernels_ms_per_step": {k: round(v / args.steps, 5) for k, v in k16.items()}}
-        s16.close()
-        del s16
-        torch.cuda.empty_cache()
-    if args.precision == "fp32" and not args.no_adjoint_leg:
-        out["adjoint"] = adjoint_leg(torch)
-    if args.precision == "fp32" and not args.no_scale_leg:
-        out["scale_512"] = scale_leg(torch)
+    if "fp16" in res and forms[0] == "fp32":
+        r16 = res["fp16"]
+        out["fp16_form"] = {"value": r16["mlups"], "unit": "MLUPS", "ms_per_step": r16["ms_per_step"],
+                            "ratio_vs_fp32": round(r16["mlups"] / head["mlups"], 3),
+                            "roofline": r16["roofline"], "density_pass_gbs": r16["density_pass_gbs"],
+                            "effective_hbm_frac": r16["effective_hbm_frac"],
+                            "fp64_mass_drift": r16["fp64_mass_drift"],
+                            "kernels_ms_per_step": r16["kernels_ms_per_step"]}
+    if not args.headline_only:
+        if not args.no_c3_leg and args.workload != "c3":
+            out["c3_leg"] = ratio_leg(torch, "c3", 50, 200)
+        if not args.no_c2_leg and args.workload != "c2":
+            out["c2_leg"] = ratio_leg(torch, "c2", 30, 300)
+        if not args.no_adjoint_leg:
+            out["adjoint"] = adjoint_leg(torch)
+            if not args.no_fd_sweep:
+                out["adjoint_fd_sweep"] = adjoint_fd_sweep(torch)
     if args.reference_model_leg:
         out["reference_model"] = reference_model_leg(torch)
     if args.shape_error_leg:
@@ -661,13 +678,11 @@ def main():
         out["reference_sweep"] = reference_sweep_leg(torch)
     if args.membrane_extras_leg:
         out["membrane_extras"] = membrane_extras_leg(torch)
-    if args.adjoint_fd_sweep:
-        out["adjoint_fd_sweep"] = adjoint_fd_sweep(torch)
     if args.precision_study > 0:
         out["precision_study"] = precision_study(torch, args.precision_study)
     if args.oracle_timing_leg:
         out["oracle_timing"] = oracle_timing_leg()
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not args.headline_only:
         print("bench: timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl)
     print(json.dumps(out), flush=True)

@@ -41,8 +41,9 @@
  *     copied, never retained.  The library owns only the host context,
  *     freed by lbm_destroy.
  *   - Streams: all device work is enqueued on the HIP stream given to
- *     lbm_init (NULL = the null stream).  Only lbm_observables, lbm_get_*,
- *     lbm_debug_* and lbm_adjoint_grads synchronise that stream.
+ *     lbm_init (NULL = the null stream).  lbm_observables, lbm_get_*,
+ *     lbm_debug_*, lbm_step_timed and the adjoint calls marked so
+ *     synchronise that stream.
  *   - Lattice arrays are [z][y][x] with x fastest; nodes are (x, y, z)
  *     triples in lattice units; angles are degrees.
  *   - D3Q19 direction order: 0 rest; 1..6 = +x -x +y -y +z -z; 7..18 =
@@ -139,15 +140,21 @@ typedef struct lbm_capsule_obs {
 
 typedef struct lbm_ctx lbm_ctx;
 
-/* Size query.  *bytes receives the device workspace size for a lattice p
- * with room for max_nodes membrane nodes and max_faces triangles in total.
- * Host-only, no device work.  LBM_EINVAL on a bad p or negative sizes. */
+/* Size query (no passage of the paper: the library's own memory contract,
+ * one caller-owned device block holding the whole state).  *bytes receives
+ * the device workspace size for a lattice p with room for max_nodes
+ * membrane nodes and max_faces triangles in total.  Host-only, no device
+ * work.  LBM_EINVAL on a bad p or negative sizes. */
 int lbm_workspace_bytes(const lbm_params* p, int64_t max_nodes, int64_t max_faces,
                         int64_t* bytes);
 
-/* Create a context.  rhoA, rhoB: host float arrays of nx*ny*nz initial
- * densities (> 0 on fluid nodes).  The populations start as the rest
- * equilibrium w_i rho (u = 0) and are streamed by the first step.
+/* Create a context: the two-component fluid of Sec. II.A (D3Q19 BGK,
+ * eqs. method:boltzmann, lbm:equilibrium, lbm:weights, relaxation times
+ * tau[2]) and Sec. II.D (Shan-Chen coupling G, eq. method:shanchen, and
+ * the pseudo-potential psi_kind), in a periodic box or between the walls of
+ * Sec. II.C (eq. method:SBB) / Sec. III.A.  rhoA, rhoB: host float arrays of
+ * nx*ny*nz initial densities (> 0 on fluid nodes).  The populations start as
+ * the rest equilibrium w_i rho (u = 0) and are streamed by the first step.
  * workspace: device pointer of at least ws_bytes bytes, 256-byte aligned,
  * ws_bytes >= lbm_workspace_bytes(p, max_nodes, max_faces).
  * hip_stream: a hipStream_t or NULL.  Validates p (tau > 0.5, sizes >= 4,
@@ -157,14 +164,20 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB,
              void* workspace, int64_t ws_bytes, int64_t max_nodes, int64_t max_faces,
              void* hip_stream, lbm_ctx** out);
 
-/* Append n_caps capsules (Sec. II.B).  Host arrays: nodes_per_cap[n_caps],
+/* Append n_caps capsules: triangulated membranes with the Skalak energy
+ * (Sec. II.B, eq. method:strain; kS, C) and the volume penalty (Sec. II.B,
+ * eq. method:volume; kV), wetting the fluid with the particle colour
+ * Delta rho = cos(theta) (Sec. II.D; Sec. III.D, eq. results:anglescaling).
+ * Host arrays: nodes_per_cap[n_caps],
  * faces_per_cap[n_caps]; xyz_rest[sum nodes][3] absolute rest positions,
  * which are also the initial positions; tri[sum faces][3] capsule-local node
  * indices, counter-clockwise seen from outside; kS (> 0), C (> -1/2),
  * kV (>= 0) and theta_deg (in [0, 180]) per capsule.  Each capsule is stored
  * as an integer anchor (its rest centroid rounded) plus FP32 offsets; the
  * reference metric, rest areas and rest volume are computed in FP64.  Only
- * before the first lbm_step (else LBM_ESTATE); LBM_ENOMEM beyond the sizes
+ * before any step has been enqueued (else LBM_ESTATE, also after a state is
+ * loaded back to step 0: the captured graphs and tile lists were built for
+ * the capsules present then); LBM_ENOMEM beyond the sizes
  * given to lbm_init.  *first_id (may be NULL) receives the index of the
  * first new capsule. */
 int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
@@ -181,7 +194,8 @@ int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
  * al. (2003) on the current mesh.  Only before the first lbm_step (else
  * LBM_ESTATE); LBM_EINVAL for a range outside the capsules added, a bad kB,
  * or kB > 0 on a context with the adjoint (ring_len > 0), which does not
- * differentiate it. */
+ * differentiate it.  Like lbm_capsules_add, refused (LBM_ESTATE) once any
+ * step has been enqueued, also after a state is loaded back to step 0. */
 int lbm_capsules_bending(lbm_ctx* ctx, int32_t first_id, int32_t n_caps, const double* kB);
 
 /* The LBM-free reference model (Sec. III.B, eq. emulatetension): nsteps of
@@ -200,7 +214,11 @@ int lbm_capsules_bending(lbm_ctx* ctx, int32_t first_id, int32_t n_caps, const d
 int lbm_reference_relax(lbm_ctx* ctx, int32_t nsteps, double gamma, double w, double z_interface,
                         double mobility);
 
-/* Advance nsteps >= 0 time steps, asynchronously on the stream.  With
+/* Advance nsteps >= 0 time steps (Sec. II.A eq. method:boltzmann: pull
+ * streaming and BGK collision with the force as an equilibrium-velocity
+ * shift; Sec. II.D eq. method:shanchen: the inter-component force with the
+ * wettability offset; Sec. II.B: membrane forces by virtual work and the
+ * forward-Euler node update), asynchronously on the stream.  With
  * use_graphs, pairs of steps are replayed from HIP graphs captured on the
  * first call (kernels only, no memory-set nodes).  With
  * check_every > 0 the FP64 mass check runs every check_every steps and
@@ -227,47 +245,62 @@ enum {
     LBM_NK = 12
 };
 
-/* As lbm_step (without the mass check), and synchronises: HIP events are
+/* Measurement (no passage of the paper, which reports no timings).
+ * As lbm_step (without the mass check), and synchronises: HIP events are
  * recorded on the stream before each kernel group, and kernel_ms[LBM_NK]
  * receives the summed elapsed milliseconds of each group over the nsteps
  * (>= 1) steps. */
 int lbm_step_timed(lbm_ctx* ctx, int32_t nsteps, double* kernel_ms);
 
-/* FP64 observables of the current state (synchronises).  caps may be NULL,
- * else it must hold one entry per capsule. */
+/* FP64 observables of the current state: the component masses whose drift
+ * Sec. II.E measures (Fig. mass-conservation), the total momentum, and per
+ * capsule the centre of mass and its height above the interface (Sec. III.D,
+ * eq. interface:contactangle), volume, area and the Taylor deformation from
+ * the volume's second moments (Sec. III.A, eq. results:taylorparameter).
+ * Synchronises.  caps may be NULL, else it must hold one entry per capsule. */
 int lbm_observables(lbm_ctx* ctx, lbm_obs* out, lbm_capsule_obs* caps);
 
-/* Macroscopic fields of the most recent collision (time level step - 1):
+/* The moments of Sec. II.A (rho = sum f, rho u = sum f c + F / 2) of the
+ * most recent collision (time level step - 1):
  * rhoA, rhoB [N] and u [3][N] (x, y, z planes of the physical velocity with
  * the half-force term).  Host buffers, any may be NULL.  LBM_ESTATE before
  * the first step.  Synchronises. */
 int lbm_get_fields(lbm_ctx* ctx, float* rhoA, float* rhoB, float* u);
 
-/* Current absolute node positions, anchor + offset, [nodes][3].  Synchronises. */
+/* Current absolute boundary-node positions (Sec. II.B), anchor + offset,
+ * [nodes][3].  Synchronises. */
 int lbm_get_nodes(lbm_ctx* ctx, double* xyz);
 
-/* Node forces F_b [nodes][3] used by the most recent step (elastic, volume
- * and wettability reaction).  Synchronises; LBM_ESTATE before the first step. */
+/* Node forces F_b = -dE/dx_b (Sec. II.B, virtual work) [nodes][3] used by the
+ * most recent step: elastic, volume, the wettability reaction (the momentum
+ * balance of Sec. II.D) and the optional bending and repulsion.
+ * Synchronises; LBM_ESTATE before the first step. */
 int lbm_get_node_forces(lbm_ctx* ctx, float* F);
 
-/* Spread fields of the most recent step: F_ib [3][N] and the virtual
- * densities phi [2][N] (A, B).  Synchronises; LBM_ESTATE before a step. */
+/* Spread fields of the most recent step (the immersed-boundary coupling,
+ * which the paper names as prior art in Sec. I and does not define):
+ * F_ib [3][N] and the virtual densities phi [2][N] (A, B) of the colour of
+ * Sec. II.D.  Synchronises; LBM_ESTATE before a step. */
 int lbm_get_spread(lbm_ctx* ctx, float* Fib, float* phi);
 
-/* Binning of the current node positions: tile_of_node[nodes] is the index
+/* Debugging (no passage of the paper: the spreading's own bookkeeping).
+ * Binning of the current node positions: tile_of_node[nodes] is the index
  * of the 4x4x4 spreading bin holding the node floor(X) (bins numbered x
  * fastest),
  * base_idx[nodes][3] the unwrapped stencil base floor(X) - 1.  Recomputed
  * from the positions on the device.  Synchronises. */
 int lbm_debug_bins(lbm_ctx* ctx, int32_t* tile_of_node, int32_t* base_idx);
 
-/* Copy the full state (populations, density buffers, node positions, step
- * counter) to / from slot 0 <= slot < n_slots inside the workspace.
- * Asynchronous on the stream. */
+/* Checkpoint and resume (no passage of the paper: the adjoint's
+ * checkpoints).  Copy the full state (populations, density buffers, node
+ * positions, step counter) to / from slot 0 <= slot < n_slots inside the
+ * workspace.  Asynchronous on the stream. */
 int lbm_state_save(lbm_ctx* ctx, int32_t slot);
 int lbm_state_load(lbm_ctx* ctx, int32_t slot);
 
-/* Discrete adjoint of the coupled step (FP32 storage, ring_len > 0, at least
+/* Discrete adjoint of the coupled step (no passage of the paper, which
+ * computes no gradients; the objectives are its observables, below) (FP32
+ * storage, ring_len > 0, at least
  * one capsule).  J is a capsule objective at the end of a run: LBM_OBJ_COM_Z
  * the node-mean height above z_interface (Sec. III.D, eq.
  * interface:contactangle) or LBM_OBJ_TAYLOR_D (Sec. III.A, eq.
@@ -291,10 +324,43 @@ int lbm_adjoint_forward(lbm_ctx* ctx, int32_t nsteps, int32_t every, int32_t obj
                         double* J);
 int lbm_adjoint_backward(lbm_ctx* ctx, double* grads);
 
-/* Free the host context (not the workspace).  NULL is ignored. */
+/* The same reverse sweep, one call per stage, for a caller that drives it
+ * (lbm_adjoint_backward is seed, then per segment in reverse lbm_state_load,
+ * lbm_adjoint_record and lbm_adjoint_step for the recorded steps, last
+ * first, then lbm_adjoint_grads).  Same preconditions as above (FP32 storage,
+ * ring_len > 0, capsules); no passage of the paper.
+ *
+ * lbm_adjoint_seed: lambda_X = dJ/dX at the current node positions for
+ * objective (LBM_OBJ_COM_Z, Sec. III.D eq. interface:contactangle, or
+ * LBM_OBJ_TAYLOR_D, Sec. III.A eq. results:taylorparameter) of capsule
+ * `capsule`; every other adjoint field and the parameter gradients are
+ * zeroed.  Synchronises.  LBM_EINVAL for an unknown objective or capsule.
+ *
+ * lbm_adjoint_record: ring entry 0 = the current state, entries 1 ..
+ * nsteps - 1 the states after each of the next nsteps - 1 recomputed steps
+ * (1 <= nsteps <= ring_len, else LBM_EINVAL).  The step counter and the
+ * population and density buffers are left as they were; the node positions
+ * are those after the recomputed steps.  Asynchronous.
+ *
+ * lbm_adjoint_step: applies the adjoint of recorded step ring_index to the
+ * adjoint state and adds its parameter derivatives.  The indices of one
+ * recording must come in reverse order, nsteps - 1 first (else
+ * LBM_ESTATE); LBM_ESTATE before lbm_adjoint_seed or lbm_adjoint_record.
+ * Leaves the node positions at those of entry ring_index.  Asynchronous.
+ *
+ * lbm_adjoint_grads: grads[3] = dJ/dtheta (per radian), dJ/dkS, dJ/dG
+ * accumulated since the seed, as for lbm_adjoint_backward.  Synchronises. */
+int lbm_adjoint_seed(lbm_ctx* ctx, int32_t objective, int32_t capsule);
+int lbm_adjoint_record(lbm_ctx* ctx, int32_t nsteps);
+int lbm_adjoint_step(lbm_ctx* ctx, int32_t ring_index);
+int lbm_adjoint_grads(lbm_ctx* ctx, double* grads);
+
+/* Teardown (no passage of the paper).  Free the host context (not the
+ * workspace).  NULL is ignored. */
 void lbm_destroy(lbm_ctx* ctx);
 
-/* Last error message of ctx, or of this thread's failed init when NULL. */
+/* Error reporting (no passage of the paper).  Last error message of ctx,
+ * or of this thread's failed init when NULL. */
 const char* lbm_last_error(const lbm_ctx* ctx);
 
 #ifdef __cplusplus

@@ -26,6 +26,24 @@ def workload_with(wl, theta_deg, kS, G):
     return w
 
 
+def reverse_sweep(sim, steps, every, objective, capsule=0):
+    """The reverse sweep after sim.adjoint_forward(steps, every, ...), one
+    library call per stage: seed dJ/dX at the final state, then for each
+    checkpoint segment, last first, reload it, recompute it into the ring and
+    apply its steps' adjoints in reverse; the state is left at the start of
+    the run.  Returns dJ/d(theta [rad], kS, G)."""
+    sim.adjoint_seed(objective, capsule)
+    nseg = (steps + every - 1) // every
+    for sgm in reversed(range(nseg)):
+        n = min(every, steps - sgm * every)
+        sim.load(sgm)
+        sim.adjoint_record(n)
+        for k in reversed(range(n)):
+            sim.adjoint_step(k)
+    sim.load(0)
+    return sim.adjoint_grads()
+
+
 class CapsuleObjective(torch.autograd.Function):
     """J = objective(capsule 0) after `steps` steps of `wl` run with
     (theta_deg, kS, G); backward returns dJ/dtheta_deg, dJ/dkS, dJ/dG."""
@@ -37,11 +55,12 @@ class CapsuleObjective(torch.autograd.Function):
                                         n_slots=nseg, ring_len=every)
         J = sim.adjoint_forward(steps, every, OBJECTIVES[objective], 0)
         ctx.sim = sim
+        ctx.steps, ctx.every, ctx.objective = steps, every, OBJECTIVES[objective]
         return torch.tensor(J, dtype=torch.float64)
 
     @staticmethod
     def backward(ctx, gJ):
-        g = ctx.sim.adjoint_backward()
+        g = reverse_sweep(ctx.sim, ctx.steps, ctx.every, ctx.objective)
         ctx.sim.close()
         s = float(gJ)
         return (torch.tensor(s * g[0] * math.pi / 180.0, dtype=torch.float64),

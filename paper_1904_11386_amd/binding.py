@@ -48,6 +48,7 @@ EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_
            "lbm_step", "lbm_step_timed", "lbm_observables",
            "lbm_get_fields", "lbm_get_nodes", "lbm_get_node_forces", "lbm_get_spread",
            "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_adjoint_forward", "lbm_adjoint_backward",
+           "lbm_adjoint_seed", "lbm_adjoint_record", "lbm_adjoint_step", "lbm_adjoint_grads",
            "lbm_destroy", "lbm_last_error"]
 LBM_OBJ_COM_Z, LBM_OBJ_TAYLOR_D = 0, 1
 
@@ -83,6 +84,10 @@ def load(path: str = None):
         "lbm_state_load": ([vp, i32], C.c_int),
         "lbm_adjoint_forward": ([vp, i32, i32, i32, i32, P(d)], C.c_int),
         "lbm_adjoint_backward": ([vp, P(d)], C.c_int),
+        "lbm_adjoint_seed": ([vp, i32, i32], C.c_int),
+        "lbm_adjoint_record": ([vp, i32], C.c_int),
+        "lbm_adjoint_step": ([vp, i32], C.c_int),
+        "lbm_adjoint_grads": ([vp, P(d)], C.c_int),
         "lbm_destroy": ([vp], None),
         "lbm_last_error": ([vp], C.c_char_p),
     }
@@ -269,6 +274,24 @@ class Sim:
         """dJ/d(theta [rad], kS, G) of the last adjoint_forward."""
         g = (C.c_double * 3)()
         self._check(self.lib.lbm_adjoint_backward(self.ctx, g))
+        return np.array(g[:])
+
+    def adjoint_seed(self, objective=LBM_OBJ_COM_Z, capsule=0):
+        """lambda_X = dJ/dX at the current positions; other adjoint state zeroed."""
+        self._check(self.lib.lbm_adjoint_seed(self.ctx, int(objective), int(capsule)))
+
+    def adjoint_record(self, nsteps):
+        """Recompute nsteps states from the current one into the ring."""
+        self._check(self.lib.lbm_adjoint_record(self.ctx, int(nsteps)))
+
+    def adjoint_step(self, ring_index):
+        """Adjoint of recorded step ring_index (reverse order, last first)."""
+        self._check(self.lib.lbm_adjoint_step(self.ctx, int(ring_index)))
+
+    def adjoint_grads(self):
+        """dJ/d(theta [rad], kS, G) accumulated since the seed."""
+        g = (C.c_double * 3)()
+        self._check(self.lib.lbm_adjoint_grads(self.ctx, g))
         return np.array(g[:])
 
     def save(self, slot):

@@ -201,6 +201,12 @@ struct lbm_ctx {
     // adjoint run description
     int adj_nsteps = 0, adj_every = 0, adj_obj = 0, adj_cap = 0;
     int64_t adj_step0 = -1;
+    // reverse sweep driven step by step (lbm_adjoint_seed / _record / _step)
+    bool adj_seeded = false;
+    int adj_p = 0;                 // parity of the adjoint population buffers
+    int rec_len = 0, rec_next = -1;
+    int64_t rec_step0 = 0;
+    bool launched = false;         // a step (or its graph) has been enqueued
     std::vector<int> tri_global;
     std::vector<FaceRef> fref;
     std::vector<int> face_cap;
@@ -408,7 +414,9 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
                      const double* xyz_rest, const int32_t* tri, const double* kS, const double* C,
                      const double* kV, const double* theta_deg, int32_t* first_id) {
     if (!c) return LBM_EINVAL;
-    if (c->step != 0) return c->fail(LBM_ESTATE, "capsules must be added before the first step");
+    // (sticky: a state loaded back to step 0 still has graphs and tile lists
+    // built for the capsules present at the first step)
+    if (c->step != 0 || c->launched) return c->fail(LBM_ESTATE, "capsules must be added before the first step");
     if (n_caps < 0) return c->fail(LBM_EINVAL, "n_caps < 0");
     if (n_caps == 0) { if (first_id) *first_id = (int32_t)c->caps.size(); return LBM_OK; }
     if (!nodes_per_cap || !faces_per_cap || !xyz_rest || !tri || !kS || !C || !kV || !theta_deg)
@@ -621,6 +629,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     const float* cs = half ? d.cscale + 2 * cur : nullptr;
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
     const bool fork = overlap && !ev && fout && ibm;
+    c->launched = true;
     hipStream_t m = fork ? c->side : s;       // the membrane kernels' stream up to the join
     if (fork) {
         (void)hipEventRecord(c->ev_fork, s);
@@ -732,7 +741,7 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
 
 int lbm_capsules_bending(lbm_ctx* c, int32_t first_id, int32_t n_caps, const double* kB) {
     if (!c) return LBM_EINVAL;
-    if (c->step != 0) return c->fail(LBM_ESTATE, "bending moduli must be set before the first step");
+    if (c->step != 0 || c->launched) return c->fail(LBM_ESTATE, "bending moduli must be set before the first step");
     if (n_caps < 0 || first_id < 0 || (int64_t)first_id + n_caps > (int64_t)c->caps.size())
         return c->fail(LBM_EINVAL, "capsule range outside the capsules added");
     if (n_caps == 0) return LBM_OK;
@@ -1178,22 +1187,24 @@ int lbm_adjoint_forward(lbm_ctx* c, int32_t nsteps, int32_t every, int32_t objec
     return LBM_OK;
 }
 
-int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
-    if (!c || !grads) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
-    if (!adjoint_ready(c) || c->adj_step0 < 0 || c->step != c->adj_step0 + c->adj_nsteps)
-        return c->fail(LBM_ESTATE, "lbm_adjoint_backward must follow lbm_adjoint_forward");
+// Seed of the reverse sweep: lambda_X = dJ/dX at the current node positions
+// (FP64 on the host), every other adjoint field and the parameter gradients
+// zero.
+int lbm_adjoint_seed(lbm_ctx* c, int32_t objective, int32_t capsule) {
+    if (!c) return LBM_EINVAL;
+    if (!adjoint_ready(c)) return c->fail(LBM_ESTATE, "the adjoint needs ring_len > 0, FP32 storage and capsules");
+    if (objective != LBM_OBJ_COM_Z && objective != LBM_OBJ_TAYLOR_D) return c->fail(LBM_EINVAL, "unknown objective");
+    if (capsule < 0 || capsule >= (int)c->caps.size()) return c->fail(LBM_EINVAL, "capsule index out of range");
     Dev& d = c->d;
-    const Lattice& L = c->L;
     hipStream_t s = c->stream;
-    const int64_t N = L.n;
+    const int64_t N = c->L.n;
     const size_t nb = c->n_nodes;
-    // seed dJ/dX at the final positions (FP64 on the host), lambda* = 0
     std::vector<float> hi(3 * nb), lo(3 * nb), seed(3 * nb, 0.0f);
     HIPCHK(c, hipMemcpyAsync(hi.data(), d.off_hi, 3 * nb * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipMemcpyAsync(lo.data(), d.off_lo, 3 * nb * 4, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
-    const CapDev& cd = c->caps[c->adj_cap];
-    if (c->adj_obj == LBM_OBJ_COM_Z) {
+    const CapDev& cd = c->caps[capsule];
+    if (objective == LBM_OBJ_COM_Z) {
         for (int b = 0; b < cd.node_count; ++b) seed[3 * (cd.node_start + b) + 2] = (float)(1.0 / cd.node_count);
     } else {
         std::vector<double> X(3 * (size_t)cd.node_count), gD;
@@ -1207,78 +1218,134 @@ int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
             for (int j = 0; j < 3; ++j) seed[3 * (cd.node_start + b) + j] = (float)gD[3 * b + j];
     }
     HIPCHK(c, hipMemcpyAsync(d.lam_X, seed.data(), 3 * nb * 4, hipMemcpyHostToDevice, s));
-    int p = 0;
-    HIPCHK(c, hipMemsetAsync(d.lam[p], 0, c->lay.fbytes, s));
+    c->adj_p = 0;
+    HIPCHK(c, hipMemsetAsync(d.lam[0], 0, c->lay.fbytes, s));
     HIPCHK(c, hipMemsetAsync(d.lam_S, 0, 6 * N * 4, s));
     HIPCHK(c, hipMemsetAsync(d.lam_rho, 0, 2 * N * 4, s));
     HIPCHK(c, hipMemsetAsync(d.lam_j, 0, 6 * N * 4, s));
     HIPCHK(c, hipMemsetAsync(d.grads, 0, 4 * 8, s));
-    const int nseg = (c->adj_nsteps + c->adj_every - 1) / c->adj_every;
-    const size_t offb = 3 * nb * 4;
-    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
-        const int len = std::min(c->adj_every, c->adj_nsteps - sgm * c->adj_every);
-        int r = lbm_state_load(c, sgm);
-        if (r != LBM_OK) return r;
-        // ring[0] = the checkpoint
-        {
-            const int cur = (int)(c->step & 1);
-            char* e0 = ring_at(c, 0);
-            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_f, d.f[cur], c->lay.fbytes, hipMemcpyDeviceToDevice, s));
-            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_rho, d.rho[cur ^ 1], 2 * N * 4, hipMemcpyDeviceToDevice, s));
-            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_off, d.off_hi, offb, hipMemcpyDeviceToDevice, s));
-            HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_off + offb, d.off_lo, offb, hipMemcpyDeviceToDevice, s));
-        }
-        const int64_t seg_step0 = c->step;
-        // recompute the segment into the ring
-        for (int k = 0; k + 1 < len; ++k) {
-            char* ek = ring_at(c, k);
-            char* en = ring_at(c, k + 1);
-            enqueue_core(c, ek + c->lay.ring_f, en + c->lay.ring_f, (float*)(en + c->lay.ring_rho),
-                         (const float*)(ek + c->lay.ring_rho), true, nullptr);
-            HIPCHK(c, hipMemcpyAsync(en + c->lay.ring_off, d.off_hi, offb, hipMemcpyDeviceToDevice, s));
-            HIPCHK(c, hipMemcpyAsync(en + c->lay.ring_off + offb, d.off_lo, offb, hipMemcpyDeviceToDevice, s));
-        }
-        // adjoint steps in reverse
-        for (int k = len - 1; k >= 0; --k) {
-            char* ek = ring_at(c, k);
-            HIPCHK(c, hipMemcpyAsync(d.off_hi, ek + c->lay.ring_off, offb, hipMemcpyDeviceToDevice, s));
-            HIPCHK(c, hipMemcpyAsync(d.off_lo, ek + c->lay.ring_off + offb, offb, hipMemcpyDeviceToDevice, s));
-            c->step = seg_step0 + k;
-            const int par = c->flip;
-            const void* fin = ek + c->lay.ring_f;
-            const float* rho_p = (const float*)(ek + c->lay.ring_rho);
-            // the densities of step k are the next ring entry's previous
-            // densities; only the segment's last step computes them again
-            float* rho_n = k + 1 < len ? (float*)(ring_at(c, k + 1) + c->lay.ring_rho) : d.rho[0];
-            if (k + 1 >= len) launch_density(L, fin, rho_p, rho_n, false, d.cscale, 0, d.dpart, s);
-            // membrane intermediates of step k: node forces, bins, spread fields
-            enqueue_core(c, fin, nullptr, rho_n, rho_p, false, nullptr);
-            launch_spread_vec(L, d, par, d.lam_X, d.lam_u, 0, s);
-            launch_adj_collide(L, fin, rho_n, rho_p, d.fib, d.tile_flag, d.lam[p], d.lam_u, d.lam_rho, d.lam_j,
-                               d.lam_S, d.lam_Fib, d.u, d.grads, s);
-            launch_adj_nodes(L, d, rho_n, c->n_nodes, s);
-            if (c->p.rep_eps > 0.0 && c->caps.size() > 1)
-                launch_adj_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
-            launch_adj_membrane(d, c->n_nodes, c->n_faces, s);
-            launch_spread_vec(L, d, par, d.lam_q, d.lam_S, 1, s);
-            launch_adj_gather(L, d.lam_S, d.lam_rho, rho_n, s);
-            launch_adj_push(L, d.lam[p], d.lam_rho, d.lam_j, d.lam[p ^ 1], s);
-            p ^= 1;
-            HIPCHK(c, hipGetLastError());
-        }
-        c->step = seg_step0;
-    }
-    // leave the state at the start of the run
-    {
-        const int r = lbm_state_load(c, 0);
-        if (r != LBM_OK) return r;
-    }
-    double g[4];
-    HIPCHK(c, hipMemcpyAsync(g, d.grads, sizeof g, hipMemcpyDeviceToHost, s));
+    // (the copy above reads a host vector that goes out of scope)
     HIPCHK(c, hipStreamSynchronize(s));
+    c->adj_seeded = true;
+    c->rec_len = 0;
+    c->rec_next = -1;
+    return LBM_OK;
+}
+
+// Ring entry 0 = the current state; entries 1 .. nsteps-1 the states after
+// each of the next nsteps - 1 recomputed steps.  The context's step counter
+// and state are left as they were at the call (node offsets aside, which
+// lbm_adjoint_step reloads from the ring).
+int lbm_adjoint_record(lbm_ctx* c, int32_t nsteps) {
+    if (!c) return LBM_EINVAL;
+    if (!adjoint_ready(c)) return c->fail(LBM_ESTATE, "the adjoint needs ring_len > 0, FP32 storage and capsules");
+    if (nsteps < 1 || nsteps > c->p.ring_len) return c->fail(LBM_EINVAL, "need 1 <= nsteps <= ring_len");
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    const int64_t N = c->L.n;
+    const size_t offb = 3 * (size_t)c->n_nodes * 4;
+    {
+        const int cur = (int)(c->step & 1);
+        char* e0 = ring_at(c, 0);
+        HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_f, d.f[cur], c->lay.fbytes, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_rho, d.rho[cur ^ 1], 2 * N * 4, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_off, d.off_hi, offb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(e0 + c->lay.ring_off + offb, d.off_lo, offb, hipMemcpyDeviceToDevice, s));
+    }
+    const int64_t step0 = c->step;
+    for (int k = 0; k + 1 < nsteps; ++k) {
+        char* ek = ring_at(c, k);
+        char* en = ring_at(c, k + 1);
+        enqueue_core(c, ek + c->lay.ring_f, en + c->lay.ring_f, (float*)(en + c->lay.ring_rho),
+                     (const float*)(ek + c->lay.ring_rho), true, nullptr);
+        HIPCHK(c, hipMemcpyAsync(en + c->lay.ring_off, d.off_hi, offb, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(en + c->lay.ring_off + offb, d.off_lo, offb, hipMemcpyDeviceToDevice, s));
+    }
+    HIPCHK(c, hipGetLastError());
+    c->step = step0;
+    c->rec_step0 = step0;
+    c->rec_len = nsteps;
+    c->rec_next = nsteps - 1;
+    return LBM_OK;
+}
+
+// The adjoint of step `ring_index` of the recorded segment, applied to the
+// adjoint state; the steps must come in reverse order, last first.
+int lbm_adjoint_step(lbm_ctx* c, int32_t ring_index) {
+    if (!c) return LBM_EINVAL;
+    if (!adjoint_ready(c) || !c->adj_seeded) return c->fail(LBM_ESTATE, "lbm_adjoint_step needs lbm_adjoint_seed first");
+    if (c->rec_len < 1) return c->fail(LBM_ESTATE, "lbm_adjoint_step needs lbm_adjoint_record first");
+    if (ring_index < 0 || ring_index >= c->rec_len) return c->fail(LBM_EINVAL, "ring_index outside the recorded segment");
+    if (ring_index != c->rec_next)
+        return c->fail(LBM_ESTATE, "adjoint steps run in reverse order: expected ring_index %d", c->rec_next);
+    Dev& d = c->d;
+    const Lattice& L = c->L;
+    hipStream_t s = c->stream;
+    const size_t offb = 3 * (size_t)c->n_nodes * 4;
+    const int k = ring_index;
+    const int len = c->rec_len;
+    char* ek = ring_at(c, k);
+    HIPCHK(c, hipMemcpyAsync(d.off_hi, ek + c->lay.ring_off, offb, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(d.off_lo, ek + c->lay.ring_off + offb, offb, hipMemcpyDeviceToDevice, s));
+    c->step = c->rec_step0 + k;
+    // (the tile-list parity alternates with each enqueued step, recorded or
+    // adjoint, so the lists the previous launch flagged are cleared next)
+    const int par = c->flip;
+    int& p = c->adj_p;
+    const void* fin = ek + c->lay.ring_f;
+    const float* rho_p = (const float*)(ek + c->lay.ring_rho);
+    // the densities of step k are the next ring entry's previous densities;
+    // only the segment's last step computes them again
+    float* rho_n = k + 1 < len ? (float*)(ring_at(c, k + 1) + c->lay.ring_rho) : d.rho[0];
+    if (k + 1 >= len) launch_density(L, fin, rho_p, rho_n, false, d.cscale, 0, d.dpart, s);
+    // membrane intermediates of step k: node forces, bins, spread fields
+    enqueue_core(c, fin, nullptr, rho_n, rho_p, false, nullptr);
+    launch_spread_vec(L, d, par, d.lam_X, d.lam_u, 0, s);
+    launch_adj_collide(L, fin, rho_n, rho_p, d.fib, d.tile_flag, d.lam[p], d.lam_u, d.lam_rho, d.lam_j,
+                       d.lam_S, d.lam_Fib, d.u, d.grads, s);
+    launch_adj_nodes(L, d, rho_n, c->n_nodes, s);
+    if (c->p.rep_eps > 0.0 && c->caps.size() > 1)
+        launch_adj_repulse(L, d, c->n_nodes, (float)c->p.rep_eps, (float)c->p.rep_d0, s);
+    launch_adj_membrane(d, c->n_nodes, c->n_faces, s);
+    launch_spread_vec(L, d, par, d.lam_q, d.lam_S, 1, s);
+    launch_adj_gather(L, d.lam_S, d.lam_rho, rho_n, s);
+    launch_adj_push(L, d.lam[p], d.lam_rho, d.lam_j, d.lam[p ^ 1], s);
+    p ^= 1;
+    HIPCHK(c, hipGetLastError());
+    c->step = c->rec_step0;
+    c->rec_next = k - 1;
+    return LBM_OK;
+}
+
+int lbm_adjoint_grads(lbm_ctx* c, double* grads) {
+    if (!c || !grads) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (!adjoint_ready(c) || !c->adj_seeded) return c->fail(LBM_ESTATE, "lbm_adjoint_grads needs lbm_adjoint_seed first");
+    double g[4];
+    HIPCHK(c, hipMemcpyAsync(g, c->d.grads, sizeof g, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     grads[0] = g[0];
     grads[1] = g[1];
     grads[2] = g[2];
+    return LBM_OK;
+}
+
+int lbm_adjoint_backward(lbm_ctx* c, double* grads) {
+    if (!c || !grads) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (!adjoint_ready(c) || c->adj_step0 < 0 || c->step != c->adj_step0 + c->adj_nsteps)
+        return c->fail(LBM_ESTATE, "lbm_adjoint_backward must follow lbm_adjoint_forward");
+    int r = lbm_adjoint_seed(c, c->adj_obj, c->adj_cap);
+    if (r != LBM_OK) return r;
+    const int nseg = (c->adj_nsteps + c->adj_every - 1) / c->adj_every;
+    for (int sgm = nseg - 1; sgm >= 0; --sgm) {
+        const int len = std::min(c->adj_every, c->adj_nsteps - sgm * c->adj_every);
+        if ((r = lbm_state_load(c, sgm)) != LBM_OK) return r;
+        if ((r = lbm_adjoint_record(c, len)) != LBM_OK) return r;
+        for (int k = len - 1; k >= 0; --k)
+            if ((r = lbm_adjoint_step(c, k)) != LBM_OK) return r;
+    }
+    // leave the state at the start of the run
+    if ((r = lbm_state_load(c, 0)) != LBM_OK) return r;
+    if ((r = lbm_adjoint_grads(c, grads)) != LBM_OK) return r;
     c->adj_step0 = -1;
     return LBM_OK;
 }

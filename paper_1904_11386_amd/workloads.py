@@ -433,3 +433,29 @@ def small(nx=40, ny=36, nz=44, ncap=2, freq=4, radius=4.0, theta=(70.0, 115.0),
                     walls=walls, wall_u_lo=(-wall_u, 0, 0) if walls else (0, 0, 0),
                     wall_u_hi=(wall_u, 0, 0) if walls else (0, 0, 0),
                     z_interface=zs - 0.5, steps=20, wet_scale=wet_scale)
+
+
+def crop(wl: Workload, x0: int, y0: int, z0: int, wx: int, wy: int, wz: int, margin: float = 4.0) -> Workload:
+    """A box of wl's initial state, [x0, x0 + wx) x [y0, y0 + wy) x
+    [z0, z0 + wz) (periodic in x and y), with the capsules that lie wholly
+    inside it at least `margin` cells from its faces, in box coordinates.
+    A bounded sample of a large workload with its shapes and value mix."""
+    xs = (x0 + np.arange(wx)) % wl.nx
+    ys = (y0 + np.arange(wy)) % wl.ny
+    zs = z0 + np.arange(wz)
+    if zs[0] < 0 or zs[-1] >= wl.nz:
+        raise ValueError("crop leaves the box in z")
+    sel = np.ix_(zs, ys, xs)
+    caps = []
+    n = np.array([wl.nx, wl.ny], np.float64)
+    for c in wl.capsules:
+        rel = np.asarray(c.centre, np.float64) - np.array([x0, y0, z0], np.float64)
+        rel[:2] = np.mod(rel[:2], n)
+        lo = c.radius + margin
+        if (lo <= rel[0] <= wx - 1 - lo and lo <= rel[1] <= wy - 1 - lo and lo <= rel[2] <= wz - 1 - lo):
+            caps.append(Capsule(_snap(rel), c.radius, c.freq, c.kS, c.C, c.kV, c.theta_deg, kB=c.kB,
+                                stretch=c.stretch))
+    return Workload(wl.name + "_crop", wx, wy, wz, np.ascontiguousarray(wl.rhoA[sel]),
+                    np.ascontiguousarray(wl.rhoB[sel]), caps, tau=wl.tau, G=wl.G,
+                    z_interface=wl.z_interface - z0, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
+                    wet_scale=wl.wet_scale, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0, psi_kind=wl.psi_kind)

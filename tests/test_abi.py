@@ -112,7 +112,15 @@ def test_every_entry_point_rejects_a_null_context():
         "lbm_state_load": (null, 0),
         "lbm_adjoint_forward": (null, 1, 1, 0, 0, None),
         "lbm_adjoint_backward": (null, None),
+        "lbm_adjoint_seed": (null, 0, 0),
+        "lbm_adjoint_record": (null, 1),
+        "lbm_adjoint_step": (null, 0),
+        "lbm_adjoint_grads": (null, None),
     }
+    # every context call is listed (the size query, init and the two
+    # context-free calls aside)
+    free = {"lbm_workspace_bytes", "lbm_init", "lbm_destroy", "lbm_last_error"}
+    assert sorted(set(calls) | free) == declared_symbols()
     for name, args in calls.items():
         assert getattr(lib, name)(*args) == B.LBM_EINVAL, name
     lib.lbm_destroy(None)

@@ -202,3 +202,75 @@ def test_adjoint_with_exponential_pseudo_potential(kind):
                 fd *= 180.0 / math.pi
             _say("  param %d gpu adjoint %.8e fp64 fd %.8e rel %.2e" % (i, g[i], fd, abs(g[i] - fd) / abs(fd)))
             assert abs(g[i] - fd) <= 1e-4 * abs(fd)
+
+
+def test_staged_reverse_sweep_matches_backward_call():
+    """The reverse sweep driven from Python one stage at a time
+    (lbm_adjoint_seed, then per checkpoint segment lbm_state_load,
+    lbm_adjoint_record and lbm_adjoint_step in reverse, then
+    lbm_adjoint_grads) gives the gradient of lbm_adjoint_backward, which runs
+    the same stages inside the library.  The recomputed forward spreads with
+    float atomics, so two sweeps agree to the rounding-order noise of the
+    recompute, not bit for bit: the bound is 1e-6 relative, and two runs of
+    lbm_adjoint_backward are compared the same way for scale."""
+    from paper_1904_11386_amd import binding
+    from paper_1904_11386_amd.adjoint import OBJECTIVES, reverse_sweep, workload_with
+    wl = W.make("c4_mini")
+    params = (75.0, 0.005, 3.6)
+    steps, every = 25, 10            # a ragged last segment of 5 steps
+    for kind in ("com_z", "taylor_D"):
+        sim = binding.sim_from_workload(workload_with(wl, *params), n_slots=3, ring_len=every)
+        J = sim.adjoint_forward(steps, every, OBJECTIVES[kind], 0)
+        g_call = sim.adjoint_backward()
+        J2 = sim.adjoint_forward(steps, every, OBJECTIVES[kind], 0)
+        g_staged = reverse_sweep(sim, steps, every, OBJECTIVES[kind])
+        J3 = sim.adjoint_forward(steps, every, OBJECTIVES[kind], 0)
+        g_call2 = sim.adjoint_backward()
+        _say("  %s J %.10e %.10e %.10e" % (kind, J, J2, J3))
+        _say("  backward call", g_call.tolist(), "staged", g_staged.tolist(), "second call", g_call2.tolist())
+        rel = np.abs(g_staged - g_call) / np.abs(g_call)
+        rel2 = np.abs(g_call2 - g_call) / np.abs(g_call)
+        _say("  staged vs call rel", rel.tolist(), "call vs call rel", rel2.tolist())
+        assert abs(J2 - J) <= 1e-6 * abs(J) and abs(J3 - J) <= 1e-6 * abs(J)
+        assert np.all(rel < 1e-6), rel
+        # the state after either sweep is the one at the start of the run
+        obs = sim.observables()
+        assert obs["step"] == 0
+        sim.close()
+
+
+def test_staged_reverse_sweep_order_and_state_errors():
+    from paper_1904_11386_amd import binding
+    from paper_1904_11386_amd.adjoint import workload_with
+    wl = W.make("c4_mini")
+    sim = binding.sim_from_workload(workload_with(wl, 75.0, 0.005, 3.6), n_slots=2, ring_len=10)
+    sim.adjoint_forward(12, 10, binding.LBM_OBJ_COM_Z, 0)
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_step(0)                      # before the seed
+    assert e.value.code == binding.LBM_ESTATE
+    sim.adjoint_seed(binding.LBM_OBJ_COM_Z, 0)
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_step(0)                      # before a recording
+    assert e.value.code == binding.LBM_ESTATE
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_seed(7, 0)
+    assert e.value.code == binding.LBM_EINVAL
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_seed(binding.LBM_OBJ_COM_Z, 5)
+    assert e.value.code == binding.LBM_EINVAL
+    sim.load(1)
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_record(11)                   # longer than the ring
+    assert e.value.code == binding.LBM_EINVAL
+    sim.adjoint_record(2)
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_step(0)                      # out of order: 1 comes first
+    assert e.value.code == binding.LBM_ESTATE
+    with pytest.raises(binding.LbmError) as e:
+        sim.adjoint_step(2)                      # outside the recording
+    assert e.value.code == binding.LBM_EINVAL
+    sim.adjoint_step(1)
+    sim.adjoint_step(0)
+    g = sim.adjoint_grads()
+    assert np.all(np.isfinite(g))
+    sim.close()
