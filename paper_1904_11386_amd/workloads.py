@@ -163,6 +163,8 @@ class Capsule:
     theta_deg: float
     kB: float = 0.0                         # Helfrich bending modulus (0 = none)
     stretch: tuple = (1.0, 1.0, 1.0)        # axis scaling of the rest mesh (ellipsoids)
+    v: tuple = (0.0, 0.0, 0.0)              # initial node velocity (bounce-back coupling)
+    prescribed: bool = False                # nodes keep v (rigid translation)
 
     def mesh(self):
         xyz, tri = icosphere(self.freq, self.radius)
@@ -191,6 +193,9 @@ class Workload:
     rep_eps: float = 0.0        # particle-particle repulsion strength (0 = off)
     rep_d0: float = 1.25        # and its cut-off
     psi_kind: int = 0           # Shan-Chen pseudo-potential: 0 psi = rho, 1 psi = 1 - exp(-rho)
+    coupling: int = 0           # 0 immersed boundary, 1 the paper's bounce-back coupling
+    node_mass: float = 5.0      # boundary-node mass of the bounce-back coupling (Sec. III)
+    mass_c0: float = 2500.0     # strength C0 of its adaptive mass correction (Sec. II.E)
     note: str = ""
 
     @property
@@ -459,3 +464,36 @@ def crop(wl: Workload, x0: int, y0: int, z0: int, wx: int, wy: int, wz: int, mar
                     np.ascontiguousarray(wl.rhoB[sel]), caps, tau=wl.tau, G=wl.G,
                     z_interface=wl.z_interface - z0, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     wet_scale=wl.wet_scale, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0, psi_kind=wl.psi_kind)
+
+
+def bb_capsule(nx=24, ny=22, nz=26, centre=(11.37, 10.61, 12.83), radius=4.0, freq=4, theta=90.0, kS=0.01,
+               kV=2.0, v=(0.0, 0.0, 0.0), prescribed=False, interior=None, layered_z=None, G=3.6,
+               rho=(0.7, 0.04), interior_mask=None, wet_scale=1.0, C0=2500.0, node_mass=5.0,
+               tau=(1.0, 1.0), psi_kind=0) -> Workload:
+    """One capsule for the bounce-back coupling (Sec. II.C-II.E) in a
+    ragged periodic box, at a centre off the lattice's symmetry planes so
+    that no lattice node lies on the membrane.  Densities: uniform `rho`
+    (A, B) everywhere, or a flat interface at layered_z (A below); interior
+    = (A, B) densities of the nodes inside the rest sphere shrunk by 0.3, or
+    of the nodes where interior_mask [nz, ny, nx] is true, when given (the
+    paper fills a capsule with the lower fluid's composition).  The
+    capsule's velocity v, and whether it is prescribed, are inputs."""
+    if layered_z is not None:
+        rhoA, rhoB = layered(nx, ny, nz, layered_z)
+    else:
+        rhoA = np.full((nz, ny, nx), rho[0], np.float32)
+        rhoB = np.full((nz, ny, nx), rho[1], np.float32)
+    c = _snap(np.array(centre, np.float64))
+    if interior is not None:
+        if interior_mask is not None:
+            ins = np.asarray(interior_mask, bool)
+        else:
+            g = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+            ins = (g[2] - c[0]) ** 2 + (g[1] - c[1]) ** 2 + (g[0] - c[2]) ** 2 < (radius - 0.3) ** 2
+        rhoA = np.where(ins, np.float32(interior[0]), rhoA).astype(np.float32)
+        rhoB = np.where(ins, np.float32(interior[1]), rhoB).astype(np.float32)
+    cap = Capsule(c, radius, freq, kS, 0.0, kV, theta, v=tuple(float(a) for a in v), prescribed=prescribed)
+    zi = (layered_z - 0.5) if layered_z is not None else nz / 2
+    return Workload("bb_capsule", nx, ny, nz, np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB), [cap],
+                    tau=tau, G=G, z_interface=zi, wet_scale=wet_scale, coupling=1, node_mass=node_mass,
+                    mass_c0=C0, psi_kind=psi_kind)
