@@ -122,12 +122,35 @@ typedef struct lbm_params {
                                differentiates it.                                */
     double rep_d0;          /* its cut-off, in (0, 2] when rep_eps > 0 (the
                                paper uses 1.25)                                  */
+    int32_t coupling;       /* fluid-structure coupling: 0 the immersed boundary
+                               (Peskin 4-point delta, massless nodes); 1 the
+                               paper's own: half-way bounce-back of the
+                               populations that cross a membrane, with the
+                               moving-element term and the momentum exchange
+                               (Sec. II.C, eqs. method:SBB and
+                               method:momentumtransfer), the Shan-Chen sum
+                               across it from densities interpolated on the
+                               viewer's side plus the colour offset (Sec. II.D,
+                               eq. method:interpolateshanchen), fresh nodes
+                               with the adaptive mass correction (Sec. II.E,
+                               eqs. method:freshnodes, method:masscorrection)
+                               and inertial nodes.  1 needs FP32 storage,
+                               walls 0, n_slots 0, ring_len 0 and rep_eps 0   */
+    double node_mass;       /* coupling 1: mass of a boundary node (> 0; the
+                               paper uses 5, Sec. III)                          */
+    double mass_c0;         /* coupling 1: strength C0 of the adaptive mass
+                               correction (>= 0; the paper uses 2500)           */
 } lbm_params;
 
 typedef struct lbm_obs {
     double mass[2];         /* sum over fluid nodes of the post-collision populations */
     double momentum[3];     /* sum over fluid nodes and components of f* c           */
     int64_t step;           /* completed time steps                                   */
+    double particle_momentum[3]; /* coupling 1: sum over boundary nodes of m V (else 0) */
+    double pending_momentum[3];  /* coupling 1: half of the last step's exchanged
+                                    momentum, which the nodes receive with the next
+                                    step (Sec. II.C); fluid + particle + pending
+                                    momentum is conserved (else 0)              */
 } lbm_obs;
 
 typedef struct lbm_capsule_obs {
@@ -185,6 +208,17 @@ int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
                      const int32_t* tri, const double* kS, const double* C,
                      const double* kV, const double* theta_deg, int32_t* first_id);
 
+/* Boundary-node velocities of the capsules first_id .. first_id + n_caps - 1
+ * under the bounce-back coupling (coupling 1; Sec. II.B, forward Euler of
+ * inertial nodes): v[n_caps][3] (finite, |v_k| < 0.5) is each capsule's
+ * initial node velocity (0 by default); with prescribed != 0 the nodes keep
+ * it, whatever the forces (the rigid translation of Sec. II.E's
+ * mass-conservation test, Fig. mass-conservation).  Only before any step has
+ * been enqueued (else LBM_ESTATE); LBM_EINVAL under the immersed boundary
+ * (coupling 0, whose nodes are massless) or for a range outside the
+ * capsules added. */
+int lbm_capsules_velocity(lbm_ctx* ctx, int32_t first_id, int32_t n_caps, const double* v, int32_t prescribed);
+
 /* Helfrich bending (Sec. II.B, eqs. method:curvature and surf_dens, zero
  * spontaneous curvature): bending moduli kB[n_caps] (finite, >= 0; 0 = none,
  * the default) of the capsules first_id .. first_id + n_caps - 1.  Each node
@@ -227,7 +261,12 @@ int lbm_reference_relax(lbm_ctx* ctx, int32_t nsteps, double gamma, double w, do
  * relative to its start. */
 int lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
-/* Kernel groups of one step, in launch order (for lbm_step_timed). */
+/* Kernel groups of one step, in launch order (for lbm_step_timed).  Under
+ * the bounce-back coupling (coupling 1) LBM_K_CLEAR holds the step's head
+ * (labels, link list, fresh nodes, the bounce-back of the crossing
+ * populations and the tile flags), LBM_K_SPREAD the Shan-Chen sum across
+ * the membranes and LBM_K_INTERP the node update; the bin and spreading
+ * groups are empty. */
 enum {
     LBM_K_CLEAR = 0,    /* zero last step's immersed-boundary tiles        */
     LBM_K_DENSITY = 1,  /* density pass over the lattice                   */
@@ -282,6 +321,18 @@ int lbm_get_node_forces(lbm_ctx* ctx, float* F);
  * F_ib [3][N] and the virtual densities phi [2][N] (A, B) of the colour of
  * Sec. II.D.  Synchronises; LBM_ESTATE before a step. */
 int lbm_get_spread(lbm_ctx* ctx, float* Fib, float* phi);
+
+/* Labels of the bounce-back coupling (coupling 1; the inside and outside of
+ * each membrane that Sec. II.C and II.D separate): labels[N] receives, per
+ * lattice node ([z][y][x], x fastest), the index of the capsule whose closed
+ * surface holds it, or -1, for the membranes at the current node positions
+ * (those the next step streams across).  Recomputed on the device from the
+ * positions.  LBM_EINVAL under coupling 0.  Synchronises. */
+int lbm_debug_labels(lbm_ctx* ctx, int32_t* labels);
+
+/* Boundary-node velocities V [nodes][3] (coupling 1; Sec. II.B), zero under
+ * the immersed boundary's massless nodes.  Synchronises. */
+int lbm_get_node_velocities(lbm_ctx* ctx, float* V);
 
 /* Debugging (no passage of the paper: the spreading's own bookkeeping).
  * Binning of the current node positions: tile_of_node[nodes] is the index

@@ -46,8 +46,10 @@ Each element quantity goes to its three nodes in equal thirds (Sec. II.C).
 
 Readings where the paper is silent (listed with the design readings):
 labels by the closed surface (a node exactly on it is measure-zero); the
-crossed element of a link is the one the segment between the two nodes
-pierces (nearest to the first node if several); the nearest element of a
+crossed element of a link, for both of its ends, is the one the segment
+between the two nodes pierces nearest the link's start node (the end from
+which it points along a positive half-direction), which a wrinkled membrane
+can make differ from the first one seen from the other end; the nearest element of a
 fresh node is the one with the nearest centroid; Delta rho^c of eq.
 method:masscorrection is the component's total mass minus its initial
 total, <rho^c> / rho_init^c the per-node average of the start, V_sys the
@@ -192,9 +194,10 @@ class BounceBackSim:
 
     def crossed_face(self, k, x, y):
         """Faces of capsule k pierced by the segments from lattice nodes x to
-        y ([K, 3] index triples, y = x + c_i): the one nearest x, or the one
-        whose centroid is nearest the segment's midpoint when no face is
-        pierced (a link grazing an edge)."""
+        y ([K, 3] index triples, y = x + c_i): the one pierced nearest x
+        (crossing parameters compared at single precision, then the lowest
+        face index), or the one whose centroid is nearest the segment's
+        midpoint when no face is pierced (a link grazing an edge)."""
         P0 = self._unwrap(k, x)
         d = (y - x).to(DT)
         n = torch.tensor([self.nx, self.ny, self.nz], dtype=DT)
@@ -204,8 +207,8 @@ class BounceBackSim:
         X, tri = self.X[k], self.caps[k]["tri"]
         cen = X[tri].mean(1)
         for s in range(0, P0.shape[0], 256):
-            t = segment_hits(P0[s:s + 256], P1[s:s + 256], X, tri)
-            tmin, arg = t.min(1)
+            t = segment_hits(P0[s:s + 256], P1[s:s + 256], X, tri).to(torch.float32)
+            tmin, arg = t.min(1)          # (the first index among equal minima)
             mid = 0.5 * (P0[s:s + 256] + P1[s:s + 256])
             near = ((cen.unsqueeze(0) - mid.unsqueeze(1)) ** 2).sum(2).argmin(1)
             out[s:s + 256] = torch.where(torch.isfinite(tmin), arg, near)
@@ -232,9 +235,13 @@ class BounceBackSim:
             la, lb = L[m], Lnb[m]
             cap = torch.where(la >= 0, la, lb)
             face = torch.empty(xs.shape[0], dtype=torch.int64)
+            # one element per link, for both of its ends: the face pierced
+            # nearest the link's start node, the end from which the link
+            # points along a positive half-direction (odd i)
+            s0, s1 = (xs, ys) if i % 2 == 1 else (ys, xs)
             for k in torch.unique(cap).tolist():
                 sel = cap == k
-                face[sel] = self.crossed_face(k, xs[sel], ys[sel])
+                face[sel] = self.crossed_face(k, s0[sel], s1[sel])
             out.append((i, xs, cap, face))
         return out
 

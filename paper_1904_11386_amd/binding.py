@@ -30,11 +30,13 @@ class Params(C.Structure):
                 ("wall_u_lo", C.c_double * 3), ("wall_u_hi", C.c_double * 3),
                 ("z_interface", C.c_double), ("mass_tol", C.c_double), ("wet_scale", C.c_double),
                 ("ring_len", C.c_int32), ("stream_policy", C.c_int32), ("zchunk", C.c_int32),
-                ("psi_kind", C.c_int32), ("rep_eps", C.c_double), ("rep_d0", C.c_double)]
+                ("psi_kind", C.c_int32), ("rep_eps", C.c_double), ("rep_d0", C.c_double),
+                ("coupling", C.c_int32), ("node_mass", C.c_double), ("mass_c0", C.c_double)]
 
 
 class Obs(C.Structure):
-    _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3), ("step", C.c_int64)]
+    _fields_ = [("mass", C.c_double * 2), ("momentum", C.c_double * 3), ("step", C.c_int64),
+                ("particle_momentum", C.c_double * 3), ("pending_momentum", C.c_double * 3)]
 
 
 class CapObs(C.Structure):
@@ -44,7 +46,8 @@ class CapObs(C.Structure):
 
 _lib = None
 
-EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_bending", "lbm_reference_relax",
+EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_velocity", "lbm_capsules_bending",
+           "lbm_reference_relax", "lbm_debug_labels", "lbm_get_node_velocities",
            "lbm_step", "lbm_step_timed", "lbm_observables",
            "lbm_get_fields", "lbm_get_nodes", "lbm_get_node_forces", "lbm_get_spread",
            "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_adjoint_forward", "lbm_adjoint_backward",
@@ -71,6 +74,9 @@ def load(path: str = None):
         "lbm_init": ([P(Params), P(C.c_float), P(C.c_float), vp, i64, i64, i64, vp, P(vp)], C.c_int),
         "lbm_capsules_add": ([vp, i32, P(i32), P(i32), P(d), P(i32), P(d), P(d), P(d), P(d), P(i32)], C.c_int),
         "lbm_capsules_bending": ([vp, i32, i32, P(d)], C.c_int),
+        "lbm_capsules_velocity": ([vp, i32, i32, P(d), i32], C.c_int),
+        "lbm_debug_labels": ([vp, P(i32)], C.c_int),
+        "lbm_get_node_velocities": ([vp, P(C.c_float)], C.c_int),
         "lbm_reference_relax": ([vp, i32, C.c_double, C.c_double, C.c_double, C.c_double], C.c_int),
         "lbm_step": ([vp, i32], C.c_int),
         "lbm_step_timed": ([vp, i32, P(d)], C.c_int),
@@ -113,7 +119,7 @@ def _ptr(a, ctype):
 def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0), wall_u_hi=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
                 check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0, stream_policy=0,
-                zchunk=0, rep_eps=0.0, rep_d0=1.25, psi_kind=0):
+                zchunk=0, rep_eps=0.0, rep_d0=1.25, psi_kind=0, coupling=0, node_mass=5.0, mass_c0=2500.0):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -136,6 +142,9 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.rep_eps = rep_eps
     p.rep_d0 = rep_d0
     p.psi_kind = psi_kind
+    p.coupling = coupling
+    p.node_mass = node_mass
+    p.mass_c0 = mass_c0
     return p
 
 
@@ -201,6 +210,26 @@ class Sim:
         self._check(self.lib.lbm_reference_relax(self.ctx, int(nsteps), float(gamma), float(w), float(z_interface),
                                                  float(mobility)))
 
+    def set_velocity(self, first_id, v, prescribed=False):
+        """Initial (and, when prescribed, fixed) node velocity of each capsule
+        first_id .. first_id + len(v) - 1 (bounce-back coupling)."""
+        v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 3))
+        self._check(self.lib.lbm_capsules_velocity(self.ctx, int(first_id), v.shape[0], _ptr(v, C.c_double),
+                                                   1 if prescribed else 0))
+
+    def labels(self):
+        """Per lattice node: the capsule whose membrane encloses it, or -1
+        (bounce-back coupling), for the current node positions."""
+        p = self.params
+        out = np.empty(self.N, np.int32)
+        self._check(self.lib.lbm_debug_labels(self.ctx, _ptr(out, C.c_int32)))
+        return out.reshape((p.nz, p.ny, p.nx))
+
+    def node_velocities(self):
+        V = np.empty((self.n_nodes, 3), np.float32)
+        self._check(self.lib.lbm_get_node_velocities(self.ctx, _ptr(V, C.c_float)))
+        return V
+
     def set_bending(self, first_id, kB):
         """Helfrich bending moduli of the capsules first_id .. first_id + len(kB) - 1."""
         kB = np.ascontiguousarray(kB, dtype=np.float64)
@@ -223,7 +252,8 @@ class Sim:
         o = Obs()
         caps = (CapObs * max(self.n_caps, 1))()
         self._check(self.lib.lbm_observables(self.ctx, C.byref(o), caps if self.n_caps else None))
-        out = dict(mass=np.array(o.mass[:]), momentum=np.array(o.momentum[:]), step=o.step, caps=[])
+        out = dict(mass=np.array(o.mass[:]), momentum=np.array(o.momentum[:]), step=o.step, caps=[],
+                   particle_momentum=np.array(o.particle_momentum[:]), pending_momentum=np.array(o.pending_momentum[:]))
         for k in range(self.n_caps):
             c = caps[k]
             out["caps"].append(dict(com=np.array(c.com[:]), V=c.volume, A=c.area, axes=np.array(c.axes[:]),
@@ -325,7 +355,8 @@ def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
                     check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len,
                     stream_policy=stream_policy, zchunk=zchunk, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0,
-                    psi_kind=wl.psi_kind)
+                    psi_kind=wl.psi_kind, coupling=getattr(wl, "coupling", 0),
+                    node_mass=getattr(wl, "node_mass", 5.0), mass_c0=getattr(wl, "mass_c0", 2500.0))
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()
@@ -333,4 +364,8 @@ def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="
         kB = np.array([c.kB for c in wl.capsules], np.float64)
         if (kB > 0).any():
             s.set_bending(first, kB)
+        if getattr(wl, "coupling", 0) == 1:
+            for k, c in enumerate(wl.capsules):
+                if any(c.v) or c.prescribed:
+                    s.set_velocity(first + k, [c.v], c.prescribed)
     return s

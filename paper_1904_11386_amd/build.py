@@ -10,7 +10,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
-SOURCES = ["k_fluid.hip", "k_ibm.hip", "lbm_api.hip"]
+SOURCES = ["k_fluid.hip", "k_ibm.hip", "k_bb.hip", "lbm_api.hip"]
 LIB = os.path.join(HERE, "liblbm.so")
 
 

@@ -1,0 +1,609 @@
+// The paper's own fluid-structure coupling (gfx950): half-way bounce-back on
+// the moving membrane (Sec. II.C, eqs. method:SBB and
+// method:momentumtransfer), the Shan-Chen sum across it with densities
+// interpolated from the viewer's side and the colour offset (Sec. II.D,
+// eq. method:interpolateshanchen), fresh nodes with the adaptive mass
+// correction (Sec. II.E, eqs. method:freshnodes and method:masscorrection)
+// and the inertial node update (Sec. II.B, first-order Euler; node mass of
+// Sec. III).  The lattice kernels are the immersed boundary's; the coupling
+// works on the few lattice nodes next to each membrane.
+//
+// Head of step n (nodes at X^n, V^n; populations f*^{n-1}):
+//   k_bb_box      per capsule: the anchor-relative box of its nodes widened by
+//                 MARGIN, the mean node offset; counters and volumes zeroed
+//   k_bb_clear    per box: new labels -1, link bits 0
+//   k_bb_links    per triangle: the lattice links it pierces (FP64
+//                 Moeller-Trumbore over its bounding box); each link listed
+//                 once; its element is the triangle pierced nearest the
+//                 link's start node (the end from which it points along a
+//                 positive half-direction; lowest index among ties at single
+//                 precision), for both of its ends; the parity of the
+//                 crossings of each +z link
+//   k_bb_label    per box column: inside where the +z crossings below are odd
+//   k_bb_detect   per box: fresh nodes (label changed) listed, once each
+//   k_bb_refill   per fresh node: the density interpolated from its side's
+//                 non-fresh neighbours, mass-corrected and clamped to their
+//                 range; the velocity of the nearest element; equilibrium
+//                 populations; removed minus created momentum to the element
+//   k_bb_commit   per box: labels := new labels
+//   k_bb_link_density  per listed link: the densities of both ends, before
+//                 any population is bounced
+//   k_bb_fixup    per listed link whose ends differ in label: each end gets
+//                 its own outgoing population back with the moving-element
+//                 term, stored where its next pull reads; the exchanged
+//                 momentum to the element's nodes
+//   k_bb_ledger   the mass the step's refills and bounce-backs added, into
+//                 the FP64 ledger the mass correction reads
+// The mass correction needs each component's mass change since the start.
+// Collision and streaming conserve mass exactly; only the moving-element
+// bounce-back term and the fresh-node refills change it, so the library
+// keeps that change as an FP64 ledger of those events (the same quantity in
+// exact arithmetic).  A sum over the FP32 lattice would carry the storage's
+// rounding, which the correction's gain (C0 sum rho_init / rho_init^c / V_sys,
+// about 0.5 per unit of mass here) would turn into density changes of 1e-4
+// at fresh nodes.
+//   k_bb_unflag, k_bb_flag  tile flags reset; per box: Shan-Chen corrections
+//                 zeroed, its tiles flagged for the collide
+// In the step, after the density pass:
+//   k_bb_sc       per listed crossing: the corrections dS of both ends'
+//                 Shan-Chen sums for the neighbour across, the force those
+//                 pairs would put on the far side to the element's nodes
+//   (the collide adds dS inside flagged tiles)
+//   k_bb_advance  per node: F = elastic + half this and half the last
+//                 exchanged momentum + reactions; V += F / m (or the
+//                 prescribed V); X += V
+// Every element quantity goes to its three nodes in equal thirds (Sec. II.C).
+#include "lbm_internal.h"
+
+namespace lbmx {
+
+namespace {
+
+constexpr int MARGIN = 3;       // box margin around a capsule's nodes, lattice units
+constexpr int CNT_LINKS = 0, CNT_FRESH = 1, CNT_FLAGS = 2;
+constexpr unsigned PARITY_BIT = 1u << 16;
+// overflow and consistency flags in bb_count[CNT_FLAGS]
+constexpr int FLAG_BOX = 1, FLAG_LINKS = 2, FLAG_FRESH = 4, FLAG_PARITY = 8;
+
+__device__ __forceinline__ int wrapi(int v, int n) {
+    v %= n;
+    return v < 0 ? v + n : v;
+}
+
+__device__ __forceinline__ int64_t lat(const Lattice& L, int x, int y, int z) {
+    return ((int64_t)wrapi(z, L.nz) * L.ny + wrapi(y, L.ny)) * L.nx + wrapi(x, L.nx);
+}
+
+// the D3Q19 direction of half-direction d = 0..8: +x, +y, +z and the six
+// diagonals with a positive first non-zero component
+__device__ __forceinline__ int half_dir(int d) { return 2 * d + 1; }
+
+__device__ __forceinline__ void node_rel(const Dev& d, int b, double p[3]) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) p[k] = (double)d.off_hi[3 * b + k] + (double)d.off_lo[3 * b + k];
+}
+
+__device__ __forceinline__ double psi_of(double r, int kind) { return kind ? 1.0 - exp(-r) : r; }
+
+// A box cell of capsule `cap` for the linear cell index c, or false.
+__device__ __forceinline__ bool box_cell(const Dev& d, int cap, int c, int q[3]) {
+    const int* bx = d.bbox + 8 * cap;
+    const int ex = bx[3] - bx[0] + 1, ey = bx[4] - bx[1] + 1, ez = bx[5] - bx[2] + 1;
+    if (c >= ex * ey * ez) return false;
+    q[0] = bx[0] + c % ex;
+    q[1] = bx[1] + (c / ex) % ey;
+    q[2] = bx[2] + c / (ex * ey);
+    return true;
+}
+
+__device__ __forceinline__ void add3(double* a, const double v[3], double s) {
+    unsafeAtomicAdd(a + 0, v[0] * s);
+    unsafeAtomicAdd(a + 1, v[1] * s);
+    unsafeAtomicAdd(a + 2, v[2] * s);
+}
+
+// ---- head of the step ----------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bb_box(Dev d, int ext) {
+    __shared__ double sh[7][256];
+    const int cap = blockIdx.x;
+    const CapDev& C = d.caps[cap];
+    double mn[3] = {1e300, 1e300, 1e300}, mx[3] = {-1e300, -1e300, -1e300}, sm[3] = {0, 0, 0};
+    for (int b = C.node_start + threadIdx.x; b < C.node_start + C.node_count; b += blockDim.x) {
+        double p[3];
+        node_rel(d, b, p);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            mn[k] = fmin(mn[k], p[k]);
+            mx[k] = fmax(mx[k], p[k]);
+            sm[k] += p[k];
+        }
+    }
+    for (int k = 0; k < 3; ++k) {
+        sh[k][threadIdx.x] = mn[k];
+        sh[3 + k][threadIdx.x] = mx[k];
+    }
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s)
+            for (int k = 0; k < 3; ++k) {
+                sh[k][threadIdx.x] = fmin(sh[k][threadIdx.x], sh[k][threadIdx.x + s]);
+                sh[3 + k][threadIdx.x] = fmax(sh[3 + k][threadIdx.x], sh[3 + k][threadIdx.x + s]);
+            }
+        __syncthreads();
+    }
+    double lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = sh[k][0];
+        hi[k] = sh[3 + k][0];
+    }
+    __syncthreads();
+    for (int k = 0; k < 3; ++k) {
+        sh[k][threadIdx.x] = sm[k];
+        __syncthreads();
+        for (int s = 128; s > 0; s >>= 1) {
+            if ((int)threadIdx.x < s) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        int* bx = d.bbox + 8 * cap;
+        for (int k = 0; k < 3; ++k) {
+            bx[k] = (int)floor(lo[k]) - MARGIN;
+            bx[3 + k] = (int)ceil(hi[k]) + MARGIN;
+            if (bx[3 + k] - bx[k] + 1 > ext) {
+                atomicOr(&d.bb_count[CNT_FLAGS], FLAG_BOX);
+                bx[3 + k] = bx[k] + ext - 1;
+            }
+            d.bb_com[3 * cap + k] = sh[k][0] / C.node_count;
+        }
+        d.capV[cap] = 0.0;
+        if (cap == 0) {
+            d.bb_count[CNT_LINKS] = 0;
+            d.bb_count[CNT_FRESH] = 0;
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bb_clear(Lattice L, Dev d) {
+    const int cap = blockIdx.y;
+    int q[3];
+    if (!box_cell(d, cap, blockIdx.x * blockDim.x + threadIdx.x, q)) return;
+    const CapDev& C = d.caps[cap];
+    const int64_t node = lat(L, C.anchor[0] + q[0], C.anchor[1] + q[1], C.anchor[2] + q[2]);
+    d.lab_new[node] = -1;
+    d.lmask[node] = 0u;
+    for (int k = 0; k < 9; ++k) d.lkey[k * L.n + node] = ~0ull;
+}
+
+// Segment p -> p + c against triangle (a, b, c): Moeller and Trumbore, FP64,
+// the crossing parameter t in [0, 1) and the closed triangle.
+__device__ __forceinline__ bool seg_hits(const double p[3], int cx_, int cy_, int cz_, const double a[3],
+                                         const double e1[3], const double e2[3], double& tout) {
+    const double dir[3] = {(double)cx_, (double)cy_, (double)cz_};
+    const double pv[3] = {dir[1] * e2[2] - dir[2] * e2[1], dir[2] * e2[0] - dir[0] * e2[2],
+                          dir[0] * e2[1] - dir[1] * e2[0]};
+    const double det = e1[0] * pv[0] + e1[1] * pv[1] + e1[2] * pv[2];
+    if (det == 0.0) return false;
+    const double inv = 1.0 / det;
+    const double tv[3] = {p[0] - a[0], p[1] - a[1], p[2] - a[2]};
+    const double u = (tv[0] * pv[0] + tv[1] * pv[1] + tv[2] * pv[2]) * inv;
+    if (u < 0.0 || u > 1.0) return false;
+    const double qv[3] = {tv[1] * e1[2] - tv[2] * e1[1], tv[2] * e1[0] - tv[0] * e1[2], tv[0] * e1[1] - tv[1] * e1[0]};
+    const double v = (dir[0] * qv[0] + dir[1] * qv[1] + dir[2] * qv[2]) * inv;
+    if (v < 0.0 || u + v > 1.0) return false;
+    const double t = (e2[0] * qv[0] + e2[1] * qv[1] + e2[2] * qv[2]) * inv;
+    tout = t;
+    return t >= 0.0 && t < 1.0;
+}
+
+__global__ __launch_bounds__(256) void k_bb_links(Lattice L, Dev d, int n_faces, int link_cap) {
+    const int f = blockIdx.x * blockDim.x + threadIdx.x;
+    if (f >= n_faces) return;
+    const CapDev& C = d.caps[d.face_cap[f]];
+    double V[3][3];
+    for (int k = 0; k < 3; ++k) node_rel(d, d.tri[3 * f + k], V[k]);
+    double e1[3], e2[3];
+    int lo[3], hi[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = V[1][k] - V[0][k];
+        e2[k] = V[2][k] - V[0][k];
+        lo[k] = (int)floor(fmin(V[0][k], fmin(V[1][k], V[2][k]))) - 1;
+        hi[k] = (int)floor(fmax(V[0][k], fmax(V[1][k], V[2][k]))) + 1;
+        if (hi[k] - lo[k] > 16) {    // a torn mesh: report, do not scan
+            atomicOr(&d.bb_count[CNT_FLAGS], FLAG_BOX);
+            return;
+        }
+    }
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y)
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                const double p[3] = {(double)x, (double)y, (double)z};
+                for (int dh = 0; dh < 9; ++dh) {
+                    const int i = half_dir(dh);
+                    double t;
+                    if (!seg_hits(p, cx(i), cy(i), cz(i), V[0], e1, e2, t)) continue;
+                    const int64_t node = lat(L, C.anchor[0] + x, C.anchor[1] + y, C.anchor[2] + z);
+                    if (i == 5) atomicXor(&d.lmask[node], PARITY_BIT);
+                    // the link's element: nearest crossing, then lowest index
+                    const unsigned long long key =
+                        ((unsigned long long)__float_as_uint((float)t) << 32) | (unsigned long long)(unsigned)f;
+                    atomicMin(&d.lkey[dh * L.n + node], key);
+                    const unsigned bit = 1u << dh;
+                    if (atomicOr(&d.lmask[node], bit) & bit) continue;       // listed by another triangle
+                    const int k = atomicAdd(&d.bb_count[CNT_LINKS], 1);
+                    if (k < link_cap)
+                        d.links[k] = make_int4((int)node, dh, 0, 0);
+                    else
+                        atomicOr(&d.bb_count[CNT_FLAGS], FLAG_LINKS);
+                }
+            }
+}
+
+__global__ __launch_bounds__(256) void k_bb_label(Lattice L, Dev d) {
+    const int cap = blockIdx.y;
+    const int* bx = d.bbox + 8 * cap;
+    const int ex = bx[3] - bx[0] + 1, ey = bx[4] - bx[1] + 1;
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= ex * ey) return;
+    const CapDev& C = d.caps[cap];
+    const int x = C.anchor[0] + bx[0] + c % ex, y = C.anchor[1] + bx[1] + c / ex;
+    bool inside = false;    // the box bottom lies outside (margin)
+    for (int z = bx[2]; z <= bx[5]; ++z) {
+        const int64_t node = lat(L, x, y, C.anchor[2] + z);
+        if (inside) d.lab_new[node] = cap;
+        inside = inside != ((d.lmask[node] & PARITY_BIT) != 0);
+    }
+    if (inside) atomicOr(&d.bb_count[CNT_FLAGS], FLAG_PARITY);
+}
+
+__global__ __launch_bounds__(256) void k_bb_detect(Lattice L, Dev d, int fresh_cap) {
+    const int cap = blockIdx.y;
+    int q[3];
+    if (!box_cell(d, cap, blockIdx.x * blockDim.x + threadIdx.x, q)) return;
+    const CapDev& C = d.caps[cap];
+    const int64_t node = lat(L, C.anchor[0] + q[0], C.anchor[1] + q[1], C.anchor[2] + q[2]);
+    const int a = d.lab_new[node], b = d.lab[node];
+    // each changed node is listed by one capsule: its new one, or its old one when it left
+    if (a != b && (a == cap || (a == -1 && b == cap))) {
+        const int k = atomicAdd(&d.bb_count[CNT_FRESH], 1);
+        if (k < fresh_cap)
+            d.fresh[k] = (int)node;
+        else
+            atomicOr(&d.bb_count[CNT_FLAGS], FLAG_FRESH);
+    }
+}
+
+// committed ledger [0..1] += the pending changes [2..3] of this head
+__global__ void k_bb_ledger(Dev d) {
+    if (threadIdx.x < 2) {
+        d.bb_mass[threadIdx.x] += d.bb_mass[2 + threadIdx.x];
+        d.bb_mass[2 + threadIdx.x] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bb_refill(Lattice L, Dev d, BBConst K, float2* __restrict__ f,
+                                                 const float* __restrict__ rho) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= min(d.bb_count[CNT_FRESH], (int)(gridDim.x * blockDim.x))) return;
+    const int64_t N = L.n;
+    const int64_t node = d.fresh[e];
+    const int x = (int)(node % L.nx), y = (int)((node / L.nx) % L.ny), z = (int)(node / ((int64_t)L.nx * L.ny));
+    const int ell = d.lab_new[node];
+    // the density interpolated from the non-fresh neighbours on the node's side
+    double sum[2] = {0, 0}, mn[2] = {1e300, 1e300}, mx[2] = {-1e300, -1e300};
+    int cnt = 0;
+    for (int i = 1; i < Q; ++i) {
+        const int64_t nb = lat(L, x + cx(i), y + cy(i), z + cz(i));
+        const int ln = d.lab_new[nb];
+        if (ln != ell || ln != d.lab[nb]) continue;
+        ++cnt;
+        for (int c = 0; c < 2; ++c) {
+            const double r = rho[c * N + nb];
+            sum[c] += r;
+            mn[c] = fmin(mn[c], r);
+            mx[c] = fmax(mx[c], r);
+        }
+    }
+    double rf[2];
+    for (int c = 0; c < 2; ++c) {
+        if (cnt == 0) {
+            rf[c] = rho[c * N + node];
+        } else {
+            const double corr = 1.0 - K.c0 * ((K.rho_init[0] + K.rho_init[1]) / K.rho_init[c]) *
+                                          d.bb_mass[c] / K.vsys;
+            rf[c] = fmin(fmax(sum[c] / cnt * corr, mn[c]), mx[c]);
+        }
+    }
+    // the nearest element (nearest centroid) of the capsule whose membrane passed
+    const int cap = ell >= 0 ? ell : d.lab[node];
+    const CapDev& C = d.caps[cap];
+    double p[3] = {(double)(x - C.anchor[0]), (double)(y - C.anchor[1]), (double)(z - C.anchor[2])};
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    for (int k = 0; k < 3; ++k) p[k] -= nn[k] * rint((p[k] - d.bb_com[3 * cap + k]) / nn[k]);
+    int best = C.face_start;
+    double bd = 1e300;
+    for (int ff = C.face_start; ff < C.face_start + C.face_count; ++ff) {
+        double s[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k) {
+            double q[3];
+            node_rel(d, d.tri[3 * ff + k], q);
+            for (int j = 0; j < 3; ++j) s[j] += q[j];
+        }
+        double dd = 0.0;
+        for (int j = 0; j < 3; ++j) {
+            const double t = s[j] / 3.0 - p[j];
+            dd += t * t;
+        }
+        if (dd < bd) {
+            bd = dd;
+            best = ff;
+        }
+    }
+    double v[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (int j = 0; j < 3; ++j) v[j] += d.node_V[3 * d.tri[3 * best + k] + j] / 3.0;
+    // removed momentum, new populations, created momentum
+    double old[3] = {0, 0, 0}, dm[2] = {0, 0};
+    const float uu = (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    for (int i = 0; i < Q; ++i) {
+        const float2 g = f[i * N + node];
+        const double s = (double)g.x + (double)g.y;
+        old[0] += s * cx(i);
+        old[1] += s * cy(i);
+        old[2] += s * cz(i);
+        const float cu = (float)(cx(i) * v[0] + cy(i) * v[1] + cz(i) * v[2]);
+        const float t = wgt(i) * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+        const float2 nf = make_float2((float)rf[0] * t, (float)rf[1] * t);
+        f[i * N + node] = nf;
+        dm[0] += (double)nf.x - (double)g.x;
+        dm[1] += (double)nf.y - (double)g.y;
+    }
+    unsafeAtomicAdd(&d.bb_mass[2], dm[0]);
+    unsafeAtomicAdd(&d.bb_mass[3], dm[1]);
+    double q[3];
+    for (int j = 0; j < 3; ++j) q[j] = (old[j] - (rf[0] + rf[1]) * v[j]) / 3.0;
+    for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * best + k], q, 1.0);
+}
+
+__global__ __launch_bounds__(256) void k_bb_commit(Lattice L, Dev d) {
+    const int cap = blockIdx.y;
+    int q[3];
+    if (!box_cell(d, cap, blockIdx.x * blockDim.x + threadIdx.x, q)) return;
+    const CapDev& C = d.caps[cap];
+    const int64_t node = lat(L, C.anchor[0] + q[0], C.anchor[1] + q[1], C.anchor[2] + q[2]);
+    d.lab[node] = d.lab_new[node];
+}
+
+__device__ __forceinline__ void node_density(const float2* __restrict__ f, int64_t N, int64_t node, double r[2]) {
+    r[0] = r[1] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+        const float2 g = f[i * N + node];
+        r[0] += g.x;
+        r[1] += g.y;
+    }
+}
+
+// The densities of both ends of each listed link, before any population is
+// bounced (a node with several crossing links has them all rewritten).
+__global__ __launch_bounds__(256) void k_bb_link_density(Lattice L, Dev d, const float2* __restrict__ f,
+                                                         int link_cap) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= min(d.bb_count[CNT_LINKS], link_cap)) return;
+    const int4 rec = d.links[e];
+    const int64_t xn = rec.x;
+    const int i = half_dir(rec.y);
+    const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
+    const int64_t yn = lat(L, x + cx(i), y + cy(i), z + cz(i));
+    double rx[2], ry[2];
+    node_density(f, L.n, xn, rx);
+    node_density(f, L.n, yn, ry);
+    d.link_rho[e] = make_double4(rx[0], rx[1], ry[0], ry[1]);
+}
+
+__global__ __launch_bounds__(256) void k_bb_fixup(Lattice L, Dev d, float2* __restrict__ f, int link_cap) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= min(d.bb_count[CNT_LINKS], link_cap)) return;
+    const int4 rec = d.links[e];
+    const int64_t N = L.n;
+    const int64_t xn = rec.x;
+    const int i = half_dir(rec.y), j = opp(i);
+    const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
+    const int64_t yn = lat(L, x + cx(i), y + cy(i), z + cz(i));
+    if (d.lab[xn] == d.lab[yn]) return;       // the link crosses the membrane twice, or not
+    const int face = (int)(unsigned)(d.lkey[rec.y * N + xn] & 0xffffffffull);
+    double v0[3] = {0, 0, 0};
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) v0[a] += d.node_V[3 * d.tri[3 * face + k] + a] / 3.0;
+    const double4 lr = d.link_rho[e];
+    const double rx[2] = {lr.x, lr.y}, ry[2] = {lr.z, lr.w};
+    const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+    const double cv = ci[0] * v0[0] + ci[1] * v0[1] + ci[2] * v0[2];      // c_i . v0 = -(c_j . v0)
+    const double w = wgt(i);
+    // the slot (x, i) is what the pull at y reads along c_i, the slot (y, j)
+    // what the pull at x reads along c_j
+    const float2 a = f[i * N + xn];      // x's outgoing population towards y
+    const float2 b = f[j * N + yn];      // y's outgoing population towards x
+    const float2 back_x = make_float2((float)((double)a.x - 6.0 * w * rx[0] * cv),
+                                      (float)((double)a.y - 6.0 * w * rx[1] * cv));     // to x along c_j
+    const float2 back_y = make_float2((float)((double)b.x + 6.0 * w * ry[0] * cv),
+                                      (float)((double)b.y + 6.0 * w * ry[1] * cv));     // to y along c_i
+    f[j * N + yn] = back_x;
+    f[i * N + xn] = back_y;
+    // the moving-element terms change each side's mass (as stored)
+    unsafeAtomicAdd(&d.bb_mass[2], ((double)back_x.x - a.x) + ((double)back_y.x - b.x));
+    unsafeAtomicAdd(&d.bb_mass[3], ((double)back_x.y - a.y) + ((double)back_y.y - b.y));
+    // momentum to the element: [out + back] c_out at each end
+    const double sx = (double)a.x + a.y + back_x.x + back_x.y;
+    const double sy = (double)b.x + b.y + back_y.x + back_y.y;
+    double dp[3];
+    for (int k = 0; k < 3; ++k) dp[k] = (sx - sy) * ci[k] / 3.0;
+    for (int k = 0; k < 3; ++k) add3(d.P_cur + 3 * d.tri[3 * face + k], dp, 1.0);
+}
+
+__global__ __launch_bounds__(256) void k_bb_unflag(Lattice L, Dev d, int n_tiles) {
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < n_tiles; t += gridDim.x * blockDim.x) d.tile_flag[t] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_bb_flag(Lattice L, Dev d) {
+    const int cap = blockIdx.y;
+    int q[3];
+    if (!box_cell(d, cap, blockIdx.x * blockDim.x + threadIdx.x, q)) return;
+    const CapDev& C = d.caps[cap];
+    const int x = wrapi(C.anchor[0] + q[0], L.nx), y = wrapi(C.anchor[1] + q[1], L.ny),
+              z = wrapi(C.anchor[2] + q[2], L.nz);
+    const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+    for (int k = 0; k < 6; ++k) d.fib[k * L.n + node] = 0.0f;
+    d.tile_flag[((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3)] = 1;
+}
+
+// ---- the Shan-Chen sum across the membrane ---------------------------------
+
+// The densities of node `of`'s neighbours with label `side`, averaged
+// (eq. method:interpolateshanchen); `of` has at least one such neighbour,
+// the node across from which it is seen.
+__device__ __forceinline__ void bound_density(const Lattice& L, const Dev& d, const float* __restrict__ rho,
+                                              int64_t of, int side, double r[2]) {
+    const int x = (int)(of % L.nx), y = (int)((of / L.nx) % L.ny), z = (int)(of / ((int64_t)L.nx * L.ny));
+    double s[2] = {0, 0};
+    int cnt = 0;
+    for (int q = 1; q < Q; ++q) {
+        const int64_t nb = lat(L, x + cx(q), y + cy(q), z + cz(q));
+        if (d.lab[nb] != side) continue;
+        ++cnt;
+        s[0] += rho[nb];
+        s[1] += rho[L.n + nb];
+    }
+    r[0] = s[0] / cnt;
+    r[1] = s[1] / cnt;
+}
+
+__global__ __launch_bounds__(256) void k_bb_sc(Lattice L, Dev d, BBConst K, const float* __restrict__ rho,
+                                              int link_cap) {
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= min(d.bb_count[CNT_LINKS], link_cap)) return;
+    const int4 rec = d.links[e];
+    const int64_t N = L.n;
+    const int64_t xn = rec.x;
+    const int i = half_dir(rec.y);
+    const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
+    const int64_t yn = lat(L, x + cx(i), y + cy(i), z + cz(i));
+    const int lx = d.lab[xn], ly = d.lab[yn];
+    if (lx == ly) return;
+    const int face = (int)(unsigned)(d.lkey[rec.y * N + xn] & 0xffffffffull);
+    const CapDev& C = d.caps[d.face_cap[face]];
+    const double w = wgt(i), G = L.G;
+    const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+    double react[3] = {0, 0, 0};
+    // end 0: x sees y along +c_i; end 1: y sees x along -c_i
+    for (int end = 0; end < 2; ++end) {
+        const int64_t self = end == 0 ? xn : yn, other = end == 0 ? yn : xn;
+        const double sg = end == 0 ? 1.0 : -1.0;
+        double rb[2];
+        bound_density(L, d, rho, other, end == 0 ? lx : ly, rb);
+        rb[C.pref] += C.rv_abs;
+        double pv[2], po[2], ps[2];
+        for (int c = 0; c < 2; ++c) {
+            pv[c] = psi_of(rb[c], K.psi_exp);
+            po[c] = psi_of(rho[c * N + other], K.psi_exp);
+            ps[c] = psi_of(rho[c * N + self], K.psi_exp);
+        }
+        // dS^c(self) += w (psi_virtual^c - psi^c(other)) c; the collide forms
+        // F^A = -G psi^A (S^B + dS^B) and F^B alike
+        for (int c = 0; c < 2; ++c)
+            for (int k = 0; k < 3; ++k)
+                if (ci[k] != 0.0)
+                    atomicAdd(&d.fib[(3 * c + k) * N + self], (float)(w * (pv[c] - po[c]) * sg * ci[k]));
+        // minus the force on self from the virtual neighbour
+        const double fr = G * w * (ps[0] * pv[1] + ps[1] * pv[0]) * sg;
+        for (int k = 0; k < 3; ++k) react[k] += fr * ci[k] / 3.0;
+    }
+    for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * face + k], react, 1.0);
+}
+
+// ---- node update ---------------------------------------------------------
+
+__global__ __launch_bounds__(256) void k_bb_advance(Dev d, BBConst K, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    const CapDev& C = d.caps[d.node_cap[b]];
+    for (int k = 0; k < 3; ++k) {
+        const double F = (double)d.node_F[3 * b + k] + 0.5 * (d.P_cur[3 * b + k] + d.P_prev[3 * b + k]) +
+                         d.QR[3 * b + k];
+        d.node_F[3 * b + k] = (float)F;
+        const float V = C.prescribed ? C.vp[k] : (float)((double)d.node_V[3 * b + k] + F * K.inv_mass);
+        d.node_V[3 * b + k] = V;
+        // compensated (hi, lo) += V, as in the immersed-boundary advection
+        const float a = d.off_hi[3 * b + k];
+        const float bb = d.off_lo[3 * b + k] + V;
+        const float s = a + bb;
+        const float bv = s - a;
+        const float err = (a - (s - bv)) + (bb - bv);
+        d.off_hi[3 * b + k] = s;
+        d.off_lo[3 * b + k] = err;
+        d.P_prev[3 * b + k] = d.P_cur[3 * b + k];
+        d.P_cur[3 * b + k] = 0.0;
+        d.QR[3 * b + k] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(256) void k_bb_init(Lattice L, Dev d) {
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < L.n; k += (int64_t)gridDim.x * blockDim.x) {
+        d.lab[k] = -1;
+        d.lab_new[k] = -1;
+        d.lmask[k] = 0u;
+    }
+}
+
+}  // namespace
+
+void launch_bb_init(const Lattice& L, Dev& d, hipStream_t s) {
+    hipLaunchKernelGGL(k_bb_init, dim3(2048), dim3(256), 0, s, L, d);
+}
+
+void launch_bb_geometry(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, int n_faces, bool detect_fresh,
+                        hipStream_t s) {
+    if (n_caps <= 0) return;
+    const int cells = z.ext * z.ext * z.ext;
+    const dim3 gbox((cells + 255) / 256, n_caps), gcol((z.ext * z.ext + 255) / 256, n_caps);
+    hipLaunchKernelGGL(k_bb_box, dim3(n_caps), dim3(256), 0, s, d, z.ext);
+    hipLaunchKernelGGL(k_bb_clear, gbox, dim3(256), 0, s, L, d);
+    hipLaunchKernelGGL(k_bb_links, dim3((n_faces + 255) / 256), dim3(256), 0, s, L, d, n_faces, z.link_cap);
+    hipLaunchKernelGGL(k_bb_label, gcol, dim3(256), 0, s, L, d);
+    if (detect_fresh) hipLaunchKernelGGL(k_bb_detect, gbox, dim3(256), 0, s, L, d, z.fresh_cap);
+}
+
+void launch_bb_refill(const Lattice& L, Dev& d, const BBSizes& z, const BBConst& k, void* fpost, const float* rho,
+                      int n_caps, hipStream_t s) {
+    if (n_caps <= 0) return;
+    const int cells = z.ext * z.ext * z.ext;
+    hipLaunchKernelGGL(k_bb_refill, dim3((z.fresh_cap + 63) / 64), dim3(64), 0, s, L, d, k, (float2*)fpost, rho);
+    hipLaunchKernelGGL(k_bb_commit, dim3((cells + 255) / 256, n_caps), dim3(256), 0, s, L, d);
+}
+
+void launch_bb_fixup(const Lattice& L, Dev& d, const BBSizes& z, void* fpost, int n_caps, hipStream_t s) {
+    if (n_caps <= 0) return;
+    const dim3 g((z.link_cap + 255) / 256);
+    hipLaunchKernelGGL(k_bb_link_density, g, dim3(256), 0, s, L, d, (const float2*)fpost, z.link_cap);
+    hipLaunchKernelGGL(k_bb_fixup, g, dim3(256), 0, s, L, d, (float2*)fpost, z.link_cap);
+    hipLaunchKernelGGL(k_bb_ledger, dim3(1), dim3(64), 0, s, d);
+}
+
+void launch_bb_flags(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, hipStream_t s) {
+    const int nt = L.ntx * L.nty * L.ntz;
+    hipLaunchKernelGGL(k_bb_unflag, dim3(std::min((nt + 255) / 256, 1024)), dim3(256), 0, s, L, d, nt);
+    if (n_caps <= 0) return;
+    const int cells = z.ext * z.ext * z.ext;
+    hipLaunchKernelGGL(k_bb_flag, dim3((cells + 255) / 256, n_caps), dim3(256), 0, s, L, d);
+}
+
+void launch_bb_shan_chen(const Lattice& L, Dev& d, const BBSizes& z, const BBConst& k, const float* rho,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_bb_sc, dim3((z.link_cap + 255) / 256), dim3(256), 0, s, L, d, k, rho, z.link_cap);
+}
+
+void launch_bb_advance(Dev& d, const BBConst& k, int n_nodes, hipStream_t s) {
+    if (n_nodes > 0) hipLaunchKernelGGL(k_bb_advance, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, k, n_nodes);
+}
+
+}  // namespace lbmx

@@ -585,8 +585,12 @@ __global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ 
 
 // ---------------------------------------------------------------------------
 // Fused pull + force + collide.  MACRO: recompute the velocity of this
-// collision without storing populations (field read-back).
-template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI>
+// collision without storing populations (field read-back).  SHARP (the
+// bounce-back coupling): flagged tiles carry, instead of the immersed
+// boundary's force and virtual densities, corrections dS^A, dS^B to the
+// Shan-Chen neighbour sums from neighbours across a membrane (fib fields
+// 0..2 and 3..5), added before the force is formed.
+template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI, bool SHARP = false>
 __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
@@ -639,7 +643,7 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
     StageRegs<2> np;
     StageRegs<2> ne;
     auto load_plane = [&](int zz) {
-        if (IBM && near_ibm)
+        if (IBM && !SHARP && near_ibm)
             stage_load<true, 2, PSI>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, fib, tile_flag, L);
         else
             stage_load<false, 2, PSI>(np, P, zz, tid, rho_n, HALF ? ccu : nullptr, nullptr, nullptr, L);
@@ -703,14 +707,25 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
             const float rsum = ra + rb;
             // the node's own pseudo-potential
             const float pa = PSI ? psi_exp(ra) : ra, pb = PSI ? psi_exp(rb) : rb;
+            bool flagged = false;
+            if (SHARP && near_ibm) {
+                const int t = ((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3);
+                flagged = tile_flag[t] != 0;
+                if (flagged) {
+#pragma unroll
+                    for (int d = 0; d < 3; ++d) {
+                        sa[d] += ldx(fib + d * N + row, xo);
+                        sb[d] += ldx(fib + (3 + d) * N + row, xo);
+                    }
+                }
+            }
             float Fa[3], Fb[3];
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 Fa[d] = -L.G * pa * sb[d];
                 Fb[d] = -L.G * pb * sa[d];
             }
-            bool flagged = false;
-            if (IBM && near_ibm) {
+            if (IBM && !SHARP && near_ibm) {
                 const int t = ((z >> 3) * L.nty + (y >> 3)) * L.ntx + (x >> 3);
                 flagged = tile_flag[t] != 0;
                 if (flagged) {
@@ -1395,7 +1410,7 @@ void launch_compensate(const Lattice& L, const double* partial, double m0a, doub
     hipLaunchKernelGGL(k_compensate, dim3(1), dim3(1024), 0, s, partial, nb, m0a, m0b, cscale, par_cur, mass_out);
 }
 
-template <bool W, bool I, bool M, bool H, bool P>
+template <bool W, bool I, bool M, bool H, bool P, bool S = false>
 static void launch_collide_t(const Lattice& L, const void* fin, void* fout, const float* rho_n,
                              const float* rho_prev, const float* fib, const int* tile_flag, float* u,
                              const float* cscale, int par_prev, int par_cur, hipStream_t s) {
@@ -1404,19 +1419,31 @@ static void launch_collide_t(const Lattice& L, const void* fin, void* fout, cons
     // the velocity read-back (M) writes no populations; it runs in one policy
     if constexpr (!M) {
         if (L.cached) {
-            hipLaunchKernelGGL((k_collide<W, I, M, H, true, P>), grid, block, 0, s, (const PopT<H>*)fin,
+            hipLaunchKernelGGL((k_collide<W, I, M, H, true, P, S>), grid, block, 0, s, (const PopT<H>*)fin,
                                (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
             return;
         }
     }
-    hipLaunchKernelGGL((k_collide<W, I, M, H, false, P>), grid, block, 0, s, (const PopT<H>*)fin, (PopT<H>*)fout,
-                       rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+    hipLaunchKernelGGL((k_collide<W, I, M, H, false, P, S>), grid, block, 0, s, (const PopT<H>*)fin,
+                       (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
 }
 
 void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,
                     const float* fib, const int* tile_flag, float* u, bool has_ibm, bool macro, bool half,
                     const float* cscale, int par_prev, int par_cur, hipStream_t s) {
     const bool w = L.walls != 0;
+    if (L.sharp) {
+        // the bounce-back coupling: periodic, FP32 storage
+#define LS(M, P) launch_collide_t<false, true, M, false, P, true>(L, fin, fout, rho_n, rho_prev, fib, tile_flag, u, \
+                                                                  cscale, par_prev, par_cur, s)
+        if (macro) {
+            if (L.psi_exp) LS(true, true); else LS(true, false);
+        } else {
+            if (L.psi_exp) LS(false, true); else LS(false, false);
+        }
+#undef LS
+        return;
+    }
 #define LC(W, I, M, H, P) \
     launch_collide_t<W, I, M, H, P>(L, fin, fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, s)
 #define LC_P(W, I, M, H) \

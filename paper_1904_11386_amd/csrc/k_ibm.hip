@@ -1301,6 +1301,9 @@ void launch_reference_step(const Dev& d, int n_nodes, int n_faces, int n_caps, b
     if (bend) launch_bending(d, n_nodes, s);
     hipLaunchKernelGGL(k_ref_advance, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes, mu);
 }
+void launch_gather_forces(const Dev& d, int n_nodes, hipStream_t s) {
+    if (n_nodes > 0) hipLaunchKernelGGL(k_ref_gather, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
+}
 void launch_spread(const Lattice& L, const Dev& d, int par, const float* rho_n, const float* cs, hipStream_t s) {
     if (L.psi_exp)
         hipLaunchKernelGGL(k_spread<true>, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par, rho_n, cs);

@@ -36,6 +36,10 @@ struct Layout {
         grads;
     size_t ring0, ring_bytes, ring_f, ring_rho, ring_off;
     int64_t tiles, max_caps;
+    // the bounce-back coupling
+    bool bb = false;
+    size_t lab, lab_new, lmask, lkey, links, link_rho, fresh, bb_count, bbox, bb_com, bb_mass, node_V, P_cur, P_prev, QR;
+    int link_cap = 0, fresh_cap = 0;
 };
 
 size_t take(size_t& cur, size_t bytes) {
@@ -62,7 +66,9 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
     l.f[1] = take(c, fbytes);
     l.rho[0] = take(c, 2 * N * sizeof(float));
     l.rho[1] = take(c, 2 * N * sizeof(float));
-    l.fib = take(c, 5 * N * sizeof(float));
+    l.bb = p->coupling == 1;
+    // (the bounce-back coupling keeps six Shan-Chen sum corrections there)
+    l.fib = take(c, (l.bb ? 6 : 5) * N * sizeof(float));
     l.u = take(c, 3 * N * sizeof(float));
     l.tile_flag = take(c, T * 4);
     l.tile_count = take(c, NB * 4);
@@ -129,6 +135,28 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
         l.ring_bytes = (r + 255) & ~size_t(255);
         l.ring0 = take(c, (size_t)p->ring_len * l.ring_bytes);
     }
+    if (l.bb) {
+        // links: a triangle of these meshes is pierced by a few links; 64 per
+        // triangle is far above what a membrane moving under 1 lu per step
+        // produces (overflow is reported as LBM_EUNSTABLE)
+        l.link_cap = (int)std::min<int64_t>(64 * nf + 1024, (int64_t)1 << 30);
+        l.fresh_cap = (int)std::min<int64_t>(std::max<int64_t>(4 * nb, 4096), (int64_t)1 << 30);
+        l.lab = take(c, N * 4);
+        l.lab_new = take(c, N * 4);
+        l.lmask = take(c, N * 4);
+        l.lkey = take(c, (size_t)9 * N * 8);
+        l.links = take(c, (size_t)l.link_cap * 16);
+        l.link_rho = take(c, (size_t)l.link_cap * 32);
+        l.fresh = take(c, (size_t)l.fresh_cap * 4);
+        l.bb_count = take(c, 8 * 4);
+        l.bbox = take(c, l.max_caps * 8 * 4);
+        l.bb_com = take(c, l.max_caps * 3 * 8);
+        l.bb_mass = take(c, 4 * 8);
+        l.node_V = take(c, 3 * nb * 4);
+        l.P_cur = take(c, 3 * nb * 8);
+        l.P_prev = take(c, 3 * nb * 8);
+        l.QR = take(c, 3 * nb * 8);
+    }
     l.total = (c + 255) & ~size_t(255);
     return l;
 }
@@ -168,6 +196,15 @@ std::string validate(const lbm_params* p) {
     if (p->psi_kind != 0 && p->psi_kind != 1) return "psi_kind must be 0 or 1";
     if (!(p->rep_eps >= 0.0) || !isfinite(p->rep_eps)) return "rep_eps must be finite and >= 0";
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
+    if (p->coupling != 0 && p->coupling != 1) return "coupling must be 0 (immersed boundary) or 1 (bounce-back)";
+    if (p->coupling == 1) {
+        if (p->precision != LBM_FP32) return "the bounce-back coupling needs FP32 storage";
+        if (p->walls != 0) return "the bounce-back coupling runs in a periodic box (walls = 0)";
+        if (p->n_slots != 0 || p->ring_len != 0) return "the bounce-back coupling has no checkpoints or adjoint";
+        if (p->rep_eps != 0.0) return "the bounce-back coupling has no particle-particle repulsion";
+        if (!(p->node_mass > 0.0) || !isfinite(p->node_mass)) return "node_mass must be finite and > 0";
+        if (!(p->mass_c0 >= 0.0) || !isfinite(p->mass_c0)) return "mass_c0 must be finite and >= 0";
+    }
     return "";
 }
 
@@ -214,6 +251,10 @@ struct lbm_ctx {
     hipGraphExec_t graph[2][2][2] = {};  // [step parity][flip][advection pending at the start]
     bool graphs_failed = false;
     bool bending = false;          // some capsule has a bending modulus
+    // the bounce-back coupling
+    BBSizes bbz{};
+    BBConst bbk{};
+    bool bb_primed = false;        // the first step detects no fresh nodes
     std::string err;
 
     bool half() const { return p.precision == LBM_FP16; }
@@ -350,6 +391,36 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     d.cap_mom = (double*)(w + lay.cap_mom);
     d.red = (double*)(w + lay.red);
     d.node_area = (float*)(w + lay.node_area);
+    L.sharp = lay.bb ? 1 : 0;
+    if (lay.bb) {
+        d.lab = (int*)(w + lay.lab);
+        d.lab_new = (int*)(w + lay.lab_new);
+        d.lmask = (unsigned*)(w + lay.lmask);
+        d.lkey = (unsigned long long*)(w + lay.lkey);
+        d.links = (int4*)(w + lay.links);
+        d.link_rho = (double4*)(w + lay.link_rho);
+        d.fresh = (int*)(w + lay.fresh);
+        d.bb_count = (int*)(w + lay.bb_count);
+        d.bbox = (int*)(w + lay.bbox);
+        d.bb_com = (double*)(w + lay.bb_com);
+        d.bb_mass = (double*)(w + lay.bb_mass);
+        d.node_V = (float*)(w + lay.node_V);
+        d.P_cur = (double*)(w + lay.P_cur);
+        d.P_prev = (double*)(w + lay.P_prev);
+        d.QR = (double*)(w + lay.QR);
+        c->bbz.link_cap = lay.link_cap;
+        c->bbz.fresh_cap = lay.fresh_cap;
+        c->bbz.ext = 0;
+        BBConst& k = c->bbk;
+        for (int j = 0; j < 2; ++j) {
+            k.m0[j] = m[j];
+            k.rho_init[j] = m[j] / (double)N;
+        }
+        k.vsys = (double)N;
+        k.c0 = p->mass_c0;
+        k.inv_mass = (float)(1.0 / p->node_mass);
+        k.psi_exp = p->psi_kind;
+    }
     if (lay.adjoint) {
         d.lam[0] = (void*)(w + lay.lam[0]);
         d.lam[1] = (void*)(w + lay.lam[1]);
@@ -389,10 +460,21 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
         return bad(er, "hipMemcpyAsync");
     // (the first step decodes with the initial densities and unit compensation)
     if (L.onsite) launch_onsite(L, d.f[0], half, d.rho[1], d.cscale + 2, s);
-    if ((er = hipMemsetAsync(d.fib, 0, 5 * N * sizeof(float), s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if ((er = hipMemsetAsync(d.fib, 0, (lay.bb ? 6 : 5) * N * sizeof(float), s)) != hipSuccess)
+        return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_flag, 0, lay.tiles * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.tile_count, 0, lay.bins * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
     if ((er = hipMemsetAsync(d.counters, 0, 8 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    if (lay.bb) {
+        const size_t nb3 = 3 * (size_t)std::max<int64_t>(max_nodes, 1);
+        launch_bb_init(L, d, s);
+        if ((er = hipMemsetAsync(d.bb_count, 0, 8 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+        if ((er = hipMemsetAsync(d.bb_mass, 0, 4 * 8, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+        if ((er = hipMemsetAsync(d.node_V, 0, nb3 * 4, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+        if ((er = hipMemsetAsync(d.P_cur, 0, nb3 * 8, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+        if ((er = hipMemsetAsync(d.P_prev, 0, nb3 * 8, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+        if ((er = hipMemsetAsync(d.QR, 0, nb3 * 8, s)) != hipSuccess) return bad(er, "hipMemsetAsync");
+    }
     if ((er = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking)) != hipSuccess)
         return bad(er, "hipStreamCreateWithFlags");
     if ((er = hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming)) != hipSuccess)
@@ -470,8 +552,35 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
                   r0[2] * (r1[0] * r2[1] - r1[1] * r2[0])) / 6.0;
         }
         if (!(V > 0.0)) return c->fail(LBM_EINVAL, "capsule %d: rest volume not positive (triangles must face outward)", k);
+        if (c->lay.bb) {
+            // the bounce-back coupling labels the lattice nodes in a box around
+            // each capsule: room for it to deform by half its size again plus
+            // the box margin, without wrapping onto itself
+            for (int j = 0; j < 3; ++j) {
+                double lo = X[j], hi = X[j];
+                for (int b = 1; b < nn; ++b) {
+                    lo = std::min(lo, X[3 * b + j]);
+                    hi = std::max(hi, X[3 * b + j]);
+                }
+                const int need = (int)ceil(1.5 * (hi - lo)) + 9;
+                if (need > std::min(c->p.nx, std::min(c->p.ny, c->p.nz)))
+                    return c->fail(LBM_EINVAL, "capsule %d: too large for the lattice under the bounce-back coupling", k);
+            }
+        }
         nofs += nn;
         fofs += nf;
+    }
+    if (c->lay.bb) {
+        for (int k = 0, o = 0; k < n_caps; o += nodes_per_cap[k], ++k)
+            for (int j = 0; j < 3; ++j) {
+                const double* X = xyz_rest + 3 * (size_t)o;
+                double lo = X[j], hi = X[j];
+                for (int b = 1; b < nodes_per_cap[k]; ++b) {
+                    lo = std::min(lo, X[3 * b + j]);
+                    hi = std::max(hi, X[3 * b + j]);
+                }
+                c->bbz.ext = std::max(c->bbz.ext, (int)ceil(1.5 * (hi - lo)) + 9);
+            }
     }
     if (first_id) *first_id = (int32_t)c->caps.size();
     nofs = fofs = 0;
@@ -498,6 +607,8 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
         cd.C = (float)C[k];
         cd.kV = (float)kV[k];
         cd.kB = 0.0f;
+        cd.vp[0] = cd.vp[1] = cd.vp[2] = 0.0f;
+        cd.prescribed = 0;
         // rest geometry in FP64, relative to the anchor
         std::vector<double> R(3 * (size_t)nn);
         for (int b = 0; b < nn; ++b)
@@ -698,7 +809,72 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     c->flip ^= 1;
 }
 
+// One step of the bounce-back coupling (see k_bb.hip), on one stream:
+// the head (labels of the membranes at X^n, fresh nodes, the bounce-back of
+// the populations that cross them, tile flags), the density pass, the
+// membrane forces, the Shan-Chen sum across the membranes, the collide and
+// the node update.
+static void enqueue_bb_step(lbm_ctx* c, hipEvent_t* ev) {
+    const Lattice& L = c->L;
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    const int ncap = (int)c->caps.size();
+    const int cur = (int)(c->step & 1), nxt = cur ^ 1;
+    void* fin = d.f[cur];
+    void* fout = d.f[nxt];
+    float* rho_n = d.rho[cur];
+    const float* rho_p = d.rho[nxt];
+    auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
+    c->launched = true;
+    mark(LBM_K_CLEAR);
+    launch_bb_geometry(L, d, c->bbz, ncap, c->n_faces, c->bb_primed, s);
+    launch_bb_refill(L, d, c->bbz, c->bbk, fin, rho_p, ncap, s);
+    launch_bb_fixup(L, d, c->bbz, fin, ncap, s);
+    launch_bb_flags(L, d, c->bbz, ncap, s);
+    c->bb_primed = true;
+    mark(LBM_K_DENSITY);
+    launch_density(L, fin, rho_p, rho_n, false, d.cscale, nxt, d.dpart, s);
+    mark(LBM_K_VOLUME);
+    launch_cap_volume(d, c->n_faces, s);
+    mark(LBM_K_FACES);
+    launch_faces(d, c->n_faces, s);
+    mark(LBM_K_NODES);
+    launch_gather_forces(d, c->n_nodes, s);
+    mark(LBM_K_SCAN);
+    mark(LBM_K_SCATTER);
+    mark(LBM_K_REPULSE);
+    mark(LBM_K_BEND);
+    if (c->bending) launch_bending(d, c->n_nodes, s);
+    mark(LBM_K_SPREAD);
+    if (ncap) launch_bb_shan_chen(L, d, c->bbz, c->bbk, rho_n, s);
+    mark(LBM_K_COLLIDE);
+    launch_collide(L, fin, fout, rho_n, rho_p, d.fib, d.tile_flag, d.u, ncap > 0, false, false, d.cscale, nxt, cur,
+                   s);
+    mark(LBM_K_INTERP);
+    launch_bb_advance(d, c->bbk, c->n_nodes, s);
+    mark(LBM_NK);
+    c->step++;
+}
+
+// The overflow and consistency flags of the bounce-back coupling's lists
+// (synchronises).
+static int check_bb(lbm_ctx* c) {
+    int cnt[8];
+    HIPCHK(c, hipMemcpyAsync(cnt, c->d.bb_count, sizeof cnt, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const int f = cnt[2];
+    if (f & 1) return c->fail(LBM_EUNSTABLE, "step %lld: a capsule outgrew its label box", (long long)c->step);
+    if (f & 2) return c->fail(LBM_EUNSTABLE, "step %lld: more membrane links than the list holds", (long long)c->step);
+    if (f & 4) return c->fail(LBM_EUNSTABLE, "step %lld: more fresh nodes than the list holds", (long long)c->step);
+    if (f & 8) return c->fail(LBM_EUNSTABLE, "step %lld: a membrane is not closed (odd crossings)", (long long)c->step);
+    return LBM_OK;
+}
+
 static void enqueue_step(lbm_ctx* c, hipEvent_t* ev, bool defer_interp = false) {
+    if (c->lay.bb) {
+        enqueue_bb_step(c, ev);
+        return;
+    }
     const int cur = (int)(c->step & 1), nxt = cur ^ 1;
     enqueue_core(c, c->d.f[cur], c->d.f[nxt], c->d.rho[cur], c->d.rho[nxt], true, ev, true, defer_interp);
 }
@@ -738,6 +914,32 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
     return ex;
 }
 
+
+int lbm_capsules_velocity(lbm_ctx* c, int32_t first_id, int32_t n_caps, const double* v, int32_t prescribed) {
+    if (!c) return LBM_EINVAL;
+    if (!c->lay.bb) return c->fail(LBM_EINVAL, "node velocities need the bounce-back coupling (coupling = 1)");
+    if (c->step != 0 || c->launched) return c->fail(LBM_ESTATE, "node velocities must be set before the first step");
+    if (n_caps < 0 || first_id < 0 || (int64_t)first_id + n_caps > (int64_t)c->caps.size())
+        return c->fail(LBM_EINVAL, "capsule range outside the capsules added");
+    if (n_caps == 0) return LBM_OK;
+    if (!v) return c->fail(LBM_EINVAL, "NULL v");
+    for (int k = 0; k < 3 * n_caps; ++k)
+        if (!isfinite(v[k]) || !(fabs(v[k]) < 0.5)) return c->fail(LBM_EINVAL, "velocities must be finite and below 0.5");
+    std::vector<float> V;
+    const int b0 = c->caps[first_id].node_start;
+    for (int k = 0; k < n_caps; ++k) {
+        CapDev& cd = c->caps[first_id + k];
+        for (int j = 0; j < 3; ++j) cd.vp[j] = (float)v[3 * k + j];
+        cd.prescribed = prescribed != 0;
+        for (int b = 0; b < cd.node_count; ++b)
+            for (int j = 0; j < 3; ++j) V.push_back(cd.vp[j]);
+    }
+    HIPCHK(c, hipMemcpyAsync(c->d.node_V + 3 * (size_t)b0, V.data(), V.size() * 4, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d.caps, c->caps.data(), c->caps.size() * sizeof(CapDev), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
 
 int lbm_capsules_bending(lbm_ctx* c, int32_t first_id, int32_t n_caps, const double* kB) {
     if (!c) return LBM_EINVAL;
@@ -784,6 +986,19 @@ int lbm_reference_relax(lbm_ctx* c, int32_t nsteps, double gamma, double w, doub
 int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");
+    if (c->lay.bb) {
+        for (int k = 0; k < nsteps; ++k) {
+            enqueue_bb_step(c, nullptr);
+            if (c->p.check_every > 0 && c->step % c->p.check_every == 0) {
+                HIPCHK(c, hipGetLastError());
+                int r = check_bb(c);
+                if (r == LBM_OK) r = check_mass(c);
+                if (r != LBM_OK) return r;
+            }
+        }
+        HIPCHK(c, hipGetLastError());
+        return nsteps > 0 ? check_bb(c) : LBM_OK;
+    }
     int left = nsteps;
     while (left > 0) {
         int chunk = left;
@@ -820,6 +1035,13 @@ int lbm_step_timed(lbm_ctx* c, int32_t nsteps, double* kernel_ms) {
     for (int k = 0; k < nsteps; ++k) enqueue_step(c, &ev[(size_t)k * (LBM_NK + 1)]);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->lay.bb) {
+        const int r = check_bb(c);
+        if (r != LBM_OK) {
+            for (auto& e : ev) (void)hipEventDestroy(e);
+            return r;
+        }
+    }
     for (int j = 0; j < LBM_NK; ++j) kernel_ms[j] = 0.0;
     for (int k = 0; k < nsteps; ++k)
         for (int j = 0; j < LBM_NK; ++j) {
@@ -879,6 +1101,20 @@ int lbm_observables(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
     out->mass[1] = acc[1];
     for (int j = 0; j < 3; ++j) out->momentum[j] = acc[2 + j];
     out->step = c->step;
+    for (int j = 0; j < 3; ++j) out->particle_momentum[j] = out->pending_momentum[j] = 0.0;
+    if (c->lay.bb && c->n_nodes) {
+        const size_t nb = c->n_nodes;
+        std::vector<float> V(3 * nb);
+        std::vector<double> P(3 * nb);
+        HIPCHK(c, hipMemcpyAsync(V.data(), d.node_V, 3 * nb * 4, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(P.data(), d.P_prev, 3 * nb * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (size_t b = 0; b < nb; ++b)
+            for (int j = 0; j < 3; ++j) {
+                out->particle_momentum[j] += c->p.node_mass * V[3 * b + j];
+                out->pending_momentum[j] += 0.5 * P[3 * b + j];
+            }
+    }
     if (caps) {
         for (int k = 0; k < ncap; ++k) {
             const double* m = &mom[(size_t)k * MOM_STRIDE];
@@ -964,6 +1200,53 @@ int lbm_get_spread(lbm_ctx* c, float* Fib, float* phi) {
     const int64_t N = c->L.n;
     if (Fib) HIPCHK(c, hipMemcpyAsync(Fib, c->d.fib, 3 * N * 4, hipMemcpyDeviceToHost, c->stream));
     if (phi) HIPCHK(c, hipMemcpyAsync(phi, c->d.fib + 3 * N, 2 * N * 4, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return LBM_OK;
+}
+
+int lbm_debug_labels(lbm_ctx* c, int32_t* labels) {
+    if (!c || !labels) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (!c->lay.bb) return c->fail(LBM_EINVAL, "labels need the bounce-back coupling (coupling = 1)");
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    // the labels of the current positions, computed as the next step's head
+    // does; the fresh-node list is not touched
+    launch_bb_geometry(c->L, d, c->bbz, (int)c->caps.size(), c->n_faces, false, s);
+    std::vector<int> box(8 * std::max<size_t>(c->caps.size(), 1));
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync(labels, d.lab, c->L.n * 4, hipMemcpyDeviceToHost, s));
+    std::vector<int> nw(c->L.n);
+    HIPCHK(c, hipMemcpyAsync(nw.data(), d.lab_new, c->L.n * 4, hipMemcpyDeviceToHost, s));
+    if (!c->caps.empty())
+        HIPCHK(c, hipMemcpyAsync(box.data(), d.bbox, box.size() * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    // the new labels are valid inside the capsules' boxes; elsewhere the
+    // committed ones (-1 away from every membrane)
+    const Lattice& L = c->L;
+    for (size_t k = 0; k < c->caps.size(); ++k) {
+        const CapDev& cd = c->caps[k];
+        const int* bx = &box[8 * k];
+        for (int z = bx[2]; z <= bx[5]; ++z)
+            for (int y = bx[1]; y <= bx[4]; ++y)
+                for (int x = bx[0]; x <= bx[3]; ++x) {
+                    auto wr = [](int v, int n) { v %= n; return v < 0 ? v + n : v; };
+                    const int64_t node = ((int64_t)wr(cd.anchor[2] + z, L.nz) * L.ny + wr(cd.anchor[1] + y, L.ny)) * L.nx +
+                                         wr(cd.anchor[0] + x, L.nx);
+                    labels[node] = nw[node];
+                }
+    }
+    return check_bb(c);
+}
+
+int lbm_get_node_velocities(lbm_ctx* c, float* V) {
+    if (!c || !V) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    const size_t nb = c->n_nodes;
+    if (!nb) return LBM_OK;
+    if (!c->lay.bb) {
+        for (size_t k = 0; k < 3 * nb; ++k) V[k] = 0.0f;
+        return LBM_OK;
+    }
+    HIPCHK(c, hipMemcpyAsync(V, c->d.node_V, 3 * nb * 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return LBM_OK;
 }

@@ -58,6 +58,7 @@ struct Lattice {
     int64_t n;             // nx*ny*nz
     int walls;             // half-way bounce-back walls: solid rows y = 0 and ny - 1
     int onsite;            // on-site velocity boundaries on the fluid rows y = 0 and ny - 1
+    int sharp;             // the bounce-back coupling: flagged tiles carry Shan-Chen sum corrections
     float G;
     float tau[2];
     float omega[2];        // 1/tau
@@ -83,6 +84,8 @@ struct CapDev {
     float kS, C, kV;
     float kB;           // Helfrich bending modulus (0 = none)
     double V0;
+    float vp[3];        // bounce-back coupling: the prescribed node velocity
+    int prescribed;     // 1: the nodes keep vp (rigid translation)
 };
 
 struct FaceRef {        // rest metric of a triangle
@@ -147,6 +150,30 @@ struct Dev {
     float* node_area;     // [nodes] rest area A_b
     double* capdV;        // [max caps] directional derivative of V
     double* grads;        // [4] dJ/dtheta, dJ/dkS, dJ/dG
+    // bounce-back coupling (allocated when it is chosen)
+    int* lab;             // [N] label of the current membranes: capsule inside, or -1
+    int* lab_new;         // [N] labels being computed (scratch, valid in the capsules' boxes)
+    unsigned* lmask;      // [N] bits 0..8: link from the node along half-direction d claimed; bit 16: parity
+                          //     of the membrane crossings of its +z link
+    int4* links;          // [link capacity] (node, half-direction, -, -)
+    unsigned long long* lkey; // [9][N] per link: (FP32 crossing parameter, triangle), the least wins
+    double4* link_rho;    // [link capacity] densities of the link's ends (A, B at the start; A, B at the end)
+    int* fresh;           // [fresh capacity] nodes whose label changed
+    int* bb_count;        // [8]: links, fresh nodes, overflow flags
+    int* bbox;            // [max caps][8]: box lo (x, y, z), hi (x, y, z), anchor-relative
+    double* bb_com;       // [max caps][3] mean node offset (anchor-relative)
+    double* bb_mass;      // [4] FP64 ledger of the mass the coupling added per component: committed [0..1],
+                          //     this step's head [2..3]
+    float* node_V;        // [nodes][3] node velocities
+    double* P_cur;        // [nodes][3] momentum exchanged at the last streaming
+    double* P_prev;       // [nodes][3] the one before
+    double* QR;           // [nodes][3] fresh-node and Shan-Chen reactions of the step
+};
+
+// sizes of the bounce-back coupling's lists and boxes
+struct BBSizes {
+    int link_cap, fresh_cap;
+    int ext;              // edge of the largest capsule box the launches cover
 };
 
 constexpr int RED_BLOCKS = 1024;
@@ -185,6 +212,26 @@ void launch_spread(const Lattice& L, const Dev& d, int parity, const float* rho_
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
 void launch_cap_moments(const Dev& d, int n_caps, hipStream_t s);
 void launch_debug_bins(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s);
+void launch_gather_forces(const Dev& d, int n_nodes, hipStream_t s);
+// the bounce-back coupling (k_bb.hip)
+struct BBConst {
+    double m0[2];         // initial component masses
+    double rho_init[2];   // their per-node averages
+    double vsys;          // fluid node count
+    double c0;            // strength of the adaptive mass correction
+    float inv_mass;       // 1 / node mass
+    int psi_exp;
+};
+void launch_bb_init(const Lattice& L, Dev& d, hipStream_t s);
+void launch_bb_geometry(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, int n_faces, bool detect_fresh,
+                        hipStream_t s);
+void launch_bb_refill(const Lattice& L, Dev& d, const BBSizes& z, const BBConst& k, void* fpost, const float* rho,
+                      int n_caps, hipStream_t s);
+void launch_bb_fixup(const Lattice& L, Dev& d, const BBSizes& z, void* fpost, int n_caps, hipStream_t s);
+void launch_bb_flags(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, hipStream_t s);
+void launch_bb_shan_chen(const Lattice& L, Dev& d, const BBSizes& z, const BBConst& k, const float* rho,
+                         hipStream_t s);
+void launch_bb_advance(Dev& d, const BBConst& k, int n_nodes, hipStream_t s);
 // adjoint (k_ibm.hip)
 void launch_spread_vec(const Lattice& L, const Dev& d, int parity, const float* val, float* target, int mode,
                        hipStream_t s);

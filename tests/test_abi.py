@@ -61,6 +61,20 @@ def test_workspace_bytes_and_validation():
                  dict(walls=2, precision=B.LBM_FP16)):
         pb = B.make_params(16, 16, 16, **good)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_OK
+    # the bounce-back coupling: FP32, periodic, no checkpoints, adjoint or
+    # repulsion; positive node mass, non-negative C0
+    for bad in (dict(coupling=2), dict(coupling=-1), dict(coupling=1, precision=B.LBM_FP16),
+                dict(coupling=1, walls=1), dict(coupling=1, walls=2), dict(coupling=1, n_slots=1),
+                dict(coupling=1, ring_len=4), dict(coupling=1, rep_eps=0.5), dict(coupling=1, node_mass=0.0),
+                dict(coupling=1, node_mass=float("inf")), dict(coupling=1, mass_c0=-1.0)):
+        pb = B.make_params(16, 16, 16, **bad)
+        assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL, bad
+    pb = B.make_params(16, 16, 16, coupling=1)
+    assert lib.lbm_workspace_bytes(C.byref(pb), 162, 320, C.byref(out)) == B.LBM_OK
+    n_bb = out.value
+    pb = B.make_params(16, 16, 16)
+    assert lib.lbm_workspace_bytes(C.byref(pb), 162, 320, C.byref(out)) == B.LBM_OK
+    assert n_bb > out.value
     # more than 2^30 nodes cannot be addressed with 32-bit offsets
     pb = B.make_params(1024, 1024, 1025)
     assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL
@@ -99,6 +113,9 @@ def test_every_entry_point_rejects_a_null_context():
     calls = {
         "lbm_capsules_add": (null, 0, None, None, None, None, None, None, None, None, None),
         "lbm_capsules_bending": (null, 0, 0, None),
+        "lbm_capsules_velocity": (null, 0, 0, None, 0),
+        "lbm_debug_labels": (null, None),
+        "lbm_get_node_velocities": (null, None),
         "lbm_reference_relax": (null, 1, 0.01, 1.0, 0.0, 0.05),
         "lbm_step": (null, 1),
         "lbm_step_timed": (null, 1, None),
