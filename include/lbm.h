@@ -299,6 +299,19 @@ int lbm_step_timed(lbm_ctx* ctx, int32_t nsteps, double* kernel_ms);
  * Synchronises.  caps may be NULL, else it must hold one entry per capsule. */
 int lbm_observables(lbm_ctx* ctx, lbm_obs* out, lbm_capsule_obs* caps);
 
+/* lbm_observables for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid it):
+ * the same results, bit for bit, with the FP64 reduction partials and the
+ * per-capsule moments kept in a fixed device array of the library (about
+ * 576 KiB per device, resolved at lbm_init and held until the process ends)
+ * instead of the context's workspace.  It calls no hipMalloc, hipFree or
+ * allocating routine; host-side partial sums go through fixed stack
+ * buffers.  At most 4096 capsules when caps is not NULL (else LBM_EINVAL).
+ * Every context on one device shares the array: calls that overlap on one
+ * device (other threads, or streams not ordered with each other) race.
+ * Synchronises. */
+int lbm_observables_noalloc(lbm_ctx* ctx, lbm_obs* out, lbm_capsule_obs* caps);
+
 /* The moments of Sec. II.A (rho = sum f, rho u = sum f c + F / 2) of the
  * most recent collision (time level step - 1):
  * rhoA, rhoB [N] and u [3][N] (x, y, z planes of the physical velocity with

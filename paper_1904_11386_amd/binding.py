@@ -48,7 +48,7 @@ _lib = None
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_init", "lbm_capsules_add", "lbm_capsules_velocity", "lbm_capsules_bending",
            "lbm_reference_relax", "lbm_debug_labels", "lbm_get_node_velocities",
-           "lbm_step", "lbm_step_timed", "lbm_observables",
+           "lbm_step", "lbm_step_timed", "lbm_observables", "lbm_observables_noalloc",
            "lbm_get_fields", "lbm_get_nodes", "lbm_get_node_forces", "lbm_get_spread",
            "lbm_debug_bins", "lbm_state_save", "lbm_state_load", "lbm_adjoint_forward", "lbm_adjoint_backward",
            "lbm_adjoint_seed", "lbm_adjoint_record", "lbm_adjoint_step", "lbm_adjoint_grads",
@@ -81,6 +81,7 @@ def load(path: str = None):
         "lbm_step": ([vp, i32], C.c_int),
         "lbm_step_timed": ([vp, i32, P(d)], C.c_int),
         "lbm_observables": ([vp, P(Obs), P(CapObs)], C.c_int),
+        "lbm_observables_noalloc": ([vp, P(Obs), P(CapObs)], C.c_int),
         "lbm_get_fields": ([vp, P(C.c_float), P(C.c_float), P(C.c_float)], C.c_int),
         "lbm_get_nodes": ([vp, P(d)], C.c_int),
         "lbm_get_node_forces": ([vp, P(C.c_float)], C.c_int),
@@ -252,6 +253,20 @@ class Sim:
         o = Obs()
         caps = (CapObs * max(self.n_caps, 1))()
         self._check(self.lib.lbm_observables(self.ctx, C.byref(o), caps if self.n_caps else None))
+        out = dict(mass=np.array(o.mass[:]), momentum=np.array(o.momentum[:]), step=o.step, caps=[],
+                   particle_momentum=np.array(o.particle_momentum[:]), pending_momentum=np.array(o.pending_momentum[:]))
+        for k in range(self.n_caps):
+            c = caps[k]
+            out["caps"].append(dict(com=np.array(c.com[:]), V=c.volume, A=c.area, axes=np.array(c.axes[:]),
+                                    D=c.taylor_D, height=c.height))
+        return out
+
+    def observables_noalloc(self):
+        """As observables(), through lbm_observables_noalloc (no device
+        allocation: the library's fixed per-device scratch)."""
+        o = Obs()
+        caps = (CapObs * max(self.n_caps, 1))()
+        self._check(self.lib.lbm_observables_noalloc(self.ctx, C.byref(o), caps if self.n_caps else None))
         out = dict(mass=np.array(o.mass[:]), momentum=np.array(o.momentum[:]), step=o.step, caps=[],
                    particle_momentum=np.array(o.particle_momentum[:]), pending_momentum=np.array(o.pending_momentum[:]))
         for k in range(self.n_caps):

@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,6 +16,37 @@
 #include "lbm_internal.h"
 
 using namespace lbmx;
+
+// lbm_observables_noalloc keeps its FP64 reduction partials and the
+// per-capsule moments in a fixed device array instead of the workspace:
+// at most NOALLOC_MAX_CAPS capsules (about 576 KiB per device)
+constexpr int NOALLOC_MAX_CAPS = 4096;
+constexpr size_t NOALLOC_DOUBLES = (size_t)RED_BLOCKS * 8 + (size_t)NOALLOC_MAX_CAPS * MOM_STRIDE;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+
+// Static scratch of lbm_observables_noalloc: the FP64 reduction partials and
+// the per-capsule moments, per device (each device holds its own copy until
+// the process ends).  Host code uses only the device address resolved at
+// lbm_init, never this name.
+static __device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+static std::mutex g_scratch_mu;
+static double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The address of `scratch` on device `dev` (current), resolved once per device.
+static hipError_t resolve_scratch(int dev, double** out) {
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = (double*)ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
+
 
 namespace {
 
@@ -226,6 +258,8 @@ struct lbm_ctx {
     bool interp_pending = false;   // the last step's advection is still to launch
     int64_t max_nodes = 0, max_faces = 0;
     int64_t step = 0;
+    int device = -1;               // the device current at lbm_init
+    double* scratch = nullptr;     // that device's address of the static scratch (lbm_observables_noalloc)
     int flip = 0;                  // parity of the immersed-boundary tile lists
     double mass0[2] = {0, 0};
     std::vector<int64_t> slot_step;
@@ -325,6 +359,16 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     }
     lbm_ctx* c = new lbm_ctx();
     c->p = *p;
+    // the static scratch of lbm_observables_noalloc on this device (once per device)
+    {
+        hipError_t er0 = hipGetDevice(&c->device);
+        if (er0 == hipSuccess) er0 = resolve_scratch(c->device, &c->scratch);
+        if (er0 != hipSuccess) {
+            g_init_error = std::string("device scratch address: ") + hipGetErrorString(er0);
+            delete c;
+            return LBM_EHIP;
+        }
+    }
     c->lay = lay;
     c->ws = (char*)workspace;
     c->stream = (hipStream_t)hip_stream;
@@ -1080,6 +1124,29 @@ static void eig3(double A[3][3], double ev[3]) {
     std::sort(ev, ev + 3);
 }
 
+// Per-capsule observables from its FP64 shape moments m[MOM_STRIDE] (origin at
+// the anchor): [0] V, [1] A, [2..4] sum of node offsets, [5..7] int x dV,
+// [8..13] int x x^T dV.
+static void cap_obs_from_moments(const CapDev& cd, const double* m, double z_interface, lbm_capsule_obs& o) {
+    const double V = m[0];
+    o.volume = V;
+    o.area = m[1];
+    for (int j = 0; j < 3; ++j) o.com[j] = cd.anchor[j] + m[2 + j] / cd.node_count;
+    const double xc[3] = {m[5] / V, m[6] / V, m[7] / V};
+    double M[3][3];
+    M[0][0] = m[8]; M[1][1] = m[9]; M[2][2] = m[10];
+    M[0][1] = M[1][0] = m[11];
+    M[0][2] = M[2][0] = m[12];
+    M[1][2] = M[2][1] = m[13];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) M[i][j] -= V * xc[i] * xc[j];
+    double ev[3];
+    eig3(M, ev);
+    for (int j = 0; j < 3; ++j) o.axes[j] = sqrt(5.0 * std::max(ev[j], 0.0) / V);
+    o.taylor_D = (o.axes[2] - o.axes[0]) / (o.axes[2] + o.axes[0]);
+    o.height = o.com[2] - z_interface;
+}
+
 int lbm_observables(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
     if (!c || !out) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
     Dev& d = c->d;
@@ -1115,28 +1182,67 @@ int lbm_observables(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
                 out->pending_momentum[j] += 0.5 * P[3 * b + j];
             }
     }
+    if (caps)
+        for (int k = 0; k < ncap; ++k) cap_obs_from_moments(c->caps[k], &mom[(size_t)k * MOM_STRIDE], c->p.z_interface,
+                                                            caps[k]);
+    return LBM_OK;
+}
+
+int lbm_observables_noalloc(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
+    if (!c || !out) return c ? c->fail(LBM_EINVAL, "NULL output") : LBM_EINVAL;
+    if (!c->scratch) return c->fail(LBM_EHIP, "the static scratch was not resolved on this context's device");
+    const int ncap = (int)c->caps.size();
+    if (caps && ncap > NOALLOC_MAX_CAPS)
+        return c->fail(LBM_EINVAL, "lbm_observables_noalloc handles at most %d capsules (%d here)", NOALLOC_MAX_CAPS, ncap);
+    Dev& d = c->d;
+    hipStream_t s = c->stream;
+    double* part = c->scratch;                               // [RED_BLOCKS][8]
+    double* mom = c->scratch + (size_t)RED_BLOCKS * 8;       // [caps][MOM_STRIDE]
+    const int pw = (int)((c->step & 1) ^ 1);
+    // (every partial and moment is stored, none accumulated: nothing to clear)
+    launch_reduce_fluid(c->L, d.f[c->step & 1], c->half(), d.rho[pw], d.cscale, pw, part, s);
+    if (caps && ncap) {
+        Dev dm = d;
+        dm.cap_mom = mom;
+        launch_cap_moments(dm, ncap, s);
+    }
+    HIPCHK(c, hipGetLastError());
+    // host side in fixed stack chunks, in the order lbm_observables sums
+    constexpr int CH = 64;
+    double buf[CH * 8];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b0 = 0; b0 < RED_BLOCKS; b0 += CH) {
+        HIPCHK(c, hipMemcpyAsync(buf, part + (size_t)b0 * 8, sizeof buf, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (int b = 0; b < CH; ++b)
+            for (int j = 0; j < 5; ++j) acc[j] += buf[b * 8 + j];
+    }
+    out->mass[0] = acc[0];
+    out->mass[1] = acc[1];
+    for (int j = 0; j < 3; ++j) out->momentum[j] = acc[2 + j];
+    out->step = c->step;
+    for (int j = 0; j < 3; ++j) out->particle_momentum[j] = out->pending_momentum[j] = 0.0;
+    if (c->lay.bb && c->n_nodes) {
+        float vb[3 * CH];
+        double pb[3 * CH];
+        for (int b0 = 0; b0 < c->n_nodes; b0 += CH) {
+            const int n = std::min(CH, c->n_nodes - b0);
+            HIPCHK(c, hipMemcpyAsync(vb, d.node_V + 3 * (size_t)b0, 3 * (size_t)n * 4, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(pb, d.P_prev + 3 * (size_t)b0, 3 * (size_t)n * 8, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            for (int b = 0; b < n; ++b)
+                for (int j = 0; j < 3; ++j) {
+                    out->particle_momentum[j] += c->p.node_mass * vb[3 * b + j];
+                    out->pending_momentum[j] += 0.5 * pb[3 * b + j];
+                }
+        }
+    }
     if (caps) {
+        double mb[MOM_STRIDE];
         for (int k = 0; k < ncap; ++k) {
-            const double* m = &mom[(size_t)k * MOM_STRIDE];
-            const CapDev& cd = c->caps[k];
-            lbm_capsule_obs& o = caps[k];
-            const double V = m[0];
-            o.volume = V;
-            o.area = m[1];
-            for (int j = 0; j < 3; ++j) o.com[j] = cd.anchor[j] + m[2 + j] / cd.node_count;
-            const double xc[3] = {m[5] / V, m[6] / V, m[7] / V};
-            double M[3][3];
-            M[0][0] = m[8]; M[1][1] = m[9]; M[2][2] = m[10];
-            M[0][1] = M[1][0] = m[11];
-            M[0][2] = M[2][0] = m[12];
-            M[1][2] = M[2][1] = m[13];
-            for (int i = 0; i < 3; ++i)
-                for (int j = 0; j < 3; ++j) M[i][j] -= V * xc[i] * xc[j];
-            double ev[3];
-            eig3(M, ev);
-            for (int j = 0; j < 3; ++j) o.axes[j] = sqrt(5.0 * std::max(ev[j], 0.0) / V);
-            o.taylor_D = (o.axes[2] - o.axes[0]) / (o.axes[2] + o.axes[0]);
-            o.height = o.com[2] - c->p.z_interface;
+            HIPCHK(c, hipMemcpyAsync(mb, mom + (size_t)k * MOM_STRIDE, sizeof mb, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            cap_obs_from_moments(c->caps[k], mb, c->p.z_interface, caps[k]);
         }
     }
     return LBM_OK;

@@ -120,6 +120,7 @@ def test_every_entry_point_rejects_a_null_context():
         "lbm_step": (null, 1),
         "lbm_step_timed": (null, 1, None),
         "lbm_observables": (null, None, None),
+        "lbm_observables_noalloc": (null, None, None),
         "lbm_get_fields": (null, None, None, None),
         "lbm_get_nodes": (null, None),
         "lbm_get_node_forces": (null, None),
