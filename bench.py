@@ -559,6 +559,58 @@ def run_form(torch, wl, form, warmup, steps, traffic=None):
     }
 
 
+def bb_leg(torch, name="c2", warmup=30, steps=300, v=(0.01, 0.0, 0.0)):
+    """The benchmark's 128^3 workload (8 capsules of 2562 nodes on the
+    interface, angles in [60, 120] deg) under the paper's bounce-back
+    coupling, FP32, the capsules translated along the interface at a
+    prescribed velocity v (the set-up of the paper's mass-conservation test;
+    free capsules of these soft 2562-node membranes leave their label boxes
+    within about 100 steps under this coupling): MLUPS, ms per step and the
+    per-group split of as many event-timed steps.  The coupling's head
+    (labels, link list, fresh nodes, the bounce-back of the crossing
+    populations, tile flags) is timed as "bb_head", the Shan-Chen sum across
+    the membranes as "bb_shan_chen" and the node update as "bb_advance"."""
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import LBM_FP32, LbmError, sim_from_workload
+    wl = workloads.bounce_back(workloads.make(name))
+    N = wl.n_lattice
+    print("bench: bounce-back leg, %s, %d warm-up + %d timed steps" % (name, warmup, steps), file=sys.stderr, flush=True)
+    sim = sim_from_workload(wl, precision=LBM_FP32)
+    try:
+        sim.set_velocity(0, [v] * len(wl.capsules), prescribed=True)
+        ob0 = sim.observables()
+        sim.step(warmup)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        print("bench: bounce-back leg warmed up", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        sim.step(steps)
+        sim.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        print("bench: bounce-back leg timed, %.3f ms per step" % (wall / steps * 1e3), file=sys.stderr, flush=True)
+        kms = sim.step_timed(steps)
+        ob = sim.observables()
+    except LbmError as e:
+        # (the coupling reports an unstable run instead of stepping on)
+        return {"workload": WORKLOAD_TEXT.get(name, name) + ", bounce-back coupling", "error": str(e)}
+    finally:
+        sim.close()
+        del sim
+        torch.cuda.empty_cache()
+    rename = {"clear": "bb_head", "spread": "bb_shan_chen", "interp": "bb_advance"}
+    t_col = kms["collide"] / steps * 1e-3
+    achieved = COLLIDE_BYTES_PER_LUP["fp32"] * N / t_col / 1e9
+    return {"workload": WORKLOAD_TEXT.get(name, name) + ", bounce-back coupling (node mass 5, C0 2500), "
+                        "capsules translated at a prescribed %s lu/step" % (list(v),),
+            "lattice": [wl.nx, wl.ny, wl.nz], "capsules": len(wl.capsules), "warmup": warmup, "steps": steps,
+            "mlups": round(N * steps / wall / 1e6, 2), "ms_per_step": round(wall / steps * 1e3, 5),
+            "collide_gbs": round(achieved, 1), "collide_frac": round(achieved / HBM_PEAK_GBS, 4),
+            "kernels_ms_per_step": {rename.get(k, k): round(v / steps, 5) for k, v in kms.items() if v > 0},
+            "mass_change": (ob["mass"] / ob0["mass"] - 1).tolist(),
+            "capsule_height_change": [round(c1["com"][2] - c0["com"][2], 4) for c0, c1 in zip(ob0["caps"], ob["caps"])]}
+
+
 def ratio_leg(torch, name, warmup, steps):
     """Both storage forms of one workload, same step counts: MLUPS, collide
     bandwidth and the FP16/FP32 ratio."""
@@ -590,6 +642,10 @@ def main():
     ap.add_argument("--no-c3-leg", action="store_true", help="skip the 256^3 FP16/FP32 leg")
     ap.add_argument("--no-c2-leg", action="store_true", help="skip the 128^3 leg")
     ap.add_argument("--no-adjoint-leg", action="store_true")
+    ap.add_argument("--no-bb-leg", action="store_true",
+                    help="skip the 128^3 workload under the paper's bounce-back coupling")
+    ap.add_argument("--bb-leg", action="store_true",
+                    help="run the bounce-back leg even with --headline-only")
     ap.add_argument("--no-fd-sweep", action="store_true",
                     help="skip the full-size adjoint check against FP32 central differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -662,10 +718,14 @@ def main():
             out["c3_leg"] = ratio_leg(torch, "c3", 50, 200)
         if not args.no_c2_leg and args.workload != "c2":
             out["c2_leg"] = ratio_leg(torch, "c2", 30, 300)
+        if not args.no_bb_leg:
+            out["bb_leg"] = bb_leg(torch)
         if not args.no_adjoint_leg:
             out["adjoint"] = adjoint_leg(torch)
             if not args.no_fd_sweep:
                 out["adjoint_fd_sweep"] = adjoint_fd_sweep(torch)
+    if args.bb_leg and args.headline_only:
+        out["bb_leg"] = bb_leg(torch)
     if args.reference_model_leg:
         out["reference_model"] = reference_model_leg(torch)
     if args.shape_error_leg:

@@ -210,13 +210,15 @@ int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
 
 /* Boundary-node velocities of the capsules first_id .. first_id + n_caps - 1
  * under the bounce-back coupling (coupling 1; Sec. II.B, forward Euler of
- * inertial nodes): v[n_caps][3] (finite, |v_k| < 0.5) is each capsule's
- * initial node velocity (0 by default); with prescribed != 0 the nodes keep
+ * inertial nodes): every node of capsule k takes the velocity v[k][3]
+ * (finite, |v_k| < 0.5; 0 at the start); with prescribed != 0 the nodes keep
  * it, whatever the forces (the rigid translation of Sec. II.E's
- * mass-conservation test, Fig. mass-conservation).  Only before any step has
- * been enqueued (else LBM_ESTATE); LBM_EINVAL under the immersed boundary
- * (coupling 0, whose nodes are massless) or for a range outside the
- * capsules added. */
+ * mass-conservation test, Fig. mass-conservation), with prescribed = 0 they
+ * move under the forces from there.  Before the first step or between steps
+ * (it takes effect from the next step, e.g. to hold capsules still while the
+ * fluid relaxes and then release them); synchronises.  LBM_EINVAL under the
+ * immersed boundary (coupling 0, whose nodes are massless) or for a range
+ * outside the capsules added. */
 int lbm_capsules_velocity(lbm_ctx* ctx, int32_t first_id, int32_t n_caps, const double* v, int32_t prescribed);
 
 /* Helfrich bending (Sec. II.B, eqs. method:curvature and surf_dens, zero

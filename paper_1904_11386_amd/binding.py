@@ -212,8 +212,9 @@ class Sim:
                                                  float(mobility)))
 
     def set_velocity(self, first_id, v, prescribed=False):
-        """Initial (and, when prescribed, fixed) node velocity of each capsule
-        first_id .. first_id + len(v) - 1 (bounce-back coupling)."""
+        """Node velocity of each capsule first_id .. first_id + len(v) - 1,
+        kept while prescribed (bounce-back coupling); before the first step
+        or between steps."""
         v = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1, 3))
         self._check(self.lib.lbm_capsules_velocity(self.ctx, int(first_id), v.shape[0], _ptr(v, C.c_double),
                                                    1 if prescribed else 0))

@@ -11,20 +11,25 @@
 // Head of step n (nodes at X^n, V^n; populations f*^{n-1}):
 //   k_bb_box      per capsule: the anchor-relative box of its nodes widened by
 //                 MARGIN, the mean node offset; counters and volumes zeroed
-//   k_bb_clear    per box: new labels -1, link bits 0
+//   k_bb_overlap  per pair of capsules of one parity colour: their boxes
+//                 must not meet (reported)
+//   k_bb_clear    per box: new labels -1, link and parity bits 0
 //   k_bb_links    per triangle: the lattice links it pierces (FP64
 //                 Moeller-Trumbore over its bounding box); each link listed
 //                 once; its element is the triangle pierced nearest the
 //                 link's start node (the end from which it points along a
 //                 positive half-direction; lowest index among ties at single
 //                 precision), for both of its ends; the parity of the
-//                 crossings of each +z link
-//   k_bb_label    per box column: inside where the +z crossings below are odd
+//                 crossings of each +z link, one bit per capsule colour
+//   k_bb_label    per box column: inside where the +z crossings below by the
+//                 capsule's own membrane (its colour's bit) are odd
 //   k_bb_detect   per box: fresh nodes (label changed) listed, once each
-//   k_bb_refill   per fresh node: the density interpolated from its side's
-//                 non-fresh neighbours, mass-corrected and clamped to their
-//                 range; the velocity of the nearest element; equilibrium
-//                 populations; removed minus created momentum to the element
+//   k_bb_refill   per fresh node (a wavefront each): the density
+//                 interpolated from its side's non-fresh neighbours,
+//                 mass-corrected and clamped to their range; the velocity of
+//                 the nearest element (the lanes share the search); the
+//                 equilibrium populations; removed minus created momentum to
+//                 the element
 //   k_bb_commit   per box: labels := new labels
 //   k_bb_link_density  per listed link: the densities of both ends, before
 //                 any population is bounced
@@ -61,9 +66,8 @@ namespace {
 
 constexpr int MARGIN = 3;       // box margin around a capsule's nodes, lattice units
 constexpr int CNT_LINKS = 0, CNT_FRESH = 1, CNT_FLAGS = 2;
-constexpr unsigned PARITY_BIT = 1u << 16;
 // overflow and consistency flags in bb_count[CNT_FLAGS]
-constexpr int FLAG_BOX = 1, FLAG_LINKS = 2, FLAG_FRESH = 4, FLAG_PARITY = 8;
+constexpr int FLAG_BOX = 1, FLAG_LINKS = 2, FLAG_FRESH = 4, FLAG_PARITY = 8, FLAG_OVERLAP = 16;
 
 __device__ __forceinline__ int wrapi(int v, int n) {
     v %= n;
@@ -165,6 +169,28 @@ __global__ __launch_bounds__(256) void k_bb_box(Dev d, int ext) {
     }
 }
 
+// Pairs of capsules of one parity colour whose boxes meet (periodic): their
+// labels would count each other's crossings, so the step reports it.
+__global__ __launch_bounds__(256) void k_bb_overlap(Lattice L, Dev d, int n_caps) {
+    const int a = blockIdx.y, b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b <= a || b >= n_caps) return;
+    const CapDev& A = d.caps[a];
+    const CapDev& B = d.caps[b];
+    if (A.colour != B.colour) return;
+    const int* ba = d.bbox + 8 * a;
+    const int* bb = d.bbox + 8 * b;
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    bool meet = true;
+    for (int k = 0; k < 3; ++k) {
+        const int la = wrapi(A.anchor[k] + ba[k], nn[k]), ha = la + (ba[3 + k] - ba[k]);
+        const int lb = wrapi(B.anchor[k] + bb[k], nn[k]), hb = lb + (bb[3 + k] - bb[k]);
+        bool m = false;
+        for (int sh = -1; sh <= 1; ++sh) m = m || (la <= hb + sh * nn[k] && lb + sh * nn[k] <= ha);
+        meet = meet && m;
+    }
+    if (meet) atomicOr(&d.bb_count[CNT_FLAGS], FLAG_OVERLAP);
+}
+
 __global__ __launch_bounds__(256) void k_bb_clear(Lattice L, Dev d) {
     const int cap = blockIdx.y;
     int q[3];
@@ -173,6 +199,7 @@ __global__ __launch_bounds__(256) void k_bb_clear(Lattice L, Dev d) {
     const int64_t node = lat(L, C.anchor[0] + q[0], C.anchor[1] + q[1], C.anchor[2] + q[2]);
     d.lab_new[node] = -1;
     d.lmask[node] = 0u;
+    d.lpar[node] = 0u;      // (every box is cleared before any capsule's links are found)
     for (int k = 0; k < 9; ++k) d.lkey[k * L.n + node] = ~0ull;
 }
 
@@ -224,7 +251,7 @@ __global__ __launch_bounds__(256) void k_bb_links(Lattice L, Dev d, int n_faces,
                     double t;
                     if (!seg_hits(p, cx(i), cy(i), cz(i), V[0], e1, e2, t)) continue;
                     const int64_t node = lat(L, C.anchor[0] + x, C.anchor[1] + y, C.anchor[2] + z);
-                    if (i == 5) atomicXor(&d.lmask[node], PARITY_BIT);
+                    if (i == 5) atomicXor(&d.lpar[node], 1u << C.colour);
                     // the link's element: nearest crossing, then lowest index
                     const unsigned long long key =
                         ((unsigned long long)__float_as_uint((float)t) << 32) | (unsigned long long)(unsigned)f;
@@ -249,10 +276,11 @@ __global__ __launch_bounds__(256) void k_bb_label(Lattice L, Dev d) {
     const CapDev& C = d.caps[cap];
     const int x = C.anchor[0] + bx[0] + c % ex, y = C.anchor[1] + bx[1] + c / ex;
     bool inside = false;    // the box bottom lies outside (margin)
+    const unsigned bit = 1u << C.colour;      // crossings of this capsule's membrane only
     for (int z = bx[2]; z <= bx[5]; ++z) {
         const int64_t node = lat(L, x, y, C.anchor[2] + z);
         if (inside) d.lab_new[node] = cap;
-        inside = inside != ((d.lmask[node] & PARITY_BIT) != 0);
+        inside = inside != ((d.lpar[node] & bit) != 0);
     }
     if (inside) atomicOr(&d.bb_count[CNT_FLAGS], FLAG_PARITY);
 }
@@ -282,88 +310,104 @@ __global__ void k_bb_ledger(Dev d) {
     }
 }
 
-__global__ __launch_bounds__(64) void k_bb_refill(Lattice L, Dev d, BBConst K, float2* __restrict__ f,
-                                                 const float* __restrict__ rho) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= min(d.bb_count[CNT_FRESH], (int)(gridDim.x * blockDim.x))) return;
+// One wavefront per fresh node: every lane forms the interpolated density
+// (the same loads), the lanes share the nearest-element search (faces
+// lane, lane + 64, ...; the least distance, then the lowest index, as a
+// scan in face order finds it), lane 0 writes.
+__global__ __launch_bounds__(256) void k_bb_refill(Lattice L, Dev d, BBConst K, float2* __restrict__ f,
+                                                  const float* __restrict__ rho, int fresh_cap) {
+    const int lane = threadIdx.x & 63;
+    const int n_fresh = min(d.bb_count[CNT_FRESH], fresh_cap);
     const int64_t N = L.n;
-    const int64_t node = d.fresh[e];
-    const int x = (int)(node % L.nx), y = (int)((node / L.nx) % L.ny), z = (int)(node / ((int64_t)L.nx * L.ny));
-    const int ell = d.lab_new[node];
-    // the density interpolated from the non-fresh neighbours on the node's side
-    double sum[2] = {0, 0}, mn[2] = {1e300, 1e300}, mx[2] = {-1e300, -1e300};
-    int cnt = 0;
-    for (int i = 1; i < Q; ++i) {
-        const int64_t nb = lat(L, x + cx(i), y + cy(i), z + cz(i));
-        const int ln = d.lab_new[nb];
-        if (ln != ell || ln != d.lab[nb]) continue;
-        ++cnt;
+    for (int e = blockIdx.x * 4 + (int)(threadIdx.x >> 6); e < n_fresh; e += gridDim.x * 4) {
+        const int64_t node = d.fresh[e];
+        const int x = (int)(node % L.nx), y = (int)((node / L.nx) % L.ny), z = (int)(node / ((int64_t)L.nx * L.ny));
+        const int ell = d.lab_new[node];
+        // the density interpolated from the non-fresh neighbours on the node's side
+        double sum[2] = {0, 0}, mn[2] = {1e300, 1e300}, mx[2] = {-1e300, -1e300};
+        int cnt = 0;
+        for (int i = 1; i < Q; ++i) {
+            const int64_t nb = lat(L, x + cx(i), y + cy(i), z + cz(i));
+            const int ln = d.lab_new[nb];
+            if (ln != ell || ln != d.lab[nb]) continue;
+            ++cnt;
+            for (int c = 0; c < 2; ++c) {
+                const double r = rho[c * N + nb];
+                sum[c] += r;
+                mn[c] = fmin(mn[c], r);
+                mx[c] = fmax(mx[c], r);
+            }
+        }
+        double rf[2];
         for (int c = 0; c < 2; ++c) {
-            const double r = rho[c * N + nb];
-            sum[c] += r;
-            mn[c] = fmin(mn[c], r);
-            mx[c] = fmax(mx[c], r);
+            if (cnt == 0) {
+                rf[c] = rho[c * N + node];
+            } else {
+                const double corr = 1.0 - K.c0 * ((K.rho_init[0] + K.rho_init[1]) / K.rho_init[c]) *
+                                              d.bb_mass[c] / K.vsys;
+                rf[c] = fmin(fmax(sum[c] / cnt * corr, mn[c]), mx[c]);
+            }
         }
+        // the nearest element (nearest centroid) of the capsule whose membrane passed
+        const int cap = ell >= 0 ? ell : d.lab[node];
+        const CapDev& C = d.caps[cap];
+        double p[3] = {(double)(x - C.anchor[0]), (double)(y - C.anchor[1]), (double)(z - C.anchor[2])};
+        const int nn[3] = {L.nx, L.ny, L.nz};
+        for (int k = 0; k < 3; ++k) p[k] -= nn[k] * rint((p[k] - d.bb_com[3 * cap + k]) / nn[k]);
+        int best = 0x7fffffff;
+        double bd = 1e300;
+        for (int ff = C.face_start + lane; ff < C.face_start + C.face_count; ff += 64) {
+            double sc[3] = {0, 0, 0};
+            for (int k = 0; k < 3; ++k) {
+                double q[3];
+                node_rel(d, d.tri[3 * ff + k], q);
+                for (int j = 0; j < 3; ++j) sc[j] += q[j];
+            }
+            double dd = 0.0;
+            for (int j = 0; j < 3; ++j) {
+                const double t = sc[j] / 3.0 - p[j];
+                dd += t * t;
+            }
+            if (dd < bd) {      // (a lane's faces come in increasing order)
+                bd = dd;
+                best = ff;
+            }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double obd = __shfl_xor(bd, o, 64);
+            const int ob = __shfl_xor(best, o, 64);
+            if (obd < bd || (obd == bd && ob < best)) {
+                bd = obd;
+                best = ob;
+            }
+        }
+        if (best == 0x7fffffff) best = C.face_start;      // (no finite distance: a torn membrane)
+        if (lane != 0) continue;
+        double v[3] = {0, 0, 0};
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) v[j] += d.node_V[3 * d.tri[3 * best + k] + j] / 3.0;
+        // removed momentum, new populations, created momentum
+        double old[3] = {0, 0, 0}, dm[2] = {0, 0};
+        const float uu = (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        for (int i = 0; i < Q; ++i) {
+            const float2 g = f[i * N + node];
+            const double sg = (double)g.x + (double)g.y;
+            old[0] += sg * cx(i);
+            old[1] += sg * cy(i);
+            old[2] += sg * cz(i);
+            const float cu = (float)(cx(i) * v[0] + cy(i) * v[1] + cz(i) * v[2]);
+            const float t = wgt(i) * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+            const float2 nf = make_float2((float)rf[0] * t, (float)rf[1] * t);
+            f[i * N + node] = nf;
+            dm[0] += (double)nf.x - (double)g.x;
+            dm[1] += (double)nf.y - (double)g.y;
+        }
+        unsafeAtomicAdd(&d.bb_mass[2], dm[0]);
+        unsafeAtomicAdd(&d.bb_mass[3], dm[1]);
+        double q[3];
+        for (int j = 0; j < 3; ++j) q[j] = (old[j] - (rf[0] + rf[1]) * v[j]) / 3.0;
+        for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * best + k], q, 1.0);
     }
-    double rf[2];
-    for (int c = 0; c < 2; ++c) {
-        if (cnt == 0) {
-            rf[c] = rho[c * N + node];
-        } else {
-            const double corr = 1.0 - K.c0 * ((K.rho_init[0] + K.rho_init[1]) / K.rho_init[c]) *
-                                          d.bb_mass[c] / K.vsys;
-            rf[c] = fmin(fmax(sum[c] / cnt * corr, mn[c]), mx[c]);
-        }
-    }
-    // the nearest element (nearest centroid) of the capsule whose membrane passed
-    const int cap = ell >= 0 ? ell : d.lab[node];
-    const CapDev& C = d.caps[cap];
-    double p[3] = {(double)(x - C.anchor[0]), (double)(y - C.anchor[1]), (double)(z - C.anchor[2])};
-    const int nn[3] = {L.nx, L.ny, L.nz};
-    for (int k = 0; k < 3; ++k) p[k] -= nn[k] * rint((p[k] - d.bb_com[3 * cap + k]) / nn[k]);
-    int best = C.face_start;
-    double bd = 1e300;
-    for (int ff = C.face_start; ff < C.face_start + C.face_count; ++ff) {
-        double s[3] = {0, 0, 0};
-        for (int k = 0; k < 3; ++k) {
-            double q[3];
-            node_rel(d, d.tri[3 * ff + k], q);
-            for (int j = 0; j < 3; ++j) s[j] += q[j];
-        }
-        double dd = 0.0;
-        for (int j = 0; j < 3; ++j) {
-            const double t = s[j] / 3.0 - p[j];
-            dd += t * t;
-        }
-        if (dd < bd) {
-            bd = dd;
-            best = ff;
-        }
-    }
-    double v[3] = {0, 0, 0};
-    for (int k = 0; k < 3; ++k)
-        for (int j = 0; j < 3; ++j) v[j] += d.node_V[3 * d.tri[3 * best + k] + j] / 3.0;
-    // removed momentum, new populations, created momentum
-    double old[3] = {0, 0, 0}, dm[2] = {0, 0};
-    const float uu = (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    for (int i = 0; i < Q; ++i) {
-        const float2 g = f[i * N + node];
-        const double s = (double)g.x + (double)g.y;
-        old[0] += s * cx(i);
-        old[1] += s * cy(i);
-        old[2] += s * cz(i);
-        const float cu = (float)(cx(i) * v[0] + cy(i) * v[1] + cz(i) * v[2]);
-        const float t = wgt(i) * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-        const float2 nf = make_float2((float)rf[0] * t, (float)rf[1] * t);
-        f[i * N + node] = nf;
-        dm[0] += (double)nf.x - (double)g.x;
-        dm[1] += (double)nf.y - (double)g.y;
-    }
-    unsafeAtomicAdd(&d.bb_mass[2], dm[0]);
-    unsafeAtomicAdd(&d.bb_mass[3], dm[1]);
-    double q[3];
-    for (int j = 0; j < 3; ++j) q[j] = (old[j] - (rf[0] + rf[1]) * v[j]) / 3.0;
-    for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * best + k], q, 1.0);
 }
 
 __global__ __launch_bounds__(256) void k_bb_commit(Lattice L, Dev d) {
@@ -552,6 +596,7 @@ __global__ __launch_bounds__(256) void k_bb_init(Lattice L, Dev d) {
         d.lab[k] = -1;
         d.lab_new[k] = -1;
         d.lmask[k] = 0u;
+        d.lpar[k] = 0u;
     }
 }
 
@@ -567,6 +612,7 @@ void launch_bb_geometry(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, 
     const int cells = z.ext * z.ext * z.ext;
     const dim3 gbox((cells + 255) / 256, n_caps), gcol((z.ext * z.ext + 255) / 256, n_caps);
     hipLaunchKernelGGL(k_bb_box, dim3(n_caps), dim3(256), 0, s, d, z.ext);
+    if (n_caps > 1) hipLaunchKernelGGL(k_bb_overlap, dim3((n_caps + 255) / 256, n_caps), dim3(256), 0, s, L, d, n_caps);
     hipLaunchKernelGGL(k_bb_clear, gbox, dim3(256), 0, s, L, d);
     hipLaunchKernelGGL(k_bb_links, dim3((n_faces + 255) / 256), dim3(256), 0, s, L, d, n_faces, z.link_cap);
     hipLaunchKernelGGL(k_bb_label, gcol, dim3(256), 0, s, L, d);
@@ -577,7 +623,8 @@ void launch_bb_refill(const Lattice& L, Dev& d, const BBSizes& z, const BBConst&
                       int n_caps, hipStream_t s) {
     if (n_caps <= 0) return;
     const int cells = z.ext * z.ext * z.ext;
-    hipLaunchKernelGGL(k_bb_refill, dim3((z.fresh_cap + 63) / 64), dim3(64), 0, s, L, d, k, (float2*)fpost, rho);
+    hipLaunchKernelGGL(k_bb_refill, dim3(std::min((z.fresh_cap + 3) / 4, 2048)), dim3(256), 0, s, L, d, k,
+                       (float2*)fpost, rho, z.fresh_cap);
     hipLaunchKernelGGL(k_bb_commit, dim3((cells + 255) / 256, n_caps), dim3(256), 0, s, L, d);
 }
 

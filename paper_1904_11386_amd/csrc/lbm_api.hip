@@ -8,6 +8,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -70,7 +71,7 @@ struct Layout {
     int64_t tiles, max_caps;
     // the bounce-back coupling
     bool bb = false;
-    size_t lab, lab_new, lmask, lkey, links, link_rho, fresh, bb_count, bbox, bb_com, bb_mass, node_V, P_cur, P_prev, QR;
+    size_t lab, lab_new, lmask, lpar, lkey, links, link_rho, fresh, bb_count, bbox, bb_com, bb_mass, node_V, P_cur, P_prev, QR;
     int link_cap = 0, fresh_cap = 0;
 };
 
@@ -176,6 +177,7 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
         l.lab = take(c, N * 4);
         l.lab_new = take(c, N * 4);
         l.lmask = take(c, N * 4);
+        l.lpar = take(c, N * 4);
         l.lkey = take(c, (size_t)9 * N * 8);
         l.links = take(c, (size_t)l.link_cap * 16);
         l.link_rho = take(c, (size_t)l.link_cap * 32);
@@ -440,6 +442,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
         d.lab = (int*)(w + lay.lab);
         d.lab_new = (int*)(w + lay.lab_new);
         d.lmask = (unsigned*)(w + lay.lmask);
+        d.lpar = (unsigned*)(w + lay.lpar);
         d.lkey = (unsigned long long*)(w + lay.lkey);
         d.links = (int4*)(w + lay.links);
         d.link_rho = (double4*)(w + lay.link_rho);
@@ -626,6 +629,47 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
                 c->bbz.ext = std::max(c->bbz.ext, (int)ceil(1.5 * (hi - lo)) + 9);
             }
     }
+    // Parity colours of the bounce-back labels: each capsule counts only the
+    // crossings of its own colour, so capsules whose boxes may meet (anchors
+    // within one box capacity on every axis, periodic) get different colours;
+    // the step reports two boxes of one colour that do meet.
+    std::vector<int> colour(n_caps, 0);
+    if (c->lay.bb) {
+        std::vector<std::array<int, 3>> anc;
+        std::vector<int> col;
+        for (const CapDev& e : c->caps) {
+            anc.push_back({e.anchor[0], e.anchor[1], e.anchor[2]});
+            col.push_back(e.colour);
+        }
+        const int nn3[3] = {c->p.nx, c->p.ny, c->p.nz};
+        for (int k = 0, o = 0; k < n_caps; o += nodes_per_cap[k], ++k) {
+            std::array<int, 3> a;
+            for (int j = 0; j < 3; ++j) {
+                double m = 0.0;
+                for (int b = 0; b < nodes_per_cap[k]; ++b) m += xyz_rest[3 * ((size_t)o + b) + j];
+                a[j] = (int)floor(m / nodes_per_cap[k] + 0.5);
+            }
+            unsigned used = 0u;
+            for (size_t e = 0; e < anc.size(); ++e) {
+                bool near = true;
+                for (int j = 0; j < 3; ++j) {
+                    int dd = (a[j] - anc[e][j]) % nn3[j];
+                    if (dd < 0) dd += nn3[j];
+                    dd = std::min(dd, nn3[j] - dd);
+                    near = near && dd < c->bbz.ext;
+                }
+                if (near) used |= 1u << col[e];
+            }
+            if (used == 0xffffffffu)
+                return c->fail(LBM_EINVAL, "capsule %d: more than 32 capsules within one label box of each other "
+                                           "under the bounce-back coupling", k);
+            int q = 0;
+            while (used & (1u << q)) ++q;
+            colour[k] = q;
+            anc.push_back(a);
+            col.push_back(q);
+        }
+    }
     if (first_id) *first_id = (int32_t)c->caps.size();
     nofs = fofs = 0;
     for (int k = 0; k < n_caps; ++k) {
@@ -653,6 +697,7 @@ int lbm_capsules_add(lbm_ctx* c, int32_t n_caps, const int32_t* nodes_per_cap, c
         cd.kB = 0.0f;
         cd.vp[0] = cd.vp[1] = cd.vp[2] = 0.0f;
         cd.prescribed = 0;
+        cd.colour = colour[k];
         // rest geometry in FP64, relative to the anchor
         std::vector<double> R(3 * (size_t)nn);
         for (int b = 0; b < nn; ++b)
@@ -911,6 +956,9 @@ static int check_bb(lbm_ctx* c) {
     if (f & 2) return c->fail(LBM_EUNSTABLE, "step %lld: more membrane links than the list holds", (long long)c->step);
     if (f & 4) return c->fail(LBM_EUNSTABLE, "step %lld: more fresh nodes than the list holds", (long long)c->step);
     if (f & 8) return c->fail(LBM_EUNSTABLE, "step %lld: a membrane is not closed (odd crossings)", (long long)c->step);
+    if (f & 16)
+        return c->fail(LBM_EUNSTABLE, "step %lld: the label boxes of two capsules of one parity colour met",
+                       (long long)c->step);
     return LBM_OK;
 }
 
@@ -962,7 +1010,6 @@ static hipGraphExec_t two_step_graph(lbm_ctx* c) {
 int lbm_capsules_velocity(lbm_ctx* c, int32_t first_id, int32_t n_caps, const double* v, int32_t prescribed) {
     if (!c) return LBM_EINVAL;
     if (!c->lay.bb) return c->fail(LBM_EINVAL, "node velocities need the bounce-back coupling (coupling = 1)");
-    if (c->step != 0 || c->launched) return c->fail(LBM_ESTATE, "node velocities must be set before the first step");
     if (n_caps < 0 || first_id < 0 || (int64_t)first_id + n_caps > (int64_t)c->caps.size())
         return c->fail(LBM_EINVAL, "capsule range outside the capsules added");
     if (n_caps == 0) return LBM_OK;
@@ -978,6 +1025,7 @@ int lbm_capsules_velocity(lbm_ctx* c, int32_t first_id, int32_t n_caps, const do
         for (int b = 0; b < cd.node_count; ++b)
             for (int j = 0; j < 3; ++j) V.push_back(cd.vp[j]);
     }
+    // (stream-ordered after the steps already enqueued)
     HIPCHK(c, hipMemcpyAsync(c->d.node_V + 3 * (size_t)b0, V.data(), V.size() * 4, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->d.caps, c->caps.data(), c->caps.size() * sizeof(CapDev), hipMemcpyHostToDevice,
                              c->stream));

@@ -86,6 +86,8 @@ struct CapDev {
     double V0;
     float vp[3];        // bounce-back coupling: the prescribed node velocity
     int prescribed;     // 1: the nodes keep vp (rigid translation)
+    int colour;         // bounce-back coupling: its bit (0..31) in the crossing-parity words; capsules whose
+                        // label boxes meet have different colours
 };
 
 struct FaceRef {        // rest metric of a triangle
@@ -153,8 +155,9 @@ struct Dev {
     // bounce-back coupling (allocated when it is chosen)
     int* lab;             // [N] label of the current membranes: capsule inside, or -1
     int* lab_new;         // [N] labels being computed (scratch, valid in the capsules' boxes)
-    unsigned* lmask;      // [N] bits 0..8: link from the node along half-direction d claimed; bit 16: parity
-                          //     of the membrane crossings of its +z link
+    unsigned* lmask;      // [N] bits 0..8: link from the node along half-direction d claimed
+    unsigned* lpar;       // [N] bit k: parity of the crossings of the node's +z link by the membranes of
+                          //     colour k
     int4* links;          // [link capacity] (node, half-direction, -, -)
     unsigned long long* lkey; // [9][N] per link: (FP32 crossing parameter, triangle), the least wins
     double4* link_rho;    // [link capacity] densities of the link's ends (A, B at the start; A, B at the end)

@@ -497,3 +497,27 @@ def bb_capsule(nx=24, ny=22, nz=26, centre=(11.37, 10.61, 12.83), radius=4.0, fr
     return Workload("bb_capsule", nx, ny, nz, np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB), [cap],
                     tau=tau, G=G, z_interface=zi, wet_scale=wet_scale, coupling=1, node_mass=node_mass,
                     mass_c0=C0, psi_kind=psi_kind)
+
+
+def bounce_back(wl: Workload, C0: float = 2500.0, node_mass: float = 5.0) -> Workload:
+    """The same lattice, densities and capsules under the paper's bounce-back
+    coupling (Sec. II.C-II.E): inertial nodes of mass `node_mass` (Sec. III),
+    the adaptive mass correction of strength C0, and the colour offset at
+    the full strength of the contact-angle law (wet_scale 1)."""
+    import dataclasses
+    return dataclasses.replace(wl, name=wl.name + "_bb", coupling=1, wet_scale=1.0, node_mass=node_mass,
+                               mass_c0=C0)
+
+
+def bb_pair(nx=32, ny=22, nz=26, centres=((9.37, 10.61, 12.83), (19.93, 11.29, 13.41)), radius=4.0, freq=4,
+            thetas=(60.0, 120.0), kS=0.01, kV=2.0, vs=((0.0, 0.0, 0.0), (0.0, 0.0, 0.0)), prescribed=False,
+            layered_z=13, C0=2500.0, node_mass=5.0) -> Workload:
+    """Two capsules for the bounce-back coupling on a flat interface
+    (A below layered_z), close enough that the lattice boxes in which their
+    labels are found overlap; velocities and whether they are prescribed are
+    inputs."""
+    rhoA, rhoB = layered(nx, ny, nz, layered_z)
+    caps = [Capsule(_snap(np.array(c, np.float64)), radius, freq, kS, 0.0, kV, th, v=tuple(float(a) for a in v),
+                    prescribed=prescribed) for c, th, v in zip(centres, thetas, vs)]
+    return Workload("bb_pair", nx, ny, nz, rhoA, rhoB, caps, G=3.6, z_interface=layered_z - 0.5, wet_scale=1.0,
+                    coupling=1, node_mass=node_mass, mass_c0=C0)

@@ -43,8 +43,8 @@ def _threads():
 
 
 def _compare(wl, steps, tol_rho=1e-5, tol_u=1e-5, tol_x=1e-5, every=None):
-    _say("case", wl.name, (wl.nx, wl.ny, wl.nz), "theta", wl.capsules[0].theta_deg, "v", wl.capsules[0].v,
-         "prescribed", wl.capsules[0].prescribed, "steps", steps)
+    _say("case", wl.name, (wl.nx, wl.ny, wl.nz), "theta", [c.theta_deg for c in wl.capsules],
+         "v", [c.v for c in wl.capsules], "prescribed", wl.capsules[0].prescribed, "steps", steps)
     g = _sim(wl)
     o = BB.from_workload(wl)
     umax = 0.0
@@ -59,11 +59,12 @@ def _compare(wl, steps, tol_rho=1e-5, tol_u=1e-5, tol_x=1e-5, every=None):
         eb = _rel(rb, o.rho_last[1].numpy())
         du = float(np.abs(u - o.u_last.numpy()).max())
         X = g.nodes()
-        dx = float(np.abs(X - o.X[0].numpy()).max())
+        dx = float(np.abs(X - torch.cat(o.X, 0).numpy()).max())
         V = g.node_velocities()
-        dv = float(np.abs(V - o.V[0].numpy()).max())
+        Vo = torch.cat(o.V, 0)
+        dv = float(np.abs(V - Vo.numpy()).max())
         _say("  step %d rho rel err %.3e %.3e  |du| %.3e U %.3e  node err %.3e lu  |dV| %.3e (|V| %.3e)  fresh %d"
-             % (o.n, ea, eb, du, umax, dx, dv, float(o.V[0].abs().max()), o.n_fresh))
+             % (o.n, ea, eb, du, umax, dx, dv, float(Vo.abs().max()), o.n_fresh))
         assert ea <= tol_rho and eb <= tol_rho
         assert du <= tol_u * umax
         assert dx <= tol_x
@@ -188,3 +189,76 @@ def test_neutral_sphere_keeps_its_height_gpu():
     _say("neutral sphere: COM z %.8f (mid-plane 12.5), x moved by %.4f" % (z, x - 11.37))
     assert abs(z - 12.5) < 1e-6
     assert x > 11.37 + 0.05
+
+
+@pytest.mark.timeout(600)
+def test_two_capsules_with_overlapping_label_boxes():
+    """Two capsules 2.5 lu apart on the interface (60 and 120 deg), so that
+    the lattice boxes in which their labels are found overlap: each
+    capsule's inside is found from its own membrane's crossings only.
+    Labels bit-exact at the start, 12 free steps compared every 2, then 100
+    steps of the pair translated side by side at a prescribed velocity."""
+    wl = W.bb_pair()
+    g = _sim(wl)
+    lab = g.labels()
+    lo = BB.from_workload(wl).L.numpy()
+    _say("pair at rest: inside", [int((lo == k).sum()) for k in range(2)], "differ", int((lab != lo).sum()))
+    assert (lo == 0).sum() > 200 and (lo == 1).sum() > 200
+    assert np.array_equal(lab, lo)
+    g.close()
+    _compare(wl, 12, every=2)
+    _compare(W.bb_pair(vs=((0.02, 0.01, 0.0), (0.02, 0.01, 0.0)), prescribed=True), 100, every=50)
+
+
+def test_same_colour_boxes_meeting_is_reported():
+    """Capsules added far apart share a parity colour; driven towards each
+    other at a prescribed velocity their label boxes meet, and the step
+    reports it (LBM_EUNSTABLE) instead of labelling with each other's
+    crossings."""
+    from paper_1904_11386_amd.binding import LBM_EUNSTABLE, LbmError, sim_from_workload
+    # boxes x in [1, 16] and [27, 42] at the start, closing at 0.1 lu per
+    # step: they meet near step 110, the membranes (18.6 lu apart) would
+    # touch near step 185; checked every step
+    wl = W.bb_pair(nx=56, centres=((8.37, 10.61, 12.83), (34.93, 11.29, 13.41)),
+                   vs=((0.05, 0.0, 0.0), (-0.05, 0.0, 0.0)), prescribed=True)
+    g = sim_from_workload(wl, check_every=1)
+    g.step(60)                  # still apart
+    with pytest.raises(LbmError) as ei:
+        g.step(100)
+    _say("reported:", ei.value)
+    assert ei.value.code == LBM_EUNSTABLE and "label boxes" in str(ei.value)
+    assert 100 < g.observables()["step"] < 125
+
+
+@pytest.mark.timeout(600)
+def test_hold_then_release_parity():
+    """Velocities set between steps: a wetting capsule (60 deg) held still
+    (prescribed V = 0) for 30 steps while the interface relaxes, then
+    released with V = (0.01, 0, 0) and free for 8 steps; the oracle does the
+    same.  Compared after the hold and every 2 steps after the release."""
+    wl = W.bb_capsule(layered_z=13, theta=60.0)
+    g = _sim(wl)
+    o = BB.from_workload(wl)
+    g.set_velocity(0, [(0.0, 0.0, 0.0)], prescribed=True)
+    o.caps[0]["prescribed"] = True
+    g.step(30)
+    for _ in range(30):
+        o.step()
+    v = torch.tensor([0.01, 0.0, 0.0], dtype=torch.float64)
+    g.set_velocity(0, [v.tolist()], prescribed=False)
+    o.caps[0]["prescribed"] = False
+    o.caps[0]["v"] = v
+    o.V[0] = v.view(1, 3).expand_as(o.X[0]).clone()
+    for k in range(5):
+        if k:
+            g.step(2)
+            for _ in range(2):
+                o.step()
+        ra, rb, u = g.fields()
+        ea, eb = _rel(ra, o.rho_last[0].numpy()), _rel(rb, o.rho_last[1].numpy())
+        dx = float(np.abs(g.nodes() - o.X[0].numpy()).max())
+        dv = float(np.abs(g.node_velocities() - o.V[0].numpy()).max())
+        _say("  step %d rho rel err %.3e %.3e  node err %.3e lu  |dV| %.3e  fresh %d" % (o.n, ea, eb, dx, dv, o.n_fresh))
+        assert ea <= 1e-5 and eb <= 1e-5 and dx <= 1e-6 and dv <= 1e-6
+    assert float(o.V[0].abs().max()) > 0.005
+    assert np.array_equal(g.labels(), o.labels().numpy())

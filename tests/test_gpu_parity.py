@@ -840,9 +840,19 @@ def test_fp16_precision_form_64_copy():
 def test_c2_64_crop_1000_steps_wetting_parity():
     """The 64^3 crop of the 128^3 workload (two R = 8, 2562-node capsules on
     the flat interface with contact angles drawn from [60, 120] deg, so the
-    wettability term is on) for 1000 FP32 steps against the FP64 oracle:
-    density <= 1e-5 relative per component, |du| <= 1e-5 U, node positions
-    within 1e-4 lu, compared every 100 steps."""
+    wettability term is on) for 1000 FP32 steps against the FP64 oracle,
+    compared every 100 steps.
+
+    Between steps 200 and 300 a wetting film closes around the lower pole of
+    the capsule that straddles the periodic y boundary, and that event
+    amplifies whatever perturbation the fields carry into it about fifteen
+    times at the same lattice nodes: the oracle with only its stored
+    populations rounded to FP32 after every step (FP64 arithmetic) moves
+    from 1.2e-7 to 1.7e-6 there; the FP32 step enters it with 2.3e-6 and
+    peaks at about 4e-5 before the film settles.  The bounds are therefore
+    two: at every checkpoint density <= 6e-5, |du| <= 2e-5 U, node positions
+    <= 1e-4 lu (the FP32 level before the event times its amplification);
+    after 1000 steps density <= 1.5e-5 and |du| <= 1e-5 U."""
     wl = W.make("c2_64")
     _say("thetas", [round(c.theta_deg, 2) for c in wl.capsules])
     assert all(abs(c.theta_deg - 90.0) > 5.0 for c in wl.capsules)
@@ -851,6 +861,7 @@ def test_c2_64_crop_1000_steps_wetting_parity():
     o = from_workload(wl)
     umax = 0.0
     worst = [0.0, 0.0, 0.0]
+    last = None
     for k in range(10):
         g.step(100)
         for _ in range(100):
@@ -862,11 +873,13 @@ def test_c2_64_crop_1000_steps_wetting_parity():
         du = float(np.abs(u - o.u_last.numpy()).max())
         dx = float(np.abs(g.nodes() - torch.cat(o.X, 0).numpy()).max())
         worst = [max(worst[0], ea, eb), max(worst[1], du / umax), max(worst[2], dx)]
+        last = (max(ea, eb), du / umax)
         _say("  step %d rho rel err %.3e %.3e  du/U %.3e (U %.3e)  node err %.3e lu"
              % ((k + 1) * 100, ea, eb, du / umax, umax, dx))
     # the phi fields were non-zero: the wettability term acted
     assert float(o.phi_last.abs().max()) > 1e-3
-    assert worst[0] <= 1e-5 and worst[1] <= 1e-5 and worst[2] <= 1e-4, worst
+    assert worst[0] <= 6e-5 and worst[1] <= 2e-5 and worst[2] <= 1e-4, worst
+    assert last[0] <= 1.5e-5 and last[1] <= 1e-5, last
 
 
 def test_fp16_walls_and_checkpoint():
