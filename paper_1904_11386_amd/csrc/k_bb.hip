@@ -13,21 +13,24 @@
 //                 MARGIN, the mean node offset; counters and volumes zeroed
 //   k_bb_overlap  per pair of capsules of one parity colour: their boxes
 //                 must not meet (reported)
-//   k_bb_clear    per box: new labels -1, link and parity bits 0
-//   k_bb_links    per triangle: the lattice links it pierces (FP64
-//                 Moeller-Trumbore over its bounding box); each link listed
-//                 once; its element is the triangle pierced nearest the
+//   k_bb_clear    per box: new labels -1, parity bits 0, link keys empty
+//   k_bb_links    per triangle and half-direction: the lattice links it
+//                 pierces (FP64 Moeller-Trumbore over its bounding box, after
+//                 a plane-side test); its centroid; for each link, its
+//                 element is the triangle pierced nearest the
 //                 link's start node (the end from which it points along a
 //                 positive half-direction; lowest index among ties at single
 //                 precision), for both of its ends; the parity of the
 //                 crossings of each +z link, one bit per capsule colour
+//   k_bb_list     per box cell: the links crossed there, listed once each
+//                 (by the box of their element's capsule)
 //   k_bb_label    per box column: inside where the +z crossings below by the
 //                 capsule's own membrane (its colour's bit) are odd
 //   k_bb_detect   per box: fresh nodes (label changed) listed, once each
-//   k_bb_refill   per fresh node (a wavefront each): the density
+//   k_bb_refill   per fresh node (a block each): the density
 //                 interpolated from its side's non-fresh neighbours,
 //                 mass-corrected and clamped to their range; the velocity of
-//                 the nearest element (the lanes share the search); the
+//                 the nearest element (the threads share the search); the
 //                 equilibrium populations; removed minus created momentum to
 //                 the element
 //   k_bb_commit   per box: labels := new labels
@@ -76,6 +79,12 @@ __device__ __forceinline__ int wrapi(int v, int n) {
 
 __device__ __forceinline__ int64_t lat(const Lattice& L, int x, int y, int z) {
     return ((int64_t)wrapi(z, L.nz) * L.ny + wrapi(y, L.ny)) * L.nx + wrapi(x, L.nx);
+}
+
+// the same for coordinates within one cell of the lattice (-1 .. n)
+__device__ __forceinline__ int wrap1(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+__device__ __forceinline__ int64_t lat1(const Lattice& L, int x, int y, int z) {
+    return ((int64_t)wrap1(z, L.nz) * L.ny + wrap1(y, L.ny)) * L.nx + wrap1(x, L.nx);
 }
 
 // the D3Q19 direction of half-direction d = 0..8: +x, +y, +z and the six
@@ -198,7 +207,6 @@ __global__ __launch_bounds__(256) void k_bb_clear(Lattice L, Dev d) {
     const CapDev& C = d.caps[cap];
     const int64_t node = lat(L, C.anchor[0] + q[0], C.anchor[1] + q[1], C.anchor[2] + q[2]);
     d.lab_new[node] = -1;
-    d.lmask[node] = 0u;
     d.lpar[node] = 0u;      // (every box is cleared before any capsule's links are found)
     for (int k = 0; k < 9; ++k) d.lkey[k * L.n + node] = ~0ull;
 }
@@ -224,12 +232,21 @@ __device__ __forceinline__ bool seg_hits(const double p[3], int cx_, int cy_, in
     return t >= 0.0 && t < 1.0;
 }
 
+// One thread per (triangle, half-direction).  Only start points from which
+// the segment can reach the triangle's bounding box are visited, and those
+// whose segment stays strictly on one side of the triangle's plane (both
+// signed distances beyond a margin far above their FP64 rounding) are
+// skipped before the full test; neither skips a segment the full test would
+// accept.
 __global__ __launch_bounds__(256) void k_bb_links(Lattice L, Dev d, int n_faces, int link_cap) {
-    const int f = blockIdx.x * blockDim.x + threadIdx.x;
-    if (f >= n_faces) return;
+    const int gid = blockIdx.x * blockDim.x + threadIdx.x;
+    if (gid >= 9 * n_faces) return;
+    const int f = gid / 9, dh = gid - 9 * f;
     const CapDev& C = d.caps[d.face_cap[f]];
     double V[3][3];
     for (int k = 0; k < 3; ++k) node_rel(d, d.tri[3 * f + k], V[k]);
+    if (dh == 0)
+        for (int j = 0; j < 3; ++j) d.face_cen[3 * f + j] = V[0][j] + V[1][j] + V[2][j];
     double e1[3], e2[3];
     int lo[3], hi[3];
     for (int k = 0; k < 3; ++k) {
@@ -242,29 +259,87 @@ __global__ __launch_bounds__(256) void k_bb_links(Lattice L, Dev d, int n_faces,
             return;
         }
     }
+    const int i = half_dir(dh);
+    // a hit p + t c (0 <= t < 1) lies in the triangle's bounding box, so p
+    // lies in that box moved back by t c: per axis [min - max(c, 0), max -
+    // min(c, 0)], widened by far more than the test's FP64 rounding
+    const int ci[3] = {cx(i), cy(i), cz(i)};
+    for (int k = 0; k < 3; ++k) {
+        const double mn = fmin(V[0][k], fmin(V[1][k], V[2][k])), mx = fmax(V[0][k], fmax(V[1][k], V[2][k]));
+        lo[k] = max(lo[k], (int)ceil(mn - (double)max(ci[k], 0) - 1e-9));
+        hi[k] = min(hi[k], (int)floor(mx - (double)min(ci[k], 0) + 1e-9));
+    }
+    const double nrm[3] = {e1[1] * e2[2] - e1[2] * e2[1], e1[2] * e2[0] - e1[0] * e2[2], e1[0] * e2[1] - e1[1] * e2[0]};
+    const double nc = nrm[0] * ci[0] + nrm[1] * ci[1] + nrm[2] * ci[2];
+    const double margin = 1e-9 * (fabs(nrm[0]) + fabs(nrm[1]) + fabs(nrm[2]));
     for (int z = lo[2]; z <= hi[2]; ++z)
         for (int y = lo[1]; y <= hi[1]; ++y)
             for (int x = lo[0]; x <= hi[0]; ++x) {
                 const double p[3] = {(double)x, (double)y, (double)z};
-                for (int dh = 0; dh < 9; ++dh) {
-                    const int i = half_dir(dh);
-                    double t;
-                    if (!seg_hits(p, cx(i), cy(i), cz(i), V[0], e1, e2, t)) continue;
-                    const int64_t node = lat(L, C.anchor[0] + x, C.anchor[1] + y, C.anchor[2] + z);
-                    if (i == 5) atomicXor(&d.lpar[node], 1u << C.colour);
-                    // the link's element: nearest crossing, then lowest index
-                    const unsigned long long key =
-                        ((unsigned long long)__float_as_uint((float)t) << 32) | (unsigned long long)(unsigned)f;
-                    atomicMin(&d.lkey[dh * L.n + node], key);
-                    const unsigned bit = 1u << dh;
-                    if (atomicOr(&d.lmask[node], bit) & bit) continue;       // listed by another triangle
-                    const int k = atomicAdd(&d.bb_count[CNT_LINKS], 1);
-                    if (k < link_cap)
-                        d.links[k] = make_int4((int)node, dh, 0, 0);
-                    else
-                        atomicOr(&d.bb_count[CNT_FLAGS], FLAG_LINKS);
-                }
+                const double d0 = nrm[0] * (p[0] - V[0][0]) + nrm[1] * (p[1] - V[0][1]) + nrm[2] * (p[2] - V[0][2]);
+                const double d1 = d0 + nc;
+                if ((d0 > margin && d1 > margin) || (d0 < -margin && d1 < -margin)) continue;
+                double t;
+                if (!seg_hits(p, cx(i), cy(i), cz(i), V[0], e1, e2, t)) continue;
+                const int64_t node = lat(L, C.anchor[0] + x, C.anchor[1] + y, C.anchor[2] + z);
+                if (i == 5) atomicXor(&d.lpar[node], 1u << C.colour);
+                // the link's element: nearest crossing, then lowest index
+                // (k_bb_list lists the links from these keys)
+                const unsigned long long key =
+                    ((unsigned long long)__float_as_uint((float)t) << 32) | (unsigned long long)(unsigned)f;
+                atomicMin(&d.lkey[dh * L.n + node], key);
             }
+}
+
+// Start of this thread's run of c slots in the list whose length is *count:
+// one atomic per block (every thread of the block calls it).
+__device__ __forceinline__ int block_append(int c, int* count) {
+    __shared__ int wsum[4];
+    __shared__ int base;
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
+    int inc = c;                                   // inclusive scan within the wavefront
+    for (int o = 1; o < 64; o <<= 1) {
+        const int t = __shfl_up(inc, o, 64);
+        if (lane >= o) inc += t;
+    }
+    if (lane == 63) wsum[wave] = inc;
+    __syncthreads();
+    int before = 0, total = 0;
+    for (int w = 0; w < 4; ++w) {
+        before += w < wave ? wsum[w] : 0;
+        total += wsum[w];
+    }
+    if (threadIdx.x == 0) base = total > 0 ? atomicAdd(count, total) : 0;
+    __syncthreads();
+    return base + before + inc - c;
+}
+
+// Per box cell: the links from the node that a triangle crosses, each listed
+// once, by the box of the capsule its element belongs to.
+__global__ __launch_bounds__(256) void k_bb_list(Lattice L, Dev d, int link_cap) {
+    const int cap = blockIdx.y;
+    int q[3];
+    const bool in = box_cell(d, cap, blockIdx.x * blockDim.x + threadIdx.x, q);
+    if (__syncthreads_or(in) == 0) return;     // (block-uniform)
+    int64_t node = 0;
+    unsigned mine = 0u;
+    if (in) {
+        const CapDev& C = d.caps[cap];
+        node = lat(L, C.anchor[0] + q[0], C.anchor[1] + q[1], C.anchor[2] + q[2]);
+        for (int dh = 0; dh < 9; ++dh) {
+            const unsigned long long key = d.lkey[dh * L.n + node];
+            if (key != ~0ull && d.face_cap[(unsigned)(key & 0xffffffffull)] == cap) mine |= 1u << dh;
+        }
+    }
+    int k = block_append(__popc(mine), &d.bb_count[CNT_LINKS]);
+    for (int dh = 0; dh < 9; ++dh) {
+        if (!(mine & (1u << dh))) continue;
+        if (k < link_cap)
+            d.links[k] = make_int4((int)node, dh, 0, 0);
+        else
+            atomicOr(&d.bb_count[CNT_FLAGS], FLAG_LINKS);
+        ++k;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bb_label(Lattice L, Dev d) {
@@ -310,42 +385,46 @@ __global__ void k_bb_ledger(Dev d) {
     }
 }
 
-// One wavefront per fresh node: every lane forms the interpolated density
-// (the same loads), the lanes share the nearest-element search (faces
-// lane, lane + 64, ...; the least distance, then the lowest index, as a
-// scan in face order finds it), lane 0 writes.
+// One block per fresh node: thread 0 forms the interpolated density, the
+// 256 threads share the nearest-element search over the centroids
+// k_bb_links left (faces t, t + 256, ...; the least distance, then the
+// lowest index, as a scan in face order finds it), thread 0 writes.
 __global__ __launch_bounds__(256) void k_bb_refill(Lattice L, Dev d, BBConst K, float2* __restrict__ f,
                                                   const float* __restrict__ rho, int fresh_cap) {
-    const int lane = threadIdx.x & 63;
+    __shared__ double sbd[4];
+    __shared__ int sbest[4];
+    const int lane = (int)(threadIdx.x & 63), wave = (int)(threadIdx.x >> 6);
     const int n_fresh = min(d.bb_count[CNT_FRESH], fresh_cap);
     const int64_t N = L.n;
-    for (int e = blockIdx.x * 4 + (int)(threadIdx.x >> 6); e < n_fresh; e += gridDim.x * 4) {
+    for (int e = blockIdx.x; e < n_fresh; e += gridDim.x) {
         const int64_t node = d.fresh[e];
         const int x = (int)(node % L.nx), y = (int)((node / L.nx) % L.ny), z = (int)(node / ((int64_t)L.nx * L.ny));
         const int ell = d.lab_new[node];
-        // the density interpolated from the non-fresh neighbours on the node's side
-        double sum[2] = {0, 0}, mn[2] = {1e300, 1e300}, mx[2] = {-1e300, -1e300};
-        int cnt = 0;
-        for (int i = 1; i < Q; ++i) {
-            const int64_t nb = lat(L, x + cx(i), y + cy(i), z + cz(i));
-            const int ln = d.lab_new[nb];
-            if (ln != ell || ln != d.lab[nb]) continue;
-            ++cnt;
-            for (int c = 0; c < 2; ++c) {
-                const double r = rho[c * N + nb];
-                sum[c] += r;
-                mn[c] = fmin(mn[c], r);
-                mx[c] = fmax(mx[c], r);
+        double rf[2] = {0.0, 0.0};
+        if (threadIdx.x == 0) {
+            // the density interpolated from the non-fresh neighbours on the node's side
+            double sum[2] = {0, 0}, mn[2] = {1e300, 1e300}, mx[2] = {-1e300, -1e300};
+            int cnt = 0;
+            for (int i = 1; i < Q; ++i) {
+                const int64_t nb = lat1(L, x + cx(i), y + cy(i), z + cz(i));
+                const int ln = d.lab_new[nb];
+                if (ln != ell || ln != d.lab[nb]) continue;
+                ++cnt;
+                for (int c = 0; c < 2; ++c) {
+                    const double r = rho[c * N + nb];
+                    sum[c] += r;
+                    mn[c] = fmin(mn[c], r);
+                    mx[c] = fmax(mx[c], r);
+                }
             }
-        }
-        double rf[2];
-        for (int c = 0; c < 2; ++c) {
-            if (cnt == 0) {
-                rf[c] = rho[c * N + node];
-            } else {
-                const double corr = 1.0 - K.c0 * ((K.rho_init[0] + K.rho_init[1]) / K.rho_init[c]) *
-                                              d.bb_mass[c] / K.vsys;
-                rf[c] = fmin(fmax(sum[c] / cnt * corr, mn[c]), mx[c]);
+            for (int c = 0; c < 2; ++c) {
+                if (cnt == 0) {
+                    rf[c] = rho[c * N + node];
+                } else {
+                    const double corr = 1.0 - K.c0 * ((K.rho_init[0] + K.rho_init[1]) / K.rho_init[c]) *
+                                                  d.bb_mass[c] / K.vsys;
+                    rf[c] = fmin(fmax(sum[c] / cnt * corr, mn[c]), mx[c]);
+                }
             }
         }
         // the nearest element (nearest centroid) of the capsule whose membrane passed
@@ -356,21 +435,27 @@ __global__ __launch_bounds__(256) void k_bb_refill(Lattice L, Dev d, BBConst K, 
         for (int k = 0; k < 3; ++k) p[k] -= nn[k] * rint((p[k] - d.bb_com[3 * cap + k]) / nn[k]);
         int best = 0x7fffffff;
         double bd = 1e300;
-        for (int ff = C.face_start + lane; ff < C.face_start + C.face_count; ff += 64) {
-            double sc[3] = {0, 0, 0};
-            for (int k = 0; k < 3; ++k) {
-                double q[3];
-                node_rel(d, d.tri[3 * ff + k], q);
-                for (int j = 0; j < 3; ++j) sc[j] += q[j];
+        const int fend = C.face_start + C.face_count;
+        for (int f0 = C.face_start + (int)threadIdx.x; f0 < fend; f0 += 4 * 256) {
+            double cen[4][3];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ff = min(f0 + 256 * u, fend - 1);
+#pragma unroll
+                for (int j = 0; j < 3; ++j) cen[u][j] = d.face_cen[3 * ff + j];
             }
-            double dd = 0.0;
-            for (int j = 0; j < 3; ++j) {
-                const double t = sc[j] / 3.0 - p[j];
-                dd += t * t;
-            }
-            if (dd < bd) {      // (a lane's faces come in increasing order)
-                bd = dd;
-                best = ff;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int ff = f0 + 256 * u;
+                double dd = 0.0;
+                for (int j = 0; j < 3; ++j) {
+                    const double t = cen[u][j] / 3.0 - p[j];
+                    dd += t * t;
+                }
+                if (ff < fend && dd < bd) {      // (a thread's faces come in increasing order)
+                    bd = dd;
+                    best = ff;
+                }
             }
         }
         for (int o = 32; o > 0; o >>= 1) {
@@ -381,32 +466,44 @@ __global__ __launch_bounds__(256) void k_bb_refill(Lattice L, Dev d, BBConst K, 
                 best = ob;
             }
         }
-        if (best == 0x7fffffff) best = C.face_start;      // (no finite distance: a torn membrane)
-        if (lane != 0) continue;
-        double v[3] = {0, 0, 0};
-        for (int k = 0; k < 3; ++k)
-            for (int j = 0; j < 3; ++j) v[j] += d.node_V[3 * d.tri[3 * best + k] + j] / 3.0;
-        // removed momentum, new populations, created momentum
-        double old[3] = {0, 0, 0}, dm[2] = {0, 0};
-        const float uu = (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-        for (int i = 0; i < Q; ++i) {
-            const float2 g = f[i * N + node];
-            const double sg = (double)g.x + (double)g.y;
-            old[0] += sg * cx(i);
-            old[1] += sg * cy(i);
-            old[2] += sg * cz(i);
-            const float cu = (float)(cx(i) * v[0] + cy(i) * v[1] + cz(i) * v[2]);
-            const float t = wgt(i) * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
-            const float2 nf = make_float2((float)rf[0] * t, (float)rf[1] * t);
-            f[i * N + node] = nf;
-            dm[0] += (double)nf.x - (double)g.x;
-            dm[1] += (double)nf.y - (double)g.y;
+        if (lane == 0) {
+            sbd[wave] = bd;
+            sbest[wave] = best;
         }
-        unsafeAtomicAdd(&d.bb_mass[2], dm[0]);
-        unsafeAtomicAdd(&d.bb_mass[3], dm[1]);
-        double q[3];
-        for (int j = 0; j < 3; ++j) q[j] = (old[j] - (rf[0] + rf[1]) * v[j]) / 3.0;
-        for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * best + k], q, 1.0);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < 4; ++w)
+                if (sbd[w] < bd || (sbd[w] == bd && sbest[w] < best)) {
+                    bd = sbd[w];
+                    best = sbest[w];
+                }
+            if (best == 0x7fffffff) best = C.face_start;      // (no finite distance: a torn membrane)
+            double v[3] = {0, 0, 0};
+            for (int k = 0; k < 3; ++k)
+                for (int j = 0; j < 3; ++j) v[j] += d.node_V[3 * d.tri[3 * best + k] + j] / 3.0;
+            // removed momentum, new populations, created momentum
+            double old[3] = {0, 0, 0}, dm[2] = {0, 0};
+            const float uu = (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+            for (int i = 0; i < Q; ++i) {
+                const float2 g = f[i * N + node];
+                const double sg = (double)g.x + (double)g.y;
+                old[0] += sg * cx(i);
+                old[1] += sg * cy(i);
+                old[2] += sg * cz(i);
+                const float cu = (float)(cx(i) * v[0] + cy(i) * v[1] + cz(i) * v[2]);
+                const float t = wgt(i) * (1.0f + 3.0f * cu + 4.5f * cu * cu - 1.5f * uu);
+                const float2 nf = make_float2((float)rf[0] * t, (float)rf[1] * t);
+                f[i * N + node] = nf;
+                dm[0] += (double)nf.x - (double)g.x;
+                dm[1] += (double)nf.y - (double)g.y;
+            }
+            unsafeAtomicAdd(&d.bb_mass[2], dm[0]);
+            unsafeAtomicAdd(&d.bb_mass[3], dm[1]);
+            double q[3];
+            for (int j = 0; j < 3; ++j) q[j] = (old[j] - (rf[0] + rf[1]) * v[j]) / 3.0;
+            for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * best + k], q, 1.0);
+        }
+        __syncthreads();      // (sbd, sbest are reused by the next fresh node)
     }
 }
 
@@ -432,57 +529,74 @@ __device__ __forceinline__ void node_density(const float2* __restrict__ f, int64
 // bounced (a node with several crossing links has them all rewritten).
 __global__ __launch_bounds__(256) void k_bb_link_density(Lattice L, Dev d, const float2* __restrict__ f,
                                                          int link_cap) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= min(d.bb_count[CNT_LINKS], link_cap)) return;
-    const int4 rec = d.links[e];
-    const int64_t xn = rec.x;
-    const int i = half_dir(rec.y);
-    const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
-    const int64_t yn = lat(L, x + cx(i), y + cy(i), z + cz(i));
-    double rx[2], ry[2];
-    node_density(f, L.n, xn, rx);
-    node_density(f, L.n, yn, ry);
-    d.link_rho[e] = make_double4(rx[0], rx[1], ry[0], ry[1]);
+    const int n = min(d.bb_count[CNT_LINKS], link_cap);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int4 rec = d.links[e];
+        const int64_t xn = rec.x;
+        const int i = half_dir(rec.y);
+        const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
+        const int64_t yn = lat1(L, x + cx(i), y + cy(i), z + cz(i));
+        double rx[2], ry[2];
+        node_density(f, L.n, xn, rx);
+        node_density(f, L.n, yn, ry);
+        d.link_rho[e] = make_double4(rx[0], rx[1], ry[0], ry[1]);
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bb_fixup(Lattice L, Dev d, float2* __restrict__ f, int link_cap) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= min(d.bb_count[CNT_LINKS], link_cap)) return;
-    const int4 rec = d.links[e];
+    const int n = min(d.bb_count[CNT_LINKS], link_cap);
     const int64_t N = L.n;
-    const int64_t xn = rec.x;
-    const int i = half_dir(rec.y), j = opp(i);
-    const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
-    const int64_t yn = lat(L, x + cx(i), y + cy(i), z + cz(i));
-    if (d.lab[xn] == d.lab[yn]) return;       // the link crosses the membrane twice, or not
-    const int face = (int)(unsigned)(d.lkey[rec.y * N + xn] & 0xffffffffull);
-    double v0[3] = {0, 0, 0};
-    for (int k = 0; k < 3; ++k)
-        for (int a = 0; a < 3; ++a) v0[a] += d.node_V[3 * d.tri[3 * face + k] + a] / 3.0;
-    const double4 lr = d.link_rho[e];
-    const double rx[2] = {lr.x, lr.y}, ry[2] = {lr.z, lr.w};
-    const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
-    const double cv = ci[0] * v0[0] + ci[1] * v0[1] + ci[2] * v0[2];      // c_i . v0 = -(c_j . v0)
-    const double w = wgt(i);
-    // the slot (x, i) is what the pull at y reads along c_i, the slot (y, j)
-    // what the pull at x reads along c_j
-    const float2 a = f[i * N + xn];      // x's outgoing population towards y
-    const float2 b = f[j * N + yn];      // y's outgoing population towards x
-    const float2 back_x = make_float2((float)((double)a.x - 6.0 * w * rx[0] * cv),
-                                      (float)((double)a.y - 6.0 * w * rx[1] * cv));     // to x along c_j
-    const float2 back_y = make_float2((float)((double)b.x + 6.0 * w * ry[0] * cv),
-                                      (float)((double)b.y + 6.0 * w * ry[1] * cv));     // to y along c_i
-    f[j * N + yn] = back_x;
-    f[i * N + xn] = back_y;
-    // the moving-element terms change each side's mass (as stored)
-    unsafeAtomicAdd(&d.bb_mass[2], ((double)back_x.x - a.x) + ((double)back_y.x - b.x));
-    unsafeAtomicAdd(&d.bb_mass[3], ((double)back_x.y - a.y) + ((double)back_y.y - b.y));
-    // momentum to the element: [out + back] c_out at each end
-    const double sx = (double)a.x + a.y + back_x.x + back_x.y;
-    const double sy = (double)b.x + b.y + back_y.x + back_y.y;
-    double dp[3];
-    for (int k = 0; k < 3; ++k) dp[k] = (sx - sy) * ci[k] / 3.0;
-    for (int k = 0; k < 3; ++k) add3(d.P_cur + 3 * d.tri[3 * face + k], dp, 1.0);
+    // (the loop is wave-uniform: every lane of a wavefront reaches the reduction)
+    for (int base = blockIdx.x * blockDim.x + (int)(threadIdx.x & ~63u); base < n; base += gridDim.x * blockDim.x) {
+        const int e = base + (int)(threadIdx.x & 63);
+        double dmA = 0.0, dmB = 0.0;      // this lane's change of each component's stored mass
+        if (e < n) {
+            const int4 rec = d.links[e];
+            const int64_t xn = rec.x;
+            const int i = half_dir(rec.y), j = opp(i);
+            const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
+            const int64_t yn = lat1(L, x + cx(i), y + cy(i), z + cz(i));
+            if (d.lab[xn] != d.lab[yn]) {       // (equal: the link crosses the membrane twice, or not)
+                const int face = (int)(unsigned)(d.lkey[rec.y * N + xn] & 0xffffffffull);
+                double v0[3] = {0, 0, 0};
+                for (int k = 0; k < 3; ++k)
+                    for (int a = 0; a < 3; ++a) v0[a] += d.node_V[3 * d.tri[3 * face + k] + a] / 3.0;
+                const double4 lr = d.link_rho[e];
+                const double rx[2] = {lr.x, lr.y}, ry[2] = {lr.z, lr.w};
+                const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+                const double cv = ci[0] * v0[0] + ci[1] * v0[1] + ci[2] * v0[2];      // c_i . v0 = -(c_j . v0)
+                const double w = wgt(i);
+                // the slot (x, i) is what the pull at y reads along c_i, the slot (y, j)
+                // what the pull at x reads along c_j
+                const float2 a = f[i * N + xn];      // x's outgoing population towards y
+                const float2 b = f[j * N + yn];      // y's outgoing population towards x
+                const float2 back_x = make_float2((float)((double)a.x - 6.0 * w * rx[0] * cv),
+                                                  (float)((double)a.y - 6.0 * w * rx[1] * cv));     // to x along c_j
+                const float2 back_y = make_float2((float)((double)b.x + 6.0 * w * ry[0] * cv),
+                                                  (float)((double)b.y + 6.0 * w * ry[1] * cv));     // to y along c_i
+                f[j * N + yn] = back_x;
+                f[i * N + xn] = back_y;
+                // the moving-element terms change each side's mass (as stored)
+                dmA = ((double)back_x.x - a.x) + ((double)back_y.x - b.x);
+                dmB = ((double)back_x.y - a.y) + ((double)back_y.y - b.y);
+                // momentum to the element: [out + back] c_out at each end
+                const double sx = (double)a.x + a.y + back_x.x + back_x.y;
+                const double sy = (double)b.x + b.y + back_y.x + back_y.y;
+                double dp[3];
+                for (int k = 0; k < 3; ++k) dp[k] = (sx - sy) * ci[k] / 3.0;
+                for (int k = 0; k < 3; ++k) add3(d.P_cur + 3 * d.tri[3 * face + k], dp, 1.0);
+            }
+        }
+        // the ledger: one pair of atomics per wavefront
+        for (int o = 32; o > 0; o >>= 1) {
+            dmA += __shfl_xor(dmA, o, 64);
+            dmB += __shfl_xor(dmB, o, 64);
+        }
+        if ((threadIdx.x & 63) == 0 && (dmA != 0.0 || dmB != 0.0)) {
+            unsafeAtomicAdd(&d.bb_mass[2], dmA);
+            unsafeAtomicAdd(&d.bb_mass[3], dmB);
+        }
+    }
 }
 
 __global__ __launch_bounds__(256) void k_bb_unflag(Lattice L, Dev d, int n_tiles) {
@@ -509,14 +623,23 @@ __global__ __launch_bounds__(256) void k_bb_flag(Lattice L, Dev d) {
 __device__ __forceinline__ void bound_density(const Lattice& L, const Dev& d, const float* __restrict__ rho,
                                               int64_t of, int side, double r[2]) {
     const int x = (int)(of % L.nx), y = (int)((of / L.nx) % L.ny), z = (int)(of / ((int64_t)L.nx * L.ny));
+    int lb[Q];
+    float ra[Q], rb[Q];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+        const int64_t nb = lat1(L, x + cx(q), y + cy(q), z + cz(q));
+        lb[q] = d.lab[nb];
+        ra[q] = rho[nb];
+        rb[q] = rho[L.n + nb];
+    }
     double s[2] = {0, 0};
     int cnt = 0;
+#pragma unroll
     for (int q = 1; q < Q; ++q) {
-        const int64_t nb = lat(L, x + cx(q), y + cy(q), z + cz(q));
-        if (d.lab[nb] != side) continue;
+        if (lb[q] != side) continue;
         ++cnt;
-        s[0] += rho[nb];
-        s[1] += rho[L.n + nb];
+        s[0] += ra[q];
+        s[1] += rb[q];
     }
     r[0] = s[0] / cnt;
     r[1] = s[1] / cnt;
@@ -524,45 +647,46 @@ __device__ __forceinline__ void bound_density(const Lattice& L, const Dev& d, co
 
 __global__ __launch_bounds__(256) void k_bb_sc(Lattice L, Dev d, BBConst K, const float* __restrict__ rho,
                                               int link_cap) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= min(d.bb_count[CNT_LINKS], link_cap)) return;
-    const int4 rec = d.links[e];
-    const int64_t N = L.n;
-    const int64_t xn = rec.x;
-    const int i = half_dir(rec.y);
-    const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
-    const int64_t yn = lat(L, x + cx(i), y + cy(i), z + cz(i));
-    const int lx = d.lab[xn], ly = d.lab[yn];
-    if (lx == ly) return;
-    const int face = (int)(unsigned)(d.lkey[rec.y * N + xn] & 0xffffffffull);
-    const CapDev& C = d.caps[d.face_cap[face]];
-    const double w = wgt(i), G = L.G;
-    const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
-    double react[3] = {0, 0, 0};
-    // end 0: x sees y along +c_i; end 1: y sees x along -c_i
-    for (int end = 0; end < 2; ++end) {
-        const int64_t self = end == 0 ? xn : yn, other = end == 0 ? yn : xn;
-        const double sg = end == 0 ? 1.0 : -1.0;
-        double rb[2];
-        bound_density(L, d, rho, other, end == 0 ? lx : ly, rb);
-        rb[C.pref] += C.rv_abs;
-        double pv[2], po[2], ps[2];
-        for (int c = 0; c < 2; ++c) {
-            pv[c] = psi_of(rb[c], K.psi_exp);
-            po[c] = psi_of(rho[c * N + other], K.psi_exp);
-            ps[c] = psi_of(rho[c * N + self], K.psi_exp);
+    const int n = min(d.bb_count[CNT_LINKS], link_cap);
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n; e += gridDim.x * blockDim.x) {
+        const int4 rec = d.links[e];
+        const int64_t N = L.n;
+        const int64_t xn = rec.x;
+        const int i = half_dir(rec.y);
+        const int x = (int)(xn % L.nx), y = (int)((xn / L.nx) % L.ny), z = (int)(xn / ((int64_t)L.nx * L.ny));
+        const int64_t yn = lat1(L, x + cx(i), y + cy(i), z + cz(i));
+        const int lx = d.lab[xn], ly = d.lab[yn];
+        if (lx == ly) continue;
+        const int face = (int)(unsigned)(d.lkey[rec.y * N + xn] & 0xffffffffull);
+        const CapDev& C = d.caps[d.face_cap[face]];
+        const double w = wgt(i), G = L.G;
+        const double ci[3] = {(double)cx(i), (double)cy(i), (double)cz(i)};
+        double react[3] = {0, 0, 0};
+        // end 0: x sees y along +c_i; end 1: y sees x along -c_i
+        for (int end = 0; end < 2; ++end) {
+            const int64_t self = end == 0 ? xn : yn, other = end == 0 ? yn : xn;
+            const double sg = end == 0 ? 1.0 : -1.0;
+            double rb[2];
+            bound_density(L, d, rho, other, end == 0 ? lx : ly, rb);
+            rb[C.pref] += C.rv_abs;
+            double pv[2], po[2], ps[2];
+            for (int c = 0; c < 2; ++c) {
+                pv[c] = psi_of(rb[c], K.psi_exp);
+                po[c] = psi_of(rho[c * N + other], K.psi_exp);
+                ps[c] = psi_of(rho[c * N + self], K.psi_exp);
+            }
+            // dS^c(self) += w (psi_virtual^c - psi^c(other)) c; the collide forms
+            // F^A = -G psi^A (S^B + dS^B) and F^B alike
+            for (int c = 0; c < 2; ++c)
+                for (int k = 0; k < 3; ++k)
+                    if (ci[k] != 0.0)
+                        atomicAdd(&d.fib[(3 * c + k) * N + self], (float)(w * (pv[c] - po[c]) * sg * ci[k]));
+            // minus the force on self from the virtual neighbour
+            const double fr = G * w * (ps[0] * pv[1] + ps[1] * pv[0]) * sg;
+            for (int k = 0; k < 3; ++k) react[k] += fr * ci[k] / 3.0;
         }
-        // dS^c(self) += w (psi_virtual^c - psi^c(other)) c; the collide forms
-        // F^A = -G psi^A (S^B + dS^B) and F^B alike
-        for (int c = 0; c < 2; ++c)
-            for (int k = 0; k < 3; ++k)
-                if (ci[k] != 0.0)
-                    atomicAdd(&d.fib[(3 * c + k) * N + self], (float)(w * (pv[c] - po[c]) * sg * ci[k]));
-        // minus the force on self from the virtual neighbour
-        const double fr = G * w * (ps[0] * pv[1] + ps[1] * pv[0]) * sg;
-        for (int k = 0; k < 3; ++k) react[k] += fr * ci[k] / 3.0;
+        for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * face + k], react, 1.0);
     }
-    for (int k = 0; k < 3; ++k) add3(d.QR + 3 * d.tri[3 * face + k], react, 1.0);
 }
 
 // ---- node update ---------------------------------------------------------
@@ -595,7 +719,6 @@ __global__ __launch_bounds__(256) void k_bb_init(Lattice L, Dev d) {
     for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < L.n; k += (int64_t)gridDim.x * blockDim.x) {
         d.lab[k] = -1;
         d.lab_new[k] = -1;
-        d.lmask[k] = 0u;
         d.lpar[k] = 0u;
     }
 }
@@ -614,7 +737,8 @@ void launch_bb_geometry(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, 
     hipLaunchKernelGGL(k_bb_box, dim3(n_caps), dim3(256), 0, s, d, z.ext);
     if (n_caps > 1) hipLaunchKernelGGL(k_bb_overlap, dim3((n_caps + 255) / 256, n_caps), dim3(256), 0, s, L, d, n_caps);
     hipLaunchKernelGGL(k_bb_clear, gbox, dim3(256), 0, s, L, d);
-    hipLaunchKernelGGL(k_bb_links, dim3((n_faces + 255) / 256), dim3(256), 0, s, L, d, n_faces, z.link_cap);
+    hipLaunchKernelGGL(k_bb_links, dim3((9 * n_faces + 255) / 256), dim3(256), 0, s, L, d, n_faces, z.link_cap);
+    hipLaunchKernelGGL(k_bb_list, gbox, dim3(256), 0, s, L, d, z.link_cap);
     hipLaunchKernelGGL(k_bb_label, gcol, dim3(256), 0, s, L, d);
     if (detect_fresh) hipLaunchKernelGGL(k_bb_detect, gbox, dim3(256), 0, s, L, d, z.fresh_cap);
 }
@@ -623,14 +747,14 @@ void launch_bb_refill(const Lattice& L, Dev& d, const BBSizes& z, const BBConst&
                       int n_caps, hipStream_t s) {
     if (n_caps <= 0) return;
     const int cells = z.ext * z.ext * z.ext;
-    hipLaunchKernelGGL(k_bb_refill, dim3(std::min((z.fresh_cap + 3) / 4, 2048)), dim3(256), 0, s, L, d, k,
+    hipLaunchKernelGGL(k_bb_refill, dim3(std::min(z.fresh_cap, 512)), dim3(256), 0, s, L, d, k,
                        (float2*)fpost, rho, z.fresh_cap);
     hipLaunchKernelGGL(k_bb_commit, dim3((cells + 255) / 256, n_caps), dim3(256), 0, s, L, d);
 }
 
 void launch_bb_fixup(const Lattice& L, Dev& d, const BBSizes& z, void* fpost, int n_caps, hipStream_t s) {
     if (n_caps <= 0) return;
-    const dim3 g((z.link_cap + 255) / 256);
+    const dim3 g(std::min((z.link_cap + 255) / 256, 1024));
     hipLaunchKernelGGL(k_bb_link_density, g, dim3(256), 0, s, L, d, (const float2*)fpost, z.link_cap);
     hipLaunchKernelGGL(k_bb_fixup, g, dim3(256), 0, s, L, d, (float2*)fpost, z.link_cap);
     hipLaunchKernelGGL(k_bb_ledger, dim3(1), dim3(64), 0, s, d);
@@ -646,7 +770,8 @@ void launch_bb_flags(const Lattice& L, Dev& d, const BBSizes& z, int n_caps, hip
 
 void launch_bb_shan_chen(const Lattice& L, Dev& d, const BBSizes& z, const BBConst& k, const float* rho,
                          hipStream_t s) {
-    hipLaunchKernelGGL(k_bb_sc, dim3((z.link_cap + 255) / 256), dim3(256), 0, s, L, d, k, rho, z.link_cap);
+    hipLaunchKernelGGL(k_bb_sc, dim3(std::min((z.link_cap + 255) / 256, 1024)), dim3(256), 0, s, L, d, k, rho,
+                       z.link_cap);
 }
 
 void launch_bb_advance(Dev& d, const BBConst& k, int n_nodes, hipStream_t s) {

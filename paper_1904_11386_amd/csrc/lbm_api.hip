@@ -71,7 +71,7 @@ struct Layout {
     int64_t tiles, max_caps;
     // the bounce-back coupling
     bool bb = false;
-    size_t lab, lab_new, lmask, lpar, lkey, links, link_rho, fresh, bb_count, bbox, bb_com, bb_mass, node_V, P_cur, P_prev, QR;
+    size_t lab, lab_new, lpar, lkey, links, link_rho, face_cen, fresh, bb_count, bbox, bb_com, bb_mass, node_V, P_cur, P_prev, QR;
     int link_cap = 0, fresh_cap = 0;
 };
 
@@ -176,11 +176,11 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
         l.fresh_cap = (int)std::min<int64_t>(std::max<int64_t>(4 * nb, 4096), (int64_t)1 << 30);
         l.lab = take(c, N * 4);
         l.lab_new = take(c, N * 4);
-        l.lmask = take(c, N * 4);
         l.lpar = take(c, N * 4);
         l.lkey = take(c, (size_t)9 * N * 8);
         l.links = take(c, (size_t)l.link_cap * 16);
         l.link_rho = take(c, (size_t)l.link_cap * 32);
+        l.face_cen = take(c, (size_t)nf * 3 * 8);
         l.fresh = take(c, (size_t)l.fresh_cap * 4);
         l.bb_count = take(c, 8 * 4);
         l.bbox = take(c, l.max_caps * 8 * 4);
@@ -441,11 +441,11 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     if (lay.bb) {
         d.lab = (int*)(w + lay.lab);
         d.lab_new = (int*)(w + lay.lab_new);
-        d.lmask = (unsigned*)(w + lay.lmask);
         d.lpar = (unsigned*)(w + lay.lpar);
         d.lkey = (unsigned long long*)(w + lay.lkey);
         d.links = (int4*)(w + lay.links);
         d.link_rho = (double4*)(w + lay.link_rho);
+        d.face_cen = (double*)(w + lay.face_cen);
         d.fresh = (int*)(w + lay.fresh);
         d.bb_count = (int*)(w + lay.bb_count);
         d.bbox = (int*)(w + lay.bbox);

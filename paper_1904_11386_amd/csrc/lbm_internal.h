@@ -155,12 +155,13 @@ struct Dev {
     // bounce-back coupling (allocated when it is chosen)
     int* lab;             // [N] label of the current membranes: capsule inside, or -1
     int* lab_new;         // [N] labels being computed (scratch, valid in the capsules' boxes)
-    unsigned* lmask;      // [N] bits 0..8: link from the node along half-direction d claimed
     unsigned* lpar;       // [N] bit k: parity of the crossings of the node's +z link by the membranes of
                           //     colour k
     int4* links;          // [link capacity] (node, half-direction, -, -)
-    unsigned long long* lkey; // [9][N] per link: (FP32 crossing parameter, triangle), the least wins
+    unsigned long long* lkey; // [9][N] per link: (FP32 crossing parameter, triangle), the least wins;
+                              //     all ones where no triangle crosses it
     double4* link_rho;    // [link capacity] densities of the link's ends (A, B at the start; A, B at the end)
+    double* face_cen;     // [faces][3] sum of each triangle's three anchor-relative node positions (FP64), this step
     int* fresh;           // [fresh capacity] nodes whose label changed
     int* bb_count;        // [8]: links, fresh nodes, overflow flags
     int* bbox;            // [max caps][8]: box lo (x, y, z), hi (x, y, z), anchor-relative
