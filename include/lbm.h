@@ -166,8 +166,9 @@ typedef struct lbm_ctx lbm_ctx;
 /* Size query (no passage of the paper: the library's own memory contract,
  * one caller-owned device block holding the whole state).  *bytes receives
  * the device workspace size for a lattice p with room for max_nodes
- * membrane nodes and max_faces triangles in total.  Host-only, no device
- * work.  LBM_EINVAL on a bad p or negative sizes. */
+ * membrane nodes and max_faces triangles in total (each in [0, 2^29]: node
+ * and face ids are 32-bit).  Host-only, no device work.  LBM_EINVAL on a bad
+ * p or sizes out of range. */
 int lbm_workspace_bytes(const lbm_params* p, int64_t max_nodes, int64_t max_faces,
                         int64_t* bytes);
 
@@ -180,9 +181,10 @@ int lbm_workspace_bytes(const lbm_params* p, int64_t max_nodes, int64_t max_face
  * the rest equilibrium w_i rho (u = 0) and are streamed by the first step.
  * workspace: device pointer of at least ws_bytes bytes, 256-byte aligned,
  * ws_bytes >= lbm_workspace_bytes(p, max_nodes, max_faces).
- * hip_stream: a hipStream_t or NULL.  Validates p (tau > 0.5, sizes >= 4,
- * G >= 0, finite wall velocities, precision in {FP32, FP16}) before any
- * device work; errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP. */
+ * hip_stream: a hipStream_t or NULL.  max_nodes, max_faces in [0, 2^29].
+ * Validates p (tau > 0.5, sizes >= 4, G >= 0, finite wall velocities,
+ * precision in {FP32, FP16}) and the sizes before any device work; *out is
+ * NULL after any failure; errors: LBM_EINVAL, LBM_ENOMEM, LBM_EHIP. */
 int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB,
              void* workspace, int64_t ws_bytes, int64_t max_nodes, int64_t max_faces,
              void* hip_stream, lbm_ctx** out);

@@ -322,22 +322,31 @@ struct lbm_ctx {
         if (e_ != hipSuccess) return (ctx)->fail(LBM_EHIP, "%s: %s", #call, hipGetErrorString(e_)); \
     } while (0)
 
+// Node and face ids are 32-bit, and the node and face arrays hold three
+// entries per id, so both counts stay below 2^29.
+constexpr int64_t MAX_IDS = (int64_t)1 << 29;
+
 extern "C" {
 
 int lbm_workspace_bytes(const lbm_params* p, int64_t max_nodes, int64_t max_faces, int64_t* bytes) {
     const std::string e = validate(p);
     if (!e.empty()) { g_init_error = e; return LBM_EINVAL; }
-    if (max_nodes < 0 || max_faces < 0 || !bytes) { g_init_error = "bad sizes or NULL output"; return LBM_EINVAL; }
+    if (max_nodes < 0 || max_faces < 0 || max_nodes > MAX_IDS || max_faces > MAX_IDS || !bytes) {
+        g_init_error = "bad sizes (max_nodes, max_faces in [0, 2^29]) or NULL output";
+        return LBM_EINVAL;
+    }
     *bytes = (int64_t)make_layout(p, max_nodes, max_faces).total;
     return LBM_OK;
 }
 
 int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* workspace, int64_t ws_bytes,
              int64_t max_nodes, int64_t max_faces, void* hip_stream, lbm_ctx** out) {
+    if (out) *out = nullptr;
     const std::string e = validate(p);
     if (!e.empty()) { g_init_error = e; return LBM_EINVAL; }
-    if (!out || !rhoA || !rhoB || !workspace || max_nodes < 0 || max_faces < 0) {
-        g_init_error = "NULL argument or negative size";
+    if (!out || !rhoA || !rhoB || !workspace || max_nodes < 0 || max_faces < 0 || max_nodes > MAX_IDS ||
+        max_faces > MAX_IDS) {
+        g_init_error = "NULL argument, or max_nodes / max_faces outside [0, 2^29]";
         return LBM_EINVAL;
     }
     if (((uintptr_t)workspace & 255) != 0) { g_init_error = "workspace must be 256-byte aligned"; return LBM_EINVAL; }
