@@ -262,7 +262,12 @@ int lbm_reference_relax(lbm_ctx* ctx, int32_t nsteps, double gamma, double w, do
  * check_every > 0 the FP64 mass check runs every check_every steps and
  * synchronises; it returns LBM_EUNSTABLE when a component mass is not
  * finite or (except with walls = 2) has drifted by more than mass_tol
- * relative to its start. */
+ * relative to its start.  Under the bounce-back coupling (coupling 1) the
+ * call also reads the coupling's list flags at its end (and at each check),
+ * synchronising, and returns LBM_EUNSTABLE when a list overflowed, a capsule
+ * outgrew its label box, a membrane is not closed, or the label boxes of two
+ * capsules of one parity colour met; its steps after the first are replayed
+ * in pairs from graphs as well. */
 int lbm_step(lbm_ctx* ctx, int32_t nsteps);
 
 /* Kernel groups of one step, in launch order (for lbm_step_timed).  Under

@@ -1088,9 +1088,24 @@ int lbm_step(lbm_ctx* c, int32_t nsteps) {
     if (!c) return LBM_EINVAL;
     if (nsteps < 0) return c->fail(LBM_EINVAL, "nsteps < 0");
     if (c->lay.bb) {
-        for (int k = 0; k < nsteps; ++k) {
-            enqueue_bb_step(c, nullptr);
-            if (c->p.check_every > 0 && c->step % c->p.check_every == 0) {
+        // After the first step (which lists no fresh nodes) a step's launches
+        // depend only on its parity: pairs of steps are replayed from the
+        // same two-step graphs, never across a check.
+        int left = nsteps;
+        while (left > 0) {
+            const int ce = c->p.check_every;
+            hipGraphExec_t ex = nullptr;
+            if (c->p.use_graphs && c->bb_primed && left >= 2 && (ce == 0 || c->step % ce + 2 <= ce))
+                ex = two_step_graph(c);
+            if (ex) {
+                HIPCHK(c, hipGraphLaunch(ex, c->stream));
+                c->step += 2;
+                left -= 2;
+            } else {
+                enqueue_bb_step(c, nullptr);
+                --left;
+            }
+            if (ce > 0 && c->step % ce == 0) {
                 HIPCHK(c, hipGetLastError());
                 int r = check_bb(c);
                 if (r == LBM_OK) r = check_mass(c);
