@@ -305,36 +305,6 @@ __device__ __forceinline__ void decode(const Lattice& L, int y, const Raw<HALF>&
     decode_all<WALLS, HALF>(L, y, R, ra_prev, rb_prev, enc, A, B, std::make_integer_sequence<int, Q>{});
 }
 
-// FP16 density pass: rho = sum_i rho_enc,i (w_i + g_i) accumulated as
-// sum_i rho_enc,i g_i (one mixed-precision FMA per direction that reads the
-// binary16 value directly) plus sum_i rho_enc,i w_i, without forming the
-// populations; a wall-bounced direction adds its decoded value.
-template <bool WALLS, int I, typename EncAt>
-__device__ __forceinline__ void density_acc(const Lattice& L, int y, const Raw<true>& R, float ra_prev, float rb_prev,
-                                            const EncAt& enc, float g[2], float w[2]) {
-    const PopT<true> v = R.v[I];
-    if (WALLS && ((cy(I) == 1 && y == 1) || (cy(I) == -1 && y == L.ny - 2))) {
-        g[0] += fmaf(ra_prev, (float)v.x, ra_prev * wgt(opp(I))) + wall_term<I>(L, ra_prev);
-        g[1] += fmaf(rb_prev, (float)v.y, rb_prev * wgt(opp(I))) + wall_term<I>(L, rb_prev);
-    } else {
-        float ea, eb;
-        enc(cx(I), cy(I), cz(I), ea, eb);
-        g[0] = fmaf(ea, (float)v.x, g[0]);
-        g[1] = fmaf(eb, (float)v.y, g[1]);
-        w[0] = fmaf(ea, wgt(I), w[0]);
-        w[1] = fmaf(eb, wgt(I), w[1]);
-    }
-}
-
-template <bool WALLS, typename EncAt, int... Is>
-__device__ __forceinline__ void density_half(const Lattice& L, int y, const Raw<true>& R, float ra_prev, float rb_prev,
-                                             const EncAt& enc, float& ra, float& rb, std::integer_sequence<int, Is...>) {
-    float g[2] = {0.0f, 0.0f}, w[2] = {0.0f, 0.0f};
-    (density_acc<WALLS, Is>(L, y, R, ra_prev, rb_prev, enc, g, w), ...);
-    ra = g[0] + w[0];
-    rb = g[1] + w[1];
-}
-
 __device__ __forceinline__ float sum_pop(const Pulled& P) {
     // rest first, then opposite pairs
     float s = P.f[0];
@@ -556,9 +526,10 @@ __global__ __launch_bounds__(BX * BY) void k_density_half(const ph2* __restrict_
                 a = e.x;
                 b = e.y;
             };
+            Pulled A, B;
             const float2 e0 = ring.v[s0][ty + 1][tx + 1];
-            float ra, rb;
-            density_half<WALLS>(L, y, rcur, e0.x, e0.y, enc, ra, rb, std::make_integer_sequence<int, Q>{});
+            decode<WALLS, true>(L, y, rcur, e0.x, e0.y, enc, A, B);
+            const float ra = sum_pop(A), rb = sum_pop(B);
             *ptrx(rho_out + row, (uint32_t)x) = ra;
             *ptrx(rho_out + L.n + row, (uint32_t)x) = rb;
             acc[0] += (double)ra;
