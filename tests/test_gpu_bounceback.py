@@ -262,3 +262,21 @@ def test_hold_then_release_parity():
         assert ea <= 1e-5 and eb <= 1e-5 and dx <= 1e-6 and dv <= 1e-6
     assert float(o.V[0].abs().max()) > 0.005
     assert np.array_equal(g.labels(), o.labels().numpy())
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_meshes_on_the_64_crop():
+    """The benchmark's membranes under this coupling: the 64^3 crop of the
+    128^3 workload (two R = 8, 2562-node capsules on the interface, angles in
+    [60, 120] deg, one across the periodic y boundary; node mass 5, C0 2500),
+    10 steps translated at a prescribed 0.01 lu/step (the bench leg's
+    set-up), then the same start free for 8 steps, each compared every few
+    steps; labels bit-exact at the end of each."""
+    import dataclasses
+    torch.set_num_threads(16)
+    base = W.bounce_back(W.make("c2_64"))
+    moved = dataclasses.replace(base, capsules=[dataclasses.replace(c, v=(0.01, 0.0, 0.0), prescribed=True)
+                                                for c in base.capsules])
+    _, o = _compare(moved, 10, every=5)
+    assert o.n_fresh > 10
+    _compare(base, 8, every=4, tol_x=1e-6)
