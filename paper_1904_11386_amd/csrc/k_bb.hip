@@ -68,6 +68,9 @@ namespace lbmx {
 namespace {
 
 constexpr int MARGIN = 3;       // box margin around a capsule's nodes, lattice units
+// Node offsets from a capsule's anchor beyond this (or not finite) mean the
+// membrane has diverged: it is reported and its box left empty.
+constexpr double COORD_MAX = 1048576.0;
 constexpr int CNT_LINKS = 0, CNT_FRESH = 1, CNT_FLAGS = 2;
 // overflow and consistency flags in bb_count[CNT_FLAGS]
 constexpr int FLAG_BOX = 1, FLAG_LINKS = 2, FLAG_FRESH = 4, FLAG_PARITY = 8, FLAG_OVERLAP = 16;
@@ -161,14 +164,19 @@ __global__ __launch_bounds__(256) void k_bb_box(Dev d, int ext) {
     }
     if (threadIdx.x == 0) {
         int* bx = d.bbox + 8 * cap;
+        // a diverged membrane (offsets not finite or beyond COORD_MAX) gets
+        // an empty box, so that no loop runs over its coordinates
+        bool sane = true;
+        for (int k = 0; k < 3; ++k) sane = sane && fabs(lo[k]) <= COORD_MAX && fabs(hi[k]) <= COORD_MAX;
+        if (!sane) atomicOr(&d.bb_count[CNT_FLAGS], FLAG_BOX);
         for (int k = 0; k < 3; ++k) {
-            bx[k] = (int)floor(lo[k]) - MARGIN;
-            bx[3 + k] = (int)ceil(hi[k]) + MARGIN;
+            bx[k] = sane ? (int)floor(lo[k]) - MARGIN : 0;
+            bx[3 + k] = sane ? (int)ceil(hi[k]) + MARGIN : -1;
             if (bx[3 + k] - bx[k] + 1 > ext) {
                 atomicOr(&d.bb_count[CNT_FLAGS], FLAG_BOX);
                 bx[3 + k] = bx[k] + ext - 1;
             }
-            d.bb_com[3 * cap + k] = sh[k][0] / C.node_count;
+            d.bb_com[3 * cap + k] = sane ? sh[k][0] / C.node_count : 0.0;
         }
         d.capV[cap] = 0.0;
         if (cap == 0) {
@@ -250,6 +258,13 @@ __global__ __launch_bounds__(256) void k_bb_links(Lattice L, Dev d, int n_faces,
     double e1[3], e2[3];
     int lo[3], hi[3];
     for (int k = 0; k < 3; ++k) {
+        // a diverged membrane: report, do not scan (the loop bounds below
+        // stay far inside the int range)
+        for (int j = 0; j < 3; ++j)
+            if (!(fabs(V[j][k]) <= COORD_MAX)) {
+                atomicOr(&d.bb_count[CNT_FLAGS], FLAG_BOX);
+                return;
+            }
         e1[k] = V[1][k] - V[0][k];
         e2[k] = V[2][k] - V[0][k];
         lo[k] = (int)floor(fmin(V[0][k], fmin(V[1][k], V[2][k]))) - 1;

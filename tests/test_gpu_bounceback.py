@@ -280,3 +280,20 @@ def test_benchmark_meshes_on_the_64_crop():
     _, o = _compare(moved, 10, every=5)
     assert o.n_fresh > 10
     _compare(base, 8, every=4, tol_x=1e-6)
+
+
+def test_diverging_membrane_is_reported():
+    """A membrane driven to diverge (node mass 1e-10, so that the first
+    node forces throw the nodes millions of lattice units away) is reported
+    as LBM_EUNSTABLE at the next check: the label and link kernels skip a
+    capsule whose offsets are not finite or beyond 2^20 lu instead of looping
+    over its coordinates, and every kernel ends."""
+    from paper_1904_11386_amd.binding import LBM_EUNSTABLE, LbmError, sim_from_workload
+    wl = W.bb_capsule(layered_z=13, theta=60.0, node_mass=1e-10)
+    g = sim_from_workload(wl, check_every=1)
+    with pytest.raises(LbmError) as ei:
+        g.step(20)
+    _say("reported:", ei.value)
+    assert ei.value.code == LBM_EUNSTABLE
+    assert g.observables()["step"] <= 5
+    g.close()
