@@ -629,6 +629,72 @@ def bb_leg(torch, name="c2", warmup=30, steps=300, v=(0.01, 0.0, 0.0)):
             "capsule_height_change": [round(c1["com"][2] - c0["com"][2], 4) for c0, c1 in zip(ob0["caps"], ob["caps"])]}
 
 
+def bb_contact_angle_leg(torch, colours=(0.259, 0.0, -0.259), steps=40000, chunk=5000, R=6.0, psi_kind=0):
+    """The contact-angle law of the paper's coupling (Sec. III.D: a rigid
+    particle's centre sits R cos(theta) from the interface, cos(theta) =
+    colour): a 48^3 flat interface (A below) relaxed for 3000 steps without a
+    capsule; in those densities a free capsule (R = 6, 642 nodes, kS 0.5,
+    node mass 200; its inside set to the relaxed A phase) placed with its
+    centre at -R colour from the interface, then `steps` free steps; its
+    offset dz from the interface far from it every `chunk` steps (positive
+    colour prefers A, below, so the law puts dz at -R colour).  The mass
+    check runs every 1000 steps at 1e-2 and the drift is reported."""
+    import dataclasses
+    import math
+    from paper_1904_11386_amd import workloads
+    from paper_1904_11386_amd.binding import LbmError, sim_from_workload
+
+    def far_interface(ra, rb):
+        zs = []
+        for (y, x) in ((0, 0), (0, 24), (24, 0), (12, 36), (36, 12)):
+            col = (ra[:, y, x] - rb[:, y, x]).astype(np.float64)
+            for z in range(8, 40):
+                if col[z] > 0 >= col[z + 1]:
+                    zs.append(z + col[z] / (col[z] - col[z + 1]))
+        return float(np.mean(zs)) if zs else float("nan")
+
+    print("bench: bounce-back contact-angle leg", file=sys.stderr, flush=True)
+    base = dataclasses.replace(workloads.bb_capsule(nx=48, ny=48, nz=48, layered_z=24), psi_kind=psi_kind)
+    g = sim_from_workload(dataclasses.replace(base, capsules=[], coupling=0))
+    g.step(3000)
+    ra0, rb0, _ = g.fields()
+    g.close()
+    zi = far_interface(ra0, rb0)
+    amaj, bmin = float(ra0[5, 0, 0]), float(rb0[5, 0, 0])
+    out = {"workload": "48^3 periodic box, flat interface (A below, relaxed 3000 steps), one free capsule R=6 "
+                       "(642 nodes), kS 0.5, node mass 200, C0 2500, psi kind %d, G 3.6" % psi_kind,
+           "steps": steps, "interface_z": round(zi, 3), "A_phase": [round(amaj, 4), round(bmin, 4)], "runs": []}
+    gz = np.meshgrid(np.arange(48), np.arange(48), np.arange(48), indexing="ij")
+    for colour in colours:
+        theta = math.degrees(math.acos(colour))
+        wl = workloads.bb_capsule(nx=48, ny=48, nz=48, centre=(23.37, 24.61, zi - R * colour), radius=R, freq=8,
+                                  theta=theta, kS=0.5, layered_z=24, node_mass=200.0, psi_kind=psi_kind)
+        c = wl.capsules[0].centre
+        ins = (gz[2] - c[0]) ** 2 + (gz[1] - c[1]) ** 2 + (gz[0] - c[2]) ** 2 < (R - 0.3) ** 2
+        wl = dataclasses.replace(wl, rhoA=np.ascontiguousarray(np.where(ins, np.float32(amaj), ra0), np.float32),
+                                 rhoB=np.ascontiguousarray(np.where(ins, np.float32(bmin), rb0), np.float32))
+        m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
+        g = sim_from_workload(wl, check_every=1000, mass_tol=1e-2)
+        trace, err = [], None
+        try:
+            for k in range(steps // chunk):
+                g.step(chunk)
+                ra, rb, _ = g.fields()
+                trace.append(round(g.observables()["caps"][0]["com"][2] - far_interface(ra, rb), 3))
+                print("bench: contact angle, colour %+.3f, step %d, dz %.3f" % (colour, (k + 1) * chunk, trace[-1]),
+                      file=sys.stderr, flush=True)
+        except LbmError as e:
+            err = str(e)
+        drift = float(np.abs(g.observables()["mass"] / m0 - 1).max())
+        g.close()
+        last = float(np.mean(trace[-2:])) if len(trace) >= 2 else float("nan")
+        out["runs"].append({"colour": colour, "theta_deg": round(theta, 2), "dz_start": round(-R * colour, 3),
+                            "dz_trace": trace, "cos_theta_measured": round(-last / R, 3), "mass_drift": drift,
+                            "error": err})
+        torch.cuda.empty_cache()
+    return out
+
+
 def ratio_leg(torch, name, warmup, steps):
     """Both storage forms of one workload, same step counts: MLUPS, collide
     bandwidth and the FP16/FP32 ratio."""
@@ -664,6 +730,9 @@ def main():
                     help="skip the 128^3 workload under the paper's bounce-back coupling")
     ap.add_argument("--bb-leg", action="store_true",
                     help="run the bounce-back leg even with --headline-only")
+    ap.add_argument("--bb-contact-angle-leg", action="store_true",
+                    help="also measure the rest position of free capsules on a flat interface under the bounce-back "
+                         "coupling against the paper's contact-angle law")
     ap.add_argument("--no-fd-sweep", action="store_true",
                     help="skip the full-size adjoint check against FP32 central differences")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -744,6 +813,8 @@ def main():
                 out["adjoint_fd_sweep"] = adjoint_fd_sweep(torch)
     if args.bb_leg and args.headline_only:
         out["bb_leg"] = bb_leg(torch)
+    if args.bb_contact_angle_leg:
+        out["bb_contact_angle"] = bb_contact_angle_leg(torch)
     if args.reference_model_leg:
         out["reference_model"] = reference_model_leg(torch)
     if args.shape_error_leg:

@@ -363,13 +363,14 @@ class Sim:
 
 
 def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1, ring_len=0,
-                      stream_policy=0, zchunk=0):
+                      stream_policy=0, zchunk=0, mass_tol=1e-3):
     """Build a Sim for a seeded workload (paper_1904_11386_amd.workloads)."""
     npc, fpc, xyz, tri = wl.meshes()
     p = make_params(wl.nx, wl.ny, wl.nz, tau=wl.tau, G=wl.G, walls=wl.walls, wall_u_lo=wl.wall_u_lo,
                     wall_u_hi=wl.wall_u_hi, rho_maj=wl.rho_maj, rho_min=wl.rho_min,
                     z_interface=wl.z_interface, precision=precision, n_slots=n_slots,
-                    check_every=check_every, wet_scale=wl.wet_scale, use_graphs=use_graphs, ring_len=ring_len,
+                    check_every=check_every, mass_tol=mass_tol, wet_scale=wl.wet_scale, use_graphs=use_graphs,
+                    ring_len=ring_len,
                     stream_policy=stream_policy, zchunk=zchunk, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0,
                     psi_kind=wl.psi_kind, coupling=getattr(wl, "coupling", 0),
                     node_mass=getattr(wl, "node_mass", 5.0), mass_c0=getattr(wl, "mass_c0", 2500.0))
