@@ -203,8 +203,12 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB,
  * before any step has been enqueued (else LBM_ESTATE, also after a state is
  * loaded back to step 0: the captured graphs and tile lists were built for
  * the capsules present then); LBM_ENOMEM beyond the sizes
- * given to lbm_init.  *first_id (may be NULL) receives the index of the
- * first new capsule. */
+ * given to lbm_init.  Under the bounce-back coupling (coupling 1) a capsule
+ * must fit the box in which its labels are found (1.5 times its extent plus
+ * 9 lattice units, within the smallest lattice edge), and no more than 32
+ * capsules may lie within one such box of each other (they are told apart by
+ * one parity bit each); else LBM_EINVAL.  *first_id (may be NULL) receives
+ * the index of the first new capsule. */
 int lbm_capsules_add(lbm_ctx* ctx, int32_t n_caps, const int32_t* nodes_per_cap,
                      const int32_t* faces_per_cap, const double* xyz_rest,
                      const int32_t* tri, const double* kS, const double* C,
