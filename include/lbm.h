@@ -140,6 +140,17 @@ typedef struct lbm_params {
                                paper uses 5, Sec. III)                          */
     double mass_c0;         /* coupling 1: strength C0 of the adaptive mass
                                correction (>= 0; the paper uses 2500)           */
+    int32_t deterministic;  /* 0 or 1, coupling 0 only.  1: the immersed
+                               boundary's sums run in a fixed order (capsule
+                               volumes per capsule, each bin's nodes by id, the
+                               lattice force and virtual-density fields
+                               gathered per cell instead of added with
+                               atomics), so a step is the same bit for bit
+                               from run to run and across a state save and
+                               load; 0 differs from it by rounding order only.
+                               A debugging mode: its gather costs more than
+                               the atomic spreading.  The adjoint's own sums
+                               keep their atomics.                            */
 } lbm_params;
 
 typedef struct lbm_obs {
@@ -151,6 +162,13 @@ typedef struct lbm_obs {
                                     momentum, which the nodes receive with the next
                                     step (Sec. II.C); fluid + particle + pending
                                     momentum is conserved (else 0)              */
+    double mass_ledger[2];  /* coupling 1: the mass per component that the
+                               moving-element bounce-back terms and the
+                               fresh-node refills changed since init, summed in
+                               FP64 as stored: the Delta rho^c the adaptive
+                               correction reads (eq. method:masscorrection);
+                               mass - initial mass - this is the FP32
+                               storage's rounding (else 0)                     */
 } lbm_obs;
 
 typedef struct lbm_capsule_obs {

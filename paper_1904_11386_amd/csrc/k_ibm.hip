@@ -162,9 +162,24 @@ __global__ __launch_bounds__(256) void k_clear_tiles(Lattice L, Dev d, int pp, i
     clear_tiles(L, d, pp, pc, n_caps, blockIdx.x, gridDim.x);
 }
 
-// FP64 enclosed volume per capsule, V = (1/6) sum_T X1 . (X2 x X3) over
-// anchor-relative offsets: one thread per triangle, a block reduction when
-// the block's triangles belong to one capsule, FP64 atomics otherwise.
+// Triangle f's part of its capsule's volume, X1 . (X2 x X3) / 6 over
+// anchor-relative offsets, in FP64.
+__device__ __forceinline__ double face_volume(const Dev& d, int f) {
+    double X[3][3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+        const int b = d.tri[3 * f + k];
+#pragma unroll
+        for (int j = 0; j < 3; ++j) X[k][j] = (double)d.off_hi[3 * b + j];
+    }
+    return (X[0][0] * (X[1][1] * X[2][2] - X[1][2] * X[2][1])
+          + X[0][1] * (X[1][2] * X[2][0] - X[1][0] * X[2][2])
+          + X[0][2] * (X[1][0] * X[2][1] - X[1][1] * X[2][0])) / 6.0;
+}
+
+// FP64 enclosed volume per capsule, V = sum_T face_volume: one thread per
+// triangle, a block reduction when the block's triangles belong to one
+// capsule, FP64 atomics otherwise.
 __global__ __launch_bounds__(256) void k_cap_volume(Dev d, int n_faces) {
     __shared__ double sh[256];
     __shared__ int cap_first, cap_last;
@@ -174,16 +189,7 @@ __global__ __launch_bounds__(256) void k_cap_volume(Dev d, int n_faces) {
     int cap = -1;
     if (f < n_faces) {
         cap = d.face_cap[f];
-        double X[3][3];
-#pragma unroll
-        for (int k = 0; k < 3; ++k) {
-            const int b = d.tri[3 * f + k];
-#pragma unroll
-            for (int j = 0; j < 3; ++j) X[k][j] = (double)d.off_hi[3 * b + j];
-        }
-        v = (X[0][0] * (X[1][1] * X[2][2] - X[1][2] * X[2][1])
-           + X[0][1] * (X[1][2] * X[2][0] - X[1][0] * X[2][2])
-           + X[0][2] * (X[1][0] * X[2][1] - X[1][1] * X[2][0])) / 6.0;
+        v = face_volume(d, f);
     }
     if (threadIdx.x == 0) {
         cap_first = d.face_cap[blockIdx.x * blockDim.x];
@@ -201,6 +207,32 @@ __global__ __launch_bounds__(256) void k_cap_volume(Dev d, int n_faces) {
         __syncthreads();
     }
     if (threadIdx.x == 0) unsafeAtomicAdd(&d.capV[cap_first], sh[0]);
+}
+
+// Deterministic mode.  Three sums of the default step take their order
+// from atomics, which differs from run to run: the capsule volumes above,
+// the node ranks within a bin (the order in which the spreading and the
+// repulsion visit a bin's nodes) and the flush of the bins' boxes into the
+// lattice fields.  With deterministic sums each capsule's volume is one
+// block's fixed-order reduction, each bin's nodes are ranked by id, and the
+// force and virtual-density fields are gathered per lattice cell over the
+// nodes in (bin, id) order, so that a step is the same bit for bit from run
+// to run (the default step differs from it by rounding order only).
+
+// one block per capsule: its triangles strided over the threads, then a
+// fixed tree
+__global__ __launch_bounds__(256) void k_cap_volume_det(Dev d) {
+    __shared__ double sh[256];
+    const CapDev& C = d.caps[blockIdx.x];
+    double v = 0.0;
+    for (int f = C.face_start + (int)threadIdx.x; f < C.face_start + C.face_count; f += 256) v += face_volume(d, f);
+    sh[threadIdx.x] = v;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.capV[blockIdx.x] = sh[0];
 }
 
 // Scalars that carry a tangent: v + e * epsilon.  The face forces below are
@@ -400,6 +432,23 @@ __global__ __launch_bounds__(256) void k_bin_scatter(Lattice L, Dev d, int n_nod
                 d.touched[par][atomicAdd(&d.counters[CNT_TOUCHED + par], 1)] = t;
         }
     }
+}
+
+// Deterministic mode: each node's rank in its home bin becomes the number
+// of the bin's nodes with a lower id (read from the order the scatter left,
+// which any rank order gives), then the nodes are placed again by it.
+__global__ __launch_bounds__(256) void k_bin_rank_det(Dev d, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_nodes) return;
+    const int t = d.node_tile[b], start = d.tile_offset[t], cnt = d.tile_count[t];
+    int r = 0;
+    for (int k = 0; k < cnt; ++k) r += d.sorted[start + k] < b;
+    d.node_rank[b] = r;
+}
+
+__global__ __launch_bounds__(256) void k_bin_place_det(Dev d, int n_nodes) {
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b < n_nodes) d.sorted[d.tile_offset[d.node_tile[b]] + d.node_rank[b]] = b;
 }
 
 // Particle-particle repulsion (Sec. III.E): a node pair of different
@@ -760,12 +809,15 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par, const
     const int64_t N = L.n;
     float* mybox = &box[wave][0][0];
     const float sc[2] = {cs ? cs[0] : 1.0f, cs ? cs[1] : 1.0f};   // FP16 form: this step's mass compensation
+    // deterministic mode: the wettability reactions only (k_spread_gather_det fills the fields)
+    const bool flush = d.det == 0;
     for (int e = blockIdx.x; e < nh; e += gridDim.x) {
         const int t = d.home[par][e];
         const int start = d.home_start[e], cnt = d.tile_count[t];
         if (cnt == 0) continue;                 // (a home bin holds a node; block-uniform)
         const int ox = (t % L.nbx) * BIN, oy = ((t / L.nbx) % L.nby) * BIN, oz = (t / (L.nbx * L.nby)) * BIN;
-        for (int k = threadIdx.x; k < 4 * 5 * B3; k += 256) (&box[0][0][0])[k] = 0.0f;
+        if (flush)
+            for (int k = threadIdx.x; k < 4 * 5 * B3; k += 256) (&box[0][0][0])[k] = 0.0f;
         // (the barrier after staging also orders the zeroing above)
         for (int c0 = 0; c0 < cnt; c0 += CH) {
             const int m = min(cnt - c0, CH);
@@ -849,7 +901,7 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par, const
                 }
                 __syncthreads();
             }
-            for (int j = wave; j < m; j += 4) {
+            for (int j = wave; flush && j < m; j += 4) {
                 const float w = sw[kx][j] * sw[4 + ky][j] * sw[8 + kz][j];
                 const int cell = scell[j] + (kz * BOX + ky) * BOX + kx;
                 mybox[0 * B3 + cell] += w * sf[0][j];
@@ -860,7 +912,7 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par, const
             }
             __syncthreads();
         }
-        for (int k = threadIdx.x; k < 5 * B3; k += 256) {
+        for (int k = threadIdx.x; flush && k < 5 * B3; k += 256) {
             const float* bx = &box[0][0][0];
             const float v = (bx[k] + bx[5 * B3 + k]) + (bx[10 * B3 + k] + bx[15 * B3 + k]);
             if (v != 0.0f) {
@@ -871,6 +923,117 @@ __global__ __launch_bounds__(256) void k_spread(Lattice L, Dev d, int par, const
             }
         }
         __syncthreads();
+    }
+}
+
+// Deterministic mode: one block per touched tile writes the five fields of
+// each of its cells, F_b delta and the virtual densities summed over the
+// nodes of the bins whose stencils can reach the tile, bins in (z, y, x)
+// order and each bin's nodes in id order (after k_spread has added the
+// wettability reactions to node_F).  A node of wrapped floor cell p reaches
+// the cells p - 1 .. p + 2 of each axis, so the tile's cells t0 .. t1 are
+// reached from the floor cells t0 - 2 .. t1 + 1; their distinct bins, in
+// the order met, are the candidates (at most 11 per axis).
+__global__ __launch_bounds__(256) void k_spread_gather_det(Lattice L, Dev d, int par) {
+    constexpr int CH = 128;
+    __shared__ float sw[12][CH];
+    __shared__ float sf[4][CH];
+    __shared__ int sp[3][CH], sfield[CH];
+    __shared__ int sb[3][11], snb[3];
+    const int nt = d.counters[CNT_TOUCHED + par];
+    const int64_t N = L.n;
+    const int nn[3] = {L.nx, L.ny, L.nz};
+    for (int e = blockIdx.x; e < nt; e += gridDim.x) {
+        const int t = d.touched[par][e];
+        const int T[3] = {t % L.ntx, (t / L.ntx) % L.nty, t / (L.ntx * L.nty)};
+        if (threadIdx.x < 3) {
+            const int a = threadIdx.x, t0 = TILE * T[a], t1 = min(t0 + TILE - 1, nn[a] - 1);
+            int nb = 0;
+            for (int c = t0 - 2; c <= t1 + 1; ++c) {
+                const int bb = wrap3(c, nn[a]) / BIN;
+                bool seen = false;
+                for (int q = 0; q < nb; ++q) seen = seen || sb[a][q] == bb;
+                if (!seen) sb[a][nb++] = bb;
+            }
+            snb[a] = nb;
+        }
+        // this thread's cells: c and c + 256 of the tile's 512
+        int cell[2][3];
+        bool in[2];
+        float acc[2][5];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int c = (int)threadIdx.x + 256 * h;
+            cell[h][0] = T[0] * TILE + (c & 7);
+            cell[h][1] = T[1] * TILE + ((c >> 3) & 7);
+            cell[h][2] = T[2] * TILE + (c >> 6);
+            in[h] = cell[h][0] < L.nx && cell[h][1] < L.ny && cell[h][2] < L.nz;
+#pragma unroll
+            for (int f = 0; f < 5; ++f) acc[h][f] = 0.0f;
+        }
+        __syncthreads();
+        for (int iz = 0; iz < snb[2]; ++iz)
+            for (int iy = 0; iy < snb[1]; ++iy)
+                for (int ix = 0; ix < snb[0]; ++ix) {
+                    const int bin = (sb[2][iz] * L.nby + sb[1][iy]) * L.nbx + sb[0][ix];
+                    const int cnt = d.tile_count[bin];
+                    const int start = cnt > 0 ? d.tile_offset[bin] : 0;
+                    for (int c0 = 0; c0 < cnt; c0 += CH) {
+                        const int m = min(cnt - c0, CH);
+                        if ((int)threadIdx.x < m) {
+                            const int b = d.sorted[start + c0 + threadIdx.x];
+                            const NodePos p = node_pos(d, b);
+                            int pw[3];
+                            wrapped_floor(L, p, pw);
+#pragma unroll
+                            for (int a = 0; a < 3; ++a) {
+                                sp[a][threadIdx.x] = pw[a];
+#pragma unroll
+                                for (int k = 0; k < 4; ++k) sw[4 * a + k][threadIdx.x] = peskin(p.r[a] + 1.0f - k);
+                            }
+                            sf[0][threadIdx.x] = d.node_F[3 * b + 0];
+                            sf[1][threadIdx.x] = d.node_F[3 * b + 1];
+                            sf[2][threadIdx.x] = d.node_F[3 * b + 2];
+                            const float wet = d.node_wet[b];
+                            sf[3][threadIdx.x] = wet;
+                            sfield[threadIdx.x] = wet != 0.0f ? 3 + d.node_anc[b].w : -1;
+                        }
+                        __syncthreads();
+                        for (int j = 0; j < m; ++j) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                // stencil index of the cell on each axis (n >= 4: at most one)
+                                float w = 1.0f;
+                                bool hit = in[h];
+#pragma unroll
+                                for (int a = 0; a < 3; ++a) {
+                                    int k = cell[h][a] - sp[a][j] + 1;
+                                    if (k < 0) k += nn[a];
+                                    if (k >= nn[a]) k -= nn[a];
+                                    hit = hit && k < 4;
+                                    w *= sw[4 * a + min(k, 3)][j];
+                                }
+                                if (hit) {
+                                    acc[h][0] += w * sf[0][j];
+                                    acc[h][1] += w * sf[1][j];
+                                    acc[h][2] += w * sf[2][j];
+                                    const int fld = sfield[j];
+                                    if (fld == 3) acc[h][3] += w * sf[3][j];
+                                    if (fld == 4) acc[h][4] += w * sf[3][j];
+                                }
+                            }
+                        }
+                        __syncthreads();
+                    }
+                }
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+            if (in[h]) {
+                const uint32_t node = (uint32_t)((cell[h][2] * L.ny + cell[h][1]) * L.nx + cell[h][0]);
+#pragma unroll
+                for (int f = 0; f < 5; ++f) d.fib[f * N + node] = acc[h][f];
+            }
+        __syncthreads();      // (sb, snb are rewritten for the next tile)
     }
 }
 
@@ -1258,8 +1421,12 @@ void launch_advect_clear(const Lattice& L, Dev& d, int n_nodes, int pp, int pc, 
     const int n_ib = (n_nodes + 15) / 16;
     hipLaunchKernelGGL(k_advect_clear, dim3(n_ib + CLEAR_GRID), dim3(256), 0, s, L, d, n_nodes, n_ib, pp, pc, n_caps);
 }
-void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s) {
-    if (n_faces > 0) hipLaunchKernelGGL(k_cap_volume, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
+void launch_cap_volume(const Dev& d, int n_faces, int n_caps, hipStream_t s) {
+    if (n_faces <= 0) return;
+    if (d.det)
+        hipLaunchKernelGGL(k_cap_volume_det, dim3(n_caps), dim3(256), 0, s, d);
+    else
+        hipLaunchKernelGGL(k_cap_volume, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
 }
 void launch_faces(const Dev& d, int n_faces, hipStream_t s) {
     if (n_faces > 0) hipLaunchKernelGGL(k_faces, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces);
@@ -1272,8 +1439,12 @@ void launch_bin_scan(const Dev& d, int n_nodes, int par, hipStream_t s) {
     if (n_nodes > 0) hipLaunchKernelGGL(k_bin_alloc, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, par);
 }
 void launch_bin_scatter(const Lattice& L, const Dev& d, int n_nodes, int par, hipStream_t s) {
-    if (n_nodes > 0)
-        hipLaunchKernelGGL(k_bin_scatter, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, par);
+    if (n_nodes <= 0) return;
+    hipLaunchKernelGGL(k_bin_scatter, dim3((n_nodes + 255) / 256), dim3(256), 0, s, L, d, n_nodes, par);
+    if (d.det) {
+        hipLaunchKernelGGL(k_bin_rank_det, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
+        hipLaunchKernelGGL(k_bin_place_det, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
+    }
 }
 void launch_repulse(const Lattice& L, const Dev& d, int n_nodes, float eps, float d0, hipStream_t s) {
     if (n_nodes > 0)
@@ -1294,7 +1465,7 @@ void launch_reference_step(const Dev& d, int n_nodes, int n_faces, int n_caps, b
                            double z_interface, float mu, hipStream_t s) {
     if (n_faces <= 0) return;
     hipLaunchKernelGGL(k_ref_zero_volume, dim3((n_caps + 255) / 256), dim3(256), 0, s, d, n_caps);
-    launch_cap_volume(d, n_faces, s);
+    launch_cap_volume(d, n_faces, n_caps, s);
     launch_faces(d, n_faces, s);
     hipLaunchKernelGGL(k_ref_tension, dim3((n_faces + 255) / 256), dim3(256), 0, s, d, n_faces, gamma, w, z_interface);
     hipLaunchKernelGGL(k_ref_gather, dim3((n_nodes + 255) / 256), dim3(256), 0, s, d, n_nodes);
@@ -1309,6 +1480,7 @@ void launch_spread(const Lattice& L, const Dev& d, int par, const float* rho_n, 
         hipLaunchKernelGGL(k_spread<true>, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par, rho_n, cs);
     else
         hipLaunchKernelGGL(k_spread<false>, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par, rho_n, cs);
+    if (d.det) hipLaunchKernelGGL(k_spread_gather_det, dim3(SPREAD_GRID), dim3(256), 0, s, L, d, par);
 }
 void launch_interp_advect(const Lattice& L, const Dev& d, int n_nodes, hipStream_t s) {
     if (n_nodes > 0)

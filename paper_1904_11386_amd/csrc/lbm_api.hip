@@ -231,6 +231,9 @@ std::string validate(const lbm_params* p) {
     if (!(p->rep_eps >= 0.0) || !isfinite(p->rep_eps)) return "rep_eps must be finite and >= 0";
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
     if (p->coupling != 0 && p->coupling != 1) return "coupling must be 0 (immersed boundary) or 1 (bounce-back)";
+    if (p->deterministic != 0 && p->deterministic != 1) return "deterministic must be 0 or 1";
+    if (p->deterministic && p->coupling == 1)
+        return "deterministic mode covers the immersed boundary (coupling 0) only";
     if (p->coupling == 1) {
         if (p->precision != LBM_FP32) return "the bounce-back coupling needs FP32 storage";
         if (p->walls != 0) return "the bounce-back coupling runs in a periodic box (walls = 0)";
@@ -407,6 +410,7 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     for (int k = 0; k < 2; ++k) { L.tau[k] = (float)p->tau[k]; L.omega[k] = (float)(1.0 / p->tau[k]); }
     for (int k = 0; k < 3; ++k) { L.uw_lo[k] = (float)p->wall_u_lo[k]; L.uw_hi[k] = (float)p->wall_u_hi[k]; }
     Dev& d = c->d;
+    d.det = p->deterministic ? 1 : 0;
     char* w = c->ws;
     d.f[0] = (void*)(w + lay.f[0]);
     d.f[1] = (void*)(w + lay.f[1]);
@@ -853,7 +857,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         launch_clear_tiles(L, d, par ^ 1, par, ncap, m);
     }
     if (fork) {
-        launch_cap_volume(d, c->n_faces, m);
+        launch_cap_volume(d, c->n_faces, ncap, m);
         launch_faces(d, c->n_faces, m);
         launch_node_gather(L, d, c->n_nodes, par, m);
         launch_bin_scan(d, c->n_nodes, par, m);
@@ -870,7 +874,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         (void)hipStreamWaitEvent(s, c->ev_join, 0);
     } else {
         mark(LBM_K_VOLUME);
-        if (ibm) launch_cap_volume(d, c->n_faces, s);
+        if (ibm) launch_cap_volume(d, c->n_faces, ncap, s);
         mark(LBM_K_FACES);
         if (ibm) launch_faces(d, c->n_faces, s);
         mark(LBM_K_NODES);
@@ -933,7 +937,7 @@ static void enqueue_bb_step(lbm_ctx* c, hipEvent_t* ev) {
     mark(LBM_K_DENSITY);
     launch_density(L, fin, rho_p, rho_n, false, d.cscale, nxt, d.dpart, s);
     mark(LBM_K_VOLUME);
-    launch_cap_volume(d, c->n_faces, s);
+    launch_cap_volume(d, c->n_faces, ncap, s);
     mark(LBM_K_FACES);
     launch_faces(d, c->n_faces, s);
     mark(LBM_K_NODES);
@@ -1254,6 +1258,11 @@ int lbm_observables(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
                 out->pending_momentum[j] += 0.5 * P[3 * b + j];
             }
     }
+    out->mass_ledger[0] = out->mass_ledger[1] = 0.0;
+    if (c->lay.bb) {
+        HIPCHK(c, hipMemcpyAsync(out->mass_ledger, d.bb_mass, 2 * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+    }
     if (caps)
         for (int k = 0; k < ncap; ++k) cap_obs_from_moments(c->caps[k], &mom[(size_t)k * MOM_STRIDE], c->p.z_interface,
                                                             caps[k]);
@@ -1308,6 +1317,11 @@ int lbm_observables_noalloc(lbm_ctx* c, lbm_obs* out, lbm_capsule_obs* caps) {
                     out->pending_momentum[j] += 0.5 * pb[3 * b + j];
                 }
         }
+    }
+    out->mass_ledger[0] = out->mass_ledger[1] = 0.0;
+    if (c->lay.bb) {
+        HIPCHK(c, hipMemcpyAsync(out->mass_ledger, d.bb_mass, 2 * 8, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
     }
     if (caps) {
         double mb[MOM_STRIDE];

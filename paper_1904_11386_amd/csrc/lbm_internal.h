@@ -172,6 +172,7 @@ struct Dev {
     double* P_cur;        // [nodes][3] momentum exchanged at the last streaming
     double* P_prev;       // [nodes][3] the one before
     double* QR;           // [nodes][3] fresh-node and Shan-Chen reactions of the step
+    int det;              // 1: the immersed boundary's sums in a fixed order (deterministic mode)
 };
 
 // sizes of the bounce-back coupling's lists and boxes
@@ -203,7 +204,7 @@ void launch_clear_tiles(const Lattice& L, Dev& d, int parity_prev, int parity_cu
                         hipStream_t s);
 void launch_advect_clear(const Lattice& L, Dev& d, int n_nodes, int parity_prev, int parity_cur, int n_caps,
                          hipStream_t s);
-void launch_cap_volume(const Dev& d, int n_faces, hipStream_t s);
+void launch_cap_volume(const Dev& d, int n_faces, int n_caps, hipStream_t s);
 void launch_faces(const Dev& d, int n_faces, hipStream_t s);
 void launch_node_gather(const Lattice& L, const Dev& d, int n_nodes, int parity, hipStream_t s);
 void launch_bin_scan(const Dev& d, int n_nodes, int parity, hipStream_t s);

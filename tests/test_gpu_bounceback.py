@@ -136,12 +136,17 @@ def test_prescribed_translation_with_mass_correction_parity():
     wl = W.bb_capsule(layered_z=13, theta=60.0, v=(0.02, 0.0, 0.0), prescribed=True)
     g, o = _compare(wl, 200, every=50)
     assert o.n_fresh > 50
-    m = g.observables()["mass"]
+    ob = g.observables()
+    m = ob["mass"]
     mo = o.mass().numpy()
     _say("  masses gpu", m.tolist(), "oracle", mo.tolist())
     # each refill adds mass the correction then steers back: the masses carry
     # the densities' own FP32 error (about 1e-6 relative here)
     assert np.allclose(m, mo, rtol=5e-6)
+    # the library's FP64 ledger is the mass change the oracle's correction reads
+    dm = mo - o.M0.numpy()
+    _say("  mass change: gpu ledger", ob["mass_ledger"].tolist(), "oracle", dm.tolist())
+    assert np.allclose(ob["mass_ledger"], dm, rtol=0, atol=5e-6 * mo.max())
 
 
 @pytest.mark.timeout(600)

@@ -14,7 +14,7 @@ pytestmark = pytest.mark.gpu
 
 def _same(a, b):
     assert a["step"] == b["step"]
-    for k in ("mass", "momentum", "particle_momentum", "pending_momentum"):
+    for k in ("mass", "momentum", "particle_momentum", "pending_momentum", "mass_ledger"):
         assert np.array_equal(a[k], b[k]), k
     assert len(a["caps"]) == len(b["caps"])
     for ca, cb in zip(a["caps"], b["caps"]):
