@@ -225,13 +225,14 @@ class Workload:
 
 
 
-def layered(nx, ny, nz, z_split):
-    """Component A at majority density for z < z_split, minority above; B the
-    opposite.  Returned float32 [nz, ny, nx]."""
+def layered(nx, ny, nz, z_split, rho=(RHO_MAJ, RHO_MIN)):
+    """Component A at majority density rho[0] for z < z_split, minority
+    rho[1] above; B the opposite.  Returned float32 [nz, ny, nx]."""
+    maj, mn = np.float32(rho[0]), np.float32(rho[1])
     z = np.arange(nz)[:, None, None]
     lower = np.broadcast_to(z < z_split, (nz, ny, nx))
-    rhoA = np.where(lower, RHO_MAJ, RHO_MIN).astype(np.float32)
-    rhoB = np.where(lower, RHO_MIN, RHO_MAJ).astype(np.float32)
+    rhoA = np.where(lower, maj, mn).astype(np.float32)
+    rhoB = np.where(lower, mn, maj).astype(np.float32)
     return np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB)
 
 
@@ -473,13 +474,14 @@ def bb_capsule(nx=24, ny=22, nz=26, centre=(11.37, 10.61, 12.83), radius=4.0, fr
     """One capsule for the bounce-back coupling (Sec. II.C-II.E) in a
     ragged periodic box, at a centre off the lattice's symmetry planes so
     that no lattice node lies on the membrane.  Densities: uniform `rho`
-    (A, B) everywhere, or a flat interface at layered_z (A below); interior
+    (A, B) everywhere, or a flat interface at layered_z (A below, at the
+    majority and minority densities rho[0], rho[1]); interior
     = (A, B) densities of the nodes inside the rest sphere shrunk by 0.3, or
     of the nodes where interior_mask [nz, ny, nx] is true, when given (the
     paper fills a capsule with the lower fluid's composition).  The
     capsule's velocity v, and whether it is prescribed, are inputs."""
     if layered_z is not None:
-        rhoA, rhoB = layered(nx, ny, nz, layered_z)
+        rhoA, rhoB = layered(nx, ny, nz, layered_z, rho)
     else:
         rhoA = np.full((nz, ny, nx), rho[0], np.float32)
         rhoB = np.full((nz, ny, nx), rho[1], np.float32)
@@ -496,7 +498,8 @@ def bb_capsule(nx=24, ny=22, nz=26, centre=(11.37, 10.61, 12.83), radius=4.0, fr
     zi = (layered_z - 0.5) if layered_z is not None else nz / 2
     return Workload("bb_capsule", nx, ny, nz, np.ascontiguousarray(rhoA), np.ascontiguousarray(rhoB), [cap],
                     tau=tau, G=G, z_interface=zi, wet_scale=wet_scale, coupling=1, node_mass=node_mass,
-                    mass_c0=C0, psi_kind=psi_kind)
+                    mass_c0=C0, psi_kind=psi_kind, rho_maj=float(np.float32(rho[0])),
+                    rho_min=float(np.float32(rho[1])))
 
 
 def bounce_back(wl: Workload, C0: float = 2500.0, node_mass: float = 5.0) -> Workload:
