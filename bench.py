@@ -77,14 +77,18 @@ def measured_traffic(workload, form):
 
 def lattice_source_hash():
     """First 16 hex digits of the SHA-256 of the lattice kernels' sources:
-    csrc/k_fluid.hip and the Lattice struct they read (the other structs of
-    lbm_internal.h do not reach these kernels)."""
+    csrc/k_fluid.hip, the Lattice struct they read and the block-shape
+    constants they are compiled with (the other parts of lbm_internal.h do
+    not reach these kernels)."""
     import hashlib
     h = hashlib.sha256()
     h.update(open(os.path.join(ROOT, "paper_1904_11386_amd/csrc/k_fluid.hip"), "rb").read())
     hdr = open(os.path.join(ROOT, "paper_1904_11386_amd/csrc/lbm_internal.h")).read()
     i0 = hdr.index("struct Lattice {")
     h.update(hdr[i0:hdr.index("\n};", i0)].encode())
+    for line in hdr.splitlines():
+        if line.startswith(("#define LBM_BX", "#define LBM_BY", "#define LBM_ZC")):
+            h.update(line.encode())
     return h.hexdigest()[:16]
 
 

@@ -35,7 +35,7 @@ constexpr int BOX = BIN + 3;   // spreading box edge: stencil reach of one bin's
 #define LBM_BX 128
 #endif
 #ifndef LBM_BY
-#define LBM_BY 2
+#define LBM_BY 4
 #endif
 #ifndef LBM_ZC
 #define LBM_ZC 8
