@@ -319,7 +319,10 @@ enum {
  * As lbm_step (without the mass check), and synchronises: HIP events are
  * recorded on the stream before each kernel group, and kernel_ms[LBM_NK]
  * receives the summed elapsed milliseconds of each group over the nsteps
- * (>= 1) steps. */
+ * (>= 1) steps.  A group that launches nothing in these steps reads 0; every
+ * other group's time includes the cost of its pair of events (about 5 us
+ * per step, what an empty group measures), which dominates the membrane
+ * groups of a few us. */
 int lbm_step_timed(lbm_ctx* ctx, int32_t nsteps, double* kernel_ms);
 
 /* FP64 observables of the current state: the component masses whose drift

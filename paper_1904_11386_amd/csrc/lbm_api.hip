@@ -261,6 +261,7 @@ struct lbm_ctx {
     hipStream_t side = nullptr;
     hipEvent_t ev_fork = nullptr, ev_join = nullptr;
     bool interp_pending = false;   // the last step's advection is still to launch
+    unsigned group_used = 0;       // bit k: kernel group k launched something in an event-timed step of the call
     int64_t max_nodes = 0, max_faces = 0;
     int64_t step = 0;
     int device = -1;               // the device current at lbm_init
@@ -843,6 +844,19 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
     const bool fork = overlap && !ev && fout && ibm;
     c->launched = true;
+    if (ev) {
+        // the groups this step launches kernels in (the others read 0 in lbm_step_timed)
+        unsigned u = 0;
+        auto use = [&](int k, bool on) { if (on) u |= 1u << k; };
+        use(LBM_K_CLEAR, c->interp_pending || ibm);
+        use(LBM_K_DENSITY, fout != nullptr);
+        for (int k : {LBM_K_VOLUME, LBM_K_FACES, LBM_K_NODES, LBM_K_SCAN, LBM_K_SCATTER, LBM_K_SPREAD}) use(k, ibm);
+        use(LBM_K_REPULSE, ibm && c->p.rep_eps > 0.0 && ncap > 1);
+        use(LBM_K_BEND, ibm && c->bending);
+        use(LBM_K_COLLIDE, fout != nullptr);
+        use(LBM_K_INTERP, fout != nullptr && ibm && advect);
+        c->group_used |= u;
+    }
     hipStream_t m = fork ? c->side : s;       // the membrane kernels' stream up to the join
     if (fork) {
         (void)hipEventRecord(c->ev_fork, s);
@@ -928,6 +942,14 @@ static void enqueue_bb_step(lbm_ctx* c, hipEvent_t* ev) {
     const float* rho_p = d.rho[nxt];
     auto mark = [&](int k) { if (ev) (void)hipEventRecord(ev[k], s); };
     c->launched = true;
+    if (ev) {
+        unsigned u = (1u << LBM_K_CLEAR) | (1u << LBM_K_DENSITY) | (1u << LBM_K_COLLIDE);
+        if (c->n_faces > 0) u |= (1u << LBM_K_VOLUME) | (1u << LBM_K_FACES);
+        if (c->n_nodes > 0) u |= (1u << LBM_K_NODES) | (1u << LBM_K_INTERP);
+        if (c->bending) u |= 1u << LBM_K_BEND;
+        if (ncap) u |= 1u << LBM_K_SPREAD;
+        c->group_used |= u;
+    }
     mark(LBM_K_CLEAR);
     launch_bb_geometry(L, d, c->bbz, ncap, c->n_faces, c->bb_primed, s);
     launch_bb_refill(L, d, c->bbz, c->bbk, fin, rho_p, ncap, s);
@@ -1152,6 +1174,7 @@ int lbm_step_timed(lbm_ctx* c, int32_t nsteps, double* kernel_ms) {
     if (nsteps < 1) return c->fail(LBM_EINVAL, "nsteps < 1");
     std::vector<hipEvent_t> ev((size_t)nsteps * (LBM_NK + 1));
     for (auto& e : ev) HIPCHK(c, hipEventCreate(&e));
+    c->group_used = 0;
     for (int k = 0; k < nsteps; ++k) enqueue_step(c, &ev[(size_t)k * (LBM_NK + 1)]);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1165,6 +1188,7 @@ int lbm_step_timed(lbm_ctx* c, int32_t nsteps, double* kernel_ms) {
     for (int j = 0; j < LBM_NK; ++j) kernel_ms[j] = 0.0;
     for (int k = 0; k < nsteps; ++k)
         for (int j = 0; j < LBM_NK; ++j) {
+            if (!(c->group_used >> j & 1u)) continue;     // (a group with no launch reads 0)
             float ms = 0.f;
             HIPCHK(c, hipEventElapsedTime(&ms, ev[(size_t)k * (LBM_NK + 1) + j], ev[(size_t)k * (LBM_NK + 1) + j + 1]));
             kernel_ms[j] += ms;

@@ -250,6 +250,31 @@ def test_graph_eager_and_chunked_stepping_agree():
         assert _rel(r, r0) < 1e-5
 
 
+def test_step_timed_reports_zero_for_groups_that_launch_nothing():
+    """lbm_step_timed: kernel groups with no launch in the timed steps read 0
+    (no repulsion, no bending here; no bins under the bounce-back coupling),
+    the others a positive time."""
+    wl = W.small(nx=40, ny=36, nz=44, ncap=2)
+    g = _sim(wl)
+    g.step(2)
+    k = g.step_timed(4)
+    g.close()
+    _say("immersed boundary groups (ms):", {a: round(b, 4) for a, b in k.items()})
+    assert k["repulse"] == 0.0 and k["bend"] == 0.0
+    for name in ("clear", "density", "volume", "faces", "nodes", "scan", "scatter", "spread", "collide", "interp"):
+        assert k[name] > 0.0, name
+    wb = W.bb_capsule(layered_z=13, theta=60.0, v=(0.02, 0.0, 0.0), prescribed=True)
+    g = _sim(wb)
+    g.step(2)
+    k = g.step_timed(4)
+    g.close()
+    _say("bounce-back groups (ms):", {a: round(b, 4) for a, b in k.items()})
+    for name in ("scan", "scatter", "repulse", "bend"):
+        assert k[name] == 0.0, name
+    for name in ("clear", "density", "volume", "faces", "nodes", "spread", "collide", "interp"):
+        assert k[name] > 0.0, name
+
+
 def test_first_step_node_forces_and_spread():
     wl = W.small(nx=40, ny=36, nz=44, ncap=2, theta=(55.0, 130.0), wet_scale=1.0)
     g = _sim(wl)
