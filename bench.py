@@ -378,47 +378,75 @@ def reference_sweep_leg(torch, betas=(10.0, 100.0, 1000.0), nus=(0.5, 0.9), ws=(
             "runs": out}
 
 
-def shape_error_leg(torch, betas=(100.0, 1000.0), steps=40000, chunk=5000, kV=2.0):
+def shape_error_leg(torch, betas=(100.0, 1000.0), steps=40000, chunk=5000, kV=2.0, coupling=0):
     """The shape errors of Sec. III.B (eq. interface:error) between the
     reference model and the coupled simulation of the same capsule (R0 = 10,
-    2562 nodes, B 1e-2, nu_s 0.9, softness beta), here immersed-boundary
-    coupled at the flat interface of a 64x64x48 two-component box (G 3.6,
-    theta 90 deg) and run to equilibrium.  Delta_p = (r_p^ref - r_p^sim) / R0
-    and Delta_i = (r_i^ref - r_i^sim) / R0 with r_p the half-axis normal to
-    the interface and r_i the mean of the two in-plane half-axes, both from
-    the volume second moments.  Both sides use the volume modulus kV = 2 (the
-    explicit coupling diverges within 250 steps at kV = 20)."""
+    2562 nodes, B 1e-2, nu_s 0.9, softness beta) at the flat interface of a
+    64x64x48 two-component box (G 3.6, theta 90 deg), run to equilibrium.
+    Delta_p = (r_p^ref - r_p^sim) / R0 and Delta_i = (r_i^ref - r_i^sim) / R0
+    with r_p the half-axis normal to the interface and r_i the mean of the two
+    in-plane half-axes, both from the volume second moments.
+    coupling 0: the immersed boundary, workloads' fluid (psi = rho, densities
+    0.7 / 0.04), volume modulus kV = 2 (the explicit coupling diverges within
+    250 steps at kV = 20).  coupling 1: the paper's bounce-back coupling with
+    its fluid (psi = 1 - exp(-rho), 0.7 / 0.042), inertial nodes of mass 5,
+    the capsule filled with the lower fluid and centred off the lattice's
+    symmetry planes; pass the paper's kV = 20.  The reference model runs with
+    the same kV."""
     import numpy as np
     from paper_1904_11386_amd import workloads
-    from paper_1904_11386_amd.binding import sim_from_workload
+    from paper_1904_11386_amd.binding import LbmError, sim_from_workload
     R0, gamma, B = 10.0, 0.0388, 1e-2
+    bb = coupling == 1
+    rho = (0.7, 0.042) if bb else (float(workloads.RHO_MAJ), float(workloads.RHO_MIN))
     out = {"workload": "64x64x48 box, interface z=23.5, one R0=10 capsule (2562 nodes), B 1e-2, nu_s 0.9, kV %g, "
-                       "theta 90 deg, G 3.6" % kV, "steps": steps, "runs": []}
+                       "theta 90 deg, G 3.6, %s" % (kV, "bounce-back coupling (node mass 5), psi 1 - exp(-rho), "
+                                                   "rho 0.7/0.042" if bb else "immersed boundary, psi rho"),
+           "steps": steps, "runs": []}
     for beta in betas:
-        print("bench: shape errors, beta %g" % beta, file=sys.stderr, flush=True)
+        print("bench: shape errors, beta %g, coupling %d" % (beta, coupling), file=sys.stderr, flush=True)
         ref = reference_model_leg(torch, kV=kV, beta=beta)
         kB = R0 * R0 * gamma / beta
         kS = kB / (B * R0 * R0)
-        ra, rb = workloads.layered(64, 64, 48, 24)
-        cap = workloads.Capsule(workloads._snap(np.array([32.0, 32.0, 24.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
-        wl = workloads.Workload("shape_error", 64, 64, 48, ra, rb, [cap], z_interface=23.5)
+        ra, rb = workloads.layered(64, 64, 48, 24, rho)
+        if bb:
+            c = workloads._snap(np.array([32.37, 32.61, 23.83]))
+            g = np.meshgrid(np.arange(48), np.arange(64), np.arange(64), indexing="ij")
+            ins = (g[2] - c[0]) ** 2 + (g[1] - c[1]) ** 2 + (g[0] - c[2]) ** 2 < (R0 - 0.3) ** 2
+            ra = np.where(ins, np.float32(rho[0]), ra).astype(np.float32)
+            rb = np.where(ins, np.float32(rho[1]), rb).astype(np.float32)
+            cap = workloads.Capsule(c, R0, 16, kS, 9.0, kV, 90.0, kB=kB)
+            wl = workloads.Workload("shape_error_bb", 64, 64, 48, ra, rb, [cap], z_interface=23.5, wet_scale=1.0,
+                                    coupling=1, node_mass=5.0, mass_c0=2500.0, psi_kind=1,
+                                    rho_maj=float(np.float32(rho[0])), rho_min=float(np.float32(rho[1])))
+        else:
+            cap = workloads.Capsule(workloads._snap(np.array([32.0, 32.0, 24.0])), R0, 16, kS, 9.0, kV, 90.0, kB=kB)
+            wl = workloads.Workload("shape_error", 64, 64, 48, ra, rb, [cap], z_interface=23.5)
         sim = sim_from_workload(wl)
         hist = []
+        err = None
         t0 = time.perf_counter()
-        for k in range(steps // chunk):
-            sim.step(chunk)
-            ax = sim.observables()["caps"][0]["axes"]
-            hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5),
-                         "r_i_mean": round(0.5 * float(ax[1] + ax[2]), 5)})
+        try:
+            for k in range(steps // chunk):
+                sim.step(chunk)
+                ob = sim.observables()["caps"][0]
+                ax = ob["axes"]
+                hist.append({"steps": (k + 1) * chunk, "r_p": round(float(ax[0]), 5),
+                             "r_i_mean": round(0.5 * float(ax[1] + ax[2]), 5), "com_z": round(float(ob["com"][2]), 4)})
+        except LbmError as e:
+            err = str(e)
         sim.synchronize()
         wall = time.perf_counter() - t0
         sim.close()
         del sim
         torch.cuda.empty_cache()
-        fin, rf = hist[-1], ref["relaxation"][-1]
-        out["runs"].append({"beta": beta, "wall_s": round(wall, 2), "coupled": hist, "reference": rf,
-                            "delta_p": round((rf["r_p"] - fin["r_p"]) / R0, 5),
-                            "delta_i": round((rf["r_i_mean"] - fin["r_i_mean"]) / R0, 5)})
+        rf = ref["relaxation"][-1]
+        run = {"beta": beta, "wall_s": round(wall, 2), "coupled": hist, "reference": rf, "error": err}
+        if hist and err is None:
+            fin = hist[-1]
+            run["delta_p"] = round((rf["r_p"] - fin["r_p"]) / R0, 5)
+            run["delta_i"] = round((rf["r_i_mean"] - fin["r_i_mean"]) / R0, 5)
+        out["runs"].append(run)
     return out
 
 
@@ -792,6 +820,9 @@ def main():
     ap.add_argument("--bb-mass-leg", action="store_true",
                     help="also run the paper's mass-conservation test of the bounce-back coupling (250 000 steps "
                          "for each mass-correction strength and colour)")
+    ap.add_argument("--bb-shape-leg", action="store_true",
+                    help="also run the shape errors of Sec. III.B under the bounce-back coupling with the paper's "
+                         "fluid (beta 100, 316, 1000; kV 20)")
     ap.add_argument("--bb-contact-angle-leg", action="store_true",
                     help="also measure the rest position of free capsules on a flat interface under the bounce-back "
                          "coupling against the paper's contact-angle law")
@@ -877,6 +908,8 @@ def main():
         out["bb_leg"] = bb_leg(torch)
     if args.bb_mass_leg:
         out["bb_mass"] = bb_mass_leg(torch)
+    if args.bb_shape_leg:
+        out["bb_shape"] = shape_error_leg(torch, betas=(100.0, 316.0, 1000.0), kV=20.0, coupling=1)
     if args.bb_contact_angle_leg:
         out["bb_contact_angle"] = bb_contact_angle_leg(torch)
     if args.reference_model_leg:
