@@ -661,16 +661,19 @@ def bb_leg(torch, name="c2", warmup=30, steps=300, v=(0.01, 0.0, 0.0)):
             "capsule_height_change": [round(c1["com"][2] - c0["com"][2], 4) for c0, c1 in zip(ob0["caps"], ob["caps"])]}
 
 
-def bb_contact_angle_leg(torch, colours=(0.259, 0.0, -0.259), steps=40000, chunk=5000, R=6.0, psi_kind=0):
+def bb_contact_angle_leg(torch, colours=(0.30, 0.0, -0.30, 0.61), steps=40000, chunk=5000, R=10.0, psi_kind=1,
+                         n=64, freq=16, rho=(0.7, 0.042), kS=0.5, node_mass=200.0, wet_scale=1.0):
     """The contact-angle law of the paper's coupling (Sec. III.D: a rigid
     particle's centre sits R cos(theta) from the interface, cos(theta) =
-    colour): a 48^3 flat interface (A below) relaxed for 3000 steps without a
-    capsule; in those densities a free capsule (R = 6, 642 nodes, kS 0.5,
-    node mass 200; its inside set to the relaxed A phase) placed with its
-    centre at -R colour from the interface, then `steps` free steps; its
-    offset dz from the interface far from it every `chunk` steps (positive
-    colour prefers A, below, so the law puts dz at -R colour).  The mass
-    check runs every 1000 steps at 1e-2 and the drift is reported."""
+    colour): an n^3 flat interface (A below) relaxed for 3000 steps without a
+    capsule; in those densities a free, stiff capsule (kS 0.5, node mass 200;
+    its inside set to the relaxed A phase) placed with its centre at
+    -R colour from the interface, then `steps` free steps; its offset dz from
+    the interface far from it every `chunk` steps (positive colour prefers A,
+    below, so the law puts dz at -R colour).  Defaults: the paper's R0 = 10
+    (2562 nodes) and fluid (psi = 1 - exp(-rho), G 3.6, densities 0.7 and
+    0.042) in a 64^3 box.  The mass check runs every 1000 steps at 1e-2 and
+    the drift is reported."""
     import dataclasses
     import math
     from paper_1904_11386_amd import workloads
@@ -678,29 +681,32 @@ def bb_contact_angle_leg(torch, colours=(0.259, 0.0, -0.259), steps=40000, chunk
 
     def far_interface(ra, rb):
         zs = []
-        for (y, x) in ((0, 0), (0, 24), (24, 0), (12, 36), (36, 12)):
+        for (y, x) in ((0, 0), (0, n // 2), (n // 2, 0), (n // 4, 3 * n // 4), (3 * n // 4, n // 4)):
             col = (ra[:, y, x] - rb[:, y, x]).astype(np.float64)
-            for z in range(8, 40):
+            for z in range(n // 6, 5 * n // 6):
                 if col[z] > 0 >= col[z + 1]:
                     zs.append(z + col[z] / (col[z] - col[z + 1]))
         return float(np.mean(zs)) if zs else float("nan")
 
     print("bench: bounce-back contact-angle leg", file=sys.stderr, flush=True)
-    base = dataclasses.replace(workloads.bb_capsule(nx=48, ny=48, nz=48, layered_z=24), psi_kind=psi_kind)
+    base = dataclasses.replace(workloads.bb_capsule(nx=n, ny=n, nz=n, layered_z=n // 2, rho=rho), psi_kind=psi_kind)
     g = sim_from_workload(dataclasses.replace(base, capsules=[], coupling=0))
     g.step(3000)
     ra0, rb0, _ = g.fields()
     g.close()
     zi = far_interface(ra0, rb0)
     amaj, bmin = float(ra0[5, 0, 0]), float(rb0[5, 0, 0])
-    out = {"workload": "48^3 periodic box, flat interface (A below, relaxed 3000 steps), one free capsule R=6 "
-                       "(642 nodes), kS 0.5, node mass 200, C0 2500, psi kind %d, G 3.6" % psi_kind,
+    out = {"workload": "%d^3 periodic box, flat interface (A below, relaxed 3000 steps), one free capsule R=%g "
+                       "(%d nodes), kS %g, node mass %g, C0 2500, psi %s, densities %g/%g, G 3.6, colour offset "
+                       "x %g" % (n, R, 10 * freq * freq + 2, kS, node_mass, "1 - exp(-rho)" if psi_kind else "rho",
+                                 rho[0], rho[1], wet_scale),
            "steps": steps, "interface_z": round(zi, 3), "A_phase": [round(amaj, 4), round(bmin, 4)], "runs": []}
-    gz = np.meshgrid(np.arange(48), np.arange(48), np.arange(48), indexing="ij")
+    gz = np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij")
     for colour in colours:
         theta = math.degrees(math.acos(colour))
-        wl = workloads.bb_capsule(nx=48, ny=48, nz=48, centre=(23.37, 24.61, zi - R * colour), radius=R, freq=8,
-                                  theta=theta, kS=0.5, layered_z=24, node_mass=200.0, psi_kind=psi_kind)
+        wl = workloads.bb_capsule(nx=n, ny=n, nz=n, centre=(n / 2 - 0.63, n / 2 + 0.61, zi - R * colour), radius=R,
+                                  freq=freq, theta=theta, kS=kS, layered_z=n // 2, node_mass=node_mass,
+                                  psi_kind=psi_kind, rho=rho, wet_scale=wet_scale)
         c = wl.capsules[0].centre
         ins = (gz[2] - c[0]) ** 2 + (gz[1] - c[1]) ** 2 + (gz[0] - c[2]) ** 2 < (R - 0.3) ** 2
         wl = dataclasses.replace(wl, rhoA=np.ascontiguousarray(np.where(ins, np.float32(amaj), ra0), np.float32),
@@ -728,7 +734,7 @@ def bb_contact_angle_leg(torch, colours=(0.259, 0.0, -0.259), steps=40000, chunk
 
 
 def bb_mass_leg(torch, c0s=(0.0, 500.0, 2500.0, 5000.0), colours=(0.0, 0.30, 0.61), steps=250000,
-                chunk=25000, R=10.0, psi_kind=1, rho=(0.7, 0.042)):
+                chunk=25000, R=10.0, psi_kind=1, rho=(0.7, 0.042), wet_scale=1.0):
     """The mass-conservation test of the paper's coupling (Sec. II.E, Fig.
     mass-conservation): a sphere of radius 10 (2562 nodes) at a flat interface
     of a (180, 60, 60) box, every node moved at a prescribed 1e-3 lu/step
@@ -747,15 +753,15 @@ def bb_mass_leg(torch, c0s=(0.0, 500.0, 2500.0, 5000.0), colours=(0.0, 0.30, 0.6
     from paper_1904_11386_amd import workloads
     from paper_1904_11386_amd.binding import LbmError, sim_from_workload
     out = {"workload": "(180, 60, 60) periodic box, flat interface at z=29.5 (A below), sphere R=10 (2562 nodes) "
-                       "translated at 1e-3 lu/step along x, bounce-back coupling, FP32, psi %s, rho %s/%s, G 3.6"
-                       % ("1 - exp(-rho)" if psi_kind else "rho", rho[0], rho[1]),
+                       "translated at 1e-3 lu/step along x, bounce-back coupling, FP32, psi %s, rho %s/%s, G 3.6, "
+                       "colour offset x %g" % ("1 - exp(-rho)" if psi_kind else "rho", rho[0], rho[1], wet_scale),
            "steps": steps, "runs": []}
     for colour in colours:
         for c0 in c0s:
             wl = workloads.bb_capsule(nx=180, ny=60, nz=60, centre=(90.37, 30.61, 29.5 - R * colour), radius=R,
                                       freq=16, theta=math.degrees(math.acos(colour)), kS=0.05, layered_z=30,
                                       v=(1e-3, 0.0, 0.0), prescribed=True, C0=c0, interior=rho, rho=rho,
-                                      psi_kind=psi_kind)
+                                      psi_kind=psi_kind, wet_scale=wet_scale)
             m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
             g = sim_from_workload(wl)
             err = None
@@ -820,6 +826,9 @@ def main():
     ap.add_argument("--bb-mass-leg", action="store_true",
                     help="also run the paper's mass-conservation test of the bounce-back coupling (250 000 steps "
                          "for each mass-correction strength and colour)")
+    ap.add_argument("--colour-offset-scale", type=float, default=1.0,
+                    help="scale of the colour offset (wet_scale) in the bounce-back mass and contact-angle legs: 1 = "
+                         "the normalisation as written, 0.25 = the one that reproduces the paper's contact-angle law")
     ap.add_argument("--bb-shape-leg", action="store_true",
                     help="also run the shape errors of Sec. III.B under the bounce-back coupling with the paper's "
                          "fluid (beta 100, 316, 1000; kV 20)")
@@ -907,11 +916,11 @@ def main():
     if args.bb_leg and args.headline_only:
         out["bb_leg"] = bb_leg(torch)
     if args.bb_mass_leg:
-        out["bb_mass"] = bb_mass_leg(torch)
+        out["bb_mass"] = bb_mass_leg(torch, wet_scale=args.colour_offset_scale)
     if args.bb_shape_leg:
         out["bb_shape"] = shape_error_leg(torch, betas=(100.0, 316.0, 1000.0), kV=20.0, coupling=1)
     if args.bb_contact_angle_leg:
-        out["bb_contact_angle"] = bb_contact_angle_leg(torch)
+        out["bb_contact_angle"] = bb_contact_angle_leg(torch, wet_scale=args.colour_offset_scale)
     if args.reference_model_leg:
         out["reference_model"] = reference_model_leg(torch)
     if args.shape_error_leg:
