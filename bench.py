@@ -734,7 +734,7 @@ def bb_contact_angle_leg(torch, colours=(0.30, 0.0, -0.30, 0.61), steps=40000, c
 
 
 def bb_mass_leg(torch, c0s=(0.0, 500.0, 2500.0, 5000.0), colours=(0.0, 0.30, 0.61), steps=250000,
-                chunk=25000, R=10.0, psi_kind=1, rho=(0.7, 0.042), wet_scale=1.0):
+                chunk=25000, R=10.0, psi_kind=1, rho=(0.7, 0.042), wet_scale=1.0, mass_fix=False):
     """The mass-conservation test of the paper's coupling (Sec. II.E, Fig.
     mass-conservation): a sphere of radius 10 (2562 nodes) at a flat interface
     of a (180, 60, 60) box, every node moved at a prescribed 1e-3 lu/step
@@ -754,7 +754,8 @@ def bb_mass_leg(torch, c0s=(0.0, 500.0, 2500.0, 5000.0), colours=(0.0, 0.30, 0.6
     from paper_1904_11386_amd.binding import LbmError, sim_from_workload
     out = {"workload": "(180, 60, 60) periodic box, flat interface at z=29.5 (A below), sphere R=10 (2562 nodes) "
                        "translated at 1e-3 lu/step along x, bounce-back coupling, FP32, psi %s, rho %s/%s, G 3.6, "
-                       "colour offset x %g" % ("1 - exp(-rho)" if psi_kind else "rho", rho[0], rho[1], wet_scale),
+                       "colour offset x %g%s" % ("1 - exp(-rho)" if psi_kind else "rho", rho[0], rho[1], wet_scale,
+                                                 ", FP32 mass compensated every 1000 steps" if mass_fix else ""),
            "steps": steps, "runs": []}
     for colour in colours:
         for c0 in c0s:
@@ -763,7 +764,8 @@ def bb_mass_leg(torch, c0s=(0.0, 500.0, 2500.0, 5000.0), colours=(0.0, 0.30, 0.6
                                       v=(1e-3, 0.0, 0.0), prescribed=True, C0=c0, interior=rho, rho=rho,
                                       psi_kind=psi_kind, wet_scale=wet_scale)
             m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
-            g = sim_from_workload(wl)
+            # mass_fix: the FP32 storage compensated to the initial mass plus the ledger every 1000 steps
+            g = sim_from_workload(wl, check_every=1000 if mass_fix else 0, mass_fix=int(mass_fix), mass_tol=0.1)
             err = None
             t0 = time.perf_counter()
             try:
@@ -829,6 +831,8 @@ def main():
     ap.add_argument("--colour-offset-scale", type=float, default=1.0,
                     help="scale of the colour offset (wet_scale) in the bounce-back mass and contact-angle legs: 1 = "
                          "the normalisation as written, 0.25 = the one that reproduces the paper's contact-angle law")
+    ap.add_argument("--fp32-mass-fix", action="store_true",
+                    help="the bounce-back mass leg with the FP32 storage's mass compensation (mass_fix)")
     ap.add_argument("--bb-shape-leg", action="store_true",
                     help="also run the shape errors of Sec. III.B under the bounce-back coupling with the paper's "
                          "fluid (beta 100, 316, 1000; kV 20)")
@@ -916,7 +920,7 @@ def main():
     if args.bb_leg and args.headline_only:
         out["bb_leg"] = bb_leg(torch)
     if args.bb_mass_leg:
-        out["bb_mass"] = bb_mass_leg(torch, wet_scale=args.colour_offset_scale)
+        out["bb_mass"] = bb_mass_leg(torch, wet_scale=args.colour_offset_scale, mass_fix=args.fp32_mass_fix)
     if args.bb_shape_leg:
         out["bb_shape"] = shape_error_leg(torch, betas=(100.0, 316.0, 1000.0), kV=20.0, coupling=1)
     if args.bb_contact_angle_leg:

@@ -151,6 +151,18 @@ typedef struct lbm_params {
                                A debugging mode: its gather costs more than
                                the atomic spreading.  The adjoint's own sums
                                keep their atomics.                            */
+    int32_t mass_fix;       /* 0 or 1, FP32 storage with check_every > 0 and
+                               walls 0 or 1.  1: at each mass check every
+                               population of a component is scaled so that the
+                               component's FP64 mass is the intended one: the
+                               initial mass (the FP64 sum of the densities
+                               given to lbm_init) plus, with coupling 1, the
+                               coupling's own change (lbm_obs.mass_ledger).
+                               FP32 rounding otherwise drifts the masses by a
+                               few 1e-9 per step in flows with interfaces; the
+                               FP16 form compensates every step by itself. The
+                               check then tests the drift from the intended
+                               mass.                                          */
 } lbm_params;
 
 typedef struct lbm_obs {

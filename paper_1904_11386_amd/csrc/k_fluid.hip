@@ -855,6 +855,27 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
     }
 }
 
+// FP32 storage, mass compensation at a mass check: each population of
+// component c at the fluid nodes times s_c, the ratio of the intended to
+// the stored FP64 mass of the component.
+__global__ __launch_bounds__(256) void k_scale_pops(pf2* __restrict__ f, float sa, float sb, Lattice L) {
+    const int64_t plane = (int64_t)L.nx * L.ny;
+    for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < L.n;
+         k += (int64_t)gridDim.x * blockDim.x) {
+        if (L.walls) {
+            const int y = (int)((k % plane) / L.nx);
+            if (y == 0 || y == L.ny - 1) continue;
+        }
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            pf2 p = f[(int64_t)i * L.n + k];
+            p.x *= sa;
+            p.y *= sb;
+            f[(int64_t)i * L.n + k] = p;
+        }
+    }
+}
+
 // FP64 mass and momentum of the post-collision state over fluid nodes:
 // per-block partial sums [mass A, mass B, px, py, pz].  FP16: decoded with
 // rho_enc = cscale * rho of the writing step.
@@ -1471,6 +1492,10 @@ void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const f
     else
         hipLaunchKernelGGL(k_reduce_fluid<false>, dim3(RED_BLOCKS), dim3(256), 0, s, (const pf2*)fpost, renc,
                            cscale, par, partial, L);
+}
+
+void launch_scale_pops(const Lattice& L, void* f, float sa, float sb, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale_pops, dim3(RED_BLOCKS), dim3(256), 0, s, (pf2*)f, sa, sb, L);
 }
 
 template <bool W, bool P>

@@ -232,6 +232,9 @@ std::string validate(const lbm_params* p) {
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
     if (p->coupling != 0 && p->coupling != 1) return "coupling must be 0 (immersed boundary) or 1 (bounce-back)";
     if (p->deterministic != 0 && p->deterministic != 1) return "deterministic must be 0 or 1";
+    if (p->mass_fix != 0 && p->mass_fix != 1) return "mass_fix must be 0 or 1";
+    if (p->mass_fix && (p->precision != LBM_FP32 || p->check_every <= 0 || p->walls == 2))
+        return "mass_fix needs FP32 storage, check_every > 0 and walls 0 or 1";
     if (p->deterministic && p->coupling == 1)
         return "deterministic mode covers the immersed boundary (coupling 0) only";
     if (p->coupling == 1) {
@@ -804,13 +807,28 @@ static int check_mass(lbm_ctx* c) {
     std::vector<double> part(RED_BLOCKS * 8);
     HIPCHK(c, hipMemcpyAsync(part.data(), d.red, part.size() * 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    // the intended masses: the start, plus the bounce-back coupling's own change when the storage is compensated
+    double target[2] = {c->mass0[0], c->mass0[1]};
+    if (c->p.mass_fix && c->lay.bb) {
+        double led[2];
+        HIPCHK(c, hipMemcpyAsync(led, d.bb_mass, sizeof led, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        target[0] += led[0];
+        target[1] += led[1];
+    }
+    double m[2] = {0.0, 0.0};
     for (int comp = 0; comp < 2; ++comp) {
-        double m = 0.0;
-        for (int b = 0; b < RED_BLOCKS; ++b) m += part[b * 8 + comp];
+        for (int b = 0; b < RED_BLOCKS; ++b) m[comp] += part[b * 8 + comp];
         // (on-site boundaries exchange mass with the outside: finiteness only)
-        if (!isfinite(m) || (!c->L.onsite && fabs(m - c->mass0[comp]) > c->p.mass_tol * fabs(c->mass0[comp])))
-            return c->fail(LBM_EUNSTABLE, "step %lld: mass of component %d is %.17g (start %.17g)",
-                           (long long)c->step, comp, m, c->mass0[comp]);
+        if (!isfinite(m[comp]) ||
+            (!c->L.onsite && fabs(m[comp] - target[comp]) > c->p.mass_tol * fabs(c->mass0[comp])))
+            return c->fail(LBM_EUNSTABLE, "step %lld: mass of component %d is %.17g (start %.17g, intended %.17g)",
+                           (long long)c->step, comp, m[comp], c->mass0[comp], target[comp]);
+    }
+    if (c->p.mass_fix && m[0] > 0.0 && m[1] > 0.0) {
+        launch_scale_pops(c->L, d.f[c->step & 1], (float)(target[0] / m[0]), (float)(target[1] / m[1]),
+                          c->stream);
+        HIPCHK(c, hipGetLastError());
     }
     return LBM_OK;
 }

@@ -196,6 +196,7 @@ void launch_collide(const Lattice& L, const void* fin, void* fout, const float* 
                     const float* fib, const int* tile_flag, float* u, bool has_ibm, bool macro, bool half,
                     const float* cscale, int par_prev, int par_cur, hipStream_t s);
 void launch_onsite(const Lattice& L, void* f, bool half, const float* rho_enc, const float* cs, hipStream_t s);
+void launch_scale_pops(const Lattice& L, void* f, float sa, float sb, hipStream_t s);
 void launch_reduce_fluid(const Lattice& L, const void* fpost, bool half, const float* renc,
                          const float* cscale, int par, double* partial, hipStream_t s);
 

@@ -66,6 +66,10 @@ int main() {
         p.deterministic = 1;
         EXPECT(ws(p, 162, 320, &n) == LBM_OK);
         p = base(16, 16, 16);
+        p.mass_fix = 1;
+        p.check_every = 10;
+        EXPECT(ws(p, 162, 320, &n) == LBM_OK);
+        p = base(16, 16, 16);
         p.coupling = 1;
         int64_t nbb = 0;
         EXPECT(ws(p, 162, 320, &nbb) == LBM_OK);
@@ -109,6 +113,10 @@ int main() {
         p = base(16, 16, 16); p.coupling = 1; p.node_mass = INFINITY; bad.push_back(p);
         p = base(16, 16, 16); p.coupling = 1; p.mass_c0 = -1.0; bad.push_back(p);
         p = base(16, 16, 16); p.deterministic = 2; bad.push_back(p);
+        p = base(16, 16, 16); p.mass_fix = 2; p.check_every = 10; bad.push_back(p);
+        p = base(16, 16, 16); p.mass_fix = 1; bad.push_back(p);                       // no mass check
+        p = base(16, 16, 16); p.mass_fix = 1; p.check_every = 10; p.precision = LBM_FP16; bad.push_back(p);
+        p = base(16, 16, 16); p.mass_fix = 1; p.check_every = 10; p.walls = 2; bad.push_back(p);
         p = base(16, 16, 16); p.deterministic = 1; p.coupling = 1; bad.push_back(p);
         p = base(3, 16, 16); bad.push_back(p);
         for (size_t k = 0; k < bad.size(); ++k) {
