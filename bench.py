@@ -2,9 +2,11 @@
 
     python bench.py [--steps K] [--warmup W] [--workload c5] [--gpus 1]
 
-Prints one JSON line.  A step is one full coupled time step (density pass,
+Prints one JSON line.  A step is one full coupled time step (densities,
 membrane forces, binning, spreading, fused collide-stream, interpolation and
-advection) over the whole lattice.  The headline workload is the largest
+advection) over the whole lattice; the FP32 form of the large lattices forms
+the densities inside the collide (one lattice pass), and the line also
+times the same steps with a separate density pass (`fp32_two_passes`).  The headline workload is the largest
 configuration, the 512^3 periodic box with 512 capsules; `value` is its
 MLUPS in FP32 storage = lattice nodes x steps / wall time of the timed
 region, with all state resident in HBM.  The FP16-storage form runs on the
@@ -14,7 +16,8 @@ against central differences) and the FP64 oracle on the host.
 
 roofline: the fused collide-stream kernel dominates; its achieved bandwidth
 is the algorithmic bytes per launch (152 B population reads + 152 B
-population writes + 8 B density reads per lattice node, FP32) over its
+population writes per lattice node in one pass, plus 8 B density reads in
+two, FP32) over its
 average duration from HIP events recorded on the library's stream around
 each launch, in a second timed region of the same number of steps run
 right after the first (the first replays HIP graphs, which carry no
@@ -43,6 +46,9 @@ HBM_PEAK_GBS = 8000.0
 # of binary16 populations + 8 B densities of step n + 8 B decode densities
 COLLIDE_BYTES_PER_LUP = {"fp32": 2 * 19 * 4 * 2 + 2 * 4, "fp16": 2 * 19 * 2 * 2 + 2 * 4 + 2 * 4}
 DENSITY_BYTES_PER_LUP = {"fp32": 2 * 19 * 4 + 2 * 4, "fp16": 2 * 19 * 2 + 2 * 4 + 2 * 4}
+# one lattice pass (FP32): the collide reads and writes the populations only
+# (152 + 152 B); it forms the densities from what it pulls
+ONE_PASS_BYTES_PER_LUP = 2 * 19 * 4 * 2
 
 WORKLOAD_TEXT = {
     "c2": "128^3 periodic two-component box, flat interface at z=64, 8 capsules R=8 (2562-node "
@@ -567,15 +573,16 @@ def precision_study(torch, steps):
     return out
 
 
-def run_form(torch, wl, form, warmup, steps, traffic=None):
+def run_form(torch, wl, form, warmup, steps, traffic=None, lattice_passes=0):
     """`steps` graph-replayed whole steps of one storage form after `warmup`,
     then the same number of event-timed steps for the per-kernel split.
     Returns MLUPS, ms per step, per-kernel ms per step, and the roofline block
     of the fused collide kernel: its algorithmic bytes per launch over its
-    average launch duration (HIP events on the library's stream)."""
+    average launch duration (HIP events on the library's stream).
+    lattice_passes as in lbm_params (0: the library's choice)."""
     from paper_1904_11386_amd.binding import LBM_FP16, LBM_FP32, sim_from_workload
     N = wl.n_lattice
-    sim = sim_from_workload(wl, precision=LBM_FP16 if form == "fp16" else LBM_FP32)
+    sim = sim_from_workload(wl, precision=LBM_FP16 if form == "fp16" else LBM_FP32, lattice_passes=lattice_passes)
     sim.step(warmup)
     sim.synchronize()
     torch.cuda.synchronize()
@@ -592,18 +599,24 @@ def run_form(torch, wl, form, warmup, steps, traffic=None):
     mlups = N * steps / wall / 1e6
     t_col = kms["collide"] / steps * 1e-3
     t_den = kms["density"] / steps * 1e-3
-    bpl = COLLIDE_BYTES_PER_LUP[form]
+    # (the density group launches nothing when the collide forms the densities)
+    one = t_den == 0.0
+    bpl = ONE_PASS_BYTES_PER_LUP if one else COLLIDE_BYTES_PER_LUP[form]
+    lattice_bytes = bpl if one else bpl + DENSITY_BYTES_PER_LUP[form]
     achieved = bpl * N / t_col / 1e9
     m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
     return {
         "mlups": round(mlups, 2), "ms_per_step": round(wall / steps * 1e3, 5), "wall_s": wall,
+        "lattice_passes": 1 if one else 2,
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                     "kernel": "k_collide (%s storage)" % form, "bytes_per_launch": bpl * N,
-                     "bytes_per_lup": bpl, "avg_launch_ms": round(t_col * 1e3, 5)},
-        "density_pass_gbs": round(DENSITY_BYTES_PER_LUP[form] * N / t_den / 1e9, 1),
-        # whole step: MLUPS times the two lattice passes' algorithmic bytes, over the peak
-        "effective_hbm_frac": round(mlups * 1e6 * (bpl + DENSITY_BYTES_PER_LUP[form]) / 1e9 / HBM_PEAK_GBS, 4),
+                     "kernel": "k_collide (%s storage, %s)" % (form, "one lattice pass" if one else "two passes"),
+                     "bytes_per_launch": bpl * N, "bytes_per_lup": bpl, "avg_launch_ms": round(t_col * 1e3, 5)},
+        "density_pass_gbs": None if one else round(DENSITY_BYTES_PER_LUP[form] * N / t_den / 1e9, 1),
+        # whole step: MLUPS times the lattice passes' algorithmic bytes, over the peak
+        "effective_hbm_frac": round(mlups * 1e6 * lattice_bytes / 1e9 / HBM_PEAK_GBS, 4),
+        # the same against the one-pass minimum of the method (304 B), for every form alike
+        "effective_hbm_frac_vs_one_pass_min": round(mlups * 1e6 * ONE_PASS_BYTES_PER_LUP / 1e9 / HBM_PEAK_GBS, 4),
         "fp64_mass_drift": float(np.abs(obs["mass"] / m0 - 1).max()),
         "kernels_ms_per_step": {k: round(v / steps, 5) for k, v in kms.items()},
     }
@@ -800,7 +813,7 @@ def ratio_leg(torch, name, warmup, steps):
     for form in ("fp32", "fp16"):
         print("bench: %s leg, %s form" % (name, form), file=sys.stderr, flush=True)
         r = run_form(torch, wl, form, warmup, steps)
-        out[form] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"],
+        out[form] = {"mlups": r["mlups"], "ms_per_step": r["ms_per_step"], "lattice_passes": r["lattice_passes"],
                      "collide_gbs": r["roofline"]["achieved"], "collide_frac": r["roofline"]["frac"],
                      "effective_hbm_frac": r["effective_hbm_frac"], "kernels_ms_per_step": r["kernels_ms_per_step"]}
     out["fp16_over_fp32"] = round(out["fp16"]["mlups"] / out["fp32"]["mlups"], 3)
@@ -820,6 +833,8 @@ def main():
                     help="only the headline workload's storage forms (for profiling that configuration)")
     ap.add_argument("--no-c3-leg", action="store_true", help="skip the 256^3 FP16/FP32 leg")
     ap.add_argument("--no-c2-leg", action="store_true", help="skip the 128^3 leg")
+    ap.add_argument("--no-two-pass-leg", action="store_true",
+                    help="skip the headline workload's FP32 form in two lattice passes")
     ap.add_argument("--no-adjoint-leg", action="store_true")
     ap.add_argument("--no-bb-leg", action="store_true",
                     help="skip the 128^3 workload under the paper's bounce-back coupling")
@@ -889,7 +904,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": WORKLOAD_TEXT.get(args.workload, args.workload), "name": args.workload,
                    "lattice": [wl.nx, wl.ny, wl.nz], "capsules": len(wl.capsules),
-                   "membrane_nodes": int(wl.meshes()[0].sum()), "storage": forms[0]},
+                   "membrane_nodes": int(wl.meshes()[0].sum()), "storage": forms[0],
+                   "lattice_passes": head["lattice_passes"]},
         "roofline": head["roofline"],
         "kernels_ms_per_step": head["kernels_ms_per_step"],
         "density_pass_gbs": head["density_pass_gbs"],
@@ -906,6 +922,17 @@ def main():
                             "effective_hbm_frac": r16["effective_hbm_frac"],
                             "fp64_mass_drift": r16["fp64_mass_drift"],
                             "kernels_ms_per_step": r16["kernels_ms_per_step"]}
+    if not args.headline_only and not args.no_two_pass_leg and "fp32" in res and head["lattice_passes"] == 1:
+        # the same FP32 steps with a density pass and the collide, for comparison
+        print("bench: %s, fp32 form in two lattice passes" % args.workload, file=sys.stderr, flush=True)
+        r2 = run_form(torch, wl, "fp32", args.warmup, args.steps, lattice_passes=2)
+        out["fp32_two_passes"] = {"value": r2["mlups"], "unit": "MLUPS", "ms_per_step": r2["ms_per_step"],
+                                  "one_pass_speedup": round(res["fp32"]["mlups"] / r2["mlups"], 3),
+                                  "roofline": r2["roofline"], "density_pass_gbs": r2["density_pass_gbs"],
+                                  "effective_hbm_frac": r2["effective_hbm_frac"],
+                                  "kernels_ms_per_step": r2["kernels_ms_per_step"]}
+        if "fp16_form" in out:
+            out["fp16_form"]["ratio_vs_fp32_two_passes"] = round(out["fp16_form"]["value"] / r2["mlups"], 3)
     if not args.headline_only:
         if not args.no_c3_leg and args.workload != "c3":
             out["c3_leg"] = ratio_leg(torch, "c3", 50, 200)

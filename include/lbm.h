@@ -163,6 +163,17 @@ typedef struct lbm_params {
                                FP16 form compensates every step by itself. The
                                check then tests the drift from the intended
                                mass.                                          */
+    int32_t lattice_passes; /* passes over the lattice per step, results equal
+                               bit for bit either way: 2 a density pass and the
+                               collide (Sec. II.A then Sec. II.D); 1 the collide
+                               forms the densities of its block and halo from
+                               the pulled populations itself, with the
+                               immersed boundary's tiles given a density pass
+                               of their own for the wettability reaction
+                               (needs FP32 storage, walls 0, coupling 0 and
+                               ring_len 0, else LBM_EINVAL); 0 chosen by the
+                               library: 1 where allowed and the populations
+                               exceed 512 MiB, else 2.                        */
 } lbm_params;
 
 typedef struct lbm_obs {

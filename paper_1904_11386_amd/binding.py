@@ -32,7 +32,7 @@ class Params(C.Structure):
                 ("ring_len", C.c_int32), ("stream_policy", C.c_int32), ("zchunk", C.c_int32),
                 ("psi_kind", C.c_int32), ("rep_eps", C.c_double), ("rep_d0", C.c_double),
                 ("coupling", C.c_int32), ("node_mass", C.c_double), ("mass_c0", C.c_double),
-                ("deterministic", C.c_int32), ("mass_fix", C.c_int32)]
+                ("deterministic", C.c_int32), ("mass_fix", C.c_int32), ("lattice_passes", C.c_int32)]
 
 
 class Obs(C.Structure):
@@ -123,7 +123,7 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
                 rho_maj=0.7, rho_min=0.04, z_interface=0.0, precision=LBM_FP32, n_slots=0,
                 check_every=0, mass_tol=1e-3, wet_scale=1.0, use_graphs=1, ring_len=0, stream_policy=0,
                 zchunk=0, rep_eps=0.0, rep_d0=1.25, psi_kind=0, coupling=0, node_mass=5.0, mass_c0=2500.0,
-                deterministic=0, mass_fix=0):
+                deterministic=0, mass_fix=0, lattice_passes=0):
     p = Params()
     p.nx, p.ny, p.nz = nx, ny, nz
     p.precision = precision
@@ -151,6 +151,7 @@ def make_params(nx, ny, nz, tau=(1.0, 1.0), G=3.6, walls=0, wall_u_lo=(0, 0, 0),
     p.mass_c0 = mass_c0
     p.deterministic = deterministic
     p.mass_fix = mass_fix
+    p.lattice_passes = lattice_passes
     return p
 
 
@@ -370,7 +371,7 @@ class Sim:
 
 
 def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="cuda", use_graphs=1, ring_len=0,
-                      stream_policy=0, zchunk=0, mass_tol=1e-3, deterministic=0, mass_fix=0):
+                      stream_policy=0, zchunk=0, mass_tol=1e-3, deterministic=0, mass_fix=0, lattice_passes=0):
     """Build a Sim for a seeded workload (paper_1904_11386_amd.workloads)."""
     npc, fpc, xyz, tri = wl.meshes()
     p = make_params(wl.nx, wl.ny, wl.nz, tau=wl.tau, G=wl.G, walls=wl.walls, wall_u_lo=wl.wall_u_lo,
@@ -381,7 +382,7 @@ def sim_from_workload(wl, precision=LBM_FP32, n_slots=0, check_every=0, device="
                     stream_policy=stream_policy, zchunk=zchunk, rep_eps=wl.rep_eps, rep_d0=wl.rep_d0,
                     psi_kind=wl.psi_kind, coupling=getattr(wl, "coupling", 0),
                     node_mass=getattr(wl, "node_mass", 5.0), mass_c0=getattr(wl, "mass_c0", 2500.0),
-                    deterministic=deterministic, mass_fix=mass_fix)
+                    deterministic=deterministic, mass_fix=mass_fix, lattice_passes=lattice_passes)
     s = Sim(p, wl.rhoA, wl.rhoB, max_nodes=int(npc.sum()), max_faces=int(fpc.sum()), device=device)
     if len(npc):
         kS, Cs, kV, th = wl.cap_params()

@@ -590,7 +590,14 @@ __global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ 
 // boundary's force and virtual densities, corrections dS^A, dS^B to the
 // Shan-Chen neighbour sums from neighbours across a membrane (fib fields
 // 0..2 and 3..5), added before the force is formed.
-template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI, bool SHARP = false>
+//
+// ONE (one lattice pass): the densities of the ring are formed here from
+// pulled populations instead of read from the density pass.  Per plane
+// each thread pulls its own node (kept in registers for its collide one
+// plane later) and one halo cell: thread row 0 the row below the block,
+// row 1 the row above, twelve lanes of row 2 the corners and the x-halo;
+// the ring values are the same bit for bit as the two-pass ones.
+template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI, bool SHARP = false, bool ONE = false>
 __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
@@ -600,12 +607,15 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                                                  int par_prev, int par_cur, Lattice L) {
     __shared__ Ring2 sp;                         // psi + phi at time n (A, B)
     __shared__ Ring2 se;                         // decode densities rho_enc^{n-1} (FP16)
+    static_assert(!ONE || (!WALLS && !HALF && !MACRO && !SHARP), "one pass: FP32, periodic, stepping only");
     const int tx = threadIdx.x, ty = uniform_ty();
     const int tid = ty * BX + tx;
     int bx, by, bz;
     // y-strips on cache-sized lattices; on larger ones the plain order
-    // measured faster for this kernel (the density passes gain either way)
-    block_xyz(bx, by, bz, CACHED);
+    // measured faster for this kernel (the density passes gain either way);
+    // the one-pass form re-reads its halo rows from the neighbouring blocks'
+    // reads, which y-strips keep on one die (10% faster at 512^3)
+    block_xyz(bx, by, bz, CACHED || ONE);
     const int x0 = bx * BX, y0 = by * BY, z0 = bz * L.zc;
     const int z1 = min(z0 + L.zc, L.nz);
     const int64_t N = L.n;
@@ -654,19 +664,79 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
         if constexpr (HALF) stage_store2(se, ne, zz, z0, tid);
     };
 
-    load_plane(z0 - 1);
-    store_plane(z0 - 1);
-    load_plane(z0);
-    store_plane(z0);
     const int x = x0 + tx, y = y0 + ty;
     const bool active = x < L.nx && y < L.ny && (!WALLS || (y > 0 && y < L.ny - 1));
-    Raw<HALF> rcur;
+    // one pass: the ring cell of a pulled node, psi(rho) plus the virtual
+    // density where its tile is flagged (as stage_load forms it)
+    auto none = [](int, int, int, float&, float&) {};
+    auto ring_cell = [&](const auto& R, int gx, int gy, int zw) {   // (generic: built for ONE only)
+        Pulled A, B;
+        decode<false, false>(L, gy, R, 0.f, 0.f, none, A, B);
+        float va = sum_pop(A), vb = sum_pop(B);
+        if constexpr (PSI) { va = psi_exp(va); vb = psi_exp(vb); }
+        if (IBM && near_ibm) {
+            const uint32_t pos = (uint32_t)((zw * L.ny + gy) * L.nx + gx);
+            const bool flag = tile_flag[((zw >> 3) * L.nty + (gy >> 3)) * L.ntx + (gx >> 3)] != 0;
+            const float pa = ldx(fib + 3 * N, pos), pb = ldx(fib + 4 * N, pos);
+            va += flag ? pa : 0.0f;
+            vb += flag ? pb : 0.0f;
+        }
+        return make_float2(va, vb);
+    };
+    // (the node itself wraps, so that a partial block still fills the ring
+    // cells its active neighbours read)
+    const int ix = wrapi(x, L.nx), iy = wrapi(y, L.ny);
+    const int hrow = ty == 0 ? 0 : BY + 1;                  // thread rows 0, 1: a halo row each
+    const int hy = wrapi(y0 - 1 + hrow, L.ny);
+    // the two edge cells (x0 - 1, x0 + BX) of the BY + 2 ring rows: ring row
+    // r by wavefront 2 BX / 64 + r % (waves left), one row per pass, so that
+    // every load of a pass has one row
+    constexpr int WV = BX * BY / 64, W0 = 2 * BX / 64, WR = WV - W0;
+    static_assert(BY >= 3 && WR >= 1, "halo rows per wavefront");
+    const int wv = __builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63;
+    const int ehx = wrapi(lane == 0 ? x0 - 1 : x0 + BX, L.nx), elx = lane == 0 ? 0 : BX + 1;
+    auto one_plane = [&](int zz, auto& R) {
+        const int zw = wrapi(zz, L.nz), sl = (zz - z0 + 1) % 3;
+        load_raw<false, false, CACHED>(fin, L, ((int64_t)zw * L.ny + iy) * L.nx + ix, ix, iy, zw, R);
+        sp.v[sl][ty + 1][tx + 1] = ring_cell(R, ix, iy, zw);
+        __builtin_amdgcn_sched_barrier(0);
+        if (ty < 2) {
+            std::remove_reference_t<decltype(R)> H;
+            load_raw<false, false, CACHED>(fin, L, ((int64_t)zw * L.ny + hy) * L.nx + ix, ix, hy, zw, H);
+            sp.v[sl][hrow][tx + 1] = ring_cell(H, ix, hy, zw);
+        }
+        if (wv >= W0) {
+            for (int r = wv - W0; r < BY + 2; r += WR) {
+                const int ey = wrapi(y0 - 1 + r, L.ny);
+                std::remove_reference_t<decltype(R)> H;
+                if (lane < 2) {
+                    load_raw<false, false, CACHED>(fin, L, ((int64_t)zw * L.ny + ey) * L.nx + ehx, ehx, ey, zw, H);
+                    sp.v[sl][r][elx] = ring_cell(H, ehx, ey, zw);
+                }
+            }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    Raw<HALF> rcur, rnext;
+    if constexpr (ONE) {
+        one_plane(z0 - 1, rnext);
+        one_plane(z0, rcur);
+    } else {
+        load_plane(z0 - 1);
+        store_plane(z0 - 1);
+        load_plane(z0);
+        store_plane(z0);
+    }
 #pragma unroll 1
     for (int z = z0; z < z1; ++z) {
-        load_plane(z + 1);
-        store_plane(z + 1);
+        if constexpr (ONE) {
+            one_plane(z + 1, rnext);
+        } else {
+            load_plane(z + 1);
+            store_plane(z + 1);
+        }
         __syncthreads();
-        if (active) load_raw<WALLS, HALF, CACHED>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
+        if (!ONE && active) load_raw<WALLS, HALF, CACHED>(fin, L, ((int64_t)z * L.ny + y) * L.nx + x, x, y, z, rcur);
         if (active) {
             const uint32_t row = (uint32_t)((z * L.ny + y) * L.nx), xo = (uint32_t)x;
             const int s0 = (z - z0 + 1) % 3;
@@ -772,7 +842,9 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                 GPtr<PopT<HALF>> fi = fo;
                 int64_t Ns = N;                    // direction stride, rebuilt per plane
                 uint32_t xs = xo;                  // 32-bit lane offset, per plane
-                asm volatile("" : "+s"(Ns), "+v"(xs));
+                // (the one-pass form with the immersed boundary trips the
+                // backend with these hints: it takes plain pointer steps)
+                if constexpr (!(ONE && IBM)) asm volatile("" : "+s"(Ns), "+v"(xs));
                 if constexpr (HALF) {
                     // BGK and the encode in one step, per opposite pair
                     // (c_{k+1} = -c_k, equal weights).  With feq_i = w_i t_i,
@@ -840,7 +912,7 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                             fs[c] = P.f[i] + L.omega[c] * (feq - P.f[i]);
                             rest[c] -= fs[c];
                         }
-                        fi = gstep(fi, Ns);
+                        fi = (ONE && IBM) ? fi + Ns : gstep(fi, Ns);
                         store_popx<!CACHED>(fi, xs, pack<HALF>(fs[0], fs[1]));
                     }
                     // rest populations close the node's mass
@@ -851,7 +923,39 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
             const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
             u_out[node] = u_out[N + node] = u_out[2 * N + node] = 0.f;
         }
+        if constexpr (ONE) rcur = rnext;
         __syncthreads();
+    }
+}
+
+// One lattice pass with capsules: this step's densities on the tiles the
+// immersed boundary touches, which the spreading's wettability reaction
+// reads before the collide forms them again (the same sums, so the same
+// values).  A bin's reaction reads cells -2 .. +6 around it and its
+// stencils flag the tiles of cells -1 .. +5; with every lattice edge a
+// multiple of the tile both lie in the same tiles, else (dil) each tile is
+// widened by one cell, wrapped.
+__global__ __launch_bounds__(256) void k_density_tiles(const pf2* __restrict__ fin, float* __restrict__ rho_out,
+                                                       const int* __restrict__ touched, const int* __restrict__ count,
+                                                       int dil, Lattice L) {
+    const int nt = *count;
+    const int E = TILE + 2 * dil, E3 = E * E * E;
+    auto none = [](int, int, int, float&, float&) {};
+    for (int e = blockIdx.x; e < nt; e += gridDim.x) {
+        const int t = touched[e];
+        const int tx = t % L.ntx, ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
+        for (int c = threadIdx.x; c < E3; c += blockDim.x) {
+            int x = tx * TILE - dil + c % E, y = ty * TILE - dil + (c / E) % E, z = tz * TILE - dil + c / (E * E);
+            if (!dil && (x >= L.nx || y >= L.ny || z >= L.nz)) continue;
+            x = wrapi(x, L.nx);
+            y = wrapi(y, L.ny);
+            z = wrapi(z, L.nz);
+            const int64_t node = ((int64_t)z * L.ny + y) * L.nx + x;
+            Pulled A, B;
+            pull<false, false>(fin, L, node, x, y, z, 0.f, 0.f, none, A, B);
+            rho_out[node] = sum_pop(A);
+            rho_out[L.n + node] = sum_pop(B);
+        }
     }
 }
 
@@ -1425,6 +1529,12 @@ void launch_density(const Lattice& L, const void* fin, const float* rho_prev, fl
 #undef LD_H
 }
 
+void launch_density_tiles(const Lattice& L, const void* fin, float* rho_out, const int* touched, const int* count,
+                          hipStream_t s) {
+    const int dil = (L.nx % TILE || L.ny % TILE || L.nz % TILE) ? 1 : 0;
+    hipLaunchKernelGGL(k_density_tiles, dim3(2048), dim3(256), 0, s, (const pf2*)fin, rho_out, touched, count, dil, L);
+}
+
 void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale, int par_cur,
                        double* mass_out, hipStream_t s) {
     const int nb = (int)density_blocks(L, true);
@@ -1437,6 +1547,17 @@ static void launch_collide_t(const Lattice& L, const void* fin, void* fout, cons
                              const float* cscale, int par_prev, int par_cur, hipStream_t s) {
     dim3 grid((L.nx + BX - 1) / BX, (L.ny + BY - 1) / BY, (L.nz + L.zc - 1) / L.zc);
     dim3 block(BX, BY);
+    if constexpr (!W && !M && !H && !S) {
+        if (L.one) {
+            if (L.cached)
+                hipLaunchKernelGGL((k_collide<W, I, M, H, true, P, S, true>), grid, block, 0, s, (const PopT<H>*)fin,
+                                   (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+            else
+                hipLaunchKernelGGL((k_collide<W, I, M, H, false, P, S, true>), grid, block, 0, s, (const PopT<H>*)fin,
+                                   (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+            return;
+        }
+    }
     // the velocity read-back (M) writes no populations; it runs in one policy
     if constexpr (!M) {
         if (L.cached) {

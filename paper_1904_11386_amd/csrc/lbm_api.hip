@@ -198,9 +198,30 @@ Layout make_layout(const lbm_params* p, int64_t max_nodes, int64_t max_faces) {
 // z planes per lattice block.  A longer march amortises the two halo planes
 // of the ring; the FP16 form gains from it when the grid still holds at
 // least 8192 blocks (32 per compute unit), the FP32 form does not.
+// Population streams: a buffer of at most 512 MiB (128^3 in FP32) streams
+// with non-temporal loads and cached stores, a larger one the other way round.
+bool lattice_cached(const lbm_params* p) {
+    const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+    if (p->stream_policy == 0) return N * 2 * Q * (p->precision == LBM_FP16 ? 2 : 4) <= ((int64_t)512 << 20);
+    return p->stream_policy == 1;
+}
+
+bool one_pass_allowed(const lbm_params* p) {
+    return p->precision == LBM_FP32 && p->walls == 0 && p->coupling == 0 && p->ring_len == 0;
+}
+
+// One lattice pass where allowed and the populations exceed the caches'
+// reach: at 256^3 and 512^3 it is 1.24x the two passes' speed on the
+// lattice, at 128^3 0.98x.
+bool one_pass_for(const lbm_params* p) {
+    if (p->lattice_passes == 1) return true;
+    return p->lattice_passes == 0 && one_pass_allowed(p) && !lattice_cached(p);
+}
+
 int zc_for(const lbm_params* p) {
     const int64_t cols = (int64_t)((p->nx + BX - 1) / BX) * ((p->ny + BY - 1) / BY);
-    if (p->precision == LBM_FP16 && cols * ((p->nz + 2 * ZC - 1) / (2 * ZC)) >= 8192) return 2 * ZC;
+    if ((p->precision == LBM_FP16 || one_pass_for(p)) && cols * ((p->nz + 2 * ZC - 1) / (2 * ZC)) >= 8192)
+        return 2 * ZC;
     return ZC;
 }
 
@@ -232,6 +253,9 @@ std::string validate(const lbm_params* p) {
     if (p->rep_eps > 0.0 && !(p->rep_d0 > 0.0 && p->rep_d0 <= 2.0)) return "rep_d0 must be in (0, 2]";
     if (p->coupling != 0 && p->coupling != 1) return "coupling must be 0 (immersed boundary) or 1 (bounce-back)";
     if (p->deterministic != 0 && p->deterministic != 1) return "deterministic must be 0 or 1";
+    if (p->lattice_passes < 0 || p->lattice_passes > 2) return "lattice_passes must be 0, 1 or 2";
+    if (p->lattice_passes == 1 && !one_pass_allowed(p))
+        return "lattice_passes 1 needs FP32 storage, walls 0, coupling 0 and ring_len 0";
     if (p->mass_fix != 0 && p->mass_fix != 1) return "mass_fix must be 0 or 1";
     if (p->mass_fix && (p->precision != LBM_FP32 || p->check_every <= 0 || p->walls == 2))
         return "mass_fix needs FP32 storage, check_every > 0 and walls 0 or 1";
@@ -402,12 +426,8 @@ int lbm_init(const lbm_params* p, const float* rhoA, const float* rhoB, void* wo
     L.n = N;
     L.psi_exp = p->psi_kind;
     L.zc = p->zchunk ? p->zchunk : zc_for(p);
-    // a population buffer of at most 512 MiB (128^3 in FP32) streams with
-    // non-temporal loads and cached stores, a larger one the other way round
-    if (p->stream_policy == 0)
-        L.cached = (int64_t)N * 2 * Q * (p->precision == LBM_FP16 ? 2 : 4) <= ((int64_t)512 << 20) ? 1 : 0;
-    else
-        L.cached = p->stream_policy == 1 ? 1 : 0;
+    L.cached = lattice_cached(p) ? 1 : 0;
+    L.one = one_pass_for(p) ? 1 : 0;
     L.walls = p->walls == 1 ? 1 : 0;
     L.onsite = p->walls == 2 ? 1 : 0;
     L.G = (float)p->G;
@@ -867,7 +887,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         unsigned u = 0;
         auto use = [&](int k, bool on) { if (on) u |= 1u << k; };
         use(LBM_K_CLEAR, c->interp_pending || ibm);
-        use(LBM_K_DENSITY, fout != nullptr);
+        use(LBM_K_DENSITY, fout != nullptr && !L.one);
         for (int k : {LBM_K_VOLUME, LBM_K_FACES, LBM_K_NODES, LBM_K_SCAN, LBM_K_SCATTER, LBM_K_SPREAD}) use(k, ibm);
         use(LBM_K_REPULSE, ibm && c->p.rep_eps > 0.0 && ncap > 1);
         use(LBM_K_BEND, ibm && c->bending);
@@ -897,7 +917,9 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
         (void)hipEventRecord(c->ev_join, m);
     }
     mark(LBM_K_DENSITY);
-    if (fout) launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
+    // (one pass: the collide forms the densities; an adjoint recompute,
+    // fout NULL, never runs in that form)
+    if (fout && !L.one) launch_density(L, fin, rho_p, rho_n, half, d.cscale, nxt, d.dpart, s);
     // (on-site boundaries exchange mass with the outside, so there is no
     // fixed total to restore: their FP16 form keeps unit compensation)
     if (half && fout && !L.onsite)
@@ -922,6 +944,10 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     mark(LBM_K_BEND);
     if (ibm && c->bending) launch_bending(d, c->n_nodes, s);
     mark(LBM_K_SPREAD);
+    // one pass: the densities of the touched tiles, for the wettability
+    // reaction (timed with the spreading)
+    // (counters[par] counts the touched tiles of list par)
+    if (ibm && L.one && fout) launch_density_tiles(L, fin, rho_n, d.touched[par], d.counters + par, s);
     if (ibm) launch_spread(L, d, par, rho_n, cs, s);
     mark(LBM_K_COLLIDE);
     if (!fout) {
@@ -1383,6 +1409,9 @@ int lbm_get_fields(lbm_ctx* c, float* rhoA, float* rhoB, float* u) {
     hipStream_t s = c->stream;
     const int last = (int)((c->step - 1) & 1);
     const int64_t N = c->L.n;
+    // one pass leaves the density field written on the touched tiles only:
+    // form it everywhere (the same sums) before it is read back
+    if (c->L.one) launch_density(c->L, d.f[last], d.rho[last ^ 1], d.rho[last], false, d.cscale, last ^ 1, d.dpart, s);
     if (u) {
         launch_collide(c->L, d.f[last], nullptr, d.rho[last], d.rho[last ^ 1], d.fib, d.tile_flag, d.u,
                        c->n_nodes > 0, true, c->half(), d.cscale, last ^ 1, last, s);

@@ -59,6 +59,7 @@ struct Lattice {
     int walls;             // half-way bounce-back walls: solid rows y = 0 and ny - 1
     int onsite;            // on-site velocity boundaries on the fluid rows y = 0 and ny - 1
     int sharp;             // the bounce-back coupling: flagged tiles carry Shan-Chen sum corrections
+    int one;               // one lattice pass: k_collide forms the step's densities itself
     float G;
     float tau[2];
     float omega[2];        // 1/tau
@@ -190,6 +191,8 @@ void launch_init_rest(const Lattice& L, void* f, const float* rhoA, const float*
 int64_t density_blocks(const Lattice& L, bool half);
 void launch_density(const Lattice& L, const void* fin, const float* rho_prev, float* rho_out, bool half,
                     const float* cscale, int par_prev, double* partial, hipStream_t s);
+void launch_density_tiles(const Lattice& L, const void* fin, float* rho_out, const int* touched, const int* count,
+                          hipStream_t s);
 void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale,
                        int par_cur, double* mass_out, hipStream_t s);
 void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,

@@ -69,6 +69,16 @@ def test_workspace_bytes_and_validation():
                 dict(coupling=1, node_mass=float("inf")), dict(coupling=1, mass_c0=-1.0)):
         pb = B.make_params(16, 16, 16, **bad)
         assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL, bad
+    # one lattice pass: FP32 storage, periodic, the immersed boundary, no adjoint ring
+    for bad in (dict(lattice_passes=3), dict(lattice_passes=-1), dict(lattice_passes=1, precision=B.LBM_FP16),
+                dict(lattice_passes=1, walls=1), dict(lattice_passes=1, walls=2),
+                dict(lattice_passes=1, coupling=1), dict(lattice_passes=1, ring_len=4)):
+        pb = B.make_params(16, 16, 16, **bad)
+        assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_EINVAL, bad
+    for good in (dict(lattice_passes=1), dict(lattice_passes=1, psi_kind=1), dict(lattice_passes=2, walls=1),
+                 dict(lattice_passes=0, precision=B.LBM_FP16), dict(lattice_passes=0, coupling=1)):
+        pb = B.make_params(16, 16, 16, **good)
+        assert lib.lbm_workspace_bytes(C.byref(pb), 0, 0, C.byref(out)) == B.LBM_OK, good
     pb = B.make_params(16, 16, 16, coupling=1)
     assert lib.lbm_workspace_bytes(C.byref(pb), 162, 320, C.byref(out)) == B.LBM_OK
     n_bb = out.value
