@@ -597,8 +597,8 @@ __global__ __launch_bounds__(1024) void k_compensate(const double* __restrict__ 
 // plane later) and one halo cell: thread row 0 the row below the block,
 // row 1 the row above, twelve lanes of row 2 the corners and the x-halo;
 // the ring values are the same bit for bit as the two-pass ones.
-template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI, bool SHARP = false, bool ONE = false>
-__global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
+template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI, bool SHARP, bool ONE>
+__device__ __forceinline__ void collide_body(const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout,
                                                  const float* __restrict__ rho_n,
                                                  const float* __restrict__ rho_p,
                                                  const float* __restrict__ fib,
@@ -838,13 +838,14 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                 }
                 // direction bases advance by the stride in scalar registers,
                 // so each store is a scalar base plus the lane's x offset
-                const GPtr<PopT<HALF>> fo = (GPtr<PopT<HALF>>)(fout + row);
+                // (row is wave-uniform; the one-pass form says so explicitly,
+                // or the backend fails to keep the store bases in scalars)
+                const GPtr<PopT<HALF>> fo =
+                    (GPtr<PopT<HALF>>)(fout + (ONE ? (uint32_t)__builtin_amdgcn_readfirstlane(row) : row));
                 GPtr<PopT<HALF>> fi = fo;
                 int64_t Ns = N;                    // direction stride, rebuilt per plane
                 uint32_t xs = xo;                  // 32-bit lane offset, per plane
-                // (the one-pass form with the immersed boundary trips the
-                // backend with these hints: it takes plain pointer steps)
-                if constexpr (!(ONE && IBM)) asm volatile("" : "+s"(Ns), "+v"(xs));
+                asm volatile("" : "+s"(Ns), "+v"(xs));
                 if constexpr (HALF) {
                     // BGK and the encode in one step, per opposite pair
                     // (c_{k+1} = -c_k, equal weights).  With feq_i = w_i t_i,
@@ -912,7 +913,7 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
                             fs[c] = P.f[i] + L.omega[c] * (feq - P.f[i]);
                             rest[c] -= fs[c];
                         }
-                        fi = (ONE && IBM) ? fi + Ns : gstep(fi, Ns);
+                        fi = gstep(fi, Ns);
                         store_popx<!CACHED>(fi, xs, pack<HALF>(fs[0], fs[1]));
                     }
                     // rest populations close the node's mass
@@ -927,6 +928,29 @@ __global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(const PopT
         __syncthreads();
     }
 }
+
+#define COLLIDE_ARGS                                                                                        \
+    const PopT<HALF>* __restrict__ fin, PopT<HALF>* __restrict__ fout, const float* __restrict__ rho_n,     \
+        const float* __restrict__ rho_p, const float* __restrict__ fib, const int* __restrict__ tile_flag, \
+        float* __restrict__ u_out, const float* __restrict__ cscale, int par_prev, int par_cur, Lattice L
+template <bool WALLS, bool IBM, bool MACRO, bool HALF, bool CACHED, bool PSI, bool SHARP = false>
+__global__ __launch_bounds__(BX * BY) LBM_COLLIDE_ATTR void k_collide(COLLIDE_ARGS) {
+    collide_body<WALLS, IBM, MACRO, HALF, CACHED, PSI, SHARP, false>(fin, fout, rho_n, rho_p, fib, tile_flag, u_out,
+                                                                     cscale, par_prev, par_cur, L);
+}
+// The one-pass form at four waves per SIMD (at most 128 VGPRs: two blocks per
+// compute unit, so one block's barrier wait overlaps the other's work);
+// left to itself the compiler takes 145 and fits one block (10.5 against
+// 9.2 ms at 512^3).
+template <bool IBM, bool CACHED, bool PSI>
+__global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(4, 8))) void k_collide_one(
+    const pf2* __restrict__ fin, pf2* __restrict__ fout, const float* __restrict__ rho_n,
+    const float* __restrict__ rho_p, const float* __restrict__ fib, const int* __restrict__ tile_flag,
+    float* __restrict__ u_out, const float* __restrict__ cscale, int par_prev, int par_cur, Lattice L) {
+    collide_body<false, IBM, false, false, CACHED, PSI, false, true>(fin, fout, rho_n, rho_p, fib, tile_flag, u_out,
+                                                                     cscale, par_prev, par_cur, L);
+}
+#undef COLLIDE_ARGS
 
 // One lattice pass with capsules: this step's densities on the tiles the
 // immersed boundary touches, which the spreading's wettability reaction
@@ -1550,11 +1574,11 @@ static void launch_collide_t(const Lattice& L, const void* fin, void* fout, cons
     if constexpr (!W && !M && !H && !S) {
         if (L.one) {
             if (L.cached)
-                hipLaunchKernelGGL((k_collide<W, I, M, H, true, P, S, true>), grid, block, 0, s, (const PopT<H>*)fin,
-                                   (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+                hipLaunchKernelGGL((k_collide_one<I, true, P>), grid, block, 0, s, (const pf2*)fin, (pf2*)fout, rho_n,
+                                   rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
             else
-                hipLaunchKernelGGL((k_collide<W, I, M, H, false, P, S, true>), grid, block, 0, s, (const PopT<H>*)fin,
-                                   (PopT<H>*)fout, rho_n, rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
+                hipLaunchKernelGGL((k_collide_one<I, false, P>), grid, block, 0, s, (const pf2*)fin, (pf2*)fout, rho_n,
+                                   rho_prev, fib, tile_flag, u, cscale, par_prev, par_cur, L);
             return;
         }
     }
