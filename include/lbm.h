@@ -320,7 +320,9 @@ int lbm_step(lbm_ctx* ctx, int32_t nsteps);
  * (labels, link list, fresh nodes, the bounce-back of the crossing
  * populations and the tile flags), LBM_K_SPREAD the Shan-Chen sum across
  * the membranes and LBM_K_INTERP the node update; the bin and spreading
- * groups are empty. */
+ * groups are empty.  In one lattice pass (lattice_passes) LBM_K_DENSITY
+ * launches nothing (the collide forms the densities) and LBM_K_SPREAD
+ * begins with the densities of the immersed boundary's tiles. */
 enum {
     LBM_K_CLEAR = 0,    /* zero last step's immersed-boundary tiles        */
     LBM_K_DENSITY = 1,  /* density pass over the lattice                   */
