@@ -912,6 +912,7 @@ def main():
         "copy_ceiling_gbs": round(copy_gbs, 1),
         "collide_frac_of_copy": round(head["roofline"]["achieved"] / copy_gbs, 4),
         "effective_hbm_frac": head["effective_hbm_frac"],
+        "effective_hbm_frac_vs_one_pass_min": head["effective_hbm_frac_vs_one_pass_min"],
         "fp64_mass_drift": head["fp64_mass_drift"],
     }
     if "fp16" in res and forms[0] == "fp32":
@@ -930,6 +931,7 @@ def main():
                                   "one_pass_speedup": round(res["fp32"]["mlups"] / r2["mlups"], 3),
                                   "roofline": r2["roofline"], "density_pass_gbs": r2["density_pass_gbs"],
                                   "effective_hbm_frac": r2["effective_hbm_frac"],
+                                  "effective_hbm_frac_vs_one_pass_min": r2["effective_hbm_frac_vs_one_pass_min"],
                                   "kernels_ms_per_step": r2["kernels_ms_per_step"]}
         if "fp16_form" in out:
             out["fp16_form"]["ratio_vs_fp32_two_passes"] = round(out["fp16_form"]["value"] / r2["mlups"], 3)
