@@ -131,3 +131,38 @@ def test_one_pass_step_timing_groups():
     assert t["density"] == 0.0
     assert t["collide"] > 0.0 and t["spread"] > 0.0
     g.close()
+
+
+def test_one_pass_checkpoint_replay_bit_identical():
+    """N steps, save, M steps; load, the same M steps again: the same state
+    bit for bit under the deterministic spreading (the state slot holds the
+    populations and nodes; one pass leaves the density field written on the
+    touched tiles only, and nothing it reads depends on the rest)."""
+    from paper_1904_11386_amd.binding import sim_from_workload
+    wl = W.small(nx=40, ny=36, nz=44, ncap=3)
+    g = sim_from_workload(wl, lattice_passes=1, deterministic=1, n_slots=1)
+    g.step(30)
+    g.save(0)
+    g.step(20)
+    a = _state(g, True)
+    g.load(0)
+    g.step(20)
+    b = _state(g, True)
+    g.close()
+    for k in a:
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_one_pass_with_mass_fix_holds_the_mass():
+    """FP32 mass compensation at the mass checks in one pass: after 2000
+    steps with checks every 200 the FP64 masses equal the initial ones to
+    the rounding of the scaling, as in two passes."""
+    from paper_1904_11386_amd.binding import sim_from_workload
+    wl = W.small(nx=40, ny=36, nz=44, ncap=3)
+    m0 = np.array([wl.rhoA.astype(np.float64).sum(), wl.rhoB.astype(np.float64).sum()])
+    g = sim_from_workload(wl, lattice_passes=1, check_every=200, mass_fix=1, mass_tol=1e-2)
+    g.step(2000)
+    rel = (g.observables()["mass"] - m0) / m0
+    g.close()
+    _say("  one pass, mass_fix: relative mass change %s" % rel.tolist())
+    assert np.abs(rel).max() < 2e-7
