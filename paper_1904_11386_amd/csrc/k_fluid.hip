@@ -959,17 +959,26 @@ __global__ __launch_bounds__(BX * BY) __attribute__((amdgpu_waves_per_eu(4, 8)))
 // stencils flag the tiles of cells -1 .. +5; with every lattice edge a
 // multiple of the tile both lie in the same tiles, else (dil) each tile is
 // widened by one cell, wrapped.
+// Without widening, a touched tile is handled with its x partner (tiles 2k
+// and 2k + 1): rows of 16 cells read whole 128-byte lines of each direction
+// (an 8-cell row reads half of one); a pair whose even tile is touched is
+// handled from that tile only.
 __global__ __launch_bounds__(256) void k_density_tiles(const pf2* __restrict__ fin, float* __restrict__ rho_out,
                                                        const int* __restrict__ touched, const int* __restrict__ count,
-                                                       int dil, Lattice L) {
+                                                       const int* __restrict__ tile_flag, int dil, Lattice L) {
     const int nt = *count;
-    const int E = TILE + 2 * dil, E3 = E * E * E;
+    const int E = TILE + 2 * dil, EX = dil ? E : 2 * TILE, N3 = EX * E * E;
     auto none = [](int, int, int, float&, float&) {};
     for (int e = blockIdx.x; e < nt; e += gridDim.x) {
         const int t = touched[e];
-        const int tx = t % L.ntx, ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
-        for (int c = threadIdx.x; c < E3; c += blockDim.x) {
-            int x = tx * TILE - dil + c % E, y = ty * TILE - dil + (c / E) % E, z = tz * TILE - dil + c / (E * E);
+        int tx = t % L.ntx;
+        const int ty = (t / L.ntx) % L.nty, tz = t / (L.ntx * L.nty);
+        if (!dil) {
+            if ((tx & 1) && tile_flag[t - 1] != 0) continue;      // (block-uniform)
+            tx &= ~1;
+        }
+        for (int c = threadIdx.x; c < N3; c += blockDim.x) {
+            int x = tx * TILE - dil + c % EX, y = ty * TILE - dil + (c / EX) % E, z = tz * TILE - dil + c / (EX * E);
             if (!dil && (x >= L.nx || y >= L.ny || z >= L.nz)) continue;
             x = wrapi(x, L.nx);
             y = wrapi(y, L.ny);
@@ -1554,9 +1563,10 @@ void launch_density(const Lattice& L, const void* fin, const float* rho_prev, fl
 }
 
 void launch_density_tiles(const Lattice& L, const void* fin, float* rho_out, const int* touched, const int* count,
-                          hipStream_t s) {
+                          const int* tile_flag, hipStream_t s) {
     const int dil = (L.nx % TILE || L.ny % TILE || L.nz % TILE) ? 1 : 0;
-    hipLaunchKernelGGL(k_density_tiles, dim3(2048), dim3(256), 0, s, (const pf2*)fin, rho_out, touched, count, dil, L);
+    hipLaunchKernelGGL(k_density_tiles, dim3(2048), dim3(256), 0, s, (const pf2*)fin, rho_out, touched, count,
+                       tile_flag, dil, L);
 }
 
 void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale, int par_cur,

@@ -952,7 +952,7 @@ static void enqueue_core(lbm_ctx* c, const void* fin, void* fout, float* rho_n, 
     // one pass: the densities of the touched tiles, for the wettability
     // reaction (timed with the spreading)
     // (counters[par] counts the touched tiles of list par)
-    if (ibm && L.one && fout) launch_density_tiles(L, fin, rho_n, d.touched[par], d.counters + par, s);
+    if (ibm && L.one && fout) launch_density_tiles(L, fin, rho_n, d.touched[par], d.counters + par, d.tile_flag, s);
     if (ibm) launch_spread(L, d, par, rho_n, cs, s);
     mark(LBM_K_COLLIDE);
     if (!fout) {

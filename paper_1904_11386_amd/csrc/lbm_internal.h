@@ -192,7 +192,7 @@ int64_t density_blocks(const Lattice& L, bool half);
 void launch_density(const Lattice& L, const void* fin, const float* rho_prev, float* rho_out, bool half,
                     const float* cscale, int par_prev, double* partial, hipStream_t s);
 void launch_density_tiles(const Lattice& L, const void* fin, float* rho_out, const int* touched, const int* count,
-                          hipStream_t s);
+                          const int* tile_flag, hipStream_t s);
 void launch_compensate(const Lattice& L, const double* partial, double m0a, double m0b, float* cscale,
                        int par_cur, double* mass_out, hipStream_t s);
 void launch_collide(const Lattice& L, const void* fin, void* fout, const float* rho_n, const float* rho_prev,
