@@ -19,7 +19,11 @@
 // node by itself, so a step is two passes over the lattice:
 //   k_density  rho^n(x) = sum_i f*_i(x - c_i)                (Sec. II.A)
 //   k_collide  pull, Shan-Chen + wettability + immersed-boundary force,
-//              equilibrium-velocity shift, BGK (Sec. II.A), store f*.
+//              equilibrium-velocity shift, BGK (Sec. II.A), store f*;
+// or, in FP32 on periodic lattices, one: k_collide_one forms the densities
+// of its block and a one-node halo from the populations it pulls (the
+// same sums), and k_density_tiles gives the immersed boundary's tiles
+// theirs for the wettability reaction that precedes the collide.
 // k_collide marches a BX x BY column of nodes up z and keeps three planes
 // of psi + phi (pseudo-potential plus virtual density) for the column and
 // its one-node halo in LDS, so the 36 neighbour reads per node come from
